@@ -1,0 +1,155 @@
+/*
+ * tt.h -- C-ABI of the MI355X tropical tensor-network library (libtt.so).
+ *
+ * Problem (Eq. 1 of Liu, Wang & Zhang, "Tropical tensor network for ground
+ * states of spin glasses"): E(sigma) = -sum_{i<j} J_ij s_i s_j - sum_i h_i s_i
+ * over sigma in {+1,-1}^n on a graph with edges (i, j). The library contracts
+ * the tensor network of Sec. II (bond tensors [[J,-J],[-J,J]], field vectors
+ * (h,-h), copy tensors as shared spin labels) over the max-plus semiring of
+ * Eq. (2), which yields -E*; with the (x, n) tuples of Eq. (4) it also yields
+ * the ground-state degeneracy g; walking the contraction backwards through
+ * its argmax choices (Sec. IV) yields one ground state sigma* and the
+ * gradients d(E*)/d(J_ij) = -s_i s_j and d(E*)/d(h_i) = -s_i.
+ *
+ * Spin encoding: index 0 <-> sigma = +1, index 1 <-> sigma = -1.
+ *
+ * Conventions for every call:
+ *   - Return value: TT_OK (0) or a negative tt_status; the message of the
+ *     last failure on the calling thread is returned by tt_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Arrays named "device" are device pointers on the current HIP device,
+ *     owned by the caller, laid out densely as stated. Host arrays are owned
+ *     by the caller and only read during the call.
+ *   - Plans are owned by the library (tt_plan_destroy frees them) and may be
+ *     shared by concurrent calls on different streams only if each call uses
+ *     its own plan; device workspace is cached inside the plan.
+ *   - Compute calls enqueue on `stream` (a hipStream_t, NULL = default
+ *     stream) and return once enqueued; outputs are valid after the stream
+ *     synchronises. tt_count additionally synchronises `stream` (its CRT
+ *     guard reads residues on the host).
+ */
+#ifndef TT_H
+#define TT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tt_status {
+  TT_OK = 0,
+  TT_E_INVAL = -1,          /* bad graph, null pointer, bad size or option */
+  TT_E_DTYPE = -2,          /* dtype not supported by this call */
+  TT_E_RANGE = -3,          /* exact-integer range of the value type exceeded */
+  TT_E_TOOBIG = -4,         /* planned device memory exceeds the budget */
+  TT_E_COUNT_OVERFLOW = -5, /* reserved: strict-mode count overflow */
+  TT_E_DEVICE = -6,         /* a HIP runtime call failed (message has the code) */
+  TT_E_NOMEM = -7           /* host allocation failed */
+} tt_status;
+
+typedef enum tt_dtype {
+  TT_F32 = 0,               /* J, h as float32; energies computed in float32 */
+  TT_I32 = 1                /* J, h as int32; computed exactly (|values| < 2^24) */
+} tt_dtype;
+
+typedef enum tt_order_kind {
+  TT_ORDER_GREEDY = 0,      /* host greedy search for a spin order (restarts) */
+  TT_ORDER_GIVEN = 1,       /* caller's spin order (opts.order) */
+  TT_ORDER_CHIMERA = 2      /* row-chain plan for a chimera graph of K_{4,4} cells */
+} tt_order_kind;
+
+/* Planner options. Zero-initialised fields take the defaults in brackets. */
+typedef struct tt_plan_opts {
+  int32_t kind;             /* tt_order_kind [GREEDY] */
+  const int32_t* order;     /* GIVEN: permutation of 0..n-1 (host) */
+  uint64_t seed;            /* GREEDY: seed of the randomised tie-breaks [0] */
+  int32_t trials;           /* GREEDY: restarts, best plan kept [32] */
+  int32_t has_field;        /* 1: instances carry fields h (else h = 0) */
+  int32_t tile_bits;        /* resident bits per tile of the energy path [14] */
+  int32_t count_tile_bits;  /* resident bits per tile of the count path [12] */
+  int32_t chimera_rows;     /* CHIMERA: unit-cell rows  */
+  int32_t chimera_cols;     /* CHIMERA: unit-cell columns */
+  int64_t max_bytes;        /* device memory budget of one call [7/8 of free] */
+} tt_plan_opts;
+
+typedef struct tt_plan_stats {
+  int32_t n_spins;
+  int64_t n_edges;
+  int32_t width;            /* log2 of the largest state (entries per instance) */
+  int32_t n_ops;            /* absorb/relabel/eliminate operations */
+  int32_t n_passes;         /* energy-path passes (kernel launches per batch) */
+  int32_t n_count_passes;   /* count-path passes */
+  double terms;             /* max-plus terms per instance (one add + one max) */
+  double reduce_terms;      /* of which the final reduction (max over the last state) */
+  double entry_updates;     /* state entries read+written per instance (energy path) */
+} tt_plan_stats;
+
+typedef struct tt_plan tt_plan;
+
+/* Build a contraction plan for a graph (Sec. III: order, then pairwise
+ * contraction). edges: host int32 [n_edges][2], 0 <= e[0] < e[1] < n_spins,
+ * no duplicates. The graph is copied. *out receives the plan. */
+int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges,
+                   const tt_plan_opts* opts, tt_plan** out);
+int tt_plan_info(const tt_plan* plan, tt_plan_stats* out);
+/* Host copy of the spin order the plan sweeps (n_spins int32). */
+int tt_plan_order(const tt_plan* plan, int32_t* order_out);
+void tt_plan_destroy(tt_plan* plan);
+
+/* Ground-state energy E* (Eq. 1, not its negative) of `batch` instances that
+ * share the plan's graph. J: device [batch][n_edges] of dtype; h: device
+ * [batch][n_spins] or NULL (required iff the plan has fields);
+ * energy: device double [batch]. */
+int tt_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
+                const void* h, double* energy, void* stream);
+
+/* Energy plus one ground state (Sec. IV): sigma device int8 [batch][n_spins]
+ * in {+1,-1}; dJ device float [batch][n_edges] = -s_i s_j and dh device
+ * float [batch][n_spins] = -s_i (either may be NULL). Ties resolve to the
+ * first argument of every max along the plan. */
+int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
+                const void* h, double* energy, int8_t* sigma, float* dJ,
+                float* dh, void* stream);
+
+/* Ground-state energy and degeneracy g (Eq. 4) for integer couplings.
+ * J: device int32 [batch][n_edges]; h: device int32 [batch][n_spins] or NULL.
+ * energy: host int64 [batch]; residues: host uint64 [batch][3], g mod the
+ * three moduli of tt_count_moduli. g counts sigma and -sigma separately. */
+int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h,
+             int64_t* energy, uint64_t* residues, void* stream);
+/* The three prime moduli (2^61-1, 2^61-31, 2^61-45). */
+int tt_count_moduli(uint64_t moduli_out[3]);
+/* Exact g from its residues by the Chinese remainder theorem, as a decimal
+ * string (host). Exact whenever g < the product of the moduli (~2^183). */
+int tt_count_to_decimal(const uint64_t residues[3], char* buf, size_t len);
+
+/* Uneven batch: n_inst instances, each with its own plan, contracted forward
+ * and backward together (one launch per pass index across instances).
+ * J: device float/int32 concatenated, instance i at j_off[i] (host int64);
+ * sigma: device int8 concatenated at s_off[i] (host int64) (may be NULL);
+ * dJ: device float laid out like J (may be NULL); energy: device double
+ * [n_inst]. Fields are not supported here (h = 0). */
+int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype,
+                       const void* J, const int64_t* j_off, double* energy,
+                       int8_t* sigma, const int64_t* s_off, float* dJ,
+                       void* stream);
+
+/* Per-kernel timing on the call's stream, for measurement tools: when on,
+ * every pass launch is bracketed by HIP events; tt_prof_read returns the
+ * summed milliseconds and launch count of the named kernel family
+ * ("sweep_pass", "sweep_backward", "final_reduce", "count_pass") since the
+ * last reset. Timing adds no work to the launches themselves. */
+int tt_prof_enable(int32_t on);
+int tt_prof_reset(void);
+int tt_prof_read(const char* name, double* total_ms, int64_t* launches);
+
+/* Thread-local message of the last failure ("" if none). */
+const char* tt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TT_H */

@@ -1,0 +1,263 @@
+"""ctypes binding of libtt.so (C-ABI in include/tt.h). Argument marshalling only.
+
+Every compute step runs inside the HIP library; this module only converts
+torch tensors (device memory and the current stream) into pointers. If the
+library has not been built, importing this module raises: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2008_06888_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+TT_OK = 0
+TT_E_INVAL, TT_E_DTYPE, TT_E_RANGE, TT_E_TOOBIG = -1, -2, -3, -4
+TT_E_COUNT_OVERFLOW, TT_E_DEVICE, TT_E_NOMEM = -5, -6, -7
+TT_F32, TT_I32 = 0, 1
+ORDER_GREEDY, ORDER_GIVEN, ORDER_CHIMERA = 0, 1, 2
+
+#: every symbol the header declares (checked by the CPU tests)
+EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy", "tt_contract",
+           "tt_backward", "tt_count", "tt_count_moduli", "tt_count_to_decimal", "tt_contract_uneven",
+           "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error")
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("order", C.POINTER(C.c_int32)), ("seed", C.c_uint64),
+                ("trials", C.c_int32), ("has_field", C.c_int32), ("tile_bits", C.c_int32),
+                ("count_tile_bits", C.c_int32), ("chimera_rows", C.c_int32),
+                ("chimera_cols", C.c_int32), ("max_bytes", C.c_int64)]
+
+
+class PlanStats(C.Structure):
+    _fields_ = [("n_spins", C.c_int32), ("n_edges", C.c_int64), ("width", C.c_int32),
+                ("n_ops", C.c_int32), ("n_passes", C.c_int32), ("n_count_passes", C.c_int32),
+                ("terms", C.c_double), ("reduce_terms", C.c_double), ("entry_updates", C.c_double)]
+
+
+_vp = C.c_void_p
+_lib.tt_plan_create.argtypes = [C.c_int32, C.c_int64, _vp, C.POINTER(PlanOpts), C.POINTER(_vp)]
+_lib.tt_plan_info.argtypes = [_vp, C.POINTER(PlanStats)]
+_lib.tt_plan_order.argtypes = [_vp, _vp]
+_lib.tt_plan_destroy.argtypes = [_vp]
+_lib.tt_plan_destroy.restype = None
+_lib.tt_contract.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
+_lib.tt_backward.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tt_count.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]
+_lib.tt_count_moduli.argtypes = [_vp]
+_lib.tt_count_to_decimal.argtypes = [_vp, C.c_char_p, C.c_size_t]
+_lib.tt_contract_uneven.argtypes = [C.c_int32, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tt_prof_enable.argtypes = [C.c_int32]
+_lib.tt_prof_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+_lib.tt_last_error.restype = C.c_char_p
+
+
+class TTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tt error {code}: {msg}")
+        self.code = code
+
+
+def _check(code: int):
+    if code != TT_OK:
+        raise TTError(code, _lib.tt_last_error().decode())
+
+
+def lib():
+    return _lib
+
+
+class Plan:
+    """A contraction plan (host object owned by the library)."""
+
+    def __init__(self, n: int, edges, *, order: Optional[Sequence[int]] = None, kind: Optional[int] = None,
+                 has_field: bool = False, seed: int = 0, trials: int = 32, tile_bits: int = 0,
+                 count_tile_bits: int = 0, chimera: Optional[tuple] = None, max_bytes: int = 0):
+        self.n = int(n)
+        self.edges = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        self.m = int(self.edges.shape[0])
+        self.has_field = bool(has_field)
+        o = PlanOpts()
+        if kind is None:
+            kind = ORDER_GIVEN if order is not None else (ORDER_CHIMERA if chimera else ORDER_GREEDY)
+        o.kind = kind
+        self._order_buf = None
+        if order is not None:
+            self._order_buf = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+            o.order = self._order_buf.ctypes.data_as(C.POINTER(C.c_int32))
+        o.seed, o.trials, o.has_field = seed, trials, int(has_field)
+        o.tile_bits, o.count_tile_bits, o.max_bytes = tile_bits, count_tile_bits, max_bytes
+        if chimera:
+            o.chimera_rows, o.chimera_cols = chimera
+        h = _vp()
+        _check(_lib.tt_plan_create(self.n, self.m, self.edges.ctypes.data, C.byref(o), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        s = PlanStats()
+        _check(_lib.tt_plan_info(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in PlanStats._fields_}
+
+    def order(self) -> np.ndarray:
+        out = np.zeros(self.n, np.int32)
+        _check(_lib.tt_plan_order(self._h, out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tt_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def moduli() -> List[int]:
+    buf = (C.c_uint64 * 3)()
+    _check(_lib.tt_count_moduli(buf))
+    return [int(x) for x in buf]
+
+
+def residues_to_int(res) -> int:
+    arr = (C.c_uint64 * 3)(*[int(x) for x in res])
+    buf = C.create_string_buffer(128)
+    _check(_lib.tt_count_to_decimal(arr, buf, 128))
+    return int(buf.value.decode())
+
+
+# ---------------------------------------------------------------------------
+# compute calls (torch tensors on the current HIP device)
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return TT_F32
+    if t.dtype == torch.int32:
+        return TT_I32
+    raise TypeError(f"J must be float32 or int32, got {t.dtype}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_inputs(plan: Plan, J, h):
+    if not J.is_cuda or not J.is_contiguous() or J.dim() != 2 or J.shape[1] != plan.m:
+        raise ValueError(f"J must be a contiguous device tensor [batch, {plan.m}]")
+    if plan.has_field:
+        if h is None or not h.is_cuda or not h.is_contiguous() or tuple(h.shape) != (J.shape[0], plan.n) \
+                or h.dtype != J.dtype:
+            raise ValueError(f"h must be a contiguous device tensor [batch, {plan.n}] of J's dtype")
+    elif h is not None:
+        raise ValueError("plan was built without fields")
+
+
+def contract(plan: Plan, J, h=None):
+    """E* of every instance (device float64 [batch])."""
+    torch = _torch()
+    _check_inputs(plan, J, h)
+    B = J.shape[0]
+    energy = torch.empty(B, dtype=torch.float64, device=J.device)
+    _check(_lib.tt_contract(plan.handle, B, _dtype_code(J), _ptr(J), _ptr(h), _ptr(energy), _stream()))
+    return energy
+
+
+def backward(plan: Plan, J, h=None, want_grad: bool = True):
+    """(E*, sigma, dE/dJ, dE/dh) with sigma int8 [batch, n] in {+1, -1}."""
+    torch = _torch()
+    _check_inputs(plan, J, h)
+    B = J.shape[0]
+    dev = J.device
+    energy = torch.empty(B, dtype=torch.float64, device=dev)
+    sigma = torch.empty(B, plan.n, dtype=torch.int8, device=dev)
+    dJ = torch.empty(B, plan.m, dtype=torch.float32, device=dev) if want_grad else None
+    dh = torch.empty(B, plan.n, dtype=torch.float32, device=dev) if (want_grad and plan.has_field) else None
+    _check(_lib.tt_backward(plan.handle, B, _dtype_code(J), _ptr(J), _ptr(h), _ptr(energy), _ptr(sigma),
+                            _ptr(dJ), _ptr(dh), _stream()))
+    return energy, sigma, dJ, dh
+
+
+def count(plan: Plan, J, h=None):
+    """(E* int64 numpy [batch], residues uint64 numpy [batch, 3], g as Python ints)."""
+    torch = _torch()
+    _check_inputs(plan, J, h)
+    if J.dtype != torch.int32:
+        raise TypeError("counting needs int32 couplings")
+    B = J.shape[0]
+    energy = np.zeros(B, np.int64)
+    res = np.zeros((B, 3), np.uint64)
+    _check(_lib.tt_count(plan.handle, B, _ptr(J), _ptr(h), energy.ctypes.data, res.ctypes.data, _stream()))
+    return energy, res, [residues_to_int(r) for r in res]
+
+
+def contract_uneven(plans: Sequence[Plan], J_list, want_sigma: bool = True):
+    """Forward (+ backward) of instances with different graphs. J_list: device tensors [m_i]."""
+    torch = _torch()
+    n = len(plans)
+    if n != len(J_list) or n == 0:
+        raise ValueError("one J per plan")
+    dt = J_list[0].dtype
+    Jcat = torch.cat([j.reshape(-1) for j in J_list]).contiguous()
+    j_off = np.zeros(n, np.int64)
+    s_off = np.zeros(n, np.int64)
+    for i in range(1, n):
+        j_off[i] = j_off[i - 1] + plans[i - 1].m
+        s_off[i] = s_off[i - 1] + plans[i - 1].n
+    for p, j in zip(plans, J_list):
+        if j.numel() != p.m or j.dtype != dt or p.has_field:
+            raise ValueError("J sizes / dtypes must match the plans (no fields)")
+    handles = (C.c_void_p * n)(*[p.handle for p in plans])
+    energy = torch.empty(n, dtype=torch.float64, device=Jcat.device)
+    sigma = torch.empty(int(sum(p.n for p in plans)), dtype=torch.int8, device=Jcat.device) if want_sigma else None
+    dJ = torch.empty_like(Jcat, dtype=torch.float32) if want_sigma else None
+    _check(_lib.tt_contract_uneven(n, handles, _dtype_code(Jcat), _ptr(Jcat), j_off.ctypes.data, _ptr(energy),
+                                   _ptr(sigma), s_off.ctypes.data, _ptr(dJ), _stream()))
+    if not want_sigma:
+        return energy, None, None
+    sig = [sigma[s_off[i]:s_off[i] + plans[i].n] for i in range(n)]
+    dj = [dJ[j_off[i]:j_off[i] + plans[i].m] for i in range(n)]
+    return energy, sig, dj
+
+
+def prof_enable(on: bool = True):
+    _check(_lib.tt_prof_enable(1 if on else 0))
+
+
+def prof_reset():
+    _check(_lib.tt_prof_reset())
+
+
+def prof_read(name: str):
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(_lib.tt_prof_read(name.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,217 @@
+// HIP kernels (gfx950) of the counting sweep: every state entry is the tuple
+// (x, n) of Eq. (4), x the tropical number (negative energy) and n the number
+// of configurations attaining it. The tropical product with a leaf tensor
+// (count 1) keeps n; the tropical sum keeps the n of the larger x and adds
+// the n's when the x's are equal. n is carried as three residues modulo the
+// primes p_r = 2^61 - 1, 2^61 - 31, 2^61 - 45 (exact recombination by CRT on
+// the host). x is an exact integer held in float32 (|x| < 2^24 is checked by
+// the caller), so every equality test of Eq. (4) is exact.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.hpp"
+#include "plan.hpp"
+
+namespace tt {
+
+constexpr int CNT = 256;
+constexpr int NRES = 3;
+
+__device__ __constant__ uint64_t c_mod[NRES] = {(1ull << 61) - 1, (1ull << 61) - 31, (1ull << 61) - 45};
+
+__device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t p) {
+  const uint64_t s = a + b;   // a, b < p < 2^61: no overflow
+  return s >= p ? s - p : s;
+}
+
+__device__ __forceinline__ int cbit(uint8_t enc, uint32_t i, uint64_t base) {
+  return enc < SLOT_FIXED ? (int)((i >> enc) & 1u) : (int)((base >> (enc - SLOT_FIXED)) & 1ull);
+}
+
+__device__ __forceinline__ void cbuild_deposit(const uint8_t* R, int t, uint64_t* lo, uint64_t* hi) {
+  for (int j = threadIdx.x; j < 256; j += blockDim.x) {
+    uint64_t a = 0, b = 0;
+    for (int k = 0; k < 8; ++k) {
+      if (k < t && ((j >> k) & 1)) a |= 1ull << R[k];
+      if (k + 8 < t && ((j >> k) & 1)) b |= 1ull << R[k + 8];
+    }
+    lo[j] = a;
+    hi[j] = b;
+  }
+}
+
+// State layout per instance: x plane [2^W] float, then residue planes
+// n[r][2^W] uint64 (sst = 2^W entries per plane).
+__global__ __launch_bounds__(CNT) void k_count_pass(DevPass P, const DevOp* __restrict__ ops,
+                                                    const int32_t* __restrict__ J, const int32_t* __restrict__ h,
+                                                    int64_t jst, int64_t hst, const float* __restrict__ xin,
+                                                    const uint64_t* __restrict__ nin, float* __restrict__ xout,
+                                                    uint64_t* __restrict__ nout, int64_t sst, int log2_tiles) {
+  extern __shared__ uint64_t csm[];
+  const uint32_t size = 1u << P.t;
+  uint64_t* tn = csm;                                        // [NRES][size]
+  float* tx = reinterpret_cast<float*>(csm + NRES * size);   // [size]
+  __shared__ uint64_t dep_lo[256], dep_hi[256];
+  const int64_t inst = (int64_t)blockIdx.x >> log2_tiles;
+  const uint64_t tile_id = (uint64_t)blockIdx.x & ((1ull << log2_tiles) - 1ull);
+  uint64_t base = 0;
+  for (int k = 0; k < P.n_free; ++k) base |= ((tile_id >> k) & 1ull) << P.fre[k];
+  cbuild_deposit(P.R, P.t, dep_lo, dep_hi);
+  __syncthreads();
+  const uint64_t in_mask = (1ull << P.in_w) - 1ull;
+  const float* xs = xin + inst * sst;
+  const uint64_t* ns = nin + inst * sst * NRES;
+  for (uint32_t i = threadIdx.x; i < size; i += CNT) {
+    const uint64_t idx = (base | dep_lo[i & 255u] | dep_hi[i >> 8]) & in_mask;
+    if (P.init) {
+      tx[i] = 0.f;
+      for (int r = 0; r < NRES; ++r) tn[r * size + i] = 1ull;
+    } else {
+      tx[i] = xs[idx];
+      for (int r = 0; r < NRES; ++r) tn[r * size + i] = ns[r * sst + idx];
+    }
+  }
+  __syncthreads();
+  const int32_t* Jrow = J + inst * jst;
+  const int32_t* hrow = h ? h + inst * hst : nullptr;
+  const DevOp* po = ops + P.op_begin;
+  for (int o = 0; o < P.n_ops; ++o) {
+    const DevOp op = po[o];
+    if (op.kind == OP_GATE || op.kind == OP_CUT) {
+      const float Jv = op.kind == OP_GATE ? (float)Jrow[op.param] : 0.f;
+      const int b = op.a;
+      const uint32_t lowmask = (1u << b) - 1u;
+      for (uint32_t p = threadIdx.x; p < (size >> 1); p += CNT) {
+        const uint32_t i0 = ((p & ~lowmask) << 1) | (p & lowmask);
+        const uint32_t i1 = i0 | (1u << b);
+        const float a0 = tx[i0], a1 = tx[i1];
+        const float c00 = a0 + Jv, c10 = a1 - Jv, c01 = a0 - Jv, c11 = a1 + Jv;
+        tx[i0] = fmaxf(c00, c10);
+        tx[i1] = fmaxf(c01, c11);
+        for (int r = 0; r < NRES; ++r) {
+          const uint64_t n0 = tn[r * size + i0], n1 = tn[r * size + i1];
+          const uint64_t both = addmod(n0, n1, c_mod[r]);
+          tn[r * size + i0] = c00 > c10 ? n0 : (c10 > c00 ? n1 : both);
+          tn[r * size + i1] = c01 > c11 ? n0 : (c11 > c01 ? n1 : both);
+        }
+      }
+      __syncthreads();
+    } else if (op.kind == OP_DIAG) {
+      const float Jv = (float)Jrow[op.param];
+      for (uint32_t i = threadIdx.x; i < size; i += CNT)
+        tx[i] += (cbit(op.a, i, base) ^ cbit(op.b, i, base)) ? -Jv : Jv;
+      __syncthreads();
+    } else if (op.kind == OP_FIELD) {
+      const float hv = (float)hrow[op.param];
+      for (uint32_t i = threadIdx.x; i < size; i += CNT) tx[i] += cbit(op.a, i, base) ? -hv : hv;
+      __syncthreads();
+    }
+  }
+  float* xd = xout + inst * sst;
+  uint64_t* nd = nout + inst * sst * NRES;
+  for (uint32_t i = threadIdx.x; i < size; i += CNT) {
+    const uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
+    if ((idx >> P.out_w) != 0) continue;
+    xd[idx] = tx[i];
+    for (int r = 0; r < NRES; ++r) nd[r * sst + idx] = tn[r * size + i];
+  }
+}
+
+// final reduction: x* = max x, n* = sum of n over entries with x = x* (Eq. 4)
+__device__ float cblock_max(float v) {
+  __shared__ float sh[CNT / 64];
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = sh[0];
+  for (int k = 1; k < CNT / 64; ++k) r = fmaxf(r, sh[k]);
+  __syncthreads();
+  return r;
+}
+
+__device__ uint64_t cblock_summod(uint64_t v, uint64_t p) {
+  __shared__ uint64_t sh[CNT / 64];
+  for (int off = 32; off > 0; off >>= 1) v = addmod(v, __shfl_xor(v, off, 64), p);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t r = sh[0];
+  for (int k = 1; k < CNT / 64; ++k) r = addmod(r, sh[k], p);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(CNT) void k_count_reduce1(const float* __restrict__ x, const uint64_t* __restrict__ nr,
+                                                       int64_t sst, int w, int log2_chunks, float* __restrict__ pv,
+                                                       uint64_t* __restrict__ pn) {
+  const int64_t inst = (int64_t)blockIdx.x >> log2_chunks;
+  const uint64_t chunk = (uint64_t)blockIdx.x & ((1ull << log2_chunks) - 1ull);
+  const uint64_t len = 1ull << (w - log2_chunks);
+  const float* xs = x + inst * sst;
+  const uint64_t* ns = nr + inst * sst * NRES;
+  float mx = -INFINITY;
+  for (uint64_t k = threadIdx.x; k < len; k += CNT) mx = fmaxf(mx, xs[chunk * len + k]);
+  mx = cblock_max(mx);
+  for (int r = 0; r < NRES; ++r) {
+    uint64_t acc = 0;
+    for (uint64_t k = threadIdx.x; k < len; k += CNT) {
+      const uint64_t idx = chunk * len + k;
+      if (xs[idx] == mx) acc = addmod(acc, ns[r * sst + idx], c_mod[r]);
+    }
+    acc = cblock_summod(acc, c_mod[r]);
+    if (threadIdx.x == 0) pn[blockIdx.x * NRES + r] = acc;
+  }
+  if (threadIdx.x == 0) pv[blockIdx.x] = mx;
+}
+
+__global__ __launch_bounds__(CNT) void k_count_reduce2(const float* __restrict__ pv, const uint64_t* __restrict__ pn,
+                                                       int log2_chunks, int64_t* __restrict__ energy,
+                                                       uint64_t* __restrict__ residues) {
+  const int64_t inst = blockIdx.x;
+  const int64_t nc = 1ll << log2_chunks;
+  float mx = -INFINITY;
+  for (int64_t k = threadIdx.x; k < nc; k += CNT) mx = fmaxf(mx, pv[inst * nc + k]);
+  mx = cblock_max(mx);
+  for (int r = 0; r < NRES; ++r) {
+    uint64_t acc = 0;
+    for (int64_t k = threadIdx.x; k < nc; k += CNT)
+      if (pv[inst * nc + k] == mx) acc = addmod(acc, pn[(inst * nc + k) * NRES + r], c_mod[r]);
+    acc = cblock_summod(acc, c_mod[r]);
+    if (threadIdx.x == 0) residues[inst * NRES + r] = acc;
+  }
+  if (threadIdx.x == 0) energy[inst] = -(int64_t)mx;
+}
+
+int count_reduce_log2_chunks(int w) {
+  int c = w - 12;
+  if (c < 0) c = 0;
+  if (c > 10) c = 10;
+  return c;
+}
+
+hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h, int64_t jst,
+                             int64_t hst, const float* xin, const uint64_t* nin, float* xout, uint64_t* nout,
+                             int64_t sst, int batch, hipStream_t stream) {
+  const size_t lds = ((size_t)1 << P.t) * (sizeof(float) + NRES * sizeof(uint64_t));
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_count_pass),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const uint64_t grid = (uint64_t)batch << P.n_free;
+  if (grid >= (1ull << 31)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_count_pass, dim3((uint32_t)grid), dim3(CNT), lds, stream, P, ops, J, h, jst, hst, xin, nin,
+                     xout, nout, sst, P.n_free);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_reduce(const float* x, const uint64_t* nres, int64_t sst, int w, int batch, float* pv,
+                               uint64_t* pn, int64_t* energy, uint64_t* residues, hipStream_t stream) {
+  const int lc = count_reduce_log2_chunks(w);
+  hipLaunchKernelGGL(k_count_reduce1, dim3((uint32_t)((uint64_t)batch << lc)), dim3(CNT), 0, stream, x, nres, sst, w,
+                     lc, pv, pn);
+  hipLaunchKernelGGL(k_count_reduce2, dim3((uint32_t)batch), dim3(CNT), 0, stream, pv, pn, lc, energy, residues);
+  return hipGetLastError();
+}
+
+}  // namespace tt

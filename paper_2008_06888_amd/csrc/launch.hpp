@@ -1,0 +1,33 @@
+// Host launch wrappers of the HIP kernels (defined next to the kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace tt {
+
+hipError_t launch_sweep_pass(const DevPass& P, const DevOp* ops, int dtype, const void* J, const void* h,
+                             int64_t jst, int64_t hst, const float* in, float* out, int64_t sst, int batch,
+                             hipStream_t stream);
+int reduce_log2_chunks(int w);
+hipError_t launch_reduce(const float* st, int64_t sst, int w, int batch, float* pv, uint64_t* pi,
+                         double* energy, uint64_t* arg, hipStream_t stream);
+size_t backward_lds_bytes(int max_t, int max_dec);
+hipError_t launch_sweep_backward(const DevPass* passes, int n_passes, const DevOp* ops, const DevSpin* spins,
+                                 int dtype, const void* J, const void* h, int64_t jst, int64_t hst,
+                                 const float* const* ckpt, int64_t sst, const uint64_t* final_idx,
+                                 const int32_t* final_slot_spin, int final_w, const int32_t* edges, int n,
+                                 int64_t m, int8_t* sigma, float* dJ, float* dh, int max_t, int max_dec,
+                                 int batch, hipStream_t stream);
+
+// counting path: state entries (x, n mod p_r), r = 0, 1, 2
+hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h,
+                             int64_t jst, int64_t hst, const float* xin, const uint64_t* nin, float* xout,
+                             uint64_t* nout, int64_t sst, int batch, hipStream_t stream);
+int count_reduce_log2_chunks(int w);
+hipError_t launch_count_reduce(const float* x, const uint64_t* nres, int64_t sst, int w, int batch, float* pv,
+                               uint64_t* pn, int64_t* energy, uint64_t* residues, hipStream_t stream);
+
+}  // namespace tt

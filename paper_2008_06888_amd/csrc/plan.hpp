@@ -1,0 +1,116 @@
+// Host-side plan IR of the tropical contraction.
+//
+// The tensor network of Sec. II (bond tensors on edges, field vectors, copy
+// tensors = shared spin labels) is contracted as a sweep, the way Sec. V casts
+// the square lattice as a tropical circuit acting on a 2^L state: one dense
+// state tensor over the "live" spins absorbs leaf tensors one at a time.
+// Each live spin occupies a slot = one bit of the state index (index bit 0 of
+// a slot <-> sigma = +1). Operations on the state x[s]:
+//
+//   INTRO  slot      a new spin enters a free slot (free slots hold values that
+//                    are constant along their bit, so this is a no-op: the
+//                    start symbol (0, 0) of App. A)
+//   FIELD  slot, i   x += h_i sigma(slot)                  (field gate, App. A)
+//   DIAG   a, b, e   x += J_e sigma(a) sigma(b)            (two-site gate, App. A)
+//   GATE   slot, e   x'[.., t, ..] = max_s x[.., s, ..] + J_e sigma(s) sigma(t):
+//                    the bond matrix [[J,-J],[-J,J]] applied as a single-site
+//                    gate; the old spin is eliminated and the new spin takes
+//                    its slot (App. A, horizontal coupling gate)
+//   CUT    slot      x'[.., t, ..] = max_s x[.., s, ..]: eliminate a spin whose
+//                    bonds are all absorbed (App. A, cut gate)
+//   GATE4  4 slots   a 16x16 tropical matrix between two groups of four spins
+//                    (Sec. V, chimera): the four old spins are eliminated and
+//                    four new spins take their slots
+//   MERGE  reg       x += y elementwise with a second state y over the same
+//                    spins in the same slots
+//
+// At the end the maximum over the remaining state is -E* (Sec. II).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace tt {
+
+enum OpKind : uint8_t {
+  OP_INTRO = 0,
+  OP_GATE = 1,
+  OP_CUT = 2,
+  OP_DIAG = 3,
+  OP_FIELD = 4,
+  OP_GATE4 = 5,
+  OP_MERGE = 6,
+};
+
+struct SweepOp {
+  uint8_t kind = 0;
+  int8_t reg = 0;          // state register the op acts on
+  int16_t slot_a = -1;     // GATE/CUT/INTRO/FIELD slot; DIAG first slot; GATE4 first slot
+  int16_t slot_b = -1;     // DIAG second slot
+  int16_t slots4[4] = {-1, -1, -1, -1};  // GATE4 slots (group order)
+  int32_t param = -1;      // GATE/DIAG: edge; FIELD: spin; GATE4: group-matrix id; MERGE: source register
+  int32_t old_spin = -1;   // spin eliminated (GATE/CUT)
+  int32_t new_spin = -1;   // spin entering (GATE/INTRO)
+  int32_t old4[4] = {-1, -1, -1, -1};
+  int32_t new4[4] = {-1, -1, -1, -1};
+  int32_t live = 0;        // live spins after the op (algorithmic state size = 2^live)
+  int32_t w_before = 0;    // physical width (highest used slot + 1) before / after
+  int32_t w_after = 0;
+};
+
+// One pass = a run of ops executed by one kernel launch; every op that mixes
+// entries along a slot (GATE, CUT, GATE4) has its slot among the t resident
+// tile bits R, so a workgroup applies the whole run to its tile on chip.
+struct Pass {
+  int32_t op_begin = 0, op_end = 0;
+  int32_t in_w = 0, out_w = 0, w_max = 0, t = 0;
+  bool init = false;       // starts from the all-zero state
+  int32_t reg = 0;         // state register of the pass
+  int32_t merge_src = -1;  // register merged by an OP_MERGE inside the pass
+  std::vector<int> R;      // tile bit -> slot (ascending)
+  int32_t n_dec = 0;       // ops that record an argmax decision
+};
+
+// Group matrices of GATE4 ops: entry [t_old][t_new] = sum over the listed
+// edges of J_e sigma(old bit) sigma(new bit).
+struct GroupMatrix {
+  int32_t edges[16];       // edge index, -1 = none
+  uint8_t old_bit[16];     // bit of the old-group index for edge k
+  uint8_t new_bit[16];     // bit of the new-group index for edge k
+  int32_t n_edges = 0;
+};
+
+struct Plan {
+  int32_t n = 0;
+  int64_t m = 0;
+  std::vector<int32_t> edges;       // [m][2]
+  bool has_field = false;
+  std::vector<int32_t> order;
+  std::vector<SweepOp> ops;
+  std::vector<GroupMatrix> groups;
+  int32_t width = 0;                // max physical width
+  int32_t final_w = 0;
+  std::vector<int32_t> final_slot_spin;   // slot -> spin after the last op, -1 free
+  int32_t n_regs = 1;               // state registers (chimera plans use two)
+  int32_t final_reg = 0;
+  int32_t tile_bits = 14, count_tile_bits = 12;
+  int32_t max_dec = 16;
+  std::vector<Pass> passes;          // energy / backward path
+  std::vector<Pass> count_passes;    // count path
+  double terms = 0;                  // algorithmic max-plus terms per instance
+  double reduce_terms = 0;           // of which the final reduction
+  int64_t max_bytes = 0;
+  void* dev = nullptr;               // device-side cache (owned, see capi)
+};
+
+// Builds ops from a spin order; returns "" or an error message.
+std::string build_sweep_ops(Plan& p);
+// Greedy order search with restarts.
+std::vector<int32_t> greedy_order(int32_t n, const std::vector<int32_t>& edges, uint64_t seed,
+                                  int trials);
+// Chimera row-chain plan (two state registers); returns "" or an error.
+std::string build_chimera_ops(Plan& p, int rows, int cols);
+// Splits ops into passes of at most `t` resident bits and `max_dec` decisions.
+std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec);
+
+}  // namespace tt

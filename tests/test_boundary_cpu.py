@@ -1,0 +1,64 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol,
+and its host-side planner and CRT helper behave (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2008_06888_amd import binding as B
+from paper_2008_06888_amd import instances as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_header_symbol_is_exported():
+    hdr = open(os.path.join(ROOT, "include", "tt.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(tt_\w+)\s*\(", hdr, re.M))
+    assert declared == set(B.EXPORTS)
+    for name in declared:
+        assert hasattr(B.lib(), name), name
+
+
+def test_moduli_and_crt():
+    P = B.moduli()
+    assert P == [2 ** 61 - 1, 2 ** 61 - 31, 2 ** 61 - 45]
+    for x in [0, 1, 2 ** 64 + 3, 2 ** 150 + 12345, (P[0] * P[1] * P[2]) - 1]:
+        assert B.residues_to_int([x % p for p in P]) == x
+
+
+def test_square_lattice_sweep_width():
+    for L in (4, 7, 16, 32):
+        p = B.Plan(L * L, I.square_lattice(L), order=list(range(L * L)))
+        info = p.info()
+        assert info["width"] == L          # the 2^L state of Sec. V
+        assert info["n_passes"] >= 1
+
+
+def test_greedy_plan_is_a_permutation_and_deterministic():
+    rng = np.random.default_rng(1)
+    e = I.random_regular(60, 3, rng)
+    a = B.Plan(60, e, seed=3, trials=8)
+    b = B.Plan(60, e, seed=3, trials=8)
+    assert sorted(a.order().tolist()) == list(range(60))
+    assert a.order().tolist() == b.order().tolist()
+    assert a.info()["width"] <= 14
+
+
+@pytest.mark.parametrize("bad", [
+    dict(edges=[[0, 0]]), dict(edges=[[1, 0]]), dict(edges=[[0, 5]]), dict(edges=[[0, 1], [0, 1]]),
+])
+def test_invalid_graphs_rejected(bad):
+    with pytest.raises(B.TTError) as ei:
+        B.Plan(3, np.array(bad["edges"]), order=[0, 1, 2])
+    assert ei.value.code == B.TT_E_INVAL
+
+
+def test_invalid_order_rejected():
+    with pytest.raises(B.TTError):
+        B.Plan(3, I.path(3), order=[0, 0, 1])
+
+
+def test_tile_bits_option_validated():
+    with pytest.raises(B.TTError):
+        B.Plan(16, I.square_lattice(4), order=list(range(16)), tile_bits=20)
