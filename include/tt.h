@@ -97,6 +97,15 @@ int tt_plan_info(const tt_plan* plan, tt_plan_stats* out);
 /* Host copy of the spin order the plan sweeps (n_spins int32). */
 int tt_plan_order(const tt_plan* plan, int32_t* order_out);
 void tt_plan_destroy(tt_plan* plan);
+/* The plan's operation list, for inspection and host-side checks: record k
+ * occupies out[8k .. 8k+7] = {kind (0 INTRO, 1 GATE, 2 CUT, 3 DIAG, 4 FIELD),
+ * slot_a, slot_b, param (edge for GATE/DIAG, spin for FIELD), old_spin,
+ * new_spin, width_before, width_after}. Returns the number of records (or a
+ * negative tt_status); writes at most cap records. final_slot_spin (may be
+ * NULL) receives the spin held by each slot after the last op (-1 = free),
+ * final_width entries. */
+int tt_plan_ops(const tt_plan* plan, int32_t* out, int64_t cap, int32_t* final_slot_spin,
+                int32_t* final_width);
 
 /* Ground-state energy E* (Eq. 1, not its negative) of `batch` instances that
  * share the plan's graph. J: device [batch][n_edges] of dtype; h: device

@@ -30,7 +30,7 @@ ORDER_GREEDY, ORDER_GIVEN, ORDER_CHIMERA = 0, 1, 2
 #: every symbol the header declares (checked by the CPU tests)
 EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy", "tt_contract",
            "tt_backward", "tt_count", "tt_count_moduli", "tt_count_to_decimal", "tt_contract_uneven",
-           "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error")
+           "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops")
 
 
 class PlanOpts(C.Structure):
@@ -50,6 +50,7 @@ _vp = C.c_void_p
 _lib.tt_plan_create.argtypes = [C.c_int32, C.c_int64, _vp, C.POINTER(PlanOpts), C.POINTER(_vp)]
 _lib.tt_plan_info.argtypes = [_vp, C.POINTER(PlanStats)]
 _lib.tt_plan_order.argtypes = [_vp, _vp]
+_lib.tt_plan_ops.argtypes = [_vp, _vp, C.c_int64, _vp, _vp]
 _lib.tt_plan_destroy.argtypes = [_vp]
 _lib.tt_plan_destroy.restype = None
 _lib.tt_contract.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
@@ -117,6 +118,18 @@ class Plan:
         out = np.zeros(self.n, np.int32)
         _check(_lib.tt_plan_order(self._h, out.ctypes.data))
         return out
+
+    def ops(self):
+        """(ops int32 [n_ops, 8], final_slot_spin int32 [final_width]); see tt_plan_ops."""
+        n = _lib.tt_plan_ops(self._h, None, 0, None, None)
+        if n < 0:
+            _check(n)
+        out = np.zeros((max(n, 1), 8), np.int32)
+        fw = C.c_int32()
+        _lib.tt_plan_ops(self._h, out.ctypes.data, n, None, C.byref(fw))
+        fs = np.zeros(max(fw.value, 1), np.int32)
+        _lib.tt_plan_ops(self._h, out.ctypes.data, n, fs.ctypes.data, C.byref(fw))
+        return out[:n], fs[:fw.value]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -392,6 +392,27 @@ int tt_plan_order(const tt_plan* plan, int32_t* order_out) {
   return TT_OK;
 }
 
+int tt_plan_ops(const tt_plan* plan, int32_t* out, int64_t cap, int32_t* final_slot_spin, int32_t* final_width) {
+  if (!plan) return fail(TT_E_INVAL, "null plan");
+  const Plan& p = *reinterpret_cast<const Plan*>(plan);
+  const int64_t n = (int64_t)p.ops.size();
+  for (int64_t k = 0; k < n && k < cap && out; ++k) {
+    const SweepOp& o = p.ops[k];
+    int32_t* r = out + 8 * k;
+    r[0] = o.kind;
+    r[1] = o.slot_a;
+    r[2] = o.slot_b;
+    r[3] = o.param;
+    r[4] = o.old_spin;
+    r[5] = o.new_spin;
+    r[6] = o.w_before;
+    r[7] = o.w_after;
+  }
+  if (final_width) *final_width = p.final_w;
+  if (final_slot_spin) std::copy(p.final_slot_spin.begin(), p.final_slot_spin.end(), final_slot_spin);
+  return (int)n;
+}
+
 void tt_plan_destroy(tt_plan* plan) {
   if (!plan) return;
   Plan* p = reinterpret_cast<Plan*>(plan);
@@ -522,7 +543,10 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
     float* pv = reinterpret_cast<float*>(en + batch);
     {
       ProfScope ps(s, "count_reduce");
-      HIP_TRY(launch_count_reduce(xb[cur], nb[cur], sst, p.final_w, batch, pv, pn, en, res, s));
+      uint64_t free_mask = 0;
+      for (int c = 0; c < p.final_w; ++c)
+        if (p.final_slot_spin[c] < 0) free_mask |= 1ull << c;
+      HIP_TRY(launch_count_reduce(xb[cur], nb[cur], sst, p.final_w, free_mask, batch, pv, pn, en, res, s));
     }
     HIP_TRY(hipMemcpyAsync(energy, en, (size_t)batch * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(residues, res, (size_t)batch * 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));

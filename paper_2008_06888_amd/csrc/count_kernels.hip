@@ -141,9 +141,11 @@ __device__ uint64_t cblock_summod(uint64_t v, uint64_t p) {
   return r;
 }
 
+// Slots that are free after the last op hold copies of every configuration
+// (their two halves are equal), so only entries with those bits zero count.
 __global__ __launch_bounds__(CNT) void k_count_reduce1(const float* __restrict__ x, const uint64_t* __restrict__ nr,
-                                                       int64_t sst, int w, int log2_chunks, float* __restrict__ pv,
-                                                       uint64_t* __restrict__ pn) {
+                                                       int64_t sst, int w, int log2_chunks, uint64_t free_mask,
+                                                       float* __restrict__ pv, uint64_t* __restrict__ pn) {
   const int64_t inst = (int64_t)blockIdx.x >> log2_chunks;
   const uint64_t chunk = (uint64_t)blockIdx.x & ((1ull << log2_chunks) - 1ull);
   const uint64_t len = 1ull << (w - log2_chunks);
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(CNT) void k_count_reduce1(const float* __restrict__
     uint64_t acc = 0;
     for (uint64_t k = threadIdx.x; k < len; k += CNT) {
       const uint64_t idx = chunk * len + k;
-      if (xs[idx] == mx) acc = addmod(acc, ns[r * sst + idx], c_mod[r]);
+      if ((idx & free_mask) == 0 && xs[idx] == mx) acc = addmod(acc, ns[r * sst + idx], c_mod[r]);
     }
     acc = cblock_summod(acc, c_mod[r]);
     if (threadIdx.x == 0) pn[blockIdx.x * NRES + r] = acc;
@@ -205,11 +207,11 @@ hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_count_reduce(const float* x, const uint64_t* nres, int64_t sst, int w, int batch, float* pv,
-                               uint64_t* pn, int64_t* energy, uint64_t* residues, hipStream_t stream) {
+hipError_t launch_count_reduce(const float* x, const uint64_t* nres, int64_t sst, int w, uint64_t free_mask, int batch,
+                               float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues, hipStream_t stream) {
   const int lc = count_reduce_log2_chunks(w);
   hipLaunchKernelGGL(k_count_reduce1, dim3((uint32_t)((uint64_t)batch << lc)), dim3(CNT), 0, stream, x, nres, sst, w,
-                     lc, pv, pn);
+                     lc, free_mask, pv, pn);
   hipLaunchKernelGGL(k_count_reduce2, dim3((uint32_t)batch), dim3(CNT), 0, stream, pv, pn, lc, energy, residues);
   return hipGetLastError();
 }

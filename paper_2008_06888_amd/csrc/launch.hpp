@@ -27,7 +27,7 @@ hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* 
                              int64_t jst, int64_t hst, const float* xin, const uint64_t* nin, float* xout,
                              uint64_t* nout, int64_t sst, int batch, hipStream_t stream);
 int count_reduce_log2_chunks(int w);
-hipError_t launch_count_reduce(const float* x, const uint64_t* nres, int64_t sst, int w, int batch, float* pv,
-                               uint64_t* pn, int64_t* energy, uint64_t* residues, hipStream_t stream);
+hipError_t launch_count_reduce(const float* x, const uint64_t* nres, int64_t sst, int w, uint64_t free_mask, int batch,
+                               float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues, hipStream_t stream);
 
 }  // namespace tt
