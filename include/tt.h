@@ -97,6 +97,12 @@ int tt_plan_info(const tt_plan* plan, tt_plan_stats* out);
 /* Host copy of the spin order the plan sweeps (n_spins int32). */
 int tt_plan_order(const tt_plan* plan, int32_t* order_out);
 void tt_plan_destroy(tt_plan* plan);
+/* The encoded energy program the kernels execute, for host-side checks:
+ * which = 0 pass descriptors, 1 stages, 2 fused ops, 3 backward candidates,
+ * 4 backward terms, 5 final bit layout. Copies at most cap bytes into out
+ * (may be NULL) and returns the total size in bytes (or a negative
+ * tt_status). The record layouts are those of the library's device.hpp. */
+int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t cap);
 /* The plan's operation list, for inspection and host-side checks: record k
  * occupies out[8k .. 8k+7] = {kind (0 INTRO, 1 GATE, 2 CUT, 3 DIAG, 4 FIELD),
  * slot_a, slot_b, param (edge for GATE/DIAG, spin for FIELD), old_spin,

@@ -30,7 +30,8 @@ ORDER_GREEDY, ORDER_GIVEN, ORDER_CHIMERA = 0, 1, 2
 #: every symbol the header declares (checked by the CPU tests)
 EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy", "tt_contract",
            "tt_backward", "tt_count", "tt_count_moduli", "tt_count_to_decimal", "tt_contract_uneven",
-           "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops")
+           "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops",
+           "tt_plan_program")
 
 
 class PlanOpts(C.Structure):
@@ -51,6 +52,8 @@ _lib.tt_plan_create.argtypes = [C.c_int32, C.c_int64, _vp, C.POINTER(PlanOpts), 
 _lib.tt_plan_info.argtypes = [_vp, C.POINTER(PlanStats)]
 _lib.tt_plan_order.argtypes = [_vp, _vp]
 _lib.tt_plan_ops.argtypes = [_vp, _vp, C.c_int64, _vp, _vp]
+_lib.tt_plan_program.argtypes = [_vp, C.c_int32, _vp, C.c_int64]
+_lib.tt_plan_program.restype = C.c_int64
 _lib.tt_plan_destroy.argtypes = [_vp]
 _lib.tt_plan_destroy.restype = None
 _lib.tt_contract.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
@@ -130,6 +133,15 @@ class Plan:
         fs = np.zeros(max(fw.value, 1), np.int32)
         _lib.tt_plan_ops(self._h, out.ctypes.data, n, fs.ctypes.data, C.byref(fw))
         return out[:n], fs[:fw.value]
+
+    def program(self, which: int) -> bytes:
+        """Raw bytes of one part of the encoded energy program (see tt_plan_program)."""
+        n = _lib.tt_plan_program(self._h, which, None, 0)
+        if n < 0:
+            _check(int(n))
+        buf = C.create_string_buffer(max(int(n), 1))
+        _lib.tt_plan_program(self._h, which, buf, n)
+        return buf.raw[:n]
 
     def close(self):
         if getattr(self, "_h", None):

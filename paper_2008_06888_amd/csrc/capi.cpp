@@ -16,6 +16,7 @@
 
 #include "../../include/tt.h"
 #include "device.hpp"
+#include "encode.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
 
@@ -93,7 +94,6 @@ void prof_drain() {
 struct Encoded {
   std::vector<DevPass> passes;
   std::vector<DevOp> ops;
-  std::vector<DevSpin> spins;
   int max_t = 0, max_dec = 0;
 };
 
@@ -119,8 +119,9 @@ struct DevBuf {
 
 struct DevCache {
   int device = -1;
-  Encoded en, cen;
-  DevBuf d_ops, d_passes, d_spins, d_final_slot, d_edges;
+  EnergyProgram ep;
+  Encoded cen;
+  DevBuf d_passes, d_stages, d_fops, d_cands, d_terms, d_final_pos, d_final_slot, d_edges;
   DevBuf d_cops;
   DevBuf state, ckpt, ckpt_ptrs, part_v, part_i, arg;
   DevBuf cx, cn, cpart;
@@ -130,7 +131,6 @@ struct DevCache {
 int encode(const Plan& p, const std::vector<Pass>& passes, Encoded& en) {
   en.passes.clear();
   en.ops.clear();
-  en.spins.clear();
   en.max_t = 0;
   en.max_dec = 0;
   for (const Pass& ps : passes) {
@@ -184,11 +184,6 @@ int encode(const Plan& p, const std::vector<Pass>& passes, Encoded& en) {
           x.g4[k] = (uint8_t)tbit[op.slots4[k]];
         }
       en.ops.push_back(x);
-      DevSpin sp;
-      sp.old_spin = op.old_spin;
-      sp.new_spin = op.new_spin;
-      for (int k = 0; k < 4; ++k) sp.old4[k] = op.old4[k];
-      en.spins.push_back(sp);
     }
     en.max_t = std::max(en.max_t, ps.t);
     en.max_dec = std::max(en.max_dec, ps.n_dec);
@@ -218,11 +213,17 @@ int ensure_device(Plan& p, DevCache*& dc) {
   if (!dc) return fail(TT_E_NOMEM, "out of host memory");
   p.dev = dc;
   dc->device = dev;
-  if (int r = encode(p, p.passes, dc->en)) return r;
+  {
+    const std::string err = encode_energy(p, p.passes, dc->ep);
+    if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
+  }
   if (int r = encode(p, p.count_passes, dc->cen)) return r;
-  if (int r = upload(dc->d_ops, dc->en.ops)) return r;
-  if (int r = upload(dc->d_passes, dc->en.passes)) return r;
-  if (int r = upload(dc->d_spins, dc->en.spins)) return r;
+  if (int r = upload(dc->d_passes, dc->ep.passes)) return r;
+  if (int r = upload(dc->d_stages, dc->ep.stages)) return r;
+  if (int r = upload(dc->d_fops, dc->ep.fops)) return r;
+  if (int r = upload(dc->d_cands, dc->ep.cands)) return r;
+  if (int r = upload(dc->d_terms, dc->ep.terms)) return r;
+  if (int r = upload(dc->d_final_pos, dc->ep.final_pos)) return r;
   if (int r = upload(dc->d_final_slot, p.final_slot_spin)) return r;
   if (int r = upload(dc->d_edges, p.edges)) return r;
   if (int r = upload(dc->d_cops, dc->cen.ops)) return r;
@@ -247,21 +248,20 @@ int check_common(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, con
   return 0;
 }
 
-// A pass may overwrite its input when every tile reads exactly the entries
-// it writes: no width change (or no read at all).
+// A count pass may overwrite its input when every tile reads exactly the
+// entries it writes: no width change (or no read at all).
 bool in_place_ok(const DevPass& P) { return P.init || (P.in_w == P.w_max && P.out_w == P.w_max); }
 
-// Runs the energy passes. keep_all: every pass writes a fresh buffer so that
-// each pass input stays available for the backward walk.
+// Runs the energy passes. Every pass writes a buffer other than its input
+// (the bit order changes between passes); keep_all gives every pass a fresh
+// buffer so that each pass input stays available for the backward walk.
 int run_forward(Plan& p, DevCache* dc, int32_t batch, int32_t dtype, const void* J, const void* h,
                 bool keep_all, hipStream_t s, float** final_state) {
   const int64_t sst = (int64_t)1 << p.width;
   const size_t per = (size_t)batch * (size_t)sst * sizeof(float);
-  const int np = (int)dc->en.passes.size();
+  const int np = (int)dc->ep.passes.size();
   if (np == 0) return fail(TT_E_INVAL, "empty plan");
-  bool all_in_place = true;
-  for (const DevPass& P : dc->en.passes) all_in_place = all_in_place && in_place_ok(P);
-  const size_t nbuf = keep_all ? (size_t)np + 1 : (all_in_place ? 1 : 2);
+  const size_t nbuf = keep_all ? (size_t)np + 1 : 2;
   const int64_t need = (int64_t)(per * nbuf);
   DevBuf& buf = keep_all ? dc->ckpt : dc->state;
   if (need > (int64_t)buf.cap && need > budget_bytes(p) + (int64_t)buf.cap)
@@ -274,19 +274,13 @@ int run_forward(Plan& p, DevCache* dc, int32_t batch, int32_t dtype, const void*
   int cur = 0;
   if (keep_all) dc->h_ckpt_ptrs.assign(np, nullptr);
   for (int q = 0; q < np; ++q) {
-    const DevPass& P = dc->en.passes[q];
-    int src, dst;
-    if (keep_all) {
-      src = q;
-      dst = q + 1;
-      dc->h_ckpt_ptrs[q] = P.init ? nullptr : bufp(src);
-    } else {
-      src = cur;
-      dst = in_place_ok(P) ? cur : (cur ^ 1);
-    }
+    const DevPass2& P = dc->ep.passes[q];
+    const int src = keep_all ? q : cur;
+    const int dst = keep_all ? q + 1 : (cur ^ 1);
+    if (keep_all) dc->h_ckpt_ptrs[q] = P.init ? nullptr : bufp(src);
     ProfScope ps(s, "sweep_pass");
-    HIP_TRY(launch_sweep_pass(P, static_cast<const DevOp*>(dc->d_ops.p), dtype, J, h, jst, hst, bufp(src),
-                              bufp(dst), sst, batch, s));
+    HIP_TRY(launch_pass(P, static_cast<const DevStage*>(dc->d_stages.p), static_cast<const FOp*>(dc->d_fops.p), dtype,
+                        J, h, jst, hst, bufp(src), bufp(dst), sst, batch, s));
     cur = dst;
   }
   *final_state = bufp(keep_all ? np : cur);
@@ -356,8 +350,8 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
     if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
     if (p->width > 40) return fail(TT_E_TOOBIG, "plan width %d exceeds 40 bits", p->width);
     p->max_dec = 16;
-    p->passes = partition_passes(*p, p->tile_bits, p->max_dec);
-    p->count_passes = partition_passes(*p, p->count_tile_bits, 1 << 20);
+    p->passes = partition_passes(*p, p->tile_bits, p->max_dec, false, 0);
+    p->count_passes = partition_passes(*p, p->count_tile_bits, 1 << 20, false, 6);
     *out = reinterpret_cast<tt_plan*>(p.release());
     return TT_OK;
   } catch (const std::bad_alloc&) {
@@ -413,6 +407,27 @@ int tt_plan_ops(const tt_plan* plan, int32_t* out, int64_t cap, int32_t* final_s
   return (int)n;
 }
 
+int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t cap) {
+  if (!plan) return fail(TT_E_INVAL, "null plan");
+  const Plan& p = *reinterpret_cast<const Plan*>(plan);
+  EnergyProgram ep;
+  const std::string err = encode_energy(p, p.passes, ep);
+  if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
+  const void* src = nullptr;
+  int64_t bytes = 0;
+  switch (which) {
+    case 0: src = ep.passes.data(); bytes = (int64_t)(ep.passes.size() * sizeof(DevPass2)); break;
+    case 1: src = ep.stages.data(); bytes = (int64_t)(ep.stages.size() * sizeof(DevStage)); break;
+    case 2: src = ep.fops.data(); bytes = (int64_t)(ep.fops.size() * sizeof(FOp)); break;
+    case 3: src = ep.cands.data(); bytes = (int64_t)(ep.cands.size() * sizeof(BCand)); break;
+    case 4: src = ep.terms.data(); bytes = (int64_t)(ep.terms.size() * sizeof(BTerm)); break;
+    case 5: src = ep.final_pos.data(); bytes = (int64_t)ep.final_pos.size(); break;
+    default: return fail(TT_E_INVAL, "unknown program part %d", which);
+  }
+  if (out && bytes) std::memcpy(out, src, (size_t)std::min(bytes, cap));
+  return bytes;
+}
+
 void tt_plan_destroy(tt_plan* plan) {
   if (!plan) return;
   Plan* p = reinterpret_cast<Plan*>(plan);
@@ -453,7 +468,7 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
     if (int r = dc->arg.ensure((size_t)batch * sizeof(uint64_t))) return r;
     uint64_t* arg = static_cast<uint64_t*>(dc->arg.p);
     if (int r = run_reduce(p, dc, batch, fin, energy, arg, s)) return r;
-    const int np = (int)dc->en.passes.size();
+    const int np = (int)dc->ep.passes.size();
     if (dc->h_ckpt_ptrs != dc->uploaded_ckpt_ptrs || dc->ckpt_ptrs.cap < np * sizeof(float*)) {
       if (int r = dc->ckpt_ptrs.ensure(np * sizeof(float*))) return r;
       HIP_TRY(hipStreamSynchronize(s));
@@ -461,13 +476,13 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
       dc->uploaded_ckpt_ptrs = dc->h_ckpt_ptrs;
     }
     {
-    ProfScope ps(s, "sweep_backward");
-    HIP_TRY(launch_sweep_backward(static_cast<const DevPass*>(dc->d_passes.p), np,
-                                  static_cast<const DevOp*>(dc->d_ops.p), static_cast<const DevSpin*>(dc->d_spins.p),
-                                  dtype, J, h, p.m, p.n, static_cast<const float* const*>(dc->ckpt_ptrs.p),
-                                  (int64_t)1 << p.width, arg, static_cast<const int32_t*>(dc->d_final_slot.p),
-                                  p.final_w, static_cast<const int32_t*>(dc->d_edges.p), p.n, p.m, sigma, dJ, dh,
-                                  dc->en.max_t, std::max(1, dc->en.max_dec), batch, s));
+      ProfScope ps(s, "sweep_backward");
+      HIP_TRY(launch_backward(static_cast<const DevPass2*>(dc->d_passes.p), np,
+                              static_cast<const BCand*>(dc->d_cands.p), static_cast<const BTerm*>(dc->d_terms.p),
+                              dtype, J, h, p.m, p.n, static_cast<const float* const*>(dc->ckpt_ptrs.p),
+                              (int64_t)1 << p.width, arg, static_cast<const uint8_t*>(dc->d_final_pos.p),
+                              static_cast<const int32_t*>(dc->d_final_slot.p), p.final_w,
+                              static_cast<const int32_t*>(dc->d_edges.p), p.n, p.m, sigma, dJ, dh, batch, s));
     }
     return TT_OK;
   } catch (...) {

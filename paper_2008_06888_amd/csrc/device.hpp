@@ -4,18 +4,20 @@
 
 namespace tt {
 
-// One operation of a pass, in tile coordinates. Slot operands are encoded as
-// a tile bit (0..31) when the slot is resident in the tile, or as
-// SLOT_FIXED + slot when it is one of the tile's fixed index bits.
+// Slot operands are encoded as a tile bit (0..31) when the slot is resident
+// in the tile, or as SLOT_FIXED + slot when it is one of the tile's fixed
+// index bits.
 constexpr uint8_t SLOT_FIXED = 64;
+constexpr uint8_t NO_POS = 0xFF;
 
+// ---- counting path (one LDS sweep per operation, identity bit order) ----
 struct DevOp {
   uint8_t kind;   // OpKind
   uint8_t a;      // first slot operand
   uint8_t b;      // second slot operand (DIAG)
-  uint8_t dec;    // decision row (GATE / CUT / GATE4) within the pass
-  int32_t param;  // edge (GATE / DIAG), spin (FIELD), group matrix (GATE4)
-  uint8_t g4[4];  // GATE4: the four tile bits
+  uint8_t dec;
+  int32_t param;  // edge (GATE / DIAG), spin (FIELD)
+  uint8_t g4[4];
 };
 
 struct DevPass {
@@ -26,18 +28,62 @@ struct DevPass {
   uint8_t fre[48];   // slots below w_max outside the tile, ascending (tile id bits)
 };
 
-// Spins eliminated / entering at an op (for the backward walk).
-struct DevSpin {
-  int32_t old_spin, new_spin;
-  int32_t old4[4];
+// ---- energy path ----
+// Fused operation: a relabelling gate (or cut) on one tile bit, followed by
+// the "star" of diagonal terms of the spin that enters: the field h and the
+// bonds to spins already in the state, all linear in sigma(new spin).
+enum FKind : uint8_t { FK_GATE = 1, FK_CUT = 2, FK_STAR = 3 };
+constexpr int STAR_TERMS = 4;
+
+struct FOp {
+  uint8_t kind;
+  uint8_t bit;     // GATE/CUT: tile bit; STAR: encoded slot of the spin
+  uint8_t lidx;    // GATE/CUT: index of `bit` among the stage bits
+  uint8_t nt;      // star terms used
+  int32_t edge;    // GATE: bond edge
+  int32_t hspin;   // star field: spin, -1 none
+  uint8_t w[STAR_TERMS];    // star partners (encoded slots)
+  int32_t te[STAR_TERMS];   // star edges
 };
 
-// Group matrix of a GATE4 op: [t_old][t_new] = sum_k J[edge_k] sigma(old bit) sigma(new bit).
-struct DevGroup {
-  int32_t edges[16];
-  uint8_t old_bit[16];
-  uint8_t new_bit[16];
-  int32_t n_edges, pad;
+// A stage: up to four gate bits applied in registers, each thread owning
+// groups of 16 entries that span the stage bits.
+struct DevStage {
+  uint8_t sb[4];     // stage tile bits
+  uint8_t nns;       // non-stage tile bits (t - 4)
+  uint8_t ns[15];    // non-stage tile bits, ascending
+  int32_t op_begin, op_end;
+  int32_t pad[2];
+};
+
+struct DevPass2 {
+  int32_t in_w, out_w, w_max, t;
+  int32_t stage_begin, n_stages, init, n_free;
+  int32_t cand_begin, n_cand, term_begin, n_lo, n_hi, n_cross;
+  uint64_t surv_mask;    // slots (< in_w) whose spin is not eliminated in the pass
+  uint8_t R[16];         // tile bit -> slot
+  uint8_t fre[48];       // slots below w_max outside the tile (tile id bits, ascending)
+  uint8_t in_pos[64];    // slot -> input address bit (NO_POS if none)
+  uint8_t out_pos[64];   // slot -> output address bit (NO_POS if none)
+  uint8_t ld_order[16];  // tile bits with an input position, ascending by position
+  uint8_t st_order[16];  // tile bits with an output position, ascending by position
+  int32_t n_ld, n_st;
+};
+
+// Backward walk: a spin eliminated in a pass (candidate bit k) and the slot it
+// held when the pass started (-1 if it entered during the pass).
+struct BCand {
+  int32_t spin;
+  int32_t start_slot;
+};
+
+// A term of the pass's energy that involves an eliminated spin:
+// coef * sigma(a) [* sigma(b)], operands = candidate k (< 64) or 64 + slot of
+// the selected output index; b = 255 for a field term.
+struct BTerm {
+  int32_t coef;     // edge (bond) or spin (field)
+  uint8_t is_field;
+  uint8_t a, b, pad;
 };
 
 }  // namespace tt

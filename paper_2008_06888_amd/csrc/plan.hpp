@@ -110,7 +110,9 @@ std::vector<int32_t> greedy_order(int32_t n, const std::vector<int32_t>& edges, 
                                   int trials);
 // Chimera row-chain plan (two state registers); returns "" or an error.
 std::string build_chimera_ops(Plan& p, int rows, int cols);
-// Splits ops into passes of at most `t` resident bits and `max_dec` decisions.
-std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec);
+// Splits ops into passes of at most `t` resident bits and `max_dec` gated
+// slots; `separable` adds the conditions of the one-argmax backward walk.
+// `low` lowest slots are kept resident in every tile (identity bit order).
+std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separable, int low);
 
 }  // namespace tt

@@ -69,21 +69,35 @@ std::string build_sweep_ops(Plan& p) {
     op.live = live;
     p.ops.push_back(op);
   };
+  std::vector<int> completed;         // live spins with every bond absorbed (eliminated lazily)
+  auto cut = [&](int x) {
+    SweepOp c;
+    c.w_before = phys_width(slot_spin);
+    c.kind = OP_CUT;
+    c.slot_a = (int16_t)slot_of[x];
+    c.old_spin = x;
+    slot_spin[slot_of[x]] = -1;
+    slot_of[x] = -1;
+    live -= 1;
+    completed.erase(std::find(completed.begin(), completed.end(), x));
+    push(c);
+  };
   for (int step = 0; step < n; ++step) {
     const int v = p.order[step];
-    // relabel candidate: a live spin whose only unabsorbed bond joins it to v
+    // relabel candidate: a live spin whose only unabsorbed bond joins it to v;
+    // the oldest such spin is preferred (the vertical bond of a lattice sweep)
     int rel_u = -1, rel_e = -1;
     for (auto [u, e] : adj.nb[v]) {
       if (processed[u] && slot_of[u] >= 0 && remaining[u] == 1 && !edge_done[e]) {
-        if (rel_u < 0 || slot_of[u] < slot_of[rel_u]) {
+        if (rel_u < 0 || pos[u] < pos[rel_u]) {
           rel_u = u;
           rel_e = e;
         }
       }
     }
     SweepOp op;
-    op.w_before = phys_width(slot_spin);
     if (rel_u >= 0) {
+      op.w_before = phys_width(slot_spin);
       const int s = slot_of[rel_u];
       op.kind = OP_GATE;
       op.slot_a = (int16_t)s;
@@ -98,7 +112,22 @@ std::string build_sweep_ops(Plan& p) {
       slot_spin[s] = v;
       push(op);
     } else {
-      const int s = lowest_free(slot_spin);
+      // a free slot, else the slot of a completed spin, else a new slot
+      int s = -1;
+      for (size_t q = 0; q < slot_spin.size(); ++q)
+        if (slot_spin[q] < 0) {
+          s = (int)q;
+          break;
+        }
+      if (s < 0 && !completed.empty()) {
+        int best = completed[0];
+        for (int x : completed)
+          if (slot_of[x] < slot_of[best]) best = x;
+        s = slot_of[best];
+        cut(best);
+      }
+      if (s < 0) s = lowest_free(slot_spin);
+      op.w_before = phys_width(slot_spin);
       op.kind = OP_INTRO;
       op.slot_a = (int16_t)s;
       op.new_spin = v;
@@ -130,20 +159,23 @@ std::string build_sweep_ops(Plan& p) {
       f.param = v;
       push(f);
     }
+    for (auto [w, e] : adj.nb[v]) {
+      (void)e;
+      if (slot_of[w] >= 0 && remaining[w] == 0 &&
+          std::find(completed.begin(), completed.end(), w) == completed.end())
+        completed.push_back(w);
+    }
+    if (slot_of[v] >= 0 && remaining[v] == 0 &&
+        std::find(completed.begin(), completed.end(), v) == completed.end())
+      completed.push_back(v);
     if (step == n - 1) break;   // the final reduction eliminates what is left
-    // eliminate spins whose bonds are all absorbed
-    for (int s = 0; s < (int)slot_spin.size(); ++s) {
-      const int x = slot_spin[s];
-      if (x < 0 || remaining[x] != 0) continue;
-      SweepOp c;
-      c.w_before = phys_width(slot_spin);
-      c.kind = OP_CUT;
-      c.slot_a = (int16_t)s;
-      c.old_spin = x;
-      slot_of[x] = -1;
-      slot_spin[s] = -1;
-      live -= 1;
-      push(c);
+    // completed spins in the highest slots are eliminated at once (the state shrinks)
+    for (;;) {
+      const int w = phys_width(slot_spin);
+      if (w == 0) break;
+      const int x = slot_spin[w - 1];
+      if (x < 0 || remaining[x] != 0) break;
+      cut(x);
     }
   }
   for (int v = 0; v < n; ++v)
@@ -269,16 +301,18 @@ std::vector<int32_t> greedy_order(int32_t n, const std::vector<int32_t>& edges, 
   return best;
 }
 
-std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec) {
+std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separable, int low) {
+  // separable: every pass can be walked back by one argmax over its gated
+  // slots (see the backward kernel): no slot gated twice, no gate on a slot
+  // that a diagonal term or an INTRO already touched in the same pass.
   std::vector<Pass> out;
   const int n_ops = (int)p.ops.size();
-  const int LOW = 6;   // low slots always resident: 64 consecutive entries per load
+  const int LOW = low;   // lowest slots always resident (consecutive entries per load)
   int i = 0;
-  bool first = true;
   while (i < n_ops) {
     const int start = i;
     const int reg = p.ops[i].reg;
-    std::set<int> need;
+    std::set<int> need, touched, intro;
     int wmax = p.ops[i].w_before;
     int ndec = 0;
     int merge_src = -1;
@@ -287,11 +321,16 @@ std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec) {
       if (op.reg != reg) break;
       std::set<int> need2 = need;
       int ndec2 = ndec;
+      bool sep_ok = true;
       if (op.kind == OP_GATE || op.kind == OP_CUT) {
+        sep_ok = !need.count(op.slot_a) && !touched.count(op.slot_a) && !intro.count(op.slot_a);
         need2.insert(op.slot_a);
         ndec2 += 1;
       } else if (op.kind == OP_GATE4) {
-        for (int k = 0; k < 4; ++k) need2.insert(op.slots4[k]);
+        for (int k = 0; k < 4; ++k) {
+          sep_ok = sep_ok && !need.count(op.slots4[k]) && !touched.count(op.slots4[k]) && !intro.count(op.slots4[k]);
+          need2.insert(op.slots4[k]);
+        }
         ndec2 += 1;
       }
       if (op.kind == OP_MERGE && merge_src >= 0 && merge_src != op.param) break;
@@ -299,11 +338,19 @@ std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec) {
       std::set<int> with_low = need2;
       for (int s = 0; s < std::min(LOW, wmax2); ++s) with_low.insert(s);
       bool ok = (wmax2 <= t) || ((int)with_low.size() <= t);
-      ok = ok && ndec2 <= max_dec;
+      ok = ok && ndec2 <= max_dec && (!separable || sep_ok);
       if (!ok && i > start) break;
       need.swap(need2);
       ndec = ndec2;
       wmax = wmax2;
+      if (op.kind == OP_DIAG) {
+        touched.insert(op.slot_a);
+        touched.insert(op.slot_b);
+      } else if (op.kind == OP_FIELD) {
+        touched.insert(op.slot_a);
+      } else if (op.kind == OP_INTRO) {
+        intro.insert(op.slot_a);
+      }
       if (op.kind == OP_MERGE) merge_src = op.param;
       ++i;
     }
@@ -320,8 +367,6 @@ std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec) {
     ps.init = true;
     for (const Pass& q : out)
       if (q.reg == reg) ps.init = false;
-    (void)first;
-    first = false;
     if (wmax <= t) {
       ps.t = wmax;
       for (int s = 0; s < wmax; ++s) ps.R.push_back(s);

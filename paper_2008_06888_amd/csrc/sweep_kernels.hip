@@ -1,17 +1,19 @@
-// HIP kernels (gfx950) of the tropical sweep: energy passes, final
+// HIP kernels (gfx950) of the tropical sweep, energy path: passes, final
 // reduction and the argmax-routing backward walk.
 //
 // A pass applies a run of operations (see plan.hpp) to the state tensor.
-// Each workgroup owns one tile: the 2^t state entries that share the values
-// of every non-resident slot. The tile is staged in LDS, every operation of
-// the run is applied there, and the tile is written back, so one pass costs
-// one read and one write of the state per run of up to t gate bits.
+// Each workgroup owns one tile: the 2^t entries that share the values of
+// every non-resident slot. The tile is read from HBM into LDS (coalesced in
+// the order of the input layout), worked on in stages, and written back in
+// the order of the output layout, so the bit order of the state changes from
+// pass to pass at no extra cost and every load and store streams whole
+// cache lines. In a stage each thread holds 16 entries spanning up to four
+// gate bits in registers and applies every operation of the stage to them.
 //
 // Arithmetic is the max-plus semiring of Eq. (2): the tropical product is a
-// float add, the tropical sum a float max. Bond entries follow the sign
-// convention of Sec. II: the bond matrix is [[J, -J], [-J, J]] with index 0
-// <-> sigma = +1, so the state holds negative energies and its final maximum
-// is -E*.
+// float add, the tropical sum a float max. Bond entries follow Sec. II: the
+// bond matrix is [[J, -J], [-J, J]] with index 0 <-> sigma = +1, so the
+// state holds negative energies and its final maximum is -E*.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -21,117 +23,203 @@
 
 namespace tt {
 
-constexpr int NT = 256;   // threads per workgroup
-
-__device__ __forceinline__ int bit_of(uint8_t enc, uint32_t i, uint64_t base) {
-  return enc < SLOT_FIXED ? (int)((i >> enc) & 1u) : (int)((base >> (enc - SLOT_FIXED)) & 1ull);
-}
+constexpr int NT = 1024;   // threads per workgroup (energy pass, backward)
+constexpr int NTR = 256;   // threads per workgroup (final reduction)
 
 template <typename IT>
 __device__ __forceinline__ float ldv(const IT* p, int64_t k) {
   return (float)p[k];
 }
 
-// Builds the two 256-entry lookup tables that scatter a tile index (t <= 16
-// bits) onto the slots R of the state index.
-__device__ __forceinline__ void build_deposit(const uint8_t* R, int t, uint64_t* lo, uint64_t* hi) {
-  for (int j = threadIdx.x; j < 256; j += blockDim.x) {
-    uint64_t a = 0, b = 0;
-    for (int k = 0; k < 8; ++k) {
-      if (k < t && ((j >> k) & 1)) a |= 1ull << R[k];
-      if (k + 8 < t && ((j >> k) & 1)) b |= 1ull << R[k + 8];
+// Value (0/1) of an encoded slot for an entry with tile index i.
+__device__ __forceinline__ uint32_t ebit(uint8_t enc, uint32_t i, uint64_t base_slots) {
+  return enc < SLOT_FIXED ? ((i >> enc) & 1u) : (uint32_t)((base_slots >> (enc - SLOT_FIXED)) & 1ull);
+}
+
+// Workgroup -> (instance, tile). With `xcd_group` the tiles of one instance
+// run on one XCD (workgroups are dispatched round-robin over the 8 XCDs), so
+// the pass-to-pass exchange of an instance stays in that XCD's L2.
+__device__ __forceinline__ bool wg_to_tile(int log2_tiles, int batch, int xcd_group, int64_t* inst,
+                                           uint64_t* tile) {
+  const uint64_t b = blockIdx.x;
+  if (xcd_group) {
+    const uint64_t xcd = b & 7ull, k = b >> 3;
+    *inst = (int64_t)(((k >> log2_tiles) << 3) | xcd);
+    *tile = k & ((1ull << log2_tiles) - 1ull);
+  } else {
+    *inst = (int64_t)(b >> log2_tiles);
+    *tile = b & ((1ull << log2_tiles) - 1ull);
+  }
+  return *inst < batch;
+}
+
+// One relabelling gate on stage bit L of the 16 register entries, with the
+// star of the entering spin: new[0] = max(a0 + J, a1 - J) + sw,
+// new[1] = max(a0 - J, a1 + J) - sw, sw = h + sum_k J_k sigma(partner_k).
+template <int L, typename IT>
+__device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16], const FOp& op, const IT* Jrow,
+                                       const IT* hrow, uint64_t bs) {
+  float sw[8];
+  const float h0 = op.hspin >= 0 ? ldv(hrow, op.hspin) : 0.f;
+#pragma unroll
+  for (int p = 0; p < 8; ++p) sw[p] = h0;
+  for (int k = 0; k < op.nt; ++k) {
+    const float Jk = ldv(Jrow, op.te[k]);
+    const uint8_t w = op.w[k];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int j = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+      sw[p] += ebit(w, ix[j], bs) ? -Jk : Jk;
     }
-    lo[j] = a;
-    hi[j] = b;
+  }
+  if (op.kind == FK_GATE) {
+    const float J = ldv(Jrow, op.edge);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+      const int j1 = j0 | (1 << L);
+      const float a0 = v[j0], a1 = v[j1];
+      v[j0] = fmaxf(a0 + J, a1 - J) + sw[p];
+      v[j1] = fmaxf(a0 - J, a1 + J) - sw[p];
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+      const int j1 = j0 | (1 << L);
+      const float m = fmaxf(v[j0], v[j1]);
+      v[j0] = m;
+      v[j1] = m;
+    }
   }
 }
 
-__device__ __forceinline__ uint64_t tile_base(const DevPass& P, uint64_t tile_id) {
-  uint64_t base = 0;
-  for (int k = 0; k < P.n_free; ++k) base |= ((tile_id >> k) & 1ull) << P.fre[k];
-  return base;
+// Star of a spin that entered without a gate: x += sigma(spin) * sw.
+template <typename IT>
+__device__ __forceinline__ void star16(float (&v)[16], const uint32_t (&ix)[16], const FOp& op, const IT* Jrow,
+                                       const IT* hrow, uint64_t bs) {
+  const float h0 = op.hspin >= 0 ? ldv(hrow, op.hspin) : 0.f;
+  float sw[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) sw[j] = h0;
+  for (int k = 0; k < op.nt; ++k) {
+    const float Jk = ldv(Jrow, op.te[k]);
+    const uint8_t w = op.w[k];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sw[j] += ebit(w, ix[j], bs) ? -Jk : Jk;
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] += ebit(op.bit, ix[j], bs) ? -sw[j] : sw[j];
 }
 
-// Applies ops [0, n_ops) of a pass to an LDS tile of 2^t floats.
-// REC: record the argmax decision of every GATE / CUT for every output entry
-// (bit i of row op.dec), ties resolving to the first argument.
-template <bool REC, typename IT>
-__device__ void apply_ops(float* tile, uint32_t* dec, int t, uint64_t base, const DevOp* ops,
-                          int n_ops, const IT* Jrow, const IT* hrow) {
-  const uint32_t size = 1u << t;
-  const uint32_t half = size >> 1;
-  const int tid = threadIdx.x;
-  for (int o = 0; o < n_ops; ++o) {
-    const DevOp op = ops[o];
-    if (op.kind == OP_GATE || op.kind == OP_CUT) {
-      const float J = op.kind == OP_GATE ? ldv(Jrow, op.param) : 0.f;
-      const int b = op.a;
-      const uint32_t lowmask = (1u << b) - 1u;
-      for (uint32_t p = tid; p < half; p += NT) {
-        const uint32_t i0 = ((p & ~lowmask) << 1) | (p & lowmask);
-        const uint32_t i1 = i0 | (1u << b);
-        const float a0 = tile[i0], a1 = tile[i1];
-        // new index 0: from old 0 with +J, from old 1 with -J; new index 1: the reverse
-        const float c00 = a0 + J, c10 = a1 - J;
-        const float c01 = a0 - J, c11 = a1 + J;
-        tile[i0] = fmaxf(c00, c10);
-        tile[i1] = fmaxf(c01, c11);
-        if (REC) {
-          uint32_t* row = dec + (size_t)op.dec * ((size + 31u) >> 5);
-          if (c10 > c00) atomicOr(&row[i0 >> 5], 1u << (i0 & 31));
-          if (c11 > c01) atomicOr(&row[i1 >> 5], 1u << (i1 & 31));
-        }
-      }
-      __syncthreads();
-    } else if (op.kind == OP_DIAG) {
-      const float J = ldv(Jrow, op.param);
-      for (uint32_t i = tid; i < size; i += NT) {
-        const int s = bit_of(op.a, i, base) ^ bit_of(op.b, i, base);
-        tile[i] += s ? -J : J;
-      }
-      __syncthreads();
-    } else if (op.kind == OP_FIELD) {
-      const float hv = ldv(hrow, op.param);
-      for (uint32_t i = tid; i < size; i += NT) {
-        tile[i] += bit_of(op.a, i, base) ? -hv : hv;
-      }
-      __syncthreads();
+// Builds the enumeration tables of a load (store): enumeration index u ->
+// tile index and address offset, tile bits taken in `order`, the first
+// `n_addr` of them carrying address bits pos[slot].
+__device__ __forceinline__ void build_enum(const DevPass2& P, const uint8_t* order, const uint8_t* pos, int n_enum,
+                                           int n_addr, uint64_t* a_lo, uint64_t* a_hi, uint16_t* i_lo,
+                                           uint16_t* i_hi) {
+  for (int j = threadIdx.x; j < 256 + 64; j += blockDim.x) {
+    const int lo = j < 256;
+    const int x = lo ? j : j - 256;
+    uint64_t a = 0;
+    uint32_t ti = 0;
+    for (int q = 0; q < 8; ++q) {
+      const int k = lo ? q : q + 8;
+      if (k >= n_enum || !((x >> q) & 1)) continue;
+      const int tb = order[k];
+      ti |= 1u << tb;
+      if (k < n_addr) a |= 1ull << pos[P.R[tb]];
     }
-    // OP_INTRO: the new slot was free, i.e. constant along its bit: nothing to do
+    if (lo) {
+      a_lo[x] = a;
+      i_lo[x] = (uint16_t)ti;
+    } else {
+      a_hi[x] = a;
+      i_hi[x] = (uint16_t)ti;
+    }
   }
 }
 
 template <typename IT>
-__global__ __launch_bounds__(NT) void k_sweep_pass(DevPass P, const DevOp* __restrict__ ops,
-                                                   const IT* __restrict__ J, const IT* __restrict__ h,
-                                                   int64_t jst, int64_t hst, const float* __restrict__ in,
-                                                   float* __restrict__ out, int64_t sst, int log2_tiles) {
+__global__ __launch_bounds__(NT) void k_pass(DevPass2 P, const DevStage* __restrict__ stages,
+                                             const FOp* __restrict__ fops, const IT* __restrict__ J,
+                                             const IT* __restrict__ h, int64_t jst, int64_t hst,
+                                             const float* __restrict__ in, float* __restrict__ out, int64_t sst,
+                                             int batch, int xcd_group) {
   extern __shared__ float tile[];
-  __shared__ uint64_t dep_lo[256], dep_hi[256];
-  const int64_t inst = (int64_t)blockIdx.x >> log2_tiles;
-  const uint64_t tile_id = (uint64_t)blockIdx.x & ((1ull << log2_tiles) - 1ull);
-  const uint64_t base = tile_base(P, tile_id);
-  build_deposit(P.R, P.t, dep_lo, dep_hi);
+  __shared__ uint64_t a_lo[256], a_hi[64];    // enumeration index -> address offset
+  __shared__ uint16_t i_lo[256], i_hi[64];    // enumeration index -> tile index
+  int64_t inst;
+  uint64_t tid_bits;
+  if (!wg_to_tile(P.n_free, batch, xcd_group, &inst, &tid_bits)) return;
+  const int tid = threadIdx.x;
+  const int t = P.t;
+  const uint32_t size = 1u << t;
+  // fixed (non-resident) slots of this tile, in slot space and in both layouts
+  uint64_t bs = 0, in_base = 0, out_base = 0;
+  bool stored = true;
+  for (int k = 0; k < P.n_free; ++k) {
+    const uint64_t b = (tid_bits >> k) & 1ull;
+    const int slot = P.fre[k];
+    bs |= b << slot;
+    if (P.in_pos[slot] != NO_POS) in_base |= b << P.in_pos[slot];
+    if (P.out_pos[slot] != NO_POS) out_base |= b << P.out_pos[slot];
+    else if (b) stored = false;   // only the copy with a dropped slot at 0 is kept
+  }
+  // load, enumerating the tile in the order of the input layout
+  build_enum(P, P.ld_order, P.in_pos, t, P.n_ld, a_lo, a_hi, i_lo, i_hi);
   __syncthreads();
-  const uint32_t size = 1u << P.t;
-  const uint64_t in_mask = (1ull << P.in_w) - 1ull;
-  const float* src = in + inst * sst;
-  for (uint32_t i = threadIdx.x; i < size; i += NT) {
-    const uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
-    tile[i] = P.init ? 0.f : src[idx & in_mask];
+  const float* src = in + inst * sst + in_base;
+  for (uint32_t u = tid; u < size; u += NT) {
+    const uint32_t ti = i_lo[u & 255u] | i_hi[u >> 8];
+    tile[ti] = P.init ? 0.f : src[a_lo[u & 255u] | a_hi[u >> 8]];
   }
   __syncthreads();
-  apply_ops<false, IT>(tile, nullptr, P.t, base, ops + P.op_begin, P.n_ops, J + inst * jst,
-                       h ? h + inst * hst : nullptr);
-  float* dst = out + inst * sst;
-  for (uint32_t i = threadIdx.x; i < size; i += NT) {
-    const uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
-    if ((idx >> P.out_w) == 0) dst[idx] = tile[i];
+  const IT* Jrow = J + inst * jst;
+  const IT* hrow = h ? h + inst * hst : nullptr;
+  for (int s = 0; s < P.n_stages; ++s) {
+    const DevStage ST = stages[P.stage_begin + s];
+    const uint32_t groups = size >> 4;
+    const uint32_t m0 = 1u << ST.sb[0], m1 = 1u << ST.sb[1], m2 = 1u << ST.sb[2], m3 = 1u << ST.sb[3];
+    for (uint32_t g = tid; g < groups; g += NT) {
+      uint32_t gb = 0;
+      for (int q = 0; q < ST.nns; ++q) gb |= ((g >> q) & 1u) << ST.ns[q];
+      uint32_t ix[16];
+      float v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        ix[j] = gb | ((j & 1) ? m0 : 0u) | ((j & 2) ? m1 : 0u) | ((j & 4) ? m2 : 0u) | ((j & 8) ? m3 : 0u);
+        v[j] = tile[ix[j]];
+      }
+      for (int o = ST.op_begin; o < ST.op_end; ++o) {
+        const FOp op = fops[o];
+        if (op.kind == FK_STAR) {
+          star16<IT>(v, ix, op, Jrow, hrow, bs);
+        } else {
+          switch (op.lidx) {
+            case 0: gate_l<0, IT>(v, ix, op, Jrow, hrow, bs); break;
+            case 1: gate_l<1, IT>(v, ix, op, Jrow, hrow, bs); break;
+            case 2: gate_l<2, IT>(v, ix, op, Jrow, hrow, bs); break;
+            default: gate_l<3, IT>(v, ix, op, Jrow, hrow, bs); break;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) tile[ix[j]] = v[j];
+    }
+    __syncthreads();
   }
+  if (!stored) return;
+  // store, enumerating the tile in the order of the output layout
+  build_enum(P, P.st_order, P.out_pos, P.n_st, P.n_st, a_lo, a_hi, i_lo, i_hi);
+  __syncthreads();
+  float* dst = out + inst * sst + out_base;
+  const uint32_t nst = 1u << P.n_st;
+  for (uint32_t u = tid; u < nst; u += NT) dst[a_lo[u & 255u] | a_hi[u >> 8]] = tile[i_lo[u & 255u] | i_hi[u >> 8]];
 }
 
 // ---------------------------------------------------------------------------
-// final reduction: max over the state and its lowest index (Sec. II: the
+// final reduction: max over the state and its lowest address (Sec. II: the
 // contraction with the product state (0, 0)^n of App. A)
 // ---------------------------------------------------------------------------
 
@@ -145,9 +233,10 @@ __device__ __forceinline__ VI vi_best(VI a, VI b) {
   return a;
 }
 
+template <int THREADS>
 __device__ VI block_best(VI x) {
-  __shared__ float sv[NT / 64];
-  __shared__ uint64_t si[NT / 64];
+  __shared__ float sv[THREADS / 64];
+  __shared__ uint64_t si[THREADS / 64];
   for (int off = 32; off > 0; off >>= 1) {
     VI y;
     y.v = __shfl_xor(x.v, off, 64);
@@ -161,7 +250,7 @@ __device__ VI block_best(VI x) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int k = 1; k < NT / 64; ++k) x = vi_best(x, VI{sv[k], si[k]});
+    for (int k = 1; k < THREADS / 64; ++k) x = vi_best(x, VI{sv[k], si[k]});
     sv[0] = x.v;
     si[0] = x.i;
   }
@@ -171,34 +260,34 @@ __device__ VI block_best(VI x) {
   return r;
 }
 
-__global__ __launch_bounds__(NT) void k_reduce_stage1(const float* __restrict__ st, int64_t sst, int w,
-                                                      int log2_chunks, float* __restrict__ pv,
-                                                      uint64_t* __restrict__ pi) {
+__global__ __launch_bounds__(NTR) void k_reduce_stage1(const float* __restrict__ st, int64_t sst, int w,
+                                                       int log2_chunks, float* __restrict__ pv,
+                                                       uint64_t* __restrict__ pi) {
   const int64_t inst = (int64_t)blockIdx.x >> log2_chunks;
   const uint64_t chunk = (uint64_t)blockIdx.x & ((1ull << log2_chunks) - 1ull);
   const uint64_t len = 1ull << (w - log2_chunks);
   const float* s = st + inst * sst;
   VI best{-INFINITY, ~0ull};
-  for (uint64_t k = threadIdx.x; k < len; k += NT) {
+  for (uint64_t k = threadIdx.x; k < len; k += NTR) {
     const uint64_t idx = chunk * len + k;
     best = vi_best(best, VI{s[idx], idx});
   }
-  best = block_best(best);
+  best = block_best<NTR>(best);
   if (threadIdx.x == 0) {
     pv[blockIdx.x] = best.v;
     pi[blockIdx.x] = best.i;
   }
 }
 
-__global__ __launch_bounds__(NT) void k_reduce_stage2(const float* __restrict__ pv,
-                                                      const uint64_t* __restrict__ pi, int log2_chunks,
-                                                      double* __restrict__ energy,
-                                                      uint64_t* __restrict__ arg) {
+__global__ __launch_bounds__(NTR) void k_reduce_stage2(const float* __restrict__ pv,
+                                                       const uint64_t* __restrict__ pi, int log2_chunks,
+                                                       double* __restrict__ energy,
+                                                       uint64_t* __restrict__ arg) {
   const int64_t inst = blockIdx.x;
   const int64_t nc = 1ll << log2_chunks;
   VI best{-INFINITY, ~0ull};
-  for (int64_t k = threadIdx.x; k < nc; k += NT) best = vi_best(best, VI{pv[inst * nc + k], pi[inst * nc + k]});
-  best = block_best(best);
+  for (int64_t k = threadIdx.x; k < nc; k += NTR) best = vi_best(best, VI{pv[inst * nc + k], pi[inst * nc + k]});
+  best = block_best<NTR>(best);
   if (threadIdx.x == 0) {
     if (energy) energy[inst] = -(double)best.v;
     if (arg) arg[inst] = best.i;
@@ -206,28 +295,47 @@ __global__ __launch_bounds__(NT) void k_reduce_stage2(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// backward: argmax routing (Sec. IV, caching intermediates and backtracking;
-// the first argument wins ties). One workgroup per instance walks the passes
-// in reverse; for each pass it reloads the tile holding the selected entry
-// from that pass's input, recomputes the pass recording every decision, and
-// routes the selected index back through the pass's ops.
+// backward: argmax routing (Sec. IV: cache intermediates, backtrack; the
+// reverse-mode derivative of E* with respect to the tensor elements picks the
+// maximising entries). One workgroup per instance walks the passes in
+// reverse. Given the selected entry t of a pass's output, the spins the pass
+// eliminated (at most 16) are the only unknowns: the workgroup scores every
+// joint assignment a of them as x_in(a, t) + (terms of the pass that touch an
+// eliminated spin) and keeps the first maximiser. That is the value the pass
+// maximised over, so the chain of choices is a ground state.
 // ---------------------------------------------------------------------------
 
 constexpr int MAX_SPINS = 8192;
 
+__device__ __forceinline__ float term_sigma(uint8_t op, uint32_t a, uint64_t t) {
+  const uint32_t b = op < 64 ? ((a >> op) & 1u) : (uint32_t)((t >> (op - 64)) & 1ull);
+  return b ? -1.f : 1.f;
+}
+
 template <typename IT>
-__global__ __launch_bounds__(NT) void k_sweep_backward(
-    const DevPass* __restrict__ passes, int n_passes, const DevOp* __restrict__ ops,
-    const DevSpin* __restrict__ spins, const IT* __restrict__ J, const IT* __restrict__ h, int64_t jst,
-    int64_t hst, const float* const* __restrict__ ckpt, int64_t sst, const uint64_t* __restrict__ final_idx,
-    const int32_t* __restrict__ final_slot_spin, int final_w, const int32_t* __restrict__ edges, int n,
-    int64_t m, int8_t* __restrict__ sigma, float* __restrict__ dJ, float* __restrict__ dh, int max_t) {
-  extern __shared__ float smem[];
-  float* tile = smem;
-  uint32_t* dec = reinterpret_cast<uint32_t*>(smem + (1u << max_t));
-  __shared__ uint64_t dep_lo[256], dep_hi[256];
+__device__ __forceinline__ float term_val(const BTerm& tm, uint32_t a, uint64_t t, const IT* Jrow,
+                                          const IT* hrow) {
+  const float c = tm.is_field ? ldv(hrow, tm.coef) : ldv(Jrow, tm.coef);
+  float s = term_sigma(tm.a, a, t);
+  if (tm.b != 255) s *= term_sigma(tm.b, a, t);
+  return c * s;
+}
+
+template <typename IT>
+__global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ passes, int n_passes,
+                                                 const BCand* __restrict__ cands, const BTerm* __restrict__ terms,
+                                                 const IT* __restrict__ J, const IT* __restrict__ h, int64_t jst,
+                                                 int64_t hst, const float* const* __restrict__ ckpt, int64_t sst,
+                                                 const uint64_t* __restrict__ final_addr,
+                                                 const uint8_t* __restrict__ final_pos,
+                                                 const int32_t* __restrict__ final_slot_spin, int final_w,
+                                                 const int32_t* __restrict__ edges, int n, int64_t m,
+                                                 int8_t* __restrict__ sigma, float* __restrict__ dJ,
+                                                 float* __restrict__ dh) {
   __shared__ int8_t s_sh[MAX_SPINS];
-  __shared__ uint64_t sh_idx, sh_base;
+  __shared__ float lut_lo[256], lut_hi[256];
+  __shared__ uint64_t ad_lo[256], ad_hi[256];
+  __shared__ uint64_t sh_t, sh_base;
   const int64_t inst = blockIdx.x;
   const int tid = threadIdx.x;
   const IT* Jrow = J + inst * jst;
@@ -235,68 +343,91 @@ __global__ __launch_bounds__(NT) void k_sweep_backward(
   for (int v = tid; v < n; v += NT) s_sh[v] = 0;
   __syncthreads();
   if (tid == 0) {
-    const uint64_t idx = final_idx[inst];
+    const uint64_t addr = final_addr[inst];
+    uint64_t t = 0;
     for (int c = 0; c < final_w; ++c) {
+      const uint64_t b = (addr >> final_pos[c]) & 1ull;
+      t |= b << c;
       const int sp = final_slot_spin[c];
-      if (sp >= 0) s_sh[sp] = (int8_t)((idx >> c) & 1ull);
+      if (sp >= 0) s_sh[sp] = (int8_t)b;
     }
-    sh_idx = idx;
+    sh_t = t;
   }
   __syncthreads();
   for (int p = n_passes - 1; p >= 0; --p) {
-    const DevPass P = passes[p];
-    const uint32_t size = 1u << P.t;
-    const uint32_t words = (size + 31u) >> 5;
-    build_deposit(P.R, P.t, dep_lo, dep_hi);
-    for (uint32_t k = tid; k < (uint32_t)P.n_dec * words; k += NT) dec[k] = 0u;
-    if (tid == 0) {
-      uint64_t rmask = 0;
-      for (int k = 0; k < P.t; ++k) rmask |= 1ull << P.R[k];
-      sh_base = sh_idx & ~rmask & ((1ull << P.w_max) - 1ull);
+    const DevPass2& P = passes[p];
+    const int nc = P.n_cand;
+    const uint64_t t = sh_t;
+    if (nc == 0) {
+      __syncthreads();
+      if (tid == 0) sh_t = t & P.surv_mask;
+      __syncthreads();
+      continue;
     }
-    __syncthreads();
-    const uint64_t base = sh_base;
-    const uint64_t in_mask = (1ull << P.in_w) - 1ull;
-    const float* src = ckpt[p];
-    for (uint32_t i = tid; i < size; i += NT) {
-      const uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
-      tile[i] = P.init ? 0.f : src[inst * sst + (idx & in_mask)];
-    }
-    __syncthreads();
-    apply_ops<true, IT>(tile, dec, P.t, base, ops + P.op_begin, P.n_ops, Jrow, hrow);
-    __syncthreads();
-    if (tid == 0) {
-      const uint64_t idx = sh_idx;
-      uint32_t i = 0;
-      for (int k = 0; k < P.t; ++k) i |= (uint32_t)((idx >> P.R[k]) & 1ull) << k;
-      uint64_t b = base;
-      for (int o = P.n_ops - 1; o >= 0; --o) {
-        const DevOp op = ops[P.op_begin + o];
-        if (op.kind == OP_GATE || op.kind == OP_CUT) {
-          const uint32_t d = (dec[(size_t)op.dec * words + (i >> 5)] >> (i & 31u)) & 1u;
-          s_sh[spins[P.op_begin + o].old_spin] = (int8_t)d;
-          i = (i & ~(1u << op.a)) | (d << op.a);
-        } else if (op.kind == OP_INTRO) {
-          if (op.a < SLOT_FIXED) i &= ~(1u << op.a);
-          else b &= ~(1ull << (op.a - SLOT_FIXED));
-        }
+    const BCand* C = cands + P.cand_begin;
+    const BTerm* T = terms + P.term_begin;
+    const int nlo = nc < 8 ? nc : 8, nhi = nc - nlo;
+    // tables over the low / high halves of the candidate bits
+    for (int a = tid; a < 512; a += NT) {
+      const int hi = a >= 256;
+      const uint32_t x = hi ? (uint32_t)(a - 256) : (uint32_t)a;
+      if (x >= (1u << (hi ? nhi : nlo))) continue;
+      const uint32_t full = hi ? (x << 8) : x;
+      float acc = 0.f;
+      const int tb = hi ? P.n_lo : 0, te = hi ? P.n_lo + P.n_hi : P.n_lo;
+      for (int k = tb; k < te; ++k) acc += term_val<IT>(T[k], full, t, Jrow, hrow);
+      uint64_t ad = 0;
+      const int kb = hi ? 8 : 0, ke = hi ? nc : nlo;
+      for (int k = kb; k < ke; ++k) {
+        const int ss = C[k].start_slot;
+        if (ss >= 0 && P.in_pos[ss] != NO_POS && ((full >> k) & 1u)) ad |= 1ull << P.in_pos[ss];
       }
-      uint64_t idx_in = b;
-      for (int k = 0; k < P.t; ++k) idx_in |= (uint64_t)((i >> k) & 1u) << P.R[k];
-      sh_idx = idx_in & in_mask;
+      if (hi) {
+        lut_hi[x] = acc;
+        ad_hi[x] = ad;
+      } else {
+        lut_lo[x] = acc;
+        ad_lo[x] = ad;
+      }
+    }
+    if (tid == 0) {
+      uint64_t base = 0;
+      for (int c = 0; c < P.in_w; ++c)
+        if (((P.surv_mask >> c) & 1ull) && ((t >> c) & 1ull)) base |= 1ull << P.in_pos[c];
+      sh_base = base;
+    }
+    __syncthreads();
+    const float* src = P.init ? nullptr : ckpt[p] + inst * sst + sh_base;
+    VI best{-INFINITY, ~0ull};
+    const uint32_t na = 1u << nc;
+    const int cross_b = P.n_lo + P.n_hi, cross_e = P.n_lo + P.n_hi + P.n_cross;
+    for (uint32_t a = tid; a < na; a += NT) {
+      float val = lut_lo[a & 255u] + lut_hi[a >> 8];
+      for (int k = cross_b; k < cross_e; ++k) val += term_val<IT>(T[k], a, t, Jrow, hrow);
+      if (src) val += src[ad_lo[a & 255u] | ad_hi[a >> 8]];
+      best = vi_best(best, VI{val, (uint64_t)a});
+    }
+    best = block_best<NT>(best);
+    if (tid == 0) {
+      const uint32_t a = (uint32_t)best.i;
+      uint64_t tin = t & P.surv_mask;
+      for (int k = 0; k < nc; ++k) {
+        const uint32_t b = (a >> k) & 1u;
+        s_sh[C[k].spin] = (int8_t)b;
+        if (C[k].start_slot >= 0) tin |= (uint64_t)b << C[k].start_slot;
+      }
+      sh_t = tin;
     }
     __syncthreads();
   }
   for (int v = tid; v < n; v += NT) {
-    const float sg = s_sh[v] ? -1.f : 1.f;
     sigma[inst * n + v] = (int8_t)(s_sh[v] ? -1 : 1);
-    if (dh) dh[inst * n + v] = -sg;
+    if (dh) dh[inst * n + v] = s_sh[v] ? 1.f : -1.f;           // -sigma_v
   }
   if (dJ) {
     for (int64_t e = tid; e < m; e += NT) {
       const int a = edges[2 * e], c = edges[2 * e + 1];
-      const float sa = s_sh[a] ? -1.f : 1.f, sc = s_sh[c] ? -1.f : 1.f;
-      dJ[inst * m + e] = -(sa * sc);
+      dJ[inst * m + e] = (s_sh[a] ^ s_sh[c]) ? 1.f : -1.f;   // -sigma_a sigma_c
     }
   }
 }
@@ -305,30 +436,32 @@ __global__ __launch_bounds__(NT) void k_sweep_backward(
 // host launch wrappers (kernels are launched from this translation unit)
 // ---------------------------------------------------------------------------
 
+// Raises the dynamic LDS limit of a kernel (static tables come on top of it).
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t bytes) {
-  if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (bytes < 32768) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
 }
 
-hipError_t launch_sweep_pass(const DevPass& P, const DevOp* ops, int dtype, const void* J, const void* h,
-                             int64_t jst, int64_t hst, const float* in, float* out, int64_t sst, int batch,
-                             hipStream_t stream) {
+hipError_t launch_pass(const DevPass2& P, const DevStage* stages, const FOp* fops, int dtype, const void* J,
+                       const void* h, int64_t jst, int64_t hst, const float* in, float* out, int64_t sst, int batch,
+                       hipStream_t stream) {
   const size_t lds = sizeof(float) << P.t;
-  const int log2_tiles = P.n_free;
-  const uint64_t grid = (uint64_t)batch << log2_tiles;
+  const uint64_t tiles = 1ull << P.n_free;
+  const int xcd_group = (batch % 8 == 0) ? 1 : 0;
+  const uint64_t grid = (uint64_t)batch * tiles;
   if (grid >= (1ull << 31)) return hipErrorInvalidConfiguration;
   if (dtype == 0) {
-    hipError_t e = allow_lds(k_sweep_pass<float>, lds);
+    hipError_t e = allow_lds(k_pass<float>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep_pass<float>, dim3((uint32_t)grid), dim3(NT), lds, stream, P, ops,
-                       (const float*)J, (const float*)h, jst, hst, in, out, sst, log2_tiles);
+    hipLaunchKernelGGL(k_pass<float>, dim3((uint32_t)grid), dim3(NT), lds, stream, P, stages, fops,
+                       (const float*)J, (const float*)h, jst, hst, in, out, sst, batch, xcd_group);
   } else {
-    hipError_t e = allow_lds(k_sweep_pass<int32_t>, lds);
+    hipError_t e = allow_lds(k_pass<int32_t>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep_pass<int32_t>, dim3((uint32_t)grid), dim3(NT), lds, stream, P, ops,
-                       (const int32_t*)J, (const int32_t*)h, jst, hst, in, out, sst, log2_tiles);
+    hipLaunchKernelGGL(k_pass<int32_t>, dim3((uint32_t)grid), dim3(NT), lds, stream, P, stages, fops,
+                       (const int32_t*)J, (const int32_t*)h, jst, hst, in, out, sst, batch, xcd_group);
   }
   return hipGetLastError();
 }
@@ -344,36 +477,25 @@ int reduce_log2_chunks(int w) {
 hipError_t launch_reduce(const float* st, int64_t sst, int w, int batch, float* pv, uint64_t* pi,
                          double* energy, uint64_t* arg, hipStream_t stream) {
   const int lc = reduce_log2_chunks(w);
-  hipLaunchKernelGGL(k_reduce_stage1, dim3((uint32_t)((uint64_t)batch << lc)), dim3(NT), 0, stream, st, sst,
-                     w, lc, pv, pi);
-  hipLaunchKernelGGL(k_reduce_stage2, dim3((uint32_t)batch), dim3(NT), 0, stream, pv, pi, lc, energy, arg);
+  hipLaunchKernelGGL(k_reduce_stage1, dim3((uint32_t)((uint64_t)batch << lc)), dim3(NTR), 0, stream, st, sst, w, lc,
+                     pv, pi);
+  hipLaunchKernelGGL(k_reduce_stage2, dim3((uint32_t)batch), dim3(NTR), 0, stream, pv, pi, lc, energy, arg);
   return hipGetLastError();
 }
 
-size_t backward_lds_bytes(int max_t, int max_dec) {
-  const size_t words = (((size_t)1 << max_t) + 31) / 32;   // decision row: whole 32-bit words
-  return (sizeof(float) << max_t) + (size_t)max_dec * words * sizeof(uint32_t);
-}
-
-hipError_t launch_sweep_backward(const DevPass* passes, int n_passes, const DevOp* ops, const DevSpin* spins,
-                                 int dtype, const void* J, const void* h, int64_t jst, int64_t hst,
-                                 const float* const* ckpt, int64_t sst, const uint64_t* final_idx,
-                                 const int32_t* final_slot_spin, int final_w, const int32_t* edges, int n,
-                                 int64_t m, int8_t* sigma, float* dJ, float* dh, int max_t, int max_dec,
-                                 int batch, hipStream_t stream) {
-  const size_t lds = backward_lds_bytes(max_t, max_dec);
+hipError_t launch_backward(const DevPass2* passes, int n_passes, const BCand* cands, const BTerm* terms, int dtype,
+                           const void* J, const void* h, int64_t jst, int64_t hst, const float* const* ckpt,
+                           int64_t sst, const uint64_t* final_addr, const uint8_t* final_pos,
+                           const int32_t* final_slot_spin, int final_w, const int32_t* edges, int n, int64_t m,
+                           int8_t* sigma, float* dJ, float* dh, int batch, hipStream_t stream) {
   if (dtype == 0) {
-    hipError_t e = allow_lds(k_sweep_backward<float>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep_backward<float>, dim3(batch), dim3(NT), lds, stream, passes, n_passes, ops, spins,
-                       (const float*)J, (const float*)h, jst, hst, ckpt, sst, final_idx, final_slot_spin,
-                       final_w, edges, n, m, sigma, dJ, dh, max_t);
+    hipLaunchKernelGGL(k_backward<float>, dim3(batch), dim3(NT), 0, stream, passes, n_passes, cands, terms,
+                       (const float*)J, (const float*)h, jst, hst, ckpt, sst, final_addr, final_pos, final_slot_spin,
+                       final_w, edges, n, m, sigma, dJ, dh);
   } else {
-    hipError_t e = allow_lds(k_sweep_backward<int32_t>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep_backward<int32_t>, dim3(batch), dim3(NT), lds, stream, passes, n_passes, ops,
-                       spins, (const int32_t*)J, (const int32_t*)h, jst, hst, ckpt, sst, final_idx,
-                       final_slot_spin, final_w, edges, n, m, sigma, dJ, dh, max_t);
+    hipLaunchKernelGGL(k_backward<int32_t>, dim3(batch), dim3(NT), 0, stream, passes, n_passes, cands, terms,
+                       (const int32_t*)J, (const int32_t*)h, jst, hst, ckpt, sst, final_addr, final_pos,
+                       final_slot_spin, final_w, edges, n, m, sigma, dJ, dh);
   }
   return hipGetLastError();
 }

@@ -1,0 +1,195 @@
+"""Host emulation of the energy kernels' algorithm (sweep_kernels.hip) on the
+encoded program the library builds (tt_plan_program): tile loads and stores
+in per-pass bit layouts, register stages of fused gates, final reduction and
+the one-argmax-per-pass backward walk. Used by CPU tests to check the
+encoder and the kernel algorithm on small cases before they run on a GPU.
+Test infrastructure only; shares no code with the HIP sources.
+"""
+import ctypes as C
+
+import numpy as np
+
+FK_GATE, FK_CUT, FK_STAR = 1, 2, 3
+SLOT_FIXED, NO_POS = 64, 0xFF
+
+
+class DevPass2(C.Structure):
+    _fields_ = [("in_w", C.c_int32), ("out_w", C.c_int32), ("w_max", C.c_int32), ("t", C.c_int32),
+                ("stage_begin", C.c_int32), ("n_stages", C.c_int32), ("init", C.c_int32), ("n_free", C.c_int32),
+                ("cand_begin", C.c_int32), ("n_cand", C.c_int32), ("term_begin", C.c_int32), ("n_lo", C.c_int32),
+                ("n_hi", C.c_int32), ("n_cross", C.c_int32), ("surv_mask", C.c_uint64),
+                ("R", C.c_uint8 * 16), ("fre", C.c_uint8 * 48), ("in_pos", C.c_uint8 * 64),
+                ("out_pos", C.c_uint8 * 64), ("ld_order", C.c_uint8 * 16), ("st_order", C.c_uint8 * 16),
+                ("n_ld", C.c_int32), ("n_st", C.c_int32)]
+
+
+class DevStage(C.Structure):
+    _fields_ = [("sb", C.c_uint8 * 4), ("nns", C.c_uint8), ("ns", C.c_uint8 * 15), ("op_begin", C.c_int32),
+                ("op_end", C.c_int32), ("pad", C.c_int32 * 2)]
+
+
+class FOp(C.Structure):
+    _fields_ = [("kind", C.c_uint8), ("bit", C.c_uint8), ("lidx", C.c_uint8), ("nt", C.c_uint8),
+                ("edge", C.c_int32), ("hspin", C.c_int32), ("w", C.c_uint8 * 4), ("te", C.c_int32 * 4)]
+
+
+class BCand(C.Structure):
+    _fields_ = [("spin", C.c_int32), ("start_slot", C.c_int32)]
+
+
+class BTerm(C.Structure):
+    _fields_ = [("coef", C.c_int32), ("is_field", C.c_uint8), ("a", C.c_uint8), ("b", C.c_uint8),
+                ("pad", C.c_uint8)]
+
+
+def _records(raw, cls):
+    n = len(raw) // C.sizeof(cls)
+    assert n * C.sizeof(cls) == len(raw)
+    arr = (cls * max(n, 1)).from_buffer_copy(raw + b"\0" * (C.sizeof(cls) * max(n, 1) - len(raw)))
+    return [arr[i] for i in range(n)]
+
+
+def load_program(plan):
+    return {
+        "passes": _records(plan.program(0), DevPass2),
+        "stages": _records(plan.program(1), DevStage),
+        "fops": _records(plan.program(2), FOp),
+        "cands": _records(plan.program(3), BCand),
+        "terms": _records(plan.program(4), BTerm),
+        "final_pos": list(plan.program(5)),
+    }
+
+
+def _ebit(enc, i, bs):
+    return (i >> enc) & 1 if enc < SLOT_FIXED else (bs >> (enc - SLOT_FIXED)) & 1
+
+
+def forward(prog, width, J, h):
+    """Runs every pass; returns the list of pass inputs and the final state."""
+    size = 1 << width
+    states = [np.zeros(size)]
+    for P in prog["passes"]:
+        src = states[-1]
+        dst = np.full(size, np.nan)
+        t = P.t
+        for tid in range(1 << P.n_free):
+            bs = in_base = out_base = 0
+            stored = True
+            for k in range(P.n_free):
+                b = (tid >> k) & 1
+                s = P.fre[k]
+                bs |= b << s
+                if P.in_pos[s] != NO_POS:
+                    in_base |= b << P.in_pos[s]
+                if P.out_pos[s] != NO_POS:
+                    out_base |= b << P.out_pos[s]
+                elif b:
+                    stored = False
+            tile = np.zeros(1 << t)
+            for u in range(1 << t):
+                ti = a = 0
+                for k in range(t):
+                    if (u >> k) & 1:
+                        tb = P.ld_order[k]
+                        ti |= 1 << tb
+                        if k < P.n_ld:
+                            a |= 1 << P.in_pos[P.R[tb]]
+                tile[ti] = 0.0 if P.init else src[in_base | a]
+            for si in range(P.n_stages):
+                ST = prog["stages"][P.stage_begin + si]
+                sb = [ST.sb[l] for l in range(4)]
+                for g in range((1 << t) >> 4):
+                    gb = 0
+                    for q in range(ST.nns):
+                        gb |= ((g >> q) & 1) << ST.ns[q]
+                    ix = [gb | sum((1 << sb[l]) for l in range(4) if (j >> l) & 1) for j in range(16)]
+                    v = [tile[i] for i in ix]
+                    for o in range(ST.op_begin, ST.op_end):
+                        op = prog["fops"][o]
+                        h0 = h[op.hspin] if op.hspin >= 0 else 0.0
+                        if op.kind == FK_STAR:
+                            for j in range(16):
+                                sw = h0 + sum((-J[op.te[k]] if _ebit(op.w[k], ix[j], bs) else J[op.te[k]])
+                                              for k in range(op.nt))
+                                v[j] += -sw if _ebit(op.bit, ix[j], bs) else sw
+                            continue
+                        L = op.lidx
+                        for p in range(8):
+                            j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1))
+                            j1 = j0 | (1 << L)
+                            sw = h0 + sum((-J[op.te[k]] if _ebit(op.w[k], ix[j0], bs) else J[op.te[k]])
+                                          for k in range(op.nt))
+                            a0, a1 = v[j0], v[j1]
+                            if op.kind == FK_GATE:
+                                Je = J[op.edge]
+                                v[j0] = max(a0 + Je, a1 - Je) + sw
+                                v[j1] = max(a0 - Je, a1 + Je) - sw
+                            else:
+                                v[j0] = v[j1] = max(a0, a1)
+                    for j in range(16):
+                        tile[ix[j]] = v[j]
+            if not stored:
+                continue
+            for u in range(1 << P.n_st):
+                ti = a = 0
+                for k in range(P.n_st):
+                    if (u >> k) & 1:
+                        tb = P.st_order[k]
+                        ti |= 1 << tb
+                        a |= 1 << P.out_pos[P.R[tb]]
+                dst[out_base | a] = tile[ti]
+        states.append(dst)
+    return states
+
+
+def backward(prog, states, final_w, final_slot_spin, n, J, h):
+    """Final argmax (lowest address) and the walk back; returns (max, sigma)."""
+    fin = states[-1][: 1 << final_w]
+    assert not np.any(np.isnan(fin)), "final state has unwritten entries"
+    mx = fin.max()
+    addr = int(np.argmax(fin == mx))
+    s = np.zeros(n, np.int64)
+    t = 0
+    for c in range(final_w):
+        b = (addr >> prog["final_pos"][c]) & 1
+        t |= b << c
+        if final_slot_spin[c] >= 0:
+            s[final_slot_spin[c]] = b
+    for pi in range(len(prog["passes"]) - 1, -1, -1):
+        P = prog["passes"][pi]
+        nc = P.n_cand
+        if nc == 0:
+            t &= P.surv_mask
+            continue
+        cands = prog["cands"][P.cand_begin:P.cand_begin + nc]
+        terms = prog["terms"][P.term_begin:P.term_begin + P.n_lo + P.n_hi + P.n_cross]
+        base = 0
+        for c in range(P.in_w):
+            if (P.surv_mask >> c) & 1 and (t >> c) & 1:
+                base |= 1 << P.in_pos[c]
+        best, best_a = -np.inf, -1
+        for a in range(1 << nc):
+            ad = base
+            for k, cd in enumerate(cands):
+                if cd.start_slot >= 0 and P.in_pos[cd.start_slot] != NO_POS and (a >> k) & 1:
+                    ad |= 1 << P.in_pos[cd.start_slot]
+            val = 0.0 if P.init else states[pi][ad]
+            assert not np.isnan(val), "backward read an unwritten entry"
+            for tm in terms:
+                c = h[tm.coef] if tm.is_field else J[tm.coef]
+                sa = ((a >> tm.a) & 1) if tm.a < 64 else ((t >> (tm.a - 64)) & 1)
+                sg = -1 if sa else 1
+                if tm.b != 255:
+                    sb_ = ((a >> tm.b) & 1) if tm.b < 64 else ((t >> (tm.b - 64)) & 1)
+                    sg *= -1 if sb_ else 1
+                val += c * sg
+            if val > best:
+                best, best_a = val, a
+        tin = t & P.surv_mask
+        for k, cd in enumerate(cands):
+            b = (best_a >> k) & 1
+            s[cd.spin] = b
+            if cd.start_slot >= 0:
+                tin |= b << cd.start_slot
+        t = tin
+    return mx, (1 - 2 * s).astype(np.int8)

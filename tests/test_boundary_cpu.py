@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_every_header_symbol_is_exported():
     hdr = open(os.path.join(ROOT, "include", "tt.h")).read()
-    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(tt_\w+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^\s*(?:int64_t|int|void|const char\*)\s+(tt_\w+)\s*\(", hdr, re.M))
     assert declared == set(B.EXPORTS)
     for name in declared:
         assert hasattr(B.lib(), name), name
