@@ -279,8 +279,9 @@ int run_forward(Plan& p, DevCache* dc, int32_t batch, int32_t dtype, const void*
     const int dst = keep_all ? q + 1 : (cur ^ 1);
     if (keep_all) dc->h_ckpt_ptrs[q] = P.init ? nullptr : bufp(src);
     ProfScope ps(s, "sweep_pass");
-    HIP_TRY(launch_pass(P, static_cast<const DevStage*>(dc->d_stages.p), static_cast<const FOp*>(dc->d_fops.p), dtype,
-                        J, h, jst, hst, bufp(src), bufp(dst), sst, batch, s));
+    HIP_TRY(launch_pass(P, static_cast<const DevPass2*>(dc->d_passes.p) + q, static_cast<const DevStage*>(dc->d_stages.p),
+                        static_cast<const FOp*>(dc->d_fops.p), dtype, J, h, jst, hst, bufp(src), bufp(dst), sst, batch,
+                        s));
     cur = dst;
   }
   *final_state = bufp(keep_all ? np : cur);

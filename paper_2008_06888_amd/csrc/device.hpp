@@ -54,6 +54,8 @@ struct DevStage {
   uint8_t ns[15];    // non-stage tile bits, ascending
   int32_t op_begin, op_end;
   int32_t pad[2];
+  uint16_t g_lo[32]; // group index (low / high 5 bits) -> its non-stage tile bits
+  uint16_t g_hi[32];
 };
 
 struct DevPass2 {

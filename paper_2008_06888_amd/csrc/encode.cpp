@@ -224,6 +224,17 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
       for (int k = 0; k < d.t; ++k)
         if (std::find(S.begin(), S.end(), k) == S.end()) st2.ns[nns++] = (uint8_t)k;
       st2.nns = (uint8_t)nns;
+      for (int x = 0; x < 32; ++x) {
+        uint16_t lo = 0, hi = 0;
+        for (int q = 0; q < 5; ++q) {
+          if ((x >> q) & 1) {
+            if (q < nns) lo |= (uint16_t)(1u << st2.ns[q]);
+            if (q + 5 < nns) hi |= (uint16_t)(1u << st2.ns[q + 5]);
+          }
+        }
+        st2.g_lo[x] = lo;
+        st2.g_hi[x] = hi;
+      }
       st2.op_begin = (int)out.fops.size();
       for (size_t k = b0; k < e; ++k) {
         FOp x = f[k];

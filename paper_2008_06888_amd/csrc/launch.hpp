@@ -8,9 +8,9 @@
 
 namespace tt {
 
-hipError_t launch_pass(const DevPass2& P, const DevStage* stages, const FOp* fops, int dtype, const void* J,
-                       const void* h, int64_t jst, int64_t hst, const float* in, float* out, int64_t sst, int batch,
-                       hipStream_t stream);
+hipError_t launch_pass(const DevPass2& P, const DevPass2* P_dev, const DevStage* stages, const FOp* fops, int dtype,
+                       const void* J, const void* h, int64_t jst, int64_t hst, const float* in, float* out,
+                       int64_t sst, int batch, hipStream_t stream);
 int reduce_log2_chunks(int w);
 hipError_t launch_reduce(const float* st, int64_t sst, int w, int batch, float* pv, uint64_t* pi,
                          double* energy, uint64_t* arg, hipStream_t stream);

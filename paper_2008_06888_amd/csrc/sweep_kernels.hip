@@ -31,6 +31,10 @@ __device__ __forceinline__ float ldv(const IT* p, int64_t k) {
   return (float)p[k];
 }
 
+// LDS position of tile entry i: the low five bits are XORed with the next
+// five, which spreads the strided accesses of a stage over the 32 banks.
+__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
+
 // Value (0/1) of an encoded slot for an entry with tile index i.
 __device__ __forceinline__ uint32_t ebit(uint8_t enc, uint32_t i, uint64_t base_slots) {
   return enc < SLOT_FIXED ? ((i >> enc) & 1u) : (uint32_t)((base_slots >> (enc - SLOT_FIXED)) & 1ull);
@@ -53,36 +57,31 @@ __device__ __forceinline__ bool wg_to_tile(int log2_tiles, int batch, int xcd_gr
   return *inst < batch;
 }
 
+// Sign of a star term for an entry: +J when the partner spin is sigma = +1.
+__device__ __forceinline__ uint32_t tbit(uint32_t ix, uint32_t w) { return __builtin_amdgcn_ubfe(ix, w, 1); }
+
 // One relabelling gate on stage bit L of the 16 register entries, with the
-// star of the entering spin: new[0] = max(a0 + J, a1 - J) + sw,
-// new[1] = max(a0 - J, a1 + J) - sw, sw = h + sum_k J_k sigma(partner_k).
+// star of the entering spin, sw = h + sum_k J_k sigma(partner_k):
+//   new[0] = max(a0 + J, a1 - J) + sw = max(a0, a1 - 2J) + (J + sw)
+//   new[1] = max(a0 - J, a1 + J) - sw = max(a0 - 2J, a1) + (J - sw).
+// Star terms whose partner is a fixed slot of the tile are folded into a
+// constant; the first term on a resident slot selects between two constants.
 template <int L, typename IT>
-__device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16], const FOp& op, const IT* Jrow,
-                                       const IT* hrow, uint64_t bs) {
-  float sw[8];
-  const float h0 = op.hspin >= 0 ? ldv(hrow, op.hspin) : 0.f;
-#pragma unroll
-  for (int p = 0; p < 8; ++p) sw[p] = h0;
-  for (int k = 0; k < op.nt; ++k) {
-    const float Jk = ldv(Jrow, op.te[k]);
-    const uint8_t w = op.w[k];
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const int j = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-      sw[p] += ebit(w, ix[j], bs) ? -Jk : Jk;
+__device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16], const FOp* __restrict__ op,
+                                       const IT* Jrow, const IT* hrow, uint64_t bs) {
+  const int nt = op->nt;
+  float cst = op->hspin >= 0 ? ldv(hrow, op->hspin) : 0.f;
+  int first = -1;
+  for (int k = 0; k < nt; ++k) {
+    const uint8_t w = op->w[k];
+    if (w >= SLOT_FIXED) {
+      const float Jk = ldv(Jrow, op->te[k]);
+      cst += ((bs >> (w - SLOT_FIXED)) & 1ull) ? -Jk : Jk;
+    } else if (first < 0) {
+      first = k;
     }
   }
-  if (op.kind == FK_GATE) {
-    const float J = ldv(Jrow, op.edge);
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-      const int j1 = j0 | (1 << L);
-      const float a0 = v[j0], a1 = v[j1];
-      v[j0] = fmaxf(a0 + J, a1 - J) + sw[p];
-      v[j1] = fmaxf(a0 - J, a1 + J) - sw[p];
-    }
-  } else {
+  if (op->kind == FK_CUT) {
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
@@ -91,25 +90,89 @@ __device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16],
       v[j0] = m;
       v[j1] = m;
     }
+    return;
+  }
+  const float J = ldv(Jrow, op->edge);
+  const float J2 = J + J;
+  if (first < 0) {
+    const float c0 = J + cst, c1 = J - cst;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+      const int j1 = j0 | (1 << L);
+      const float a0 = v[j0], a1 = v[j1];
+      v[j0] = fmaxf(a0, a1 - J2) + c0;
+      v[j1] = fmaxf(a0 - J2, a1) + c1;
+    }
+    return;
+  }
+  float e0[8], e1[8];
+  {
+    const float Jf = ldv(Jrow, op->te[first]);
+    const uint32_t wf = op->w[first];
+    const float p0 = J + cst + Jf, m0 = J + cst - Jf, p1 = J - cst - Jf, m1 = J - cst + Jf;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+      const bool b = tbit(ix[j0], wf) != 0u;
+      e0[p] = b ? m0 : p0;
+      e1[p] = b ? m1 : p1;
+    }
+    for (int k = first + 1; k < nt; ++k) {
+      const uint32_t w = op->w[k];
+      if (w >= SLOT_FIXED) continue;
+      const float Jk = ldv(Jrow, op->te[k]);
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+        const float sk = tbit(ix[j0], w) ? -Jk : Jk;
+        e0[p] += sk;
+        e1[p] -= sk;
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+    const int j1 = j0 | (1 << L);
+    const float a0 = v[j0], a1 = v[j1];
+    v[j0] = fmaxf(a0, a1 - J2) + e0[p];
+    v[j1] = fmaxf(a0 - J2, a1) + e1[p];
   }
 }
 
 // Star of a spin that entered without a gate: x += sigma(spin) * sw.
 template <typename IT>
-__device__ __forceinline__ void star16(float (&v)[16], const uint32_t (&ix)[16], const FOp& op, const IT* Jrow,
-                                       const IT* hrow, uint64_t bs) {
-  const float h0 = op.hspin >= 0 ? ldv(hrow, op.hspin) : 0.f;
+__device__ __forceinline__ void star16(float (&v)[16], const uint32_t (&ix)[16], const FOp* __restrict__ op,
+                                       const IT* Jrow, const IT* hrow, uint64_t bs) {
+  const int nt = op->nt;
+  float cst = op->hspin >= 0 ? ldv(hrow, op->hspin) : 0.f;
+  for (int k = 0; k < nt; ++k) {
+    const uint8_t w = op->w[k];
+    if (w >= SLOT_FIXED) {
+      const float Jk = ldv(Jrow, op->te[k]);
+      cst += ((bs >> (w - SLOT_FIXED)) & 1ull) ? -Jk : Jk;
+    }
+  }
   float sw[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) sw[j] = h0;
-  for (int k = 0; k < op.nt; ++k) {
-    const float Jk = ldv(Jrow, op.te[k]);
-    const uint8_t w = op.w[k];
+  for (int j = 0; j < 16; ++j) sw[j] = cst;
+  for (int k = 0; k < nt; ++k) {
+    const uint32_t w = op->w[k];
+    if (w >= SLOT_FIXED) continue;
+    const float Jk = ldv(Jrow, op->te[k]);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) sw[j] += ebit(w, ix[j], bs) ? -Jk : Jk;
+    for (int j = 0; j < 16; ++j) sw[j] += tbit(ix[j], w) ? -Jk : Jk;
   }
+  const uint8_t b = op->bit;
+  if (b >= SLOT_FIXED) {
+    const bool neg = (bs >> (b - SLOT_FIXED)) & 1ull;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] += ebit(op.bit, ix[j], bs) ? -sw[j] : sw[j];
+    for (int j = 0; j < 16; ++j) v[j] += neg ? -sw[j] : sw[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] += tbit(ix[j], b) ? -sw[j] : sw[j];
+  }
 }
 
 // Builds the enumeration tables of a load (store): enumeration index u ->
@@ -141,7 +204,7 @@ __device__ __forceinline__ void build_enum(const DevPass2& P, const uint8_t* ord
 }
 
 template <typename IT>
-__global__ __launch_bounds__(NT) void k_pass(DevPass2 P, const DevStage* __restrict__ stages,
+__global__ __launch_bounds__(NT) void k_pass(const DevPass2* __restrict__ Pp, const DevStage* __restrict__ stages,
                                              const FOp* __restrict__ fops, const IT* __restrict__ J,
                                              const IT* __restrict__ h, int64_t jst, int64_t hst,
                                              const float* __restrict__ in, float* __restrict__ out, int64_t sst,
@@ -149,6 +212,7 @@ __global__ __launch_bounds__(NT) void k_pass(DevPass2 P, const DevStage* __restr
   extern __shared__ float tile[];
   __shared__ uint64_t a_lo[256], a_hi[64];    // enumeration index -> address offset
   __shared__ uint16_t i_lo[256], i_hi[64];    // enumeration index -> tile index
+  const DevPass2& P = *Pp;
   int64_t inst;
   uint64_t tid_bits;
   if (!wg_to_tile(P.n_free, batch, xcd_group, &inst, &tid_bits)) return;
@@ -172,31 +236,32 @@ __global__ __launch_bounds__(NT) void k_pass(DevPass2 P, const DevStage* __restr
   const float* src = in + inst * sst + in_base;
   for (uint32_t u = tid; u < size; u += NT) {
     const uint32_t ti = i_lo[u & 255u] | i_hi[u >> 8];
-    tile[ti] = P.init ? 0.f : src[a_lo[u & 255u] | a_hi[u >> 8]];
+    tile[swz(ti)] = P.init ? 0.f : src[a_lo[u & 255u] | a_hi[u >> 8]];
   }
   __syncthreads();
   const IT* Jrow = J + inst * jst;
   const IT* hrow = h ? h + inst * hst : nullptr;
-  for (int s = 0; s < P.n_stages; ++s) {
-    const DevStage ST = stages[P.stage_begin + s];
+  const int n_stages = P.n_stages;
+  for (int s = 0; s < n_stages; ++s) {
+    const DevStage* __restrict__ ST = stages + P.stage_begin + s;
     const uint32_t groups = size >> 4;
-    const uint32_t m0 = 1u << ST.sb[0], m1 = 1u << ST.sb[1], m2 = 1u << ST.sb[2], m3 = 1u << ST.sb[3];
+    const uint32_t m0 = 1u << ST->sb[0], m1 = 1u << ST->sb[1], m2 = 1u << ST->sb[2], m3 = 1u << ST->sb[3];
+    const int ob = ST->op_begin, oe = ST->op_end;
     for (uint32_t g = tid; g < groups; g += NT) {
-      uint32_t gb = 0;
-      for (int q = 0; q < ST.nns; ++q) gb |= ((g >> q) & 1u) << ST.ns[q];
+      const uint32_t gb = (uint32_t)ST->g_lo[g & 31u] | (uint32_t)ST->g_hi[g >> 5];
       uint32_t ix[16];
       float v[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         ix[j] = gb | ((j & 1) ? m0 : 0u) | ((j & 2) ? m1 : 0u) | ((j & 4) ? m2 : 0u) | ((j & 8) ? m3 : 0u);
-        v[j] = tile[ix[j]];
+        v[j] = tile[swz(ix[j])];
       }
-      for (int o = ST.op_begin; o < ST.op_end; ++o) {
-        const FOp op = fops[o];
-        if (op.kind == FK_STAR) {
+      for (int o = ob; o < oe; ++o) {
+        const FOp* __restrict__ op = fops + o;
+        if (op->kind == FK_STAR) {
           star16<IT>(v, ix, op, Jrow, hrow, bs);
         } else {
-          switch (op.lidx) {
+          switch (op->lidx) {
             case 0: gate_l<0, IT>(v, ix, op, Jrow, hrow, bs); break;
             case 1: gate_l<1, IT>(v, ix, op, Jrow, hrow, bs); break;
             case 2: gate_l<2, IT>(v, ix, op, Jrow, hrow, bs); break;
@@ -205,7 +270,7 @@ __global__ __launch_bounds__(NT) void k_pass(DevPass2 P, const DevStage* __restr
         }
       }
 #pragma unroll
-      for (int j = 0; j < 16; ++j) tile[ix[j]] = v[j];
+      for (int j = 0; j < 16; ++j) tile[swz(ix[j])] = v[j];
     }
     __syncthreads();
   }
@@ -215,7 +280,8 @@ __global__ __launch_bounds__(NT) void k_pass(DevPass2 P, const DevStage* __restr
   __syncthreads();
   float* dst = out + inst * sst + out_base;
   const uint32_t nst = 1u << P.n_st;
-  for (uint32_t u = tid; u < nst; u += NT) dst[a_lo[u & 255u] | a_hi[u >> 8]] = tile[i_lo[u & 255u] | i_hi[u >> 8]];
+  for (uint32_t u = tid; u < nst; u += NT)
+    dst[a_lo[u & 255u] | a_hi[u >> 8]] = tile[swz(i_lo[u & 255u] | i_hi[u >> 8])];
 }
 
 // ---------------------------------------------------------------------------
@@ -436,17 +502,22 @@ __global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ pa
 // host launch wrappers (kernels are launched from this translation unit)
 // ---------------------------------------------------------------------------
 
-// Raises the dynamic LDS limit of a kernel (static tables come on top of it).
+// Raises the dynamic LDS limit of a kernel once (static tables come on top).
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t bytes) {
   if (bytes < 32768) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+  static int done[2] = {0, 0};
+  const int slot = (reinterpret_cast<const void*>(kernel) == reinterpret_cast<const void*>(k_pass<float>)) ? 0 : 1;
+  if (done[slot]) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+  if (e == hipSuccess) done[slot] = 1;
+  return e;
 }
 
-hipError_t launch_pass(const DevPass2& P, const DevStage* stages, const FOp* fops, int dtype, const void* J,
-                       const void* h, int64_t jst, int64_t hst, const float* in, float* out, int64_t sst, int batch,
-                       hipStream_t stream) {
+hipError_t launch_pass(const DevPass2& P, const DevPass2* P_dev, const DevStage* stages, const FOp* fops, int dtype,
+                       const void* J, const void* h, int64_t jst, int64_t hst, const float* in, float* out,
+                       int64_t sst, int batch, hipStream_t stream) {
   const size_t lds = sizeof(float) << P.t;
   const uint64_t tiles = 1ull << P.n_free;
   const int xcd_group = (batch % 8 == 0) ? 1 : 0;
@@ -455,12 +526,12 @@ hipError_t launch_pass(const DevPass2& P, const DevStage* stages, const FOp* fop
   if (dtype == 0) {
     hipError_t e = allow_lds(k_pass<float>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pass<float>, dim3((uint32_t)grid), dim3(NT), lds, stream, P, stages, fops,
+    hipLaunchKernelGGL(k_pass<float>, dim3((uint32_t)grid), dim3(NT), lds, stream, P_dev, stages, fops,
                        (const float*)J, (const float*)h, jst, hst, in, out, sst, batch, xcd_group);
   } else {
     hipError_t e = allow_lds(k_pass<int32_t>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pass<int32_t>, dim3((uint32_t)grid), dim3(NT), lds, stream, P, stages, fops,
+    hipLaunchKernelGGL(k_pass<int32_t>, dim3((uint32_t)grid), dim3(NT), lds, stream, P_dev, stages, fops,
                        (const int32_t*)J, (const int32_t*)h, jst, hst, in, out, sst, batch, xcd_group);
   }
   return hipGetLastError();

@@ -25,7 +25,8 @@ class DevPass2(C.Structure):
 
 class DevStage(C.Structure):
     _fields_ = [("sb", C.c_uint8 * 4), ("nns", C.c_uint8), ("ns", C.c_uint8 * 15), ("op_begin", C.c_int32),
-                ("op_end", C.c_int32), ("pad", C.c_int32 * 2)]
+                ("op_end", C.c_int32), ("pad", C.c_int32 * 2), ("g_lo", C.c_uint16 * 32),
+                ("g_hi", C.c_uint16 * 32)]
 
 
 class FOp(C.Structure):
@@ -99,9 +100,7 @@ def forward(prog, width, J, h):
                 ST = prog["stages"][P.stage_begin + si]
                 sb = [ST.sb[l] for l in range(4)]
                 for g in range((1 << t) >> 4):
-                    gb = 0
-                    for q in range(ST.nns):
-                        gb |= ((g >> q) & 1) << ST.ns[q]
+                    gb = ST.g_lo[g & 31] | ST.g_hi[g >> 5]
                     ix = [gb | sum((1 << sb[l]) for l in range(4) if (j >> l) & 1) for j in range(16)]
                     v = [tile[i] for i in ix]
                     for o in range(ST.op_begin, ST.op_end):
