@@ -53,7 +53,20 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_event_pool;
 std::map<std::string, std::pair<double, int64_t>> g_prof_acc;
+
+hipEvent_t pool_get() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
 
 struct ProfScope {
   hipStream_t s;
@@ -61,10 +74,10 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   bool on;
   ProfScope(hipStream_t s_, const char* n) : s(s_), name(n), on(g_prof_on) {
-    if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
-      on = hipEventRecord(a, s) == hipSuccess;
-    else
-      on = false;
+    if (!on) return;
+    a = pool_get();
+    b = pool_get();
+    on = a && b && hipEventRecord(a, s) == hipSuccess;
   }
   ~ProfScope() {
     if (!on) return;
@@ -82,8 +95,8 @@ void prof_drain() {
     auto& acc = g_prof_acc[r.name];
     acc.first += ms;
     acc.second += 1;
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    g_event_pool.push_back(r.a);
+    g_event_pool.push_back(r.b);
   }
   g_prof_pending.clear();
 }

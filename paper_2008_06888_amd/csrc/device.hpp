@@ -70,6 +70,20 @@ struct DevPass2 {
   uint8_t ld_order[16];  // tile bits with an input position, ascending by position
   uint8_t st_order[16];  // tile bits with an output position, ascending by position
   int32_t n_ld, n_st;
+  // bit q of the load (store) enumeration index -> tile-index bit, address bit
+  uint16_t ld_bti[16], st_bti[16];
+  uint64_t ld_bad[16], st_bad[16];
+};
+
+// An op with its constants resolved for one instance and one tile (built in
+// LDS at the start of a pass): GATE keeps 2J and the four constants J +- cst
+// +- J_first; STAR keeps cst; extra star terms on resident slots follow.
+struct ROp {
+  float J2, p0, m0, p1, m1;
+  uint8_t kind, lidx, wf, nx;   // wf: first resident partner bit (255: none)
+  uint8_t xw[3];                // further resident partners
+  uint8_t sbit;                 // STAR: tile bit of the spin (255: fixed slot, sign folded)
+  float xJ[3];
 };
 
 // Backward walk: a spin eliminated in a pass (candidate bit k) and the slot it

@@ -142,6 +142,10 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
     for (int k = 0; k < d.t; ++k) {
       d.ld_order[k] = (uint8_t)ld[k];
       d.st_order[k] = (uint8_t)st[k];
+      d.ld_bti[k] = (uint16_t)(1u << ld[k]);
+      d.st_bti[k] = (uint16_t)(1u << st[k]);
+      d.ld_bad[k] = k < d.n_ld ? (1ull << d.in_pos[R[q][ld[k]]]) : 0ull;
+      d.st_bad[k] = k < d.n_st ? (1ull << d.out_pos[R[q][st[k]]]) : 0ull;
     }
     auto enc = [&](int slot) -> uint8_t {
       return tbit[slot] >= 0 ? (uint8_t)tbit[slot] : (uint8_t)(SLOT_FIXED + slot);
@@ -319,6 +323,7 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
       const bool any_hi = (ca && ka >= 8) || (cb && kb >= 8);
       (any_lo && any_hi ? cross : (any_hi ? hi : lo)).push_back(tm);
     }
+    if (lo.size() + hi.size() + cross.size() > 1024) return "too many energy terms in one pass";
     d.term_begin = (int)out.terms.size();
     d.n_lo = (int)lo.size();
     d.n_hi = (int)hi.size();

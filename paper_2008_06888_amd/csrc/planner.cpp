@@ -20,6 +20,8 @@ namespace tt {
 
 namespace {
 
+constexpr int MAX_OPS_PER_PASS = 256;   // the energy kernel holds a pass's ops in LDS
+
 struct Adj {
   std::vector<std::vector<std::pair<int, int>>> nb;  // (neighbour, edge)
   Adj(int n, const std::vector<int32_t>& e) : nb(n) {
@@ -338,7 +340,7 @@ std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separ
       std::set<int> with_low = need2;
       for (int s = 0; s < std::min(LOW, wmax2); ++s) with_low.insert(s);
       bool ok = (wmax2 <= t) || ((int)with_low.size() <= t);
-      ok = ok && ndec2 <= max_dec && (!separable || sep_ok);
+      ok = ok && ndec2 <= max_dec && (!separable || sep_ok) && (i - start) < MAX_OPS_PER_PASS;
       if (!ok && i > start) break;
       need.swap(need2);
       ndec = ndec2;

@@ -57,31 +57,75 @@ __device__ __forceinline__ bool wg_to_tile(int log2_tiles, int batch, int xcd_gr
   return *inst < batch;
 }
 
-// Sign of a star term for an entry: +J when the partner spin is sigma = +1.
+// Value (0/1) of tile bit w of an entry index.
 __device__ __forceinline__ uint32_t tbit(uint32_t ix, uint32_t w) { return __builtin_amdgcn_ubfe(ix, w, 1); }
+
+constexpr int MAX_PASS_OPS = 256;   // fused ops of one pass held in LDS (the planner keeps passes below)
+
+// Resolves one op of a pass for this instance and tile into its LDS record
+// (see ROp). Fields are written in place: no private arrays.
+template <typename IT>
+__device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, const IT* hrow, uint64_t bs) {
+  float cst = op->hspin >= 0 ? ldv(hrow, op->hspin) : 0.f;
+  const uint8_t kind = op->kind;
+  const int nt = op->nt;
+  for (int k = 0; k < nt; ++k) {
+    const uint8_t w = op->w[k];
+    if (w >= SLOT_FIXED) cst += ((bs >> (w - SLOT_FIXED)) & 1ull) ? -ldv(Jrow, op->te[k]) : ldv(Jrow, op->te[k]);
+  }
+  r->kind = kind;
+  r->lidx = op->lidx;
+  r->nx = 0;
+  r->sbit = 255;
+  r->wf = 255;
+  r->J2 = r->p0 = r->m0 = r->p1 = r->m1 = 0.f;
+  float sg = 1.f;
+  float J = 0.f;
+  if (kind == FK_STAR) {
+    if (op->bit >= SLOT_FIXED) {
+      if ((bs >> (op->bit - SLOT_FIXED)) & 1ull) sg = -1.f;
+    } else {
+      r->sbit = op->bit;
+    }
+    r->p0 = sg * cst;
+  } else if (kind == FK_GATE) {
+    J = ldv(Jrow, op->edge);
+    r->J2 = J + J;
+    r->p0 = r->m0 = J + cst;
+    r->p1 = r->m1 = J - cst;
+  } else {
+    return;
+  }
+  for (int k = 0; k < nt; ++k) {
+    const uint8_t w = op->w[k];
+    if (w >= SLOT_FIXED) continue;
+    const float Jk = ldv(Jrow, op->te[k]);
+    if (r->wf == 255) {
+      r->wf = w;
+      if (kind == FK_STAR) {
+        r->m0 = sg * Jk;
+      } else {
+        r->p0 = J + cst + Jk;
+        r->m0 = J + cst - Jk;
+        r->p1 = J - cst - Jk;
+        r->m1 = J - cst + Jk;
+      }
+    } else {
+      const int x = r->nx;
+      r->xw[x] = w;
+      r->xJ[x] = kind == FK_STAR ? sg * Jk : Jk;
+      r->nx = (uint8_t)(x + 1);
+    }
+  }
+}
 
 // One relabelling gate on stage bit L of the 16 register entries, with the
 // star of the entering spin, sw = h + sum_k J_k sigma(partner_k):
 //   new[0] = max(a0 + J, a1 - J) + sw = max(a0, a1 - 2J) + (J + sw)
 //   new[1] = max(a0 - J, a1 + J) - sw = max(a0 - 2J, a1) + (J - sw).
-// Star terms whose partner is a fixed slot of the tile are folded into a
-// constant; the first term on a resident slot selects between two constants.
-template <int L, typename IT>
-__device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16], const FOp* __restrict__ op,
-                                       const IT* Jrow, const IT* hrow, uint64_t bs) {
-  const int nt = op->nt;
-  float cst = op->hspin >= 0 ? ldv(hrow, op->hspin) : 0.f;
-  int first = -1;
-  for (int k = 0; k < nt; ++k) {
-    const uint8_t w = op->w[k];
-    if (w >= SLOT_FIXED) {
-      const float Jk = ldv(Jrow, op->te[k]);
-      cst += ((bs >> (w - SLOT_FIXED)) & 1ull) ? -Jk : Jk;
-    } else if (first < 0) {
-      first = k;
-    }
-  }
-  if (op->kind == FK_CUT) {
+template <int L>
+__device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16], const ROp& r) {
+  if (r.kind == FK_CUT) {
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
@@ -92,10 +136,9 @@ __device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16],
     }
     return;
   }
-  const float J = ldv(Jrow, op->edge);
-  const float J2 = J + J;
-  if (first < 0) {
-    const float c0 = J + cst, c1 = J - cst;
+  const float J2 = r.J2;
+  if (r.wf == 255) {
+    const float c0 = r.p0, c1 = r.p1;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
@@ -107,28 +150,23 @@ __device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16],
     return;
   }
   float e0[8], e1[8];
-  {
-    const float Jf = ldv(Jrow, op->te[first]);
-    const uint32_t wf = op->w[first];
-    const float p0 = J + cst + Jf, m0 = J + cst - Jf, p1 = J - cst - Jf, m1 = J - cst + Jf;
+  const uint32_t wf = r.wf;
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+    const bool b = tbit(ix[j0], wf) != 0u;
+    e0[p] = b ? r.m0 : r.p0;
+    e1[p] = b ? r.m1 : r.p1;
+  }
+  for (int k = 0; k < r.nx; ++k) {
+    const uint32_t w = r.xw[k];
+    const float Jk = r.xJ[k];
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-      const bool b = tbit(ix[j0], wf) != 0u;
-      e0[p] = b ? m0 : p0;
-      e1[p] = b ? m1 : p1;
-    }
-    for (int k = first + 1; k < nt; ++k) {
-      const uint32_t w = op->w[k];
-      if (w >= SLOT_FIXED) continue;
-      const float Jk = ldv(Jrow, op->te[k]);
-#pragma unroll
-      for (int p = 0; p < 8; ++p) {
-        const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-        const float sk = tbit(ix[j0], w) ? -Jk : Jk;
-        e0[p] += sk;
-        e1[p] -= sk;
-      }
+      const float sk = tbit(ix[j0], w) ? -Jk : Jk;
+      e0[p] += sk;
+      e1[p] -= sk;
     }
   }
 #pragma unroll
@@ -142,64 +180,29 @@ __device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16],
 }
 
 // Star of a spin that entered without a gate: x += sigma(spin) * sw.
-template <typename IT>
-__device__ __forceinline__ void star16(float (&v)[16], const uint32_t (&ix)[16], const FOp* __restrict__ op,
-                                       const IT* Jrow, const IT* hrow, uint64_t bs) {
-  const int nt = op->nt;
-  float cst = op->hspin >= 0 ? ldv(hrow, op->hspin) : 0.f;
-  for (int k = 0; k < nt; ++k) {
-    const uint8_t w = op->w[k];
-    if (w >= SLOT_FIXED) {
-      const float Jk = ldv(Jrow, op->te[k]);
-      cst += ((bs >> (w - SLOT_FIXED)) & 1ull) ? -Jk : Jk;
-    }
-  }
+__device__ __forceinline__ void star16(float (&v)[16], const uint32_t (&ix)[16], const ROp& r) {
   float sw[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) sw[j] = cst;
-  for (int k = 0; k < nt; ++k) {
-    const uint32_t w = op->w[k];
-    if (w >= SLOT_FIXED) continue;
-    const float Jk = ldv(Jrow, op->te[k]);
+  for (int j = 0; j < 16; ++j) sw[j] = r.p0;
+  if (r.wf != 255) {
+    const uint32_t w = r.wf;
+    const float Jk = r.m0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) sw[j] += tbit(ix[j], w) ? -Jk : Jk;
   }
-  const uint8_t b = op->bit;
-  if (b >= SLOT_FIXED) {
-    const bool neg = (bs >> (b - SLOT_FIXED)) & 1ull;
+  for (int k = 0; k < r.nx; ++k) {
+    const uint32_t w = r.xw[k];
+    const float Jk = r.xJ[k];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] += neg ? -sw[j] : sw[j];
+    for (int j = 0; j < 16; ++j) sw[j] += tbit(ix[j], w) ? -Jk : Jk;
+  }
+  if (r.sbit == 255) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] += sw[j];
   } else {
+    const uint32_t b = r.sbit;
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] += tbit(ix[j], b) ? -sw[j] : sw[j];
-  }
-}
-
-// Builds the enumeration tables of a load (store): enumeration index u ->
-// tile index and address offset, tile bits taken in `order`, the first
-// `n_addr` of them carrying address bits pos[slot].
-__device__ __forceinline__ void build_enum(const DevPass2& P, const uint8_t* order, const uint8_t* pos, int n_enum,
-                                           int n_addr, uint64_t* a_lo, uint64_t* a_hi, uint16_t* i_lo,
-                                           uint16_t* i_hi) {
-  for (int j = threadIdx.x; j < 256 + 64; j += blockDim.x) {
-    const int lo = j < 256;
-    const int x = lo ? j : j - 256;
-    uint64_t a = 0;
-    uint32_t ti = 0;
-    for (int q = 0; q < 8; ++q) {
-      const int k = lo ? q : q + 8;
-      if (k >= n_enum || !((x >> q) & 1)) continue;
-      const int tb = order[k];
-      ti |= 1u << tb;
-      if (k < n_addr) a |= 1ull << pos[P.R[tb]];
-    }
-    if (lo) {
-      a_lo[x] = a;
-      i_lo[x] = (uint16_t)ti;
-    } else {
-      a_hi[x] = a;
-      i_hi[x] = (uint16_t)ti;
-    }
   }
 }
 
@@ -210,8 +213,7 @@ __global__ __launch_bounds__(NT) void k_pass(const DevPass2* __restrict__ Pp, co
                                              const float* __restrict__ in, float* __restrict__ out, int64_t sst,
                                              int batch, int xcd_group) {
   extern __shared__ float tile[];
-  __shared__ uint64_t a_lo[256], a_hi[64];    // enumeration index -> address offset
-  __shared__ uint16_t i_lo[256], i_hi[64];    // enumeration index -> tile index
+  __shared__ ROp rops[MAX_PASS_OPS];
   const DevPass2& P = *Pp;
   int64_t inst;
   uint64_t tid_bits;
@@ -230,23 +232,44 @@ __global__ __launch_bounds__(NT) void k_pass(const DevPass2* __restrict__ Pp, co
     if (P.out_pos[slot] != NO_POS) out_base |= b << P.out_pos[slot];
     else if (b) stored = false;   // only the copy with a dropped slot at 0 is kept
   }
-  // load, enumerating the tile in the order of the input layout
-  build_enum(P, P.ld_order, P.in_pos, t, P.n_ld, a_lo, a_hi, i_lo, i_hi);
-  __syncthreads();
-  const float* src = in + inst * sst + in_base;
-  for (uint32_t u = tid; u < size; u += NT) {
-    const uint32_t ti = i_lo[u & 255u] | i_hi[u >> 8];
-    tile[swz(ti)] = P.init ? 0.f : src[a_lo[u & 255u] | a_hi[u >> 8]];
-  }
-  __syncthreads();
   const IT* Jrow = J + inst * jst;
   const IT* hrow = h ? h + inst * hst : nullptr;
+  // resolve the pass's ops for this instance and tile
+  const int op0 = stages[P.stage_begin].op_begin;
+  const int n_ops = P.n_stages ? stages[P.stage_begin + P.n_stages - 1].op_end - op0 : 0;
+  for (int o = tid; o < n_ops; o += NT) resolve_op<IT>(fops + op0 + o, rops + o, Jrow, hrow, bs);
+  // load: enumeration index u = tid + 1024 k; bit q of u -> tile bit / address bit
+  {
+    uint32_t ti_lo = 0;
+    uint64_t ad_lo = 0;
+    const int nb = t < 10 ? t : 10;
+    for (int q = 0; q < nb; ++q)
+      if ((tid >> q) & 1) {
+        ti_lo |= P.ld_bti[q];
+        ad_lo |= P.ld_bad[q];
+      }
+    const float* src = in + inst * sst + in_base;
+    if (tid < (int)size) {
+      const int nk = t > 10 ? (1 << (t - 10)) : 1;
+      for (int k = 0; k < nk; ++k) {
+        uint32_t ti = ti_lo;
+        uint64_t ad = ad_lo;
+        for (int q = 0; q < t - 10; ++q)
+          if ((k >> q) & 1) {
+            ti |= P.ld_bti[10 + q];
+            ad |= P.ld_bad[10 + q];
+          }
+        tile[swz(ti)] = P.init ? 0.f : src[ad];
+      }
+    }
+  }
+  __syncthreads();
   const int n_stages = P.n_stages;
   for (int s = 0; s < n_stages; ++s) {
     const DevStage* __restrict__ ST = stages + P.stage_begin + s;
     const uint32_t groups = size >> 4;
     const uint32_t m0 = 1u << ST->sb[0], m1 = 1u << ST->sb[1], m2 = 1u << ST->sb[2], m3 = 1u << ST->sb[3];
-    const int ob = ST->op_begin, oe = ST->op_end;
+    const int ob = ST->op_begin - op0, oe = ST->op_end - op0;
     for (uint32_t g = tid; g < groups; g += NT) {
       const uint32_t gb = (uint32_t)ST->g_lo[g & 31u] | (uint32_t)ST->g_hi[g >> 5];
       uint32_t ix[16];
@@ -257,15 +280,15 @@ __global__ __launch_bounds__(NT) void k_pass(const DevPass2* __restrict__ Pp, co
         v[j] = tile[swz(ix[j])];
       }
       for (int o = ob; o < oe; ++o) {
-        const FOp* __restrict__ op = fops + o;
-        if (op->kind == FK_STAR) {
-          star16<IT>(v, ix, op, Jrow, hrow, bs);
+        const ROp& r = rops[o];
+        if (r.kind == FK_STAR) {
+          star16(v, ix, r);
         } else {
-          switch (op->lidx) {
-            case 0: gate_l<0, IT>(v, ix, op, Jrow, hrow, bs); break;
-            case 1: gate_l<1, IT>(v, ix, op, Jrow, hrow, bs); break;
-            case 2: gate_l<2, IT>(v, ix, op, Jrow, hrow, bs); break;
-            default: gate_l<3, IT>(v, ix, op, Jrow, hrow, bs); break;
+          switch (r.lidx) {
+            case 0: gate_l<0>(v, ix, r); break;
+            case 1: gate_l<1>(v, ix, r); break;
+            case 2: gate_l<2>(v, ix, r); break;
+            default: gate_l<3>(v, ix, r); break;
           }
         }
       }
@@ -276,12 +299,31 @@ __global__ __launch_bounds__(NT) void k_pass(const DevPass2* __restrict__ Pp, co
   }
   if (!stored) return;
   // store, enumerating the tile in the order of the output layout
-  build_enum(P, P.st_order, P.out_pos, P.n_st, P.n_st, a_lo, a_hi, i_lo, i_hi);
-  __syncthreads();
-  float* dst = out + inst * sst + out_base;
-  const uint32_t nst = 1u << P.n_st;
-  for (uint32_t u = tid; u < nst; u += NT)
-    dst[a_lo[u & 255u] | a_hi[u >> 8]] = tile[swz(i_lo[u & 255u] | i_hi[u >> 8])];
+  {
+    const int ns = P.n_st;
+    uint32_t ti_lo = 0;
+    uint64_t ad_lo = 0;
+    const int nb = ns < 10 ? ns : 10;
+    for (int q = 0; q < nb; ++q)
+      if ((tid >> q) & 1) {
+        ti_lo |= P.st_bti[q];
+        ad_lo |= P.st_bad[q];
+      }
+    float* dst = out + inst * sst + out_base;
+    if (tid < (1 << nb)) {
+      const int nk = ns > 10 ? (1 << (ns - 10)) : 1;
+      for (int k = 0; k < nk; ++k) {
+        uint32_t ti = ti_lo;
+        uint64_t ad = ad_lo;
+        for (int q = 0; q < ns - 10; ++q)
+          if ((k >> q) & 1) {
+            ti |= P.st_bti[10 + q];
+            ad |= P.st_bad[10 + q];
+          }
+        dst[ad] = tile[swz(ti)];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -372,19 +414,22 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage2(const float* __restrict__
 // ---------------------------------------------------------------------------
 
 constexpr int MAX_SPINS = 8192;
+constexpr int MAX_BTERMS = 1024;   // terms of one pass staged in LDS
+
+struct LTerm {      // a backward term with its coefficient resolved
+  float c;
+  uint8_t a, b, pad0, pad1;
+};
 
 __device__ __forceinline__ float term_sigma(uint8_t op, uint32_t a, uint64_t t) {
   const uint32_t b = op < 64 ? ((a >> op) & 1u) : (uint32_t)((t >> (op - 64)) & 1ull);
   return b ? -1.f : 1.f;
 }
 
-template <typename IT>
-__device__ __forceinline__ float term_val(const BTerm& tm, uint32_t a, uint64_t t, const IT* Jrow,
-                                          const IT* hrow) {
-  const float c = tm.is_field ? ldv(hrow, tm.coef) : ldv(Jrow, tm.coef);
+__device__ __forceinline__ float lterm_val(const LTerm& tm, uint32_t a, uint64_t t) {
   float s = term_sigma(tm.a, a, t);
   if (tm.b != 255) s *= term_sigma(tm.b, a, t);
-  return c * s;
+  return tm.c * s;
 }
 
 template <typename IT>
@@ -402,6 +447,9 @@ __global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ pa
   __shared__ float lut_lo[256], lut_hi[256];
   __shared__ uint64_t ad_lo[256], ad_hi[256];
   __shared__ uint64_t sh_t, sh_base;
+  __shared__ LTerm lt[MAX_BTERMS];
+  __shared__ BCand lc[16];
+  __shared__ uint8_t l_in_pos[64];
   const int64_t inst = blockIdx.x;
   const int tid = threadIdx.x;
   const IT* Jrow = J + inst * jst;
@@ -421,17 +469,32 @@ __global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ pa
   }
   __syncthreads();
   for (int p = n_passes - 1; p >= 0; --p) {
-    const DevPass2& P = passes[p];
-    const int nc = P.n_cand;
+    const DevPass2* __restrict__ P = passes + p;
+    const int nc = P->n_cand;
+    const uint64_t surv = P->surv_mask;
     const uint64_t t = sh_t;
     if (nc == 0) {
       __syncthreads();
-      if (tid == 0) sh_t = t & P.surv_mask;
+      if (tid == 0) sh_t = t & surv;
       __syncthreads();
       continue;
     }
-    const BCand* C = cands + P.cand_begin;
-    const BTerm* T = terms + P.term_begin;
+    const int n_lo = P->n_lo, n_hi = P->n_hi, n_cr = P->n_cross;
+    const int nterm = n_lo + n_hi + n_cr;
+    const int in_w = P->in_w;
+    // stage this pass's candidates, terms (coefficients resolved) and input layout
+    if (tid < nc) lc[tid] = cands[P->cand_begin + tid];
+    if (tid < 64) l_in_pos[tid] = P->in_pos[tid];
+    for (int k = tid; k < nterm; k += NT) {
+      const BTerm b = terms[P->term_begin + k];
+      LTerm x;
+      x.c = b.is_field ? ldv(hrow, b.coef) : ldv(Jrow, b.coef);
+      x.a = b.a;
+      x.b = b.b;
+      x.pad0 = x.pad1 = 0;
+      lt[k] = x;
+    }
+    __syncthreads();
     const int nlo = nc < 8 ? nc : 8, nhi = nc - nlo;
     // tables over the low / high halves of the candidate bits
     for (int a = tid; a < 512; a += NT) {
@@ -440,13 +503,13 @@ __global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ pa
       if (x >= (1u << (hi ? nhi : nlo))) continue;
       const uint32_t full = hi ? (x << 8) : x;
       float acc = 0.f;
-      const int tb = hi ? P.n_lo : 0, te = hi ? P.n_lo + P.n_hi : P.n_lo;
-      for (int k = tb; k < te; ++k) acc += term_val<IT>(T[k], full, t, Jrow, hrow);
+      const int tb = hi ? n_lo : 0, te = hi ? n_lo + n_hi : n_lo;
+      for (int k = tb; k < te; ++k) acc += lterm_val(lt[k], full, t);
       uint64_t ad = 0;
       const int kb = hi ? 8 : 0, ke = hi ? nc : nlo;
       for (int k = kb; k < ke; ++k) {
-        const int ss = C[k].start_slot;
-        if (ss >= 0 && P.in_pos[ss] != NO_POS && ((full >> k) & 1u)) ad |= 1ull << P.in_pos[ss];
+        const int ss = lc[k].start_slot;
+        if (ss >= 0 && l_in_pos[ss] != NO_POS && ((full >> k) & 1u)) ad |= 1ull << l_in_pos[ss];
       }
       if (hi) {
         lut_hi[x] = acc;
@@ -458,29 +521,29 @@ __global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ pa
     }
     if (tid == 0) {
       uint64_t base = 0;
-      for (int c = 0; c < P.in_w; ++c)
-        if (((P.surv_mask >> c) & 1ull) && ((t >> c) & 1ull)) base |= 1ull << P.in_pos[c];
+      for (int c = 0; c < in_w; ++c)
+        if (((surv >> c) & 1ull) && ((t >> c) & 1ull)) base |= 1ull << l_in_pos[c];
       sh_base = base;
     }
     __syncthreads();
-    const float* src = P.init ? nullptr : ckpt[p] + inst * sst + sh_base;
+    const float* src = P->init ? nullptr : ckpt[p] + inst * sst + sh_base;
     VI best{-INFINITY, ~0ull};
     const uint32_t na = 1u << nc;
-    const int cross_b = P.n_lo + P.n_hi, cross_e = P.n_lo + P.n_hi + P.n_cross;
+    const int cross_b = n_lo + n_hi;
     for (uint32_t a = tid; a < na; a += NT) {
       float val = lut_lo[a & 255u] + lut_hi[a >> 8];
-      for (int k = cross_b; k < cross_e; ++k) val += term_val<IT>(T[k], a, t, Jrow, hrow);
+      for (int k = cross_b; k < nterm; ++k) val += lterm_val(lt[k], a, t);
       if (src) val += src[ad_lo[a & 255u] | ad_hi[a >> 8]];
       best = vi_best(best, VI{val, (uint64_t)a});
     }
     best = block_best<NT>(best);
     if (tid == 0) {
       const uint32_t a = (uint32_t)best.i;
-      uint64_t tin = t & P.surv_mask;
+      uint64_t tin = t & surv;
       for (int k = 0; k < nc; ++k) {
         const uint32_t b = (a >> k) & 1u;
-        s_sh[C[k].spin] = (int8_t)b;
-        if (C[k].start_slot >= 0) tin |= (uint64_t)b << C[k].start_slot;
+        s_sh[lc[k].spin] = (int8_t)b;
+        if (lc[k].start_slot >= 0) tin |= (uint64_t)b << lc[k].start_slot;
       }
       sh_t = tin;
     }

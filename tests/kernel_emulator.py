@@ -20,7 +20,8 @@ class DevPass2(C.Structure):
                 ("n_hi", C.c_int32), ("n_cross", C.c_int32), ("surv_mask", C.c_uint64),
                 ("R", C.c_uint8 * 16), ("fre", C.c_uint8 * 48), ("in_pos", C.c_uint8 * 64),
                 ("out_pos", C.c_uint8 * 64), ("ld_order", C.c_uint8 * 16), ("st_order", C.c_uint8 * 16),
-                ("n_ld", C.c_int32), ("n_st", C.c_int32)]
+                ("n_ld", C.c_int32), ("n_st", C.c_int32), ("ld_bti", C.c_uint16 * 16), ("st_bti", C.c_uint16 * 16),
+                ("ld_bad", C.c_uint64 * 16), ("st_bad", C.c_uint64 * 16)]
 
 
 class DevStage(C.Structure):
@@ -86,16 +87,15 @@ def forward(prog, width, J, h):
                     out_base |= b << P.out_pos[s]
                 elif b:
                     stored = False
-            tile = np.zeros(1 << t)
+            tile = np.full(1 << t, np.nan)
             for u in range(1 << t):
                 ti = a = 0
                 for k in range(t):
                     if (u >> k) & 1:
-                        tb = P.ld_order[k]
-                        ti |= 1 << tb
-                        if k < P.n_ld:
-                            a |= 1 << P.in_pos[P.R[tb]]
+                        ti |= P.ld_bti[k]
+                        a |= P.ld_bad[k]
                 tile[ti] = 0.0 if P.init else src[in_base | a]
+            assert not np.any(np.isnan(tile))
             for si in range(P.n_stages):
                 ST = prog["stages"][P.stage_begin + si]
                 sb = [ST.sb[l] for l in range(4)]
@@ -133,9 +133,8 @@ def forward(prog, width, J, h):
                 ti = a = 0
                 for k in range(P.n_st):
                     if (u >> k) & 1:
-                        tb = P.st_order[k]
-                        ti |= 1 << tb
-                        a |= 1 << P.out_pos[P.R[tb]]
+                        ti |= P.st_bti[k]
+                        a |= P.st_bad[k]
                 dst[out_base | a] = tile[ti]
         states.append(dst)
     return states
