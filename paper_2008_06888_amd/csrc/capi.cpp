@@ -136,9 +136,8 @@ struct DevCache {
   Encoded cen;
   DevBuf d_passes, d_stages, d_fops, d_cands, d_terms, d_final_pos, d_final_slot, d_edges;
   DevBuf d_cops;
-  DevBuf state, ckpt, ckpt_ptrs, part_v, part_i, arg;
+  DevBuf state, ckpt, arg, part_v, part_i;
   DevBuf cx, cn, cpart;
-  std::vector<float*> h_ckpt_ptrs, uploaded_ckpt_ptrs;
 };
 
 int encode(const Plan& p, const std::vector<Pass>& passes, Encoded& en) {
@@ -265,52 +264,284 @@ int check_common(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, con
 // entries it writes: no width change (or no read at all).
 bool in_place_ok(const DevPass& P) { return P.init || (P.in_w == P.w_max && P.out_w == P.w_max); }
 
-// Runs the energy passes. Every pass writes a buffer other than its input
-// (the bit order changes between passes); keep_all gives every pass a fresh
-// buffer so that each pass input stays available for the backward walk.
-int run_forward(Plan& p, DevCache* dc, int32_t batch, int32_t dtype, const void* J, const void* h,
-                bool keep_all, hipStream_t s, float** final_state) {
-  const int64_t sst = (int64_t)1 << p.width;
-  const size_t per = (size_t)batch * (size_t)sst * sizeof(float);
-  const int np = (int)dc->ep.passes.size();
-  if (np == 0) return fail(TT_E_INVAL, "empty plan");
-  const size_t nbuf = keep_all ? (size_t)np + 1 : 2;
-  const int64_t need = (int64_t)(per * nbuf);
-  DevBuf& buf = keep_all ? dc->ckpt : dc->state;
-  if (need > (int64_t)buf.cap && need > budget_bytes(p) + (int64_t)buf.cap)
-    return fail(TT_E_TOOBIG, "plan needs %lld bytes of device state (budget %lld)", (long long)need,
-                (long long)budget_bytes(p));
-  if (int r = buf.ensure(per * nbuf)) return r;
-  char* base = static_cast<char*>(buf.p);
-  auto bufp = [&](size_t k) { return reinterpret_cast<float*>(base + per * k); };
-  const int64_t jst = p.m, hst = p.n;
-  int cur = 0;
-  if (keep_all) dc->h_ckpt_ptrs.assign(np, nullptr);
-  for (int q = 0; q < np; ++q) {
-    const DevPass2& P = dc->ep.passes[q];
-    const int src = keep_all ? q : cur;
-    const int dst = keep_all ? q + 1 : (cur ^ 1);
-    if (keep_all) dc->h_ckpt_ptrs[q] = P.init ? nullptr : bufp(src);
-    ProfScope ps(s, "sweep_pass");
-    HIP_TRY(launch_pass(P, static_cast<const DevPass2*>(dc->d_passes.p) + q, static_cast<const DevStage*>(dc->d_stages.p),
-                        static_cast<const FOp*>(dc->d_fops.p), dtype, J, h, jst, hst, bufp(src), bufp(dst), sst, batch,
-                        s));
-    cur = dst;
+// ----------------------------------------------------------------------------
+// launch tables: assembled on the host for a whole call, uploaded once
+// (pinned staging buffer, double-buffered), then referenced by every launch
+// ----------------------------------------------------------------------------
+struct Blob {
+  std::vector<char> bytes;
+  template <typename T>
+  size_t add(const T* v, size_t n) {
+    size_t off = (bytes.size() + 15) & ~size_t(15);
+    bytes.resize(off + n * sizeof(T));
+    if (n) std::memcpy(bytes.data() + off, v, n * sizeof(T));
+    return off;
   }
-  *final_state = bufp(keep_all ? np : cur);
+};
+
+constexpr int N_SLOTS = 4;   // calls that may be in flight per device
+struct Stager {
+  char* host[N_SLOTS] = {};
+  char* dev[N_SLOTS] = {};
+  size_t cap[N_SLOTS] = {};
+  hipEvent_t ev[N_SLOTS] = {};
+  int k = 0;
+};
+std::mutex g_stage_mu;
+std::map<int, Stager> g_stagers;
+
+// Reserves a staging slot of n bytes: host (pinned) and device addresses.
+// The kernels of the slot's previous call have finished when this returns.
+int stage_reserve(size_t n, char** host, char** dev, int* slot) {
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  std::lock_guard<std::mutex> g(g_stage_mu);
+  Stager& st = g_stagers[device];
+  st.k = (st.k + 1) % N_SLOTS;
+  const int k = st.k;
+  *slot = k;
+  if (st.ev[k]) HIP_TRY(hipEventSynchronize(st.ev[k]));
+  else HIP_TRY(hipEventCreateWithFlags(&st.ev[k], hipEventDisableTiming));
+  n = std::max<size_t>(n, 16);
+  if (n > st.cap[k]) {
+    if (st.host[k]) HIP_TRY(hipHostFree(st.host[k]));
+    if (st.dev[k]) HIP_TRY(hipFree(st.dev[k]));
+    st.host[k] = nullptr;
+    st.dev[k] = nullptr;
+    st.cap[k] = 0;
+    const size_t c = std::max<size_t>(n * 2, 1 << 16);
+    HIP_TRY(hipHostMalloc((void**)&st.host[k], c, hipHostMallocDefault));
+    HIP_TRY(hipMalloc((void**)&st.dev[k], c));
+    st.cap[k] = c;
+  }
+  *host = st.host[k];
+  *dev = st.dev[k];
   return 0;
 }
 
-int run_reduce(Plan& p, DevCache* dc, int32_t batch, const float* st, double* energy, uint64_t* arg,
-               hipStream_t s) {
-  const int lc = reduce_log2_chunks(p.final_w);
-  const size_t nparts = (size_t)batch << lc;
-  if (int r = dc->part_v.ensure(nparts * sizeof(float))) return r;
-  if (int r = dc->part_i.ensure(nparts * sizeof(uint64_t))) return r;
-  ProfScope ps(s, "final_reduce");
-  HIP_TRY(launch_reduce(st, (int64_t)1 << p.width, p.final_w, batch, static_cast<float*>(dc->part_v.p),
-                        static_cast<uint64_t*>(dc->part_i.p), energy, arg, s));
+// Uploads a slot (filled through its host address) on stream s.
+int stage_commit(int slot, size_t n, hipStream_t s) {
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  std::lock_guard<std::mutex> g(g_stage_mu);
+  Stager& st = g_stagers[device];
+  HIP_TRY(hipMemcpyAsync(st.dev[slot], st.host[slot], n, hipMemcpyHostToDevice, s));
   return 0;
+}
+
+// Marks the end of the slot's use: after the call's last kernel on stream s.
+int stage_release(int slot, hipStream_t s) {
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  std::lock_guard<std::mutex> g(g_stage_mu);
+  HIP_TRY(hipEventRecord(g_stagers[device].ev[slot], s));
+  return 0;
+}
+
+// One group = one plan over `batch` instances whose J (h, outputs) rows are
+// contiguous: the same-graph batch is one group, an uneven batch one group
+// per instance.
+struct Group {
+  Plan* p = nullptr;
+  DevCache* dc = nullptr;
+  int32_t batch = 1;
+  const void* J = nullptr;
+  const void* h = nullptr;
+  double* energy = nullptr;
+  int8_t* sigma = nullptr;
+  float* dJ = nullptr;
+  float* dh = nullptr;
+  // state buffers: bufs[q] is the input of pass q (q < np), bufs[np] the final state
+  std::vector<float*> bufs;
+  std::vector<int64_t> strides;   // per-instance stride of bufs[q] (entries)
+  uint64_t* arg = nullptr;
+};
+
+int prepare_group(Group& g, bool keep_all) {
+  if (int r = ensure_device(*g.p, g.dc)) return r;
+  const EnergyProgram& ep = g.dc->ep;
+  const int np = (int)ep.passes.size();
+  if (np == 0) return fail(TT_E_INVAL, "empty plan");
+  const Plan& p = *g.p;
+  g.bufs.assign(np + 1, nullptr);
+  g.strides.assign(np + 1, 0);
+  for (int q = 0; q <= np; ++q) g.strides[q] = (int64_t)1 << (q < np ? ep.passes[q].in_w : ep.passes[np - 1].out_w);
+  size_t need = 0;
+  std::vector<size_t> off(np + 1, 0);
+  if (keep_all) {
+    for (int q = 0; q <= np; ++q) {
+      off[q] = need;
+      need += (size_t)g.batch * (size_t)g.strides[q] * sizeof(float);
+      need = (need + 255) & ~size_t(255);
+    }
+  } else {
+    need = 2 * (size_t)g.batch * ((size_t)1 << p.width) * sizeof(float);
+  }
+  DevBuf& buf = keep_all ? g.dc->ckpt : g.dc->state;
+  if ((int64_t)need > (int64_t)buf.cap && (int64_t)need > budget_bytes(p) + (int64_t)buf.cap)
+    return fail(TT_E_TOOBIG, "plan needs %lld bytes of device state (budget %lld)", (long long)need,
+                (long long)budget_bytes(p));
+  if (int r = buf.ensure(need)) return r;
+  char* base = static_cast<char*>(buf.p);
+  if (keep_all) {
+    for (int q = 0; q <= np; ++q) g.bufs[q] = reinterpret_cast<float*>(base + off[q]);
+  } else {
+    float* pp[2] = {reinterpret_cast<float*>(base),
+                    reinterpret_cast<float*>(base + need / 2)};
+    for (int q = 0; q <= np; ++q) g.bufs[q] = pp[q & 1];
+  }
+  if (int r = g.dc->arg.ensure((size_t)g.batch * sizeof(uint64_t))) return r;
+  g.arg = static_cast<uint64_t*>(g.dc->arg.p);
+  return 0;
+}
+
+// Forward passes (one launch per pass index across groups), the final
+// reduction and, with `backward`, the argmax-routing walk.
+int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStream_t s) {
+  for (Group& g : groups)
+    if (int r = prepare_group(g, backward)) return r;
+  Blob blob;
+  struct Launch {
+    size_t off;
+    int n;
+    int64_t n_wg;
+  };
+  std::vector<Launch> levels;
+  int max_np = 0;
+  for (Group& g : groups) max_np = std::max(max_np, (int)g.dc->ep.passes.size());
+  const size_t MAXI = 32;   // items per launch
+  for (int q = 0; q < max_np; ++q) {
+    std::vector<PassItem> items;
+    int64_t wg = 0;
+    auto flush = [&]() {
+      if (items.empty()) return;
+      levels.push_back({blob.add(items.data(), items.size()), (int)items.size(), wg});
+      items.clear();
+      wg = 0;
+    };
+    for (Group& g : groups) {
+      const EnergyProgram& ep = g.dc->ep;
+      if (q >= (int)ep.passes.size()) continue;
+      const DevPass2& P = ep.passes[q];
+      PassItem it;
+      std::memset(&it, 0, sizeof(it));
+      it.P = static_cast<const DevPass2*>(g.dc->d_passes.p) + q;
+      it.stages = static_cast<const DevStage*>(g.dc->d_stages.p);
+      it.fops = static_cast<const FOp*>(g.dc->d_fops.p);
+      it.J = g.J;
+      it.h = g.h;
+      it.jst = g.p->m;
+      it.hst = g.p->n;
+      it.in = g.bufs[q];
+      it.out = g.bufs[q + 1];
+      it.in_st = g.strides[q];
+      it.out_st = g.strides[q + 1];
+      it.batch = g.batch;
+      it.xcd_group = (g.batch % 8 == 0) ? 1 : 0;
+      it.wg_begin = wg;
+      const int64_t n_wg = ((int64_t)g.batch << P.n_free);
+      wg += (n_wg + 7) & ~int64_t(7);
+      items.push_back(it);
+      if (items.size() == MAXI) flush();
+    }
+    flush();
+  }
+  // final reduction items
+  std::vector<RedItem> red;
+  int64_t chunks = 0;
+  for (Group& g : groups) {
+    const int fw = g.p->final_w;
+    const int lc = reduce_log2_chunks(fw);
+    const int np = (int)g.dc->ep.passes.size();
+    for (int b = 0; b < g.batch; ++b) {
+      RedItem r;
+      r.st = g.bufs[np] + (int64_t)b * g.strides[np];
+      r.chunk_begin = chunks;
+      r.energy = g.energy ? g.energy + b : nullptr;
+      r.arg = g.arg + b;
+      r.w = fw;
+      r.log2_chunks = lc;
+      red.push_back(r);
+      chunks += (int64_t)1 << lc;
+    }
+  }
+  const size_t red_off = blob.add(red.data(), red.size());
+  // backward items
+  std::vector<BwdItem> bwd;
+  size_t bwd_off = 0, ckpt_off = 0;
+  std::vector<size_t> ckpt_first;
+  if (backward) {
+    std::vector<const float*> ptrs;
+    std::vector<size_t> ptr_first;
+    for (Group& g : groups) {
+      const int np = (int)g.dc->ep.passes.size();
+      for (int b = 0; b < g.batch; ++b) {
+        ptr_first.push_back(ptrs.size());
+        for (int q = 0; q < np; ++q) ptrs.push_back(g.bufs[q] + (int64_t)b * g.strides[q]);
+      }
+    }
+    const size_t ptr_off = blob.add(ptrs.data(), ptrs.size());
+    size_t k = 0;
+    const size_t esz = dtype == TT_F32 ? sizeof(float) : sizeof(int32_t);
+    for (Group& g : groups) {
+      const int np = (int)g.dc->ep.passes.size();
+      for (int b = 0; b < g.batch; ++b, ++k) {
+        BwdItem it;
+        std::memset(&it, 0, sizeof(it));
+        it.passes = static_cast<const DevPass2*>(g.dc->d_passes.p);
+        it.cands = static_cast<const BCand*>(g.dc->d_cands.p);
+        it.terms = static_cast<const BTerm*>(g.dc->d_terms.p);
+        it.J = static_cast<const char*>(g.J) + (size_t)b * g.p->m * esz;
+        it.h = g.h ? static_cast<const char*>(g.h) + (size_t)b * g.p->n * esz : nullptr;
+        it.ckpt = nullptr;   // set once the blob's device address is known
+        it.final_addr = g.arg + b;
+        it.final_pos = static_cast<const uint8_t*>(g.dc->d_final_pos.p);
+        it.final_slot_spin = static_cast<const int32_t*>(g.dc->d_final_slot.p);
+        it.edges = static_cast<const int32_t*>(g.dc->d_edges.p);
+        it.sigma = g.sigma + (size_t)b * g.p->n;
+        it.dJ = g.dJ ? g.dJ + (size_t)b * g.p->m : nullptr;
+        it.dh = g.dh ? g.dh + (size_t)b * g.p->n : nullptr;
+        it.m = g.p->m;
+        it.n_passes = np;
+        it.final_w = g.p->final_w;
+        it.n = g.p->n;
+        bwd.push_back(it);
+      }
+    }
+    bwd_off = blob.add(bwd.data(), bwd.size());
+    ckpt_first.swap(ptr_first);
+    ckpt_off = ptr_off;
+  }
+  char* host = nullptr;
+  char* dev = nullptr;
+  int slot = 0;
+  if (int r = stage_reserve(blob.bytes.size(), &host, &dev, &slot)) return r;
+  if (backward) {
+    BwdItem* bi = reinterpret_cast<BwdItem*>(blob.bytes.data() + bwd_off);
+    for (size_t k = 0; k < bwd.size(); ++k)
+      bi[k].ckpt = reinterpret_cast<const float* const*>(dev + ckpt_off + ckpt_first[k] * sizeof(float*));
+  }
+  std::memcpy(host, blob.bytes.data(), blob.bytes.size());
+  if (int r = stage_commit(slot, blob.bytes.size(), s)) return r;
+  // reduction partials live in the first group's plan cache
+  DevCache* dc0 = groups[0].dc;
+  if (int r = dc0->part_v.ensure((size_t)chunks * sizeof(float))) return r;
+  if (int r = dc0->part_i.ensure((size_t)chunks * sizeof(uint64_t))) return r;
+  float* pv = static_cast<float*>(dc0->part_v.p);
+  uint64_t* pi = static_cast<uint64_t*>(dc0->part_i.p);
+  for (const Launch& L : levels) {
+    ProfScope ps(s, "sweep_pass");
+    HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, dtype, s));
+  }
+  {
+    ProfScope ps(s, "final_reduce");
+    HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + red_off), (int)red.size(), chunks, pv, pi, s));
+  }
+  if (backward) {
+    ProfScope ps(s, "sweep_backward");
+    HIP_TRY(launch_backward(reinterpret_cast<const BwdItem*>(dev + bwd_off), (int)bwd.size(), dtype, s));
+  }
+  return stage_release(slot, s);
 }
 
 }  // namespace
@@ -454,13 +685,13 @@ int tt_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
   try {
     if (int r = check_common(plan, batch, dtype, J, h)) return r;
     if (!energy) return fail(TT_E_INVAL, "null energy");
-    Plan& p = *reinterpret_cast<Plan*>(plan);
-    DevCache* dc = nullptr;
-    if (int r = ensure_device(p, dc)) return r;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    float* fin = nullptr;
-    if (int r = run_forward(p, dc, batch, dtype, J, h, false, s, &fin)) return r;
-    return run_reduce(p, dc, batch, fin, energy, nullptr, s);
+    std::vector<Group> g(1);
+    g[0].p = reinterpret_cast<Plan*>(plan);
+    g[0].batch = batch;
+    g[0].J = J;
+    g[0].h = h;
+    g[0].energy = energy;
+    return run_groups(g, dtype, false, static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
   }
@@ -474,31 +705,16 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
     Plan& p = *reinterpret_cast<Plan*>(plan);
     if (p.n_regs != 1) return fail(TT_E_INVAL, "backward over multi-register plans is not supported");
     if (p.n > 8192) return fail(TT_E_INVAL, "too many spins for the backward walk");
-    DevCache* dc = nullptr;
-    if (int r = ensure_device(p, dc)) return r;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    float* fin = nullptr;
-    if (int r = run_forward(p, dc, batch, dtype, J, h, true, s, &fin)) return r;
-    if (int r = dc->arg.ensure((size_t)batch * sizeof(uint64_t))) return r;
-    uint64_t* arg = static_cast<uint64_t*>(dc->arg.p);
-    if (int r = run_reduce(p, dc, batch, fin, energy, arg, s)) return r;
-    const int np = (int)dc->ep.passes.size();
-    if (dc->h_ckpt_ptrs != dc->uploaded_ckpt_ptrs || dc->ckpt_ptrs.cap < np * sizeof(float*)) {
-      if (int r = dc->ckpt_ptrs.ensure(np * sizeof(float*))) return r;
-      HIP_TRY(hipStreamSynchronize(s));
-      HIP_TRY(hipMemcpy(dc->ckpt_ptrs.p, dc->h_ckpt_ptrs.data(), np * sizeof(float*), hipMemcpyHostToDevice));
-      dc->uploaded_ckpt_ptrs = dc->h_ckpt_ptrs;
-    }
-    {
-      ProfScope ps(s, "sweep_backward");
-      HIP_TRY(launch_backward(static_cast<const DevPass2*>(dc->d_passes.p), np,
-                              static_cast<const BCand*>(dc->d_cands.p), static_cast<const BTerm*>(dc->d_terms.p),
-                              dtype, J, h, p.m, p.n, static_cast<const float* const*>(dc->ckpt_ptrs.p),
-                              (int64_t)1 << p.width, arg, static_cast<const uint8_t*>(dc->d_final_pos.p),
-                              static_cast<const int32_t*>(dc->d_final_slot.p), p.final_w,
-                              static_cast<const int32_t*>(dc->d_edges.p), p.n, p.m, sigma, dJ, dh, batch, s));
-    }
-    return TT_OK;
+    std::vector<Group> g(1);
+    g[0].p = &p;
+    g[0].batch = batch;
+    g[0].J = J;
+    g[0].h = h;
+    g[0].energy = energy;
+    g[0].sigma = sigma;
+    g[0].dJ = dJ;
+    g[0].dh = dh;
+    return run_groups(g, dtype, true, static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
   }
@@ -663,20 +879,33 @@ int tt_count_to_decimal(const uint64_t residues[3], char* buf, size_t len) {
 
 int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype, const void* J, const int64_t* j_off,
                        double* energy, int8_t* sigma, const int64_t* s_off, float* dJ, void* stream) {
-  if (n_inst < 1 || !plans || !j_off || !energy) return fail(TT_E_INVAL, "bad uneven-batch arguments");
-  if (sigma && !s_off) return fail(TT_E_INVAL, "sigma needs s_off");
-  const size_t esz = dtype == TT_F32 ? sizeof(float) : sizeof(int32_t);
-  for (int i = 0; i < n_inst; ++i) {
-    const void* Ji = static_cast<const char*>(J) + (size_t)j_off[i] * esz;
-    int r;
-    if (sigma)
-      r = tt_backward(plans[i], 1, dtype, Ji, nullptr, energy + i, sigma + s_off[i], dJ ? dJ + j_off[i] : nullptr,
-                      nullptr, stream);
-    else
-      r = tt_contract(plans[i], 1, dtype, Ji, nullptr, energy + i, stream);
-    if (r) return r;
+  try {
+    if (n_inst < 1 || !plans || !j_off || !energy || !J) return fail(TT_E_INVAL, "bad uneven-batch arguments");
+    if (sigma && !s_off) return fail(TT_E_INVAL, "sigma needs s_off");
+    if (dtype != TT_F32 && dtype != TT_I32) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
+    const size_t esz = dtype == TT_F32 ? sizeof(float) : sizeof(int32_t);
+    std::vector<Group> groups(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      if (!plans[i]) return fail(TT_E_INVAL, "null plan %d", i);
+      Plan& p = *reinterpret_cast<Plan*>(plans[i]);
+      if (p.has_field) return fail(TT_E_INVAL, "uneven batches take no fields");
+      if (p.n_regs != 1) return fail(TT_E_INVAL, "multi-register plans are not supported here");
+      for (int k = 0; k < i; ++k)
+        if (plans[k] == plans[i]) return fail(TT_E_INVAL, "each instance needs its own plan object");
+      Group& g = groups[i];
+      g.p = &p;
+      g.batch = 1;
+      g.J = static_cast<const char*>(J) + (size_t)j_off[i] * esz;
+      g.energy = energy + i;
+      if (sigma) {
+        g.sigma = sigma + s_off[i];
+        g.dJ = dJ ? dJ + j_off[i] : nullptr;
+      }
+    }
+    return run_groups(groups, dtype, sigma != nullptr, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(TT_E_INVAL, "unexpected failure");
   }
-  return TT_OK;
 }
 
 int tt_prof_enable(int32_t on) {

@@ -73,6 +73,9 @@ struct DevPass2 {
   // bit q of the load (store) enumeration index -> tile-index bit, address bit
   uint16_t ld_bti[16], st_bti[16];
   uint64_t ld_bad[16], st_bad[16];
+  // the same maps for the index bits above 10 (k = u >> 10), all 16 combinations
+  uint16_t ld_hti[16], st_hti[16];
+  uint64_t ld_had[16], st_had[16];
 };
 
 // An op with its constants resolved for one instance and one tile (built in
@@ -100,6 +103,50 @@ struct BTerm {
   int32_t coef;     // edge (bond) or spin (field)
   uint8_t is_field;
   uint8_t a, b, pad;
+};
+
+// ---- launch tables ----
+// One item of a pass launch: one pass of one plan over `batch` instances.
+struct PassItem {
+  const DevPass2* P;
+  const DevStage* stages;
+  const FOp* fops;
+  const void* J;         // row of the item's first instance
+  const void* h;         // (NULL without fields)
+  int64_t jst, hst;      // row strides between instances
+  const float* in;       // input state of the first instance
+  float* out;
+  int64_t in_st, out_st; // state strides between instances (2^in_w, 2^out_w)
+  int64_t wg_begin;      // first workgroup of the item in the launch
+  int32_t batch, xcd_group;
+};
+
+// Final reduction of one instance's state (2^w entries).
+struct RedItem {
+  const float* st;
+  int64_t chunk_begin;   // first partial of the instance
+  double* energy;        // may be NULL
+  uint64_t* arg;         // may be NULL
+  int32_t w, log2_chunks;
+};
+
+// Backward walk of one instance.
+struct BwdItem {
+  const DevPass2* passes;
+  const BCand* cands;
+  const BTerm* terms;
+  const void* J;
+  const void* h;
+  const float* const* ckpt;   // per-pass input states of this instance
+  const uint64_t* final_addr;
+  const uint8_t* final_pos;
+  const int32_t* final_slot_spin;
+  const int32_t* edges;
+  int8_t* sigma;
+  float* dJ;
+  float* dh;
+  int64_t m;
+  int32_t n_passes, final_w, n, pad;
 };
 
 }  // namespace tt

@@ -147,6 +147,25 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
       d.ld_bad[k] = k < d.n_ld ? (1ull << d.in_pos[R[q][ld[k]]]) : 0ull;
       d.st_bad[k] = k < d.n_st ? (1ull << d.out_pos[R[q][st[k]]]) : 0ull;
     }
+    for (int kk = 0; kk < 16; ++kk) {
+      uint32_t lt = 0, stt = 0;
+      uint64_t la = 0, sa = 0;
+      for (int b = 0; b < 4; ++b) {
+        if (!((kk >> b) & 1)) continue;
+        if (10 + b < d.t) {
+          lt |= d.ld_bti[10 + b];
+          la |= d.ld_bad[10 + b];
+        }
+        if (10 + b < d.n_st) {
+          stt |= d.st_bti[10 + b];
+          sa |= d.st_bad[10 + b];
+        }
+      }
+      d.ld_hti[kk] = (uint16_t)lt;
+      d.ld_had[kk] = la;
+      d.st_hti[kk] = (uint16_t)stt;
+      d.st_had[kk] = sa;
+    }
     auto enc = [&](int slot) -> uint8_t {
       return tbit[slot] >= 0 ? (uint8_t)tbit[slot] : (uint8_t)(SLOT_FIXED + slot);
     };

@@ -8,17 +8,11 @@
 
 namespace tt {
 
-hipError_t launch_pass(const DevPass2& P, const DevPass2* P_dev, const DevStage* stages, const FOp* fops, int dtype,
-                       const void* J, const void* h, int64_t jst, int64_t hst, const float* in, float* out,
-                       int64_t sst, int batch, hipStream_t stream);
+hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int dtype, hipStream_t stream);
 int reduce_log2_chunks(int w);
-hipError_t launch_reduce(const float* st, int64_t sst, int w, int batch, float* pv, uint64_t* pi,
-                         double* energy, uint64_t* arg, hipStream_t stream);
-hipError_t launch_backward(const DevPass2* passes, int n_passes, const BCand* cands, const BTerm* terms, int dtype,
-                           const void* J, const void* h, int64_t jst, int64_t hst, const float* const* ckpt,
-                           int64_t sst, const uint64_t* final_addr, const uint8_t* final_pos,
-                           const int32_t* final_slot_spin, int final_w, const int32_t* edges, int n, int64_t m,
-                           int8_t* sigma, float* dJ, float* dh, int batch, hipStream_t stream);
+hipError_t launch_reduce(const RedItem* items, int n_items, int64_t n_chunks, float* pv, uint64_t* pi,
+                         hipStream_t stream);
+hipError_t launch_backward(const BwdItem* items, int n_items, int dtype, hipStream_t stream);
 
 // counting path: state entries (x, n mod p_r), r = 0, 1, 2
 hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h,

@@ -43,9 +43,8 @@ __device__ __forceinline__ uint32_t ebit(uint8_t enc, uint32_t i, uint64_t base_
 // Workgroup -> (instance, tile). With `xcd_group` the tiles of one instance
 // run on one XCD (workgroups are dispatched round-robin over the 8 XCDs), so
 // the pass-to-pass exchange of an instance stays in that XCD's L2.
-__device__ __forceinline__ bool wg_to_tile(int log2_tiles, int batch, int xcd_group, int64_t* inst,
+__device__ __forceinline__ bool wg_to_tile(uint64_t b, int log2_tiles, int batch, int xcd_group, int64_t* inst,
                                            uint64_t* tile) {
-  const uint64_t b = blockIdx.x;
   if (xcd_group) {
     const uint64_t xcd = b & 7ull, k = b >> 3;
     *inst = (int64_t)(((k >> log2_tiles) << 3) | xcd);
@@ -207,17 +206,19 @@ __device__ __forceinline__ void star16(float (&v)[16], const uint32_t (&ix)[16],
 }
 
 template <typename IT>
-__global__ __launch_bounds__(NT) void k_pass(const DevPass2* __restrict__ Pp, const DevStage* __restrict__ stages,
-                                             const FOp* __restrict__ fops, const IT* __restrict__ J,
-                                             const IT* __restrict__ h, int64_t jst, int64_t hst,
-                                             const float* __restrict__ in, float* __restrict__ out, int64_t sst,
-                                             int batch, int xcd_group) {
+__global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items, int n_items) {
   extern __shared__ float tile[];
   __shared__ ROp rops[MAX_PASS_OPS];
-  const DevPass2& P = *Pp;
+  const int64_t wg = blockIdx.x;
+  int it = 0;
+  while (it + 1 < n_items && wg >= items[it + 1].wg_begin) ++it;
+  const PassItem& I = items[it];
+  const DevPass2& P = *I.P;
+  const DevStage* __restrict__ stages = I.stages;
+  const FOp* __restrict__ fops = I.fops;
   int64_t inst;
   uint64_t tid_bits;
-  if (!wg_to_tile(P.n_free, batch, xcd_group, &inst, &tid_bits)) return;
+  if (!wg_to_tile((uint64_t)(wg - I.wg_begin), P.n_free, I.batch, I.xcd_group, &inst, &tid_bits)) return;
   const int tid = threadIdx.x;
   const int t = P.t;
   const uint32_t size = 1u << t;
@@ -232,13 +233,16 @@ __global__ __launch_bounds__(NT) void k_pass(const DevPass2* __restrict__ Pp, co
     if (P.out_pos[slot] != NO_POS) out_base |= b << P.out_pos[slot];
     else if (b) stored = false;   // only the copy with a dropped slot at 0 is kept
   }
-  const IT* Jrow = J + inst * jst;
-  const IT* hrow = h ? h + inst * hst : nullptr;
+  const IT* Jrow = static_cast<const IT*>(I.J) + inst * I.jst;
+  const IT* hrow = I.h ? static_cast<const IT*>(I.h) + inst * I.hst : nullptr;
+  const float* in = I.in + inst * I.in_st;
+  float* out = I.out + inst * I.out_st;
   // resolve the pass's ops for this instance and tile
-  const int op0 = stages[P.stage_begin].op_begin;
+  const int op0 = P.n_stages ? stages[P.stage_begin].op_begin : 0;
   const int n_ops = P.n_stages ? stages[P.stage_begin + P.n_stages - 1].op_end - op0 : 0;
   for (int o = tid; o < n_ops; o += NT) resolve_op<IT>(fops + op0 + o, rops + o, Jrow, hrow, bs);
-  // load: enumeration index u = tid + 1024 k; bit q of u -> tile bit / address bit
+  // load: enumeration index u = tid + 1024 k; bit q of u -> tile bit / address
+  // bit. All loads of a thread are issued before any is consumed.
   {
     uint32_t ti_lo = 0;
     uint64_t ad_lo = 0;
@@ -248,19 +252,16 @@ __global__ __launch_bounds__(NT) void k_pass(const DevPass2* __restrict__ Pp, co
         ti_lo |= P.ld_bti[q];
         ad_lo |= P.ld_bad[q];
       }
-    const float* src = in + inst * sst + in_base;
+    const float* src = in + in_base;
     if (tid < (int)size) {
       const int nk = t > 10 ? (1 << (t - 10)) : 1;
-      for (int k = 0; k < nk; ++k) {
-        uint32_t ti = ti_lo;
-        uint64_t ad = ad_lo;
-        for (int q = 0; q < t - 10; ++q)
-          if ((k >> q) & 1) {
-            ti |= P.ld_bti[10 + q];
-            ad |= P.ld_bad[10 + q];
-          }
-        tile[swz(ti)] = P.init ? 0.f : src[ad];
-      }
+      float vals[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk) vals[k] = P.init ? 0.f : src[ad_lo | P.ld_had[k]];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk) tile[swz(ti_lo | P.ld_hti[k])] = vals[k];
     }
   }
   __syncthreads();
@@ -309,19 +310,16 @@ __global__ __launch_bounds__(NT) void k_pass(const DevPass2* __restrict__ Pp, co
         ti_lo |= P.st_bti[q];
         ad_lo |= P.st_bad[q];
       }
-    float* dst = out + inst * sst + out_base;
+    float* dst = out + out_base;
     if (tid < (1 << nb)) {
       const int nk = ns > 10 ? (1 << (ns - 10)) : 1;
-      for (int k = 0; k < nk; ++k) {
-        uint32_t ti = ti_lo;
-        uint64_t ad = ad_lo;
-        for (int q = 0; q < ns - 10; ++q)
-          if ((k >> q) & 1) {
-            ti |= P.st_bti[10 + q];
-            ad |= P.st_bad[10 + q];
-          }
-        dst[ad] = tile[swz(ti)];
-      }
+      float vals[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk) vals[k] = tile[swz(ti_lo | P.st_hti[k])];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk) dst[ad_lo | P.st_had[k]] = vals[k];
     }
   }
 }
@@ -368,13 +366,15 @@ __device__ VI block_best(VI x) {
   return r;
 }
 
-__global__ __launch_bounds__(NTR) void k_reduce_stage1(const float* __restrict__ st, int64_t sst, int w,
-                                                       int log2_chunks, float* __restrict__ pv,
-                                                       uint64_t* __restrict__ pi) {
-  const int64_t inst = (int64_t)blockIdx.x >> log2_chunks;
-  const uint64_t chunk = (uint64_t)blockIdx.x & ((1ull << log2_chunks) - 1ull);
-  const uint64_t len = 1ull << (w - log2_chunks);
-  const float* s = st + inst * sst;
+__global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict__ items, int n_items,
+                                                       float* __restrict__ pv, uint64_t* __restrict__ pi) {
+  const int64_t wg = blockIdx.x;
+  int it = 0;
+  while (it + 1 < n_items && wg >= items[it + 1].chunk_begin) ++it;
+  const RedItem& I = items[it];
+  const uint64_t chunk = (uint64_t)(wg - I.chunk_begin);
+  const uint64_t len = 1ull << (I.w - I.log2_chunks);
+  const float* s = I.st;
   VI best{-INFINITY, ~0ull};
   for (uint64_t k = threadIdx.x; k < len; k += NTR) {
     const uint64_t idx = chunk * len + k;
@@ -382,23 +382,22 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const float* __restrict__
   }
   best = block_best<NTR>(best);
   if (threadIdx.x == 0) {
-    pv[blockIdx.x] = best.v;
-    pi[blockIdx.x] = best.i;
+    pv[wg] = best.v;
+    pi[wg] = best.i;
   }
 }
 
-__global__ __launch_bounds__(NTR) void k_reduce_stage2(const float* __restrict__ pv,
-                                                       const uint64_t* __restrict__ pi, int log2_chunks,
-                                                       double* __restrict__ energy,
-                                                       uint64_t* __restrict__ arg) {
-  const int64_t inst = blockIdx.x;
-  const int64_t nc = 1ll << log2_chunks;
+__global__ __launch_bounds__(NTR) void k_reduce_stage2(const RedItem* __restrict__ items,
+                                                       const float* __restrict__ pv,
+                                                       const uint64_t* __restrict__ pi) {
+  const RedItem& I = items[blockIdx.x];
+  const int64_t nc = 1ll << I.log2_chunks;
   VI best{-INFINITY, ~0ull};
-  for (int64_t k = threadIdx.x; k < nc; k += NTR) best = vi_best(best, VI{pv[inst * nc + k], pi[inst * nc + k]});
+  for (int64_t k = threadIdx.x; k < nc; k += NTR) best = vi_best(best, VI{pv[I.chunk_begin + k], pi[I.chunk_begin + k]});
   best = block_best<NTR>(best);
   if (threadIdx.x == 0) {
-    if (energy) energy[inst] = -(double)best.v;
-    if (arg) arg[inst] = best.i;
+    if (I.energy) *I.energy = -(double)best.v;
+    if (I.arg) *I.arg = best.i;
   }
 }
 
@@ -433,16 +432,7 @@ __device__ __forceinline__ float lterm_val(const LTerm& tm, uint32_t a, uint64_t
 }
 
 template <typename IT>
-__global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ passes, int n_passes,
-                                                 const BCand* __restrict__ cands, const BTerm* __restrict__ terms,
-                                                 const IT* __restrict__ J, const IT* __restrict__ h, int64_t jst,
-                                                 int64_t hst, const float* const* __restrict__ ckpt, int64_t sst,
-                                                 const uint64_t* __restrict__ final_addr,
-                                                 const uint8_t* __restrict__ final_pos,
-                                                 const int32_t* __restrict__ final_slot_spin, int final_w,
-                                                 const int32_t* __restrict__ edges, int n, int64_t m,
-                                                 int8_t* __restrict__ sigma, float* __restrict__ dJ,
-                                                 float* __restrict__ dh) {
+__global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ items) {
   __shared__ int8_t s_sh[MAX_SPINS];
   __shared__ float lut_lo[256], lut_hi[256];
   __shared__ uint64_t ad_lo[256], ad_hi[256];
@@ -450,14 +440,22 @@ __global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ pa
   __shared__ LTerm lt[MAX_BTERMS];
   __shared__ BCand lc[16];
   __shared__ uint8_t l_in_pos[64];
-  const int64_t inst = blockIdx.x;
+  const BwdItem& I = items[blockIdx.x];
   const int tid = threadIdx.x;
-  const IT* Jrow = J + inst * jst;
-  const IT* hrow = h ? h + inst * hst : nullptr;
+  const IT* Jrow = static_cast<const IT*>(I.J);
+  const IT* hrow = static_cast<const IT*>(I.h);
+  const DevPass2* __restrict__ passes = I.passes;
+  const BCand* __restrict__ cands = I.cands;
+  const BTerm* __restrict__ terms = I.terms;
+  const int n_passes = I.n_passes, final_w = I.final_w, n = I.n;
+  const int64_t m = I.m;
+  const int32_t* __restrict__ final_slot_spin = I.final_slot_spin;
+  const uint8_t* __restrict__ final_pos = I.final_pos;
+  const int32_t* __restrict__ edges = I.edges;
   for (int v = tid; v < n; v += NT) s_sh[v] = 0;
   __syncthreads();
   if (tid == 0) {
-    const uint64_t addr = final_addr[inst];
+    const uint64_t addr = *I.final_addr;
     uint64_t t = 0;
     for (int c = 0; c < final_w; ++c) {
       const uint64_t b = (addr >> final_pos[c]) & 1ull;
@@ -526,15 +524,26 @@ __global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ pa
       sh_base = base;
     }
     __syncthreads();
-    const float* src = P->init ? nullptr : ckpt[p] + inst * sst + sh_base;
+    const float* src = P->init ? nullptr : I.ckpt[p] + sh_base;
     VI best{-INFINITY, ~0ull};
     const uint32_t na = 1u << nc;
     const int cross_b = n_lo + n_hi;
-    for (uint32_t a = tid; a < na; a += NT) {
-      float val = lut_lo[a & 255u] + lut_hi[a >> 8];
-      for (int k = cross_b; k < nterm; ++k) val += lterm_val(lt[k], a, t);
-      if (src) val += src[ad_lo[a & 255u] | ad_hi[a >> 8]];
-      best = vi_best(best, VI{val, (uint64_t)a});
+    // candidates in batches of 8 per thread: all loads of a batch in flight together
+    for (uint32_t a0 = tid; a0 < na; a0 += 8u * NT) {
+      float x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t a = a0 + (uint32_t)j * NT;
+        x[j] = (src && a < na) ? src[ad_lo[a & 255u] | ad_hi[a >> 8]] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t a = a0 + (uint32_t)j * NT;
+        if (a >= na) break;
+        float val = lut_lo[a & 255u] + lut_hi[a >> 8] + x[j];
+        for (int k = cross_b; k < nterm; ++k) val += lterm_val(lt[k], a, t);
+        best = vi_best(best, VI{val, (uint64_t)a});
+      }
     }
     best = block_best<NT>(best);
     if (tid == 0) {
@@ -550,13 +559,13 @@ __global__ __launch_bounds__(NT) void k_backward(const DevPass2* __restrict__ pa
     __syncthreads();
   }
   for (int v = tid; v < n; v += NT) {
-    sigma[inst * n + v] = (int8_t)(s_sh[v] ? -1 : 1);
-    if (dh) dh[inst * n + v] = s_sh[v] ? 1.f : -1.f;           // -sigma_v
+    I.sigma[v] = (int8_t)(s_sh[v] ? -1 : 1);
+    if (I.dh) I.dh[v] = s_sh[v] ? 1.f : -1.f;           // -sigma_v
   }
-  if (dJ) {
+  if (I.dJ) {
     for (int64_t e = tid; e < m; e += NT) {
       const int a = edges[2 * e], c = edges[2 * e + 1];
-      dJ[inst * m + e] = (s_sh[a] ^ s_sh[c]) ? 1.f : -1.f;   // -sigma_a sigma_c
+      I.dJ[e] = (s_sh[a] ^ s_sh[c]) ? 1.f : -1.f;   // -sigma_a sigma_c
     }
   }
 }
@@ -578,24 +587,17 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
   return e;
 }
 
-hipError_t launch_pass(const DevPass2& P, const DevPass2* P_dev, const DevStage* stages, const FOp* fops, int dtype,
-                       const void* J, const void* h, int64_t jst, int64_t hst, const float* in, float* out,
-                       int64_t sst, int batch, hipStream_t stream) {
-  const size_t lds = sizeof(float) << P.t;
-  const uint64_t tiles = 1ull << P.n_free;
-  const int xcd_group = (batch % 8 == 0) ? 1 : 0;
-  const uint64_t grid = (uint64_t)batch * tiles;
-  if (grid >= (1ull << 31)) return hipErrorInvalidConfiguration;
+hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int dtype, hipStream_t stream) {
+  const size_t lds = 65536;
+  if (n_wg >= (1ll << 31)) return hipErrorInvalidConfiguration;
   if (dtype == 0) {
     hipError_t e = allow_lds(k_pass<float>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pass<float>, dim3((uint32_t)grid), dim3(NT), lds, stream, P_dev, stages, fops,
-                       (const float*)J, (const float*)h, jst, hst, in, out, sst, batch, xcd_group);
+    hipLaunchKernelGGL(k_pass<float>, dim3((uint32_t)n_wg), dim3(NT), lds, stream, items, n_items);
   } else {
     hipError_t e = allow_lds(k_pass<int32_t>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pass<int32_t>, dim3((uint32_t)grid), dim3(NT), lds, stream, P_dev, stages, fops,
-                       (const int32_t*)J, (const int32_t*)h, jst, hst, in, out, sst, batch, xcd_group);
+    hipLaunchKernelGGL(k_pass<int32_t>, dim3((uint32_t)n_wg), dim3(NT), lds, stream, items, n_items);
   }
   return hipGetLastError();
 }
@@ -608,29 +610,18 @@ int reduce_log2_chunks(int w) {
   return c;
 }
 
-hipError_t launch_reduce(const float* st, int64_t sst, int w, int batch, float* pv, uint64_t* pi,
-                         double* energy, uint64_t* arg, hipStream_t stream) {
-  const int lc = reduce_log2_chunks(w);
-  hipLaunchKernelGGL(k_reduce_stage1, dim3((uint32_t)((uint64_t)batch << lc)), dim3(NTR), 0, stream, st, sst, w, lc,
-                     pv, pi);
-  hipLaunchKernelGGL(k_reduce_stage2, dim3((uint32_t)batch), dim3(NTR), 0, stream, pv, pi, lc, energy, arg);
+hipError_t launch_reduce(const RedItem* items, int n_items, int64_t n_chunks, float* pv, uint64_t* pi,
+                         hipStream_t stream) {
+  hipLaunchKernelGGL(k_reduce_stage1, dim3((uint32_t)n_chunks), dim3(NTR), 0, stream, items, n_items, pv, pi);
+  hipLaunchKernelGGL(k_reduce_stage2, dim3((uint32_t)n_items), dim3(NTR), 0, stream, items, pv, pi);
   return hipGetLastError();
 }
 
-hipError_t launch_backward(const DevPass2* passes, int n_passes, const BCand* cands, const BTerm* terms, int dtype,
-                           const void* J, const void* h, int64_t jst, int64_t hst, const float* const* ckpt,
-                           int64_t sst, const uint64_t* final_addr, const uint8_t* final_pos,
-                           const int32_t* final_slot_spin, int final_w, const int32_t* edges, int n, int64_t m,
-                           int8_t* sigma, float* dJ, float* dh, int batch, hipStream_t stream) {
-  if (dtype == 0) {
-    hipLaunchKernelGGL(k_backward<float>, dim3(batch), dim3(NT), 0, stream, passes, n_passes, cands, terms,
-                       (const float*)J, (const float*)h, jst, hst, ckpt, sst, final_addr, final_pos, final_slot_spin,
-                       final_w, edges, n, m, sigma, dJ, dh);
-  } else {
-    hipLaunchKernelGGL(k_backward<int32_t>, dim3(batch), dim3(NT), 0, stream, passes, n_passes, cands, terms,
-                       (const int32_t*)J, (const int32_t*)h, jst, hst, ckpt, sst, final_addr, final_pos,
-                       final_slot_spin, final_w, edges, n, m, sigma, dJ, dh);
-  }
+hipError_t launch_backward(const BwdItem* items, int n_items, int dtype, hipStream_t stream) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_backward<float>, dim3(n_items), dim3(NT), 0, stream, items);
+  else
+    hipLaunchKernelGGL(k_backward<int32_t>, dim3(n_items), dim3(NT), 0, stream, items);
   return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ class DevPass2(C.Structure):
                 ("R", C.c_uint8 * 16), ("fre", C.c_uint8 * 48), ("in_pos", C.c_uint8 * 64),
                 ("out_pos", C.c_uint8 * 64), ("ld_order", C.c_uint8 * 16), ("st_order", C.c_uint8 * 16),
                 ("n_ld", C.c_int32), ("n_st", C.c_int32), ("ld_bti", C.c_uint16 * 16), ("st_bti", C.c_uint16 * 16),
-                ("ld_bad", C.c_uint64 * 16), ("st_bad", C.c_uint64 * 16)]
+                ("ld_bad", C.c_uint64 * 16), ("st_bad", C.c_uint64 * 16), ("ld_hti", C.c_uint16 * 16),
+                ("st_hti", C.c_uint16 * 16), ("ld_had", C.c_uint64 * 16), ("st_had", C.c_uint64 * 16)]
 
 
 class DevStage(C.Structure):
@@ -89,11 +90,14 @@ def forward(prog, width, J, h):
                     stored = False
             tile = np.full(1 << t, np.nan)
             for u in range(1 << t):
+                lo, hi = u & 1023, u >> 10
                 ti = a = 0
-                for k in range(t):
-                    if (u >> k) & 1:
+                for k in range(min(t, 10)):
+                    if (lo >> k) & 1:
                         ti |= P.ld_bti[k]
                         a |= P.ld_bad[k]
+                ti |= P.ld_hti[hi]
+                a |= P.ld_had[hi]
                 tile[ti] = 0.0 if P.init else src[in_base | a]
             assert not np.any(np.isnan(tile))
             for si in range(P.n_stages):
@@ -130,11 +134,14 @@ def forward(prog, width, J, h):
             if not stored:
                 continue
             for u in range(1 << P.n_st):
+                lo, hi = u & 1023, u >> 10
                 ti = a = 0
-                for k in range(P.n_st):
-                    if (u >> k) & 1:
+                for k in range(min(P.n_st, 10)):
+                    if (lo >> k) & 1:
                         ti |= P.st_bti[k]
                         a |= P.st_bad[k]
+                ti |= P.st_hti[hi]
+                a |= P.st_had[hi]
                 dst[out_base | a] = tile[ti]
         states.append(dst)
     return states

@@ -215,3 +215,40 @@ def test_uneven_regular3_small():
         s = sig[b].cpu().numpy()
         assert abs(O.energy(x.n, x.edges, x.J, None, s) - ref["energy"]) <= tol(x.n)
         assert np.array_equal(s, ref["sigma"]) or np.array_equal(s, -ref["sigma"])
+
+
+@pytest.mark.parametrize("case", ["isolated", "no_edges", "two_components"])
+def test_degenerate_graphs(case):
+    rng = np.random.default_rng(7)
+    if case == "isolated":
+        n, e = 5, np.array([[0, 1], [1, 2]], np.int32)
+    elif case == "no_edges":
+        n, e = 4, np.zeros((0, 2), np.int32)
+    else:
+        n, e = 10, np.concatenate([I.ring(5), I.path(5) + 5]).astype(np.int32)
+    J = I.pm1(len(e), rng) if len(e) else np.zeros(0, np.int32)
+    say("degenerate", case)
+    plan = B.Plan(n, e, seed=1, trials=2, tile_bits=7, count_tile_bits=7)
+    Jd = dev(J[None].astype(np.int32)) if len(e) else torch.zeros((1, 0), dtype=torch.int32, device=DEV)
+    E, sig, _, _ = B.backward(plan, Jd)
+    Ec, _, g = B.count(plan, Jd)
+    ref = O.eliminate(n, e, J, None, counts="exact")
+    assert E[0].item() == ref["energy"] and Ec[0] == ref["energy"] and g[0] == ref["count"]
+    assert O.energy(n, e, J, None, sig[0].cpu().numpy()) == ref["energy"]
+
+
+def test_uneven_matches_per_instance_calls():
+    insts = I.config_instances(3, batch=5, L=None)[:5]
+    small = []
+    for b, n in enumerate([20, 26, 32, 40, 24]):
+        rng = np.random.default_rng([9, b])
+        small.append(I.make(I.random_regular(n, 3, rng), n, rng, "gauss"))
+    say("uneven vs per-instance")
+    plans = [B.Plan(x.n, x.edges, seed=2, trials=8, tile_bits=8) for x in small]
+    E, sig, dJ = B.contract_uneven(plans, [dev(x.J) for x in small])
+    for b, x in enumerate(small):
+        p1 = B.Plan(x.n, x.edges, seed=2, trials=8, tile_bits=8)
+        E1, s1, dJ1, _ = B.backward(p1, dev(x.J[None]))
+        assert E1[0].item() == E[b].item()
+        assert torch.equal(s1[0], sig[b]) and torch.equal(dJ1[0], dJ[b])
+    del insts

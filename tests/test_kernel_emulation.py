@@ -62,3 +62,21 @@ def test_families(fam):
     ref = O.eliminate(n, e, J, None)
     assert E == ref["energy"]
     assert O.energy(n, e, J, None, sig) == ref["energy"]
+
+
+@pytest.mark.parametrize("case", ["isolated", "no_edges", "two_components"])
+def test_degenerate_graphs(case):
+    rng = np.random.default_rng(7)
+    if case == "isolated":
+        n, e = 5, np.array([[0, 1], [1, 2]], np.int32)
+    elif case == "no_edges":
+        n, e = 4, np.zeros((0, 2), np.int32)
+    else:
+        n, e = 10, np.concatenate([I.ring(5), I.path(5) + 5]).astype(np.int32)
+    J = I.pm1(len(e), rng) if len(e) else np.zeros(0, np.int32)
+    for order in (None, list(range(n))):
+        plan = B.Plan(n, e, order=order, seed=1, trials=2, tile_bits=7)
+        E, sig = _run(plan, n, e, J)
+        ref = O.eliminate(n, e, J, None)
+        assert E == ref["energy"]
+        assert O.energy(n, e, J, None, sig) == ref["energy"]
