@@ -44,6 +44,7 @@ struct FOp {
   int32_t hspin;   // star field: spin, -1 none
   uint8_t w[STAR_TERMS];    // star partners (encoded slots)
   int32_t te[STAR_TERMS];   // star edges
+  uint8_t wl[STAR_TERMS];   // partner's index among the stage bits (255: not a stage bit)
 };
 
 // A stage: up to four gate bits applied in registers, each thread owning
@@ -56,6 +57,9 @@ struct DevStage {
   int32_t pad[2];
   uint16_t g_lo[32]; // group index (low / high 5 bits) -> its non-stage tile bits
   uint16_t g_hi[32];
+  uint16_t sg_lo[32]; // the same, LDS-swizzled (the swizzle is linear over GF(2))
+  uint16_t sg_hi[32];
+  uint16_t soff[16];  // swizzled LDS offset of register entry j (stage bits of j)
 };
 
 struct DevPass2 {
@@ -87,6 +91,10 @@ struct ROp {
   uint8_t xw[3];                // further resident partners
   uint8_t sbit;                 // STAR: tile bit of the spin (255: fixed slot, sign folded)
   float xJ[3];
+  uint8_t wl;                   // wf's index among the stage bits (4: not a stage bit)
+  uint8_t sl;                   // STAR: sbit's index among the stage bits (4: not a stage bit)
+  uint8_t xl[3];                // xw's indices among the stage bits (4: not a stage bit)
+  uint8_t pad[3];
 };
 
 // Backward walk: a spin eliminated in a pass (candidate bit k) and the slot it

@@ -21,6 +21,9 @@ namespace {
 
 constexpr int LOW_BITS = 6;   // 64 consecutive floats per run
 
+// LDS swizzle of a tile index (must match the kernel's swz()).
+uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
+
 std::vector<int> gate_slots(const Plan& p, const Pass& ps) {
   std::vector<int> g;
   for (int o = ps.op_begin; o < ps.op_end; ++o) {
@@ -257,11 +260,26 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
         }
         st2.g_lo[x] = lo;
         st2.g_hi[x] = hi;
+        st2.sg_lo[x] = (uint16_t)swz(lo);
+        st2.sg_hi[x] = (uint16_t)swz(hi);
+      }
+      for (int j = 0; j < 16; ++j) {
+        uint32_t sj = 0;
+        for (int l = 0; l < 4; ++l)
+          if ((j >> l) & 1) sj |= 1u << S[l];
+        st2.soff[j] = (uint16_t)swz(sj);
       }
       st2.op_begin = (int)out.fops.size();
       for (size_t k = b0; k < e; ++k) {
         FOp x = f[k];
         if (x.kind != FK_STAR) x.lidx = (uint8_t)(std::find(S.begin(), S.end(), (int)x.bit) - S.begin());
+        for (int q = 0; q < STAR_TERMS; ++q) {
+          x.wl[q] = 255;
+          if (q < x.nt && x.w[q] < SLOT_FIXED) {
+            auto it = std::find(S.begin(), S.end(), (int)x.w[q]);
+            if (it != S.end()) x.wl[q] = (uint8_t)(it - S.begin());
+          }
+        }
         out.fops.push_back(x);
       }
       st2.op_end = (int)out.fops.size();

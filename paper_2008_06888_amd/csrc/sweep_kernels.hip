@@ -64,7 +64,8 @@ constexpr int MAX_PASS_OPS = 256;   // fused ops of one pass held in LDS (the pl
 // Resolves one op of a pass for this instance and tile into its LDS record
 // (see ROp). Fields are written in place: no private arrays.
 template <typename IT>
-__device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, const IT* hrow, uint64_t bs) {
+__device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, const IT* hrow, uint64_t bs,
+                           const uint8_t* sb) {
   float cst = op->hspin >= 0 ? ldv(hrow, op->hspin) : 0.f;
   const uint8_t kind = op->kind;
   const int nt = op->nt;
@@ -76,7 +77,9 @@ __device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, c
   r->lidx = op->lidx;
   r->nx = 0;
   r->sbit = 255;
+  r->sl = 4;
   r->wf = 255;
+  r->wl = 4;
   r->J2 = r->p0 = r->m0 = r->p1 = r->m1 = 0.f;
   float sg = 1.f;
   float J = 0.f;
@@ -85,6 +88,8 @@ __device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, c
       if ((bs >> (op->bit - SLOT_FIXED)) & 1ull) sg = -1.f;
     } else {
       r->sbit = op->bit;
+      for (int l = 0; l < 4; ++l)
+        if (sb[l] == op->bit) r->sl = (uint8_t)l;
     }
     r->p0 = sg * cst;
   } else if (kind == FK_GATE) {
@@ -99,8 +104,10 @@ __device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, c
     const uint8_t w = op->w[k];
     if (w >= SLOT_FIXED) continue;
     const float Jk = ldv(Jrow, op->te[k]);
+    const uint8_t wl = op->wl[k] < 4 ? op->wl[k] : 4;
     if (r->wf == 255) {
       r->wf = w;
+      r->wl = wl;
       if (kind == FK_STAR) {
         r->m0 = sg * Jk;
       } else {
@@ -112,9 +119,35 @@ __device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, c
     } else {
       const int x = r->nx;
       r->xw[x] = w;
+      r->xl[x] = wl;
       r->xJ[x] = kind == FK_STAR ? sg * Jk : Jk;
       r->nx = (uint8_t)(x + 1);
     }
+  }
+}
+
+// Bit (0/1) of register entry J (a compile-time index) for a slot that is
+// stage bit l (< 4) or the non-stage tile bit w (from the group base gb).
+template <int J>
+__device__ __forceinline__ uint32_t rbit(uint32_t l, uint32_t w, uint32_t gb) {
+  return l < 4 ? ((uint32_t)J >> l) & 1u : tbit(gb, w);
+}
+
+// Extra star terms of a gate (rare: more than one resident partner).
+template <int L>
+__device__ __forceinline__ void gate_extra(float (&e0)[8], float (&e1)[8], const ROp& r, uint32_t gb) {
+  for (int k = 0; k < r.nx; ++k) {
+    const uint32_t w = r.xw[k], l = r.xl[k];
+    const float Jk = r.xJ[k];
+#define TT_EXTRA(P)                                                            \
+  {                                                                           \
+    constexpr int j0 = ((P >> L) << (L + 1)) | (P & ((1 << L) - 1));         \
+    const float sk = rbit<j0>(l, w, gb) ? -Jk : Jk;                            \
+    e0[P] += sk;                                                              \
+    e1[P] -= sk;                                                              \
+  }
+    TT_EXTRA(0) TT_EXTRA(1) TT_EXTRA(2) TT_EXTRA(3) TT_EXTRA(4) TT_EXTRA(5) TT_EXTRA(6) TT_EXTRA(7)
+#undef TT_EXTRA
   }
 }
 
@@ -122,52 +155,30 @@ __device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, c
 // star of the entering spin, sw = h + sum_k J_k sigma(partner_k):
 //   new[0] = max(a0 + J, a1 - J) + sw = max(a0, a1 - 2J) + (J + sw)
 //   new[1] = max(a0 - J, a1 + J) - sw = max(a0 - 2J, a1) + (J - sw).
-template <int L>
-__device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16], const ROp& r) {
-  if (r.kind == FK_CUT) {
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-      const int j1 = j0 | (1 << L);
-      const float m = fmaxf(v[j0], v[j1]);
-      v[j0] = m;
-      v[j1] = m;
-    }
-    return;
-  }
+// W < 4: the first partner is stage bit W, so its sign per pair is known at
+// compile time; W == 4: the partner is constant over the group (or absent).
+template <int L, int W>
+__device__ __forceinline__ void gate_lw(float (&v)[16], uint32_t gb, const ROp& r) {
   const float J2 = r.J2;
-  if (r.wf == 255) {
-    const float c0 = r.p0, c1 = r.p1;
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-      const int j1 = j0 | (1 << L);
-      const float a0 = v[j0], a1 = v[j1];
-      v[j0] = fmaxf(a0, a1 - J2) + c0;
-      v[j1] = fmaxf(a0 - J2, a1) + c1;
-    }
-    return;
-  }
   float e0[8], e1[8];
-  const uint32_t wf = r.wf;
+  if (W == 4) {
+    const bool b = r.wf != 255 && tbit(gb, r.wf);
+    const float c0 = b ? r.m0 : r.p0, c1 = b ? r.m1 : r.p1;
 #pragma unroll
-  for (int p = 0; p < 8; ++p) {
-    const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-    const bool b = tbit(ix[j0], wf) != 0u;
-    e0[p] = b ? r.m0 : r.p0;
-    e1[p] = b ? r.m1 : r.p1;
-  }
-  for (int k = 0; k < r.nx; ++k) {
-    const uint32_t w = r.xw[k];
-    const float Jk = r.xJ[k];
+    for (int p = 0; p < 8; ++p) {
+      e0[p] = c0;
+      e1[p] = c1;
+    }
+  } else {
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-      const float sk = tbit(ix[j0], w) ? -Jk : Jk;
-      e0[p] += sk;
-      e1[p] -= sk;
+      const bool b = (j0 >> W) & 1;
+      e0[p] = b ? r.m0 : r.p0;
+      e1[p] = b ? r.m1 : r.p1;
     }
   }
+  if (r.nx) gate_extra<L>(e0, e1, r, gb);
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
     const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
@@ -178,30 +189,41 @@ __device__ __forceinline__ void gate_l(float (&v)[16], const uint32_t (&ix)[16],
   }
 }
 
+template <int L>
+__device__ __forceinline__ void cut_l(float (&v)[16]) {
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+    const int j1 = j0 | (1 << L);
+    const float m = fmaxf(v[j0], v[j1]);
+    v[j0] = m;
+    v[j1] = m;
+  }
+}
+
 // Star of a spin that entered without a gate: x += sigma(spin) * sw.
-__device__ __forceinline__ void star16(float (&v)[16], const uint32_t (&ix)[16], const ROp& r) {
-  float sw[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) sw[j] = r.p0;
-  if (r.wf != 255) {
-    const uint32_t w = r.wf;
-    const float Jk = r.m0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) sw[j] += tbit(ix[j], w) ? -Jk : Jk;
+__device__ __forceinline__ void star16(float (&v)[16], uint32_t gb, const ROp& r) {
+  const uint32_t wl = r.wl, wf = r.wf, sl = r.sl, sbit = r.sbit;
+#define TT_STAR(J)                                                              \
+  {                                                                            \
+    float sw = r.p0;                                                           \
+    if (wf != 255) sw += rbit<J>(wl, wf, gb) ? -r.m0 : r.m0;                   \
+    for (int k = 0; k < r.nx; ++k) sw += rbit<J>(r.xl[k], r.xw[k], gb) ? -r.xJ[k] : r.xJ[k]; \
+    v[J] += (sbit != 255 && rbit<J>(sl, sbit, gb)) ? -sw : sw;                \
   }
-  for (int k = 0; k < r.nx; ++k) {
-    const uint32_t w = r.xw[k];
-    const float Jk = r.xJ[k];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) sw[j] += tbit(ix[j], w) ? -Jk : Jk;
-  }
-  if (r.sbit == 255) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] += sw[j];
-  } else {
-    const uint32_t b = r.sbit;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] += tbit(ix[j], b) ? -sw[j] : sw[j];
+  TT_STAR(0) TT_STAR(1) TT_STAR(2) TT_STAR(3) TT_STAR(4) TT_STAR(5) TT_STAR(6) TT_STAR(7)
+  TT_STAR(8) TT_STAR(9) TT_STAR(10) TT_STAR(11) TT_STAR(12) TT_STAR(13) TT_STAR(14) TT_STAR(15)
+#undef TT_STAR
+}
+
+template <int L>
+__device__ __forceinline__ void gate_dispatch_w(float (&v)[16], uint32_t gb, const ROp& r) {
+  switch (r.wl) {
+    case 0: gate_lw<L, 0>(v, gb, r); break;
+    case 1: gate_lw<L, 1>(v, gb, r); break;
+    case 2: gate_lw<L, 2>(v, gb, r); break;
+    case 3: gate_lw<L, 3>(v, gb, r); break;
+    default: gate_lw<L, 4>(v, gb, r); break;
   }
 }
 
@@ -240,7 +262,12 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   // resolve the pass's ops for this instance and tile
   const int op0 = P.n_stages ? stages[P.stage_begin].op_begin : 0;
   const int n_ops = P.n_stages ? stages[P.stage_begin + P.n_stages - 1].op_end - op0 : 0;
-  for (int o = tid; o < n_ops; o += NT) resolve_op<IT>(fops + op0 + o, rops + o, Jrow, hrow, bs);
+  for (int o = tid; o < n_ops; o += NT) {
+    // the stage of op o (for the stage indices of its bits)
+    int si = 0;
+    while (si + 1 < P.n_stages && stages[P.stage_begin + si + 1].op_begin <= op0 + o) ++si;
+    resolve_op<IT>(fops + op0 + o, rops + o, Jrow, hrow, bs, stages[P.stage_begin + si].sb);
+  }
   // load: enumeration index u = tid + 1024 k; bit q of u -> tile bit / address
   // bit. All loads of a thread are issued before any is consumed.
   {
@@ -269,32 +296,38 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   for (int s = 0; s < n_stages; ++s) {
     const DevStage* __restrict__ ST = stages + P.stage_begin + s;
     const uint32_t groups = size >> 4;
-    const uint32_t m0 = 1u << ST->sb[0], m1 = 1u << ST->sb[1], m2 = 1u << ST->sb[2], m3 = 1u << ST->sb[3];
     const int ob = ST->op_begin - op0, oe = ST->op_end - op0;
+    uint32_t so[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) so[j] = ST->soff[j];
     for (uint32_t g = tid; g < groups; g += NT) {
       const uint32_t gb = (uint32_t)ST->g_lo[g & 31u] | (uint32_t)ST->g_hi[g >> 5];
-      uint32_t ix[16];
+      const uint32_t sg = (uint32_t)ST->sg_lo[g & 31u] ^ (uint32_t)ST->sg_hi[g >> 5];
       float v[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        ix[j] = gb | ((j & 1) ? m0 : 0u) | ((j & 2) ? m1 : 0u) | ((j & 4) ? m2 : 0u) | ((j & 8) ? m3 : 0u);
-        v[j] = tile[swz(ix[j])];
-      }
+      for (int j = 0; j < 16; ++j) v[j] = tile[sg ^ so[j]];
       for (int o = ob; o < oe; ++o) {
         const ROp& r = rops[o];
         if (r.kind == FK_STAR) {
-          star16(v, ix, r);
+          star16(v, gb, r);
+        } else if (r.kind == FK_CUT) {
+          switch (r.lidx) {
+            case 0: cut_l<0>(v); break;
+            case 1: cut_l<1>(v); break;
+            case 2: cut_l<2>(v); break;
+            default: cut_l<3>(v); break;
+          }
         } else {
           switch (r.lidx) {
-            case 0: gate_l<0>(v, ix, r); break;
-            case 1: gate_l<1>(v, ix, r); break;
-            case 2: gate_l<2>(v, ix, r); break;
-            default: gate_l<3>(v, ix, r); break;
+            case 0: gate_dispatch_w<0>(v, gb, r); break;
+            case 1: gate_dispatch_w<1>(v, gb, r); break;
+            case 2: gate_dispatch_w<2>(v, gb, r); break;
+            default: gate_dispatch_w<3>(v, gb, r); break;
           }
         }
       }
 #pragma unroll
-      for (int j = 0; j < 16; ++j) tile[swz(ix[j])] = v[j];
+      for (int j = 0; j < 16; ++j) tile[sg ^ so[j]] = v[j];
     }
     __syncthreads();
   }

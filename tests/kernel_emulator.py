@@ -28,12 +28,14 @@ class DevPass2(C.Structure):
 class DevStage(C.Structure):
     _fields_ = [("sb", C.c_uint8 * 4), ("nns", C.c_uint8), ("ns", C.c_uint8 * 15), ("op_begin", C.c_int32),
                 ("op_end", C.c_int32), ("pad", C.c_int32 * 2), ("g_lo", C.c_uint16 * 32),
-                ("g_hi", C.c_uint16 * 32)]
+                ("g_hi", C.c_uint16 * 32), ("sg_lo", C.c_uint16 * 32), ("sg_hi", C.c_uint16 * 32),
+                ("soff", C.c_uint16 * 16)]
 
 
 class FOp(C.Structure):
     _fields_ = [("kind", C.c_uint8), ("bit", C.c_uint8), ("lidx", C.c_uint8), ("nt", C.c_uint8),
-                ("edge", C.c_int32), ("hspin", C.c_int32), ("w", C.c_uint8 * 4), ("te", C.c_int32 * 4)]
+                ("edge", C.c_int32), ("hspin", C.c_int32), ("w", C.c_uint8 * 4), ("te", C.c_int32 * 4),
+                ("wl", C.c_uint8 * 4)]
 
 
 class BCand(C.Structure):
@@ -61,6 +63,10 @@ def load_program(plan):
         "terms": _records(plan.program(4), BTerm),
         "final_pos": list(plan.program(5)),
     }
+
+
+def _swz(i):
+    return i ^ ((i >> 5) & 31)
 
 
 def _ebit(enc, i, bs):
@@ -103,6 +109,18 @@ def forward(prog, width, J, h):
             for si in range(P.n_stages):
                 ST = prog["stages"][P.stage_begin + si]
                 sb = [ST.sb[l] for l in range(4)]
+                # encoded tables agree with their definitions
+                for x in range(32):
+                    assert ST.sg_lo[x] == _swz(ST.g_lo[x]) and ST.sg_hi[x] == _swz(ST.g_hi[x])
+                for j in range(16):
+                    assert ST.soff[j] == _swz(sum((1 << sb[l]) for l in range(4) if (j >> l) & 1))
+                for o in range(ST.op_begin, ST.op_end):
+                    op = prog["fops"][o]
+                    for k in range(op.nt):
+                        if op.w[k] < SLOT_FIXED and op.w[k] in sb:
+                            assert op.wl[k] == sb.index(op.w[k])
+                        else:
+                            assert op.wl[k] == 255
                 for g in range((1 << t) >> 4):
                     gb = ST.g_lo[g & 31] | ST.g_hi[g >> 5]
                     ix = [gb | sum((1 << sb[l]) for l in range(4) if (j >> l) & 1) for j in range(16)]
