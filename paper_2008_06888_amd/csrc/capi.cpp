@@ -134,7 +134,7 @@ struct DevCache {
   int device = -1;
   EnergyProgram ep;
   Encoded cen;
-  DevBuf d_passes, d_stages, d_fops, d_cands, d_terms, d_final_pos, d_final_slot, d_edges;
+  DevBuf d_passes, d_stages, d_fops, d_cands, d_terms, d_final_pos, d_final_slot, d_edges, d_chunks;
   DevBuf d_cops;
   DevBuf state, ckpt, arg, part_v, part_i;
   DevBuf cx, cn, cpart;
@@ -236,6 +236,7 @@ int ensure_device(Plan& p, DevCache*& dc) {
   if (int r = upload(dc->d_cands, dc->ep.cands)) return r;
   if (int r = upload(dc->d_terms, dc->ep.terms)) return r;
   if (int r = upload(dc->d_final_pos, dc->ep.final_pos)) return r;
+  if (int r = upload(dc->d_chunks, dc->ep.chunks)) return r;
   if (int r = upload(dc->d_final_slot, p.final_slot_spin)) return r;
   if (int r = upload(dc->d_edges, p.edges)) return r;
   if (int r = upload(dc->d_cops, dc->cen.ops)) return r;
@@ -489,6 +490,8 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
         BwdItem it;
         std::memset(&it, 0, sizeof(it));
         it.passes = static_cast<const DevPass2*>(g.dc->d_passes.p);
+        it.chunks = static_cast<const BChunk*>(g.dc->d_chunks.p);
+        it.n_chunks = (int32_t)g.dc->ep.chunks.size();
         it.cands = static_cast<const BCand*>(g.dc->d_cands.p);
         it.terms = static_cast<const BTerm*>(g.dc->d_terms.p);
         it.J = static_cast<const char*>(g.J) + (size_t)b * g.p->m * esz;

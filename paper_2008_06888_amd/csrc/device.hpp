@@ -104,6 +104,14 @@ struct BCand {
   int32_t start_slot;
 };
 
+// A run of consecutive passes whose backward data fits in LDS at once.
+struct BChunk {
+  int32_t p_lo, p_hi;          // passes p_lo..p_hi (inclusive)
+  int32_t cand_begin, n_cand;  // their candidates (contiguous)
+  int32_t term_begin, n_term;  // their terms (contiguous)
+};
+constexpr int BCH_PASSES = 64, BCH_CANDS = 1024, BCH_TERMS = 2048;
+
 // A term of the pass's energy that involves an eliminated spin:
 // coef * sigma(a) [* sigma(b)], operands = candidate k (< 64) or 64 + slot of
 // the selected output index; b = 255 for a field term.
@@ -141,6 +149,8 @@ struct RedItem {
 // Backward walk of one instance.
 struct BwdItem {
   const DevPass2* passes;
+  const BChunk* chunks;
+  int32_t n_chunks, pad2;
   const BCand* cands;
   const BTerm* terms;
   const void* J;

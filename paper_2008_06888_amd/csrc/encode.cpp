@@ -370,6 +370,29 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
     out.terms.insert(out.terms.end(), cross.begin(), cross.end());
     out.passes.push_back(d);
   }
+  // backward chunks, from the last pass down
+  for (int hi = np - 1; hi >= 0;) {
+    int lo = hi, nc = 0, nt = 0;
+    while (lo >= 0) {
+      const DevPass2& d = out.passes[lo];
+      const int c = d.n_cand, t = d.n_lo + d.n_hi + d.n_cross;
+      if (hi - lo + 1 > BCH_PASSES || nc + c > BCH_CANDS || nt + t > BCH_TERMS) break;
+      nc += c;
+      nt += t;
+      --lo;
+    }
+    ++lo;
+    if (lo > hi) return "internal: a pass's backward data exceeds the LDS chunk";
+    BChunk ch;
+    ch.p_lo = lo;
+    ch.p_hi = hi;
+    ch.cand_begin = out.passes[lo].cand_begin;
+    ch.n_cand = nc;
+    ch.term_begin = out.passes[lo].term_begin;
+    ch.n_term = nt;
+    out.chunks.push_back(ch);
+    hi = lo - 1;
+  }
   return "";
 }
 

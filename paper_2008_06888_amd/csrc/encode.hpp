@@ -15,6 +15,7 @@ struct EnergyProgram {
   std::vector<BCand> cands;
   std::vector<BTerm> terms;
   std::vector<uint8_t> final_pos;   // slot -> address bit of the final state
+  std::vector<BChunk> chunks;       // backward: pass runs staged in LDS together (last run first)
   int max_cand = 0;
 };
 

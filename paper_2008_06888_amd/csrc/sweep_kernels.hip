@@ -446,7 +446,6 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage2(const RedItem* __restrict
 // ---------------------------------------------------------------------------
 
 constexpr int MAX_SPINS = 8192;
-constexpr int MAX_BTERMS = 1024;   // terms of one pass staged in LDS
 
 struct LTerm {      // a backward term with its coefficient resolved
   float c;
@@ -464,60 +463,73 @@ __device__ __forceinline__ float lterm_val(const LTerm& tm, uint32_t a, uint64_t
   return tm.c * s;
 }
 
+// Per-pass backward data held in LDS for a chunk of passes.
+struct LPass {
+  uint64_t surv;
+  int32_t n_cand, n_lo, n_hi, n_cross;
+  int32_t in_w, init, cand_off, term_off;   // offsets inside the chunk
+};
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
+  for (int off = 32; off > 0; off >>= 1) x |= __shfl_xor(x, off, 64);
+  return x;
+}
+
 template <typename IT>
 __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ items) {
   __shared__ int8_t s_sh[MAX_SPINS];
   __shared__ float lut_lo[256], lut_hi[256];
   __shared__ uint64_t ad_lo[256], ad_hi[256];
   __shared__ uint64_t sh_t, sh_base;
-  __shared__ LTerm lt[MAX_BTERMS];
-  __shared__ BCand lc[16];
-  __shared__ uint8_t l_in_pos[64];
+  __shared__ LTerm lt[BCH_TERMS];
+  __shared__ BCand lc[BCH_CANDS];
+  __shared__ LPass lp[BCH_PASSES];
+  __shared__ uint8_t lpos[BCH_PASSES][64];
   const BwdItem& I = items[blockIdx.x];
   const int tid = threadIdx.x;
   const IT* Jrow = static_cast<const IT*>(I.J);
   const IT* hrow = static_cast<const IT*>(I.h);
   const DevPass2* __restrict__ passes = I.passes;
-  const BCand* __restrict__ cands = I.cands;
-  const BTerm* __restrict__ terms = I.terms;
-  const int n_passes = I.n_passes, final_w = I.final_w, n = I.n;
+  const int final_w = I.final_w, n = I.n;
   const int64_t m = I.m;
-  const int32_t* __restrict__ final_slot_spin = I.final_slot_spin;
-  const uint8_t* __restrict__ final_pos = I.final_pos;
-  const int32_t* __restrict__ edges = I.edges;
   for (int v = tid; v < n; v += NT) s_sh[v] = 0;
   __syncthreads();
-  if (tid == 0) {
+  if (tid < 64) {
+    // final state: address -> slot index; spins still in a slot take its bit
     const uint64_t addr = *I.final_addr;
-    uint64_t t = 0;
-    for (int c = 0; c < final_w; ++c) {
-      const uint64_t b = (addr >> final_pos[c]) & 1ull;
-      t |= b << c;
-      const int sp = final_slot_spin[c];
+    uint64_t tb = 0;
+    if (tid < final_w) {
+      const uint64_t b = (addr >> I.final_pos[tid]) & 1ull;
+      tb = b << tid;
+      const int sp = I.final_slot_spin[tid];
       if (sp >= 0) s_sh[sp] = (int8_t)b;
     }
-    sh_t = t;
+    tb = wave_or(tb);
+    if (tid == 0) sh_t = tb;
   }
   __syncthreads();
-  for (int p = n_passes - 1; p >= 0; --p) {
-    const DevPass2* __restrict__ P = passes + p;
-    const int nc = P->n_cand;
-    const uint64_t surv = P->surv_mask;
-    const uint64_t t = sh_t;
-    if (nc == 0) {
-      __syncthreads();
-      if (tid == 0) sh_t = t & surv;
-      __syncthreads();
-      continue;
+  for (int ci = 0; ci < I.n_chunks; ++ci) {
+    const BChunk CH = I.chunks[ci];
+    // stage the chunk: pass fields and layouts, candidates, terms (coefficients resolved)
+    for (int q = tid; q <= CH.p_hi - CH.p_lo; q += NT) {
+      const DevPass2* P = passes + CH.p_lo + q;
+      LPass x;
+      x.surv = P->surv_mask;
+      x.n_cand = P->n_cand;
+      x.n_lo = P->n_lo;
+      x.n_hi = P->n_hi;
+      x.n_cross = P->n_cross;
+      x.in_w = P->in_w;
+      x.init = P->init;
+      x.cand_off = P->cand_begin - CH.cand_begin;
+      x.term_off = P->term_begin - CH.term_begin;
+      lp[q] = x;
     }
-    const int n_lo = P->n_lo, n_hi = P->n_hi, n_cr = P->n_cross;
-    const int nterm = n_lo + n_hi + n_cr;
-    const int in_w = P->in_w;
-    // stage this pass's candidates, terms (coefficients resolved) and input layout
-    if (tid < nc) lc[tid] = cands[P->cand_begin + tid];
-    if (tid < 64) l_in_pos[tid] = P->in_pos[tid];
-    for (int k = tid; k < nterm; k += NT) {
-      const BTerm b = terms[P->term_begin + k];
+    for (int k = tid; k < (CH.p_hi - CH.p_lo + 1) * 64; k += NT)
+      lpos[k >> 6][k & 63] = passes[CH.p_lo + (k >> 6)].in_pos[k & 63];
+    for (int k = tid; k < CH.n_cand; k += NT) lc[k] = I.cands[CH.cand_begin + k];
+    for (int k = tid; k < CH.n_term; k += NT) {
+      const BTerm b = I.terms[CH.term_begin + k];
       LTerm x;
       x.c = b.is_field ? ldv(hrow, b.coef) : ldv(Jrow, b.coef);
       x.a = b.a;
@@ -526,70 +538,90 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       lt[k] = x;
     }
     __syncthreads();
-    const int nlo = nc < 8 ? nc : 8, nhi = nc - nlo;
-    // tables over the low / high halves of the candidate bits
-    for (int a = tid; a < 512; a += NT) {
-      const int hi = a >= 256;
-      const uint32_t x = hi ? (uint32_t)(a - 256) : (uint32_t)a;
-      if (x >= (1u << (hi ? nhi : nlo))) continue;
-      const uint32_t full = hi ? (x << 8) : x;
-      float acc = 0.f;
-      const int tb = hi ? n_lo : 0, te = hi ? n_lo + n_hi : n_lo;
-      for (int k = tb; k < te; ++k) acc += lterm_val(lt[k], full, t);
-      uint64_t ad = 0;
-      const int kb = hi ? 8 : 0, ke = hi ? nc : nlo;
-      for (int k = kb; k < ke; ++k) {
-        const int ss = lc[k].start_slot;
-        if (ss >= 0 && l_in_pos[ss] != NO_POS && ((full >> k) & 1u)) ad |= 1ull << l_in_pos[ss];
+    for (int p = CH.p_hi; p >= CH.p_lo; --p) {
+      const LPass& P = lp[p - CH.p_lo];
+      const uint8_t* ipos = lpos[p - CH.p_lo];
+      const int nc = P.n_cand;
+      const uint64_t surv = P.surv;
+      const uint64_t t = sh_t;
+      if (nc == 0) {
+        __syncthreads();
+        if (tid == 0) sh_t = t & surv;
+        __syncthreads();
+        continue;
       }
-      if (hi) {
-        lut_hi[x] = acc;
-        ad_hi[x] = ad;
-      } else {
-        lut_lo[x] = acc;
-        ad_lo[x] = ad;
+      const BCand* C = lc + P.cand_off;
+      const LTerm* T = lt + P.term_off;
+      const int n_lo = P.n_lo, n_hi = P.n_hi;
+      const int nterm = n_lo + n_hi + P.n_cross;
+      const int nlo = nc < 8 ? nc : 8, nhi = nc - nlo;
+      // tables over the low / high halves of the candidate bits (threads 0..511);
+      // the address of the surviving slots (one wave of threads 512..575)
+      if (tid < 512) {
+        const int hi = tid >= 256;
+        const uint32_t x = hi ? (uint32_t)(tid - 256) : (uint32_t)tid;
+        if (x < (1u << (hi ? nhi : nlo))) {
+          const uint32_t full = hi ? (x << 8) : x;
+          float acc = 0.f;
+          const int tb = hi ? n_lo : 0, te = hi ? n_lo + n_hi : n_lo;
+          for (int k = tb; k < te; ++k) acc += lterm_val(T[k], full, t);
+          uint64_t ad = 0;
+          const int kb = hi ? 8 : 0, ke = hi ? nc : nlo;
+          for (int k = kb; k < ke; ++k) {
+            const int ss = C[k].start_slot;
+            if (ss >= 0 && ipos[ss] != NO_POS && ((full >> k) & 1u)) ad |= 1ull << ipos[ss];
+          }
+          if (hi) {
+            lut_hi[x] = acc;
+            ad_hi[x] = ad;
+          } else {
+            lut_lo[x] = acc;
+            ad_lo[x] = ad;
+          }
+        }
+      } else if (tid < 576) {
+        const int c = tid - 512;
+        uint64_t b = 0;
+        if (c < P.in_w && ((surv >> c) & 1ull) && ((t >> c) & 1ull)) b = 1ull << ipos[c];
+        b = wave_or(b);
+        if (c == 0) sh_base = b;
       }
-    }
-    if (tid == 0) {
-      uint64_t base = 0;
-      for (int c = 0; c < in_w; ++c)
-        if (((surv >> c) & 1ull) && ((t >> c) & 1ull)) base |= 1ull << l_in_pos[c];
-      sh_base = base;
-    }
-    __syncthreads();
-    const float* src = P->init ? nullptr : I.ckpt[p] + sh_base;
-    VI best{-INFINITY, ~0ull};
-    const uint32_t na = 1u << nc;
-    const int cross_b = n_lo + n_hi;
-    // candidates in batches of 8 per thread: all loads of a batch in flight together
-    for (uint32_t a0 = tid; a0 < na; a0 += 8u * NT) {
-      float x[8];
+      __syncthreads();
+      const float* src = P.init ? nullptr : I.ckpt[p] + sh_base;
+      VI best{-INFINITY, ~0ull};
+      const uint32_t na = 1u << nc;
+      const int cross_b = n_lo + n_hi;
+      // candidates in batches of 8 per thread: all loads of a batch in flight together
+      for (uint32_t a0 = tid; a0 < na; a0 += 8u * NT) {
+        float x[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t a = a0 + (uint32_t)j * NT;
-        x[j] = (src && a < na) ? src[ad_lo[a & 255u] | ad_hi[a >> 8]] : 0.f;
-      }
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t a = a0 + (uint32_t)j * NT;
+          x[j] = (src && a < na) ? src[ad_lo[a & 255u] | ad_hi[a >> 8]] : 0.f;
+        }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t a = a0 + (uint32_t)j * NT;
-        if (a >= na) break;
-        float val = lut_lo[a & 255u] + lut_hi[a >> 8] + x[j];
-        for (int k = cross_b; k < nterm; ++k) val += lterm_val(lt[k], a, t);
-        best = vi_best(best, VI{val, (uint64_t)a});
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t a = a0 + (uint32_t)j * NT;
+          if (a >= na) break;
+          float val = lut_lo[a & 255u] + lut_hi[a >> 8] + x[j];
+          for (int k = cross_b; k < nterm; ++k) val += lterm_val(T[k], a, t);
+          best = vi_best(best, VI{val, (uint64_t)a});
+        }
       }
-    }
-    best = block_best<NT>(best);
-    if (tid == 0) {
-      const uint32_t a = (uint32_t)best.i;
-      uint64_t tin = t & surv;
-      for (int k = 0; k < nc; ++k) {
-        const uint32_t b = (a >> k) & 1u;
-        s_sh[lc[k].spin] = (int8_t)b;
-        if (lc[k].start_slot >= 0) tin |= (uint64_t)b << lc[k].start_slot;
+      best = block_best<NT>(best);
+      if (tid < 64) {
+        const uint32_t a = (uint32_t)best.i;
+        uint64_t b = 0;
+        if (tid < nc) {
+          const uint32_t bit = (a >> tid) & 1u;
+          s_sh[C[tid].spin] = (int8_t)bit;
+          if (C[tid].start_slot >= 0) b = (uint64_t)bit << C[tid].start_slot;
+        }
+        b = wave_or(b);
+        if (tid == 0) sh_t = (t & surv) | b;
       }
-      sh_t = tin;
+      __syncthreads();
     }
-    __syncthreads();
   }
   for (int v = tid; v < n; v += NT) {
     I.sigma[v] = (int8_t)(s_sh[v] ? -1 : 1);
@@ -597,7 +629,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   }
   if (I.dJ) {
     for (int64_t e = tid; e < m; e += NT) {
-      const int a = edges[2 * e], c = edges[2 * e + 1];
+      const int a = I.edges[2 * e], c = I.edges[2 * e + 1];
       I.dJ[e] = (s_sh[a] ^ s_sh[c]) ? 1.f : -1.f;   // -sigma_a sigma_c
     }
   }
