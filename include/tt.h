@@ -151,6 +151,14 @@ int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype,
                        int8_t* sigma, const int64_t* s_off, float* dJ,
                        void* stream);
 
+/* HIP-graph replay of repeated calls (on by default): tt_contract,
+ * tt_backward and tt_contract_uneven calls whose plans, sizes and device
+ * addresses equal those of an earlier call are captured once (on their
+ * second occurrence) and then replayed as one graph launch on an internal
+ * stream, ordered after and before `stream` by events. A replay reads the
+ * current contents of the inputs, so it is equivalent to the eager call. */
+int tt_graphs_enable(int32_t on);
+
 /* Per-kernel timing on the call's stream, for measurement tools: when on,
  * every pass launch is bracketed by HIP events; tt_prof_read returns the
  * summed milliseconds and launch count of the named kernel family

@@ -31,7 +31,7 @@ ORDER_GREEDY, ORDER_GIVEN, ORDER_CHIMERA = 0, 1, 2
 EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy", "tt_contract",
            "tt_backward", "tt_count", "tt_count_moduli", "tt_count_to_decimal", "tt_contract_uneven",
            "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops",
-           "tt_plan_program")
+           "tt_plan_program", "tt_graphs_enable")
 
 
 class PlanOpts(C.Structure):
@@ -63,6 +63,7 @@ _lib.tt_count_moduli.argtypes = [_vp]
 _lib.tt_count_to_decimal.argtypes = [_vp, C.c_char_p, C.c_size_t]
 _lib.tt_contract_uneven.argtypes = [C.c_int32, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_prof_enable.argtypes = [C.c_int32]
+_lib.tt_graphs_enable.argtypes = [C.c_int32]
 _lib.tt_prof_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
 _lib.tt_last_error.restype = C.c_char_p
 
@@ -271,6 +272,11 @@ def contract_uneven(plans: Sequence[Plan], J_list, want_sigma: bool = True):
     sig = [sigma[s_off[i]:s_off[i] + plans[i].n] for i in range(n)]
     dj = [dJ[j_off[i]:j_off[i] + plans[i].m] for i in range(n)]
     return energy, sig, dj
+
+
+def graphs_enable(on: bool = True):
+    """Replay repeated calls as HIP graphs (default on)."""
+    _check(_lib.tt_graphs_enable(1 if on else 0))
 
 
 def prof_enable(on: bool = True):

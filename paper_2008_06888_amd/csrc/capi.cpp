@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -68,6 +69,13 @@ hipEvent_t pool_get() {
   return e;
 }
 
+// Events recorded while a graph is being captured become event-record nodes
+// of that graph; they are registered with the capture instead of drained.
+struct CaptureRec {
+  std::vector<ProfRec> events;
+};
+thread_local CaptureRec* g_capture = nullptr;
+
 struct ProfScope {
   hipStream_t s;
   const char* name;
@@ -75,13 +83,22 @@ struct ProfScope {
   bool on;
   ProfScope(hipStream_t s_, const char* n) : s(s_), name(n), on(g_prof_on) {
     if (!on) return;
-    a = pool_get();
-    b = pool_get();
-    on = a && b && hipEventRecord(a, s) == hipSuccess;
+    if (g_capture) {
+      on = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+    } else {
+      a = pool_get();
+      b = pool_get();
+      on = a && b;
+    }
+    on = on && hipEventRecord(a, s) == hipSuccess;
   }
   ~ProfScope() {
     if (!on) return;
     if (hipEventRecord(b, s) != hipSuccess) return;
+    if (g_capture) {
+      g_capture->events.push_back({name, a, b});
+      return;
+    }
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof_pending.push_back({name, a, b});
   }
@@ -130,8 +147,13 @@ struct DevBuf {
   }
 };
 
+struct GraphEntry;
+
 struct DevCache {
   int device = -1;
+  std::vector<GraphEntry*> graphs;   // captured calls, most recent last
+  std::vector<std::vector<uint64_t>> seen;   // keys met once (captured on the second meeting)
+  ~DevCache();
   EnergyProgram ep;
   Encoded cen;
   DevBuf d_passes, d_stages, d_fops, d_cands, d_terms, d_final_pos, d_final_slot, d_edges, d_chunks;
@@ -396,11 +418,8 @@ int prepare_group(Group& g, bool keep_all) {
   return 0;
 }
 
-// Forward passes (one launch per pass index across groups), the final
-// reduction and, with `backward`, the argmax-routing walk.
-int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStream_t s) {
-  for (Group& g : groups)
-    if (int r = prepare_group(g, backward)) return r;
+// The launch tables of one call and where each launch finds its items.
+struct CallTables {
   Blob blob;
   struct Launch {
     size_t off;
@@ -408,6 +427,13 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
     int64_t n_wg;
   };
   std::vector<Launch> levels;
+  size_t red_off = 0, bwd_off = 0, ckpt_off = 0;
+  int n_red = 0, n_bwd = 0;
+  int64_t chunks = 0;
+  std::vector<size_t> ckpt_first;
+};
+
+void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, CallTables& ct) {
   int max_np = 0;
   for (Group& g : groups) max_np = std::max(max_np, (int)g.dc->ep.passes.size());
   const size_t MAXI = 32;   // items per launch
@@ -416,7 +442,7 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
     int64_t wg = 0;
     auto flush = [&]() {
       if (items.empty()) return;
-      levels.push_back({blob.add(items.data(), items.size()), (int)items.size(), wg});
+      ct.levels.push_back({ct.blob.add(items.data(), items.size()), (int)items.size(), wg});
       items.clear();
       wg = 0;
     };
@@ -447,9 +473,7 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
     }
     flush();
   }
-  // final reduction items
   std::vector<RedItem> red;
-  int64_t chunks = 0;
   for (Group& g : groups) {
     const int fw = g.p->final_w;
     const int lc = reduce_log2_chunks(fw);
@@ -457,93 +481,273 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
     for (int b = 0; b < g.batch; ++b) {
       RedItem r;
       r.st = g.bufs[np] + (int64_t)b * g.strides[np];
-      r.chunk_begin = chunks;
+      r.chunk_begin = ct.chunks;
       r.energy = g.energy ? g.energy + b : nullptr;
       r.arg = g.arg + b;
       r.w = fw;
       r.log2_chunks = lc;
       red.push_back(r);
-      chunks += (int64_t)1 << lc;
+      ct.chunks += (int64_t)1 << lc;
     }
   }
-  const size_t red_off = blob.add(red.data(), red.size());
-  // backward items
+  ct.red_off = ct.blob.add(red.data(), red.size());
+  ct.n_red = (int)red.size();
+  if (!backward) return;
+  std::vector<const float*> ptrs;
+  for (Group& g : groups) {
+    const int np = (int)g.dc->ep.passes.size();
+    for (int b = 0; b < g.batch; ++b) {
+      ct.ckpt_first.push_back(ptrs.size());
+      for (int q = 0; q < np; ++q) ptrs.push_back(g.bufs[q] + (int64_t)b * g.strides[q]);
+    }
+  }
+  ct.ckpt_off = ct.blob.add(ptrs.data(), ptrs.size());
   std::vector<BwdItem> bwd;
-  size_t bwd_off = 0, ckpt_off = 0;
-  std::vector<size_t> ckpt_first;
-  if (backward) {
-    std::vector<const float*> ptrs;
-    std::vector<size_t> ptr_first;
-    for (Group& g : groups) {
-      const int np = (int)g.dc->ep.passes.size();
-      for (int b = 0; b < g.batch; ++b) {
-        ptr_first.push_back(ptrs.size());
-        for (int q = 0; q < np; ++q) ptrs.push_back(g.bufs[q] + (int64_t)b * g.strides[q]);
-      }
+  const size_t esz = dtype == TT_F32 ? sizeof(float) : sizeof(int32_t);
+  for (Group& g : groups) {
+    const int np = (int)g.dc->ep.passes.size();
+    for (int b = 0; b < g.batch; ++b) {
+      BwdItem it;
+      std::memset(&it, 0, sizeof(it));
+      it.passes = static_cast<const DevPass2*>(g.dc->d_passes.p);
+      it.chunks = static_cast<const BChunk*>(g.dc->d_chunks.p);
+      it.n_chunks = (int32_t)g.dc->ep.chunks.size();
+      it.cands = static_cast<const BCand*>(g.dc->d_cands.p);
+      it.terms = static_cast<const BTerm*>(g.dc->d_terms.p);
+      it.J = static_cast<const char*>(g.J) + (size_t)b * g.p->m * esz;
+      it.h = g.h ? static_cast<const char*>(g.h) + (size_t)b * g.p->n * esz : nullptr;
+      it.ckpt = nullptr;   // set once the tables' device address is known
+      it.final_addr = g.arg + b;
+      it.final_pos = static_cast<const uint8_t*>(g.dc->d_final_pos.p);
+      it.final_slot_spin = static_cast<const int32_t*>(g.dc->d_final_slot.p);
+      it.edges = static_cast<const int32_t*>(g.dc->d_edges.p);
+      it.sigma = g.sigma + (size_t)b * g.p->n;
+      it.dJ = g.dJ ? g.dJ + (size_t)b * g.p->m : nullptr;
+      it.dh = g.dh ? g.dh + (size_t)b * g.p->n : nullptr;
+      it.m = g.p->m;
+      it.n_passes = np;
+      it.final_w = g.p->final_w;
+      it.n = g.p->n;
+      bwd.push_back(it);
     }
-    const size_t ptr_off = blob.add(ptrs.data(), ptrs.size());
-    size_t k = 0;
-    const size_t esz = dtype == TT_F32 ? sizeof(float) : sizeof(int32_t);
-    for (Group& g : groups) {
-      const int np = (int)g.dc->ep.passes.size();
-      for (int b = 0; b < g.batch; ++b, ++k) {
-        BwdItem it;
-        std::memset(&it, 0, sizeof(it));
-        it.passes = static_cast<const DevPass2*>(g.dc->d_passes.p);
-        it.chunks = static_cast<const BChunk*>(g.dc->d_chunks.p);
-        it.n_chunks = (int32_t)g.dc->ep.chunks.size();
-        it.cands = static_cast<const BCand*>(g.dc->d_cands.p);
-        it.terms = static_cast<const BTerm*>(g.dc->d_terms.p);
-        it.J = static_cast<const char*>(g.J) + (size_t)b * g.p->m * esz;
-        it.h = g.h ? static_cast<const char*>(g.h) + (size_t)b * g.p->n * esz : nullptr;
-        it.ckpt = nullptr;   // set once the blob's device address is known
-        it.final_addr = g.arg + b;
-        it.final_pos = static_cast<const uint8_t*>(g.dc->d_final_pos.p);
-        it.final_slot_spin = static_cast<const int32_t*>(g.dc->d_final_slot.p);
-        it.edges = static_cast<const int32_t*>(g.dc->d_edges.p);
-        it.sigma = g.sigma + (size_t)b * g.p->n;
-        it.dJ = g.dJ ? g.dJ + (size_t)b * g.p->m : nullptr;
-        it.dh = g.dh ? g.dh + (size_t)b * g.p->n : nullptr;
-        it.m = g.p->m;
-        it.n_passes = np;
-        it.final_w = g.p->final_w;
-        it.n = g.p->n;
-        bwd.push_back(it);
-      }
-    }
-    bwd_off = blob.add(bwd.data(), bwd.size());
-    ckpt_first.swap(ptr_first);
-    ckpt_off = ptr_off;
   }
-  char* host = nullptr;
-  char* dev = nullptr;
-  int slot = 0;
-  if (int r = stage_reserve(blob.bytes.size(), &host, &dev, &slot)) return r;
-  if (backward) {
-    BwdItem* bi = reinterpret_cast<BwdItem*>(blob.bytes.data() + bwd_off);
-    for (size_t k = 0; k < bwd.size(); ++k)
-      bi[k].ckpt = reinterpret_cast<const float* const*>(dev + ckpt_off + ckpt_first[k] * sizeof(float*));
-  }
-  std::memcpy(host, blob.bytes.data(), blob.bytes.size());
-  if (int r = stage_commit(slot, blob.bytes.size(), s)) return r;
-  // reduction partials live in the first group's plan cache
-  DevCache* dc0 = groups[0].dc;
-  if (int r = dc0->part_v.ensure((size_t)chunks * sizeof(float))) return r;
-  if (int r = dc0->part_i.ensure((size_t)chunks * sizeof(uint64_t))) return r;
-  float* pv = static_cast<float*>(dc0->part_v.p);
-  uint64_t* pi = static_cast<uint64_t*>(dc0->part_i.p);
-  for (const Launch& L : levels) {
+  ct.bwd_off = ct.blob.add(bwd.data(), bwd.size());
+  ct.n_bwd = (int)bwd.size();
+}
+
+// Points the backward items at the checkpoint tables once the device address is known.
+void patch_tables(CallTables& ct, char* dev) {
+  if (!ct.n_bwd) return;
+  BwdItem* bi = reinterpret_cast<BwdItem*>(ct.blob.bytes.data() + ct.bwd_off);
+  for (int k = 0; k < ct.n_bwd; ++k)
+    bi[k].ckpt = reinterpret_cast<const float* const*>(dev + ct.ckpt_off + ct.ckpt_first[k] * sizeof(float*));
+}
+
+int enqueue_launches(const CallTables& ct, const char* dev, DevCache* dc0, int32_t dtype, hipStream_t s) {
+  for (const CallTables::Launch& L : ct.levels) {
     ProfScope ps(s, "sweep_pass");
     HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, dtype, s));
   }
   {
     ProfScope ps(s, "final_reduce");
-    HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + red_off), (int)red.size(), chunks, pv, pi, s));
+    HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks,
+                          static_cast<float*>(dc0->part_v.p), static_cast<uint64_t*>(dc0->part_i.p), s));
   }
-  if (backward) {
+  if (ct.n_bwd) {
     ProfScope ps(s, "sweep_backward");
-    HIP_TRY(launch_backward(reinterpret_cast<const BwdItem*>(dev + bwd_off), (int)bwd.size(), dtype, s));
+    HIP_TRY(launch_backward(reinterpret_cast<const BwdItem*>(dev + ct.bwd_off), ct.n_bwd, dtype, s));
   }
+  return 0;
+}
+
+// ----------------------------------------------------------------------------
+// HIP graphs: a call whose pointers repeat is captured once (on its second
+// occurrence) and replayed as one graph launch on an internal stream that is
+// ordered after / before the caller's stream by events. The graph owns its
+// launch tables. With kernel timing on, its event-record nodes are pointed at
+// fresh events before every replay.
+// ----------------------------------------------------------------------------
+bool g_graphs_on = true;
+
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  DevBuf tables;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<std::pair<std::string, std::pair<hipGraphNode_t, hipGraphNode_t>>> prof;
+  std::vector<hipEvent_t> owned;
+  ~GraphEntry() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    for (hipEvent_t e : owned) (void)hipEventDestroy(e);
+  }
+};
+
+DevCache::~DevCache() {
+  for (GraphEntry* g : graphs) delete g;
+}
+
+std::mutex g_is_mu;
+std::map<int, hipStream_t> g_internal;
+
+int internal_stream(hipStream_t* out) {
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  std::lock_guard<std::mutex> g(g_is_mu);
+  auto it = g_internal.find(device);
+  if (it == g_internal.end()) {
+    hipStream_t st = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    it = g_internal.emplace(device, st).first;
+  }
+  *out = it->second;
+  return 0;
+}
+
+uint64_t plan_serial(const Plan* p) { return p->serial; }
+
+std::vector<uint64_t> call_key(const std::vector<Group>& groups, int32_t dtype, bool backward) {
+  std::vector<uint64_t> k = {(uint64_t)dtype, (uint64_t)backward, (uint64_t)g_prof_on, groups.size()};
+  auto P = [&](const void* x) { k.push_back((uint64_t)(uintptr_t)x); };
+  for (const Group& g : groups) {
+    k.push_back(plan_serial(g.p));
+    k.push_back((uint64_t)g.batch);
+    P(g.dc);
+    P(g.J);
+    P(g.h);
+    P(g.energy);
+    P(g.sigma);
+    P(g.dJ);
+    P(g.dh);
+    P(g.bufs.empty() ? nullptr : g.bufs[0]);
+    P(g.bufs.empty() ? nullptr : g.bufs.back());
+    P(g.arg);
+  }
+  P(groups[0].dc->part_v.p);
+  P(groups[0].dc->part_i.p);
+  return k;
+}
+
+int capture(std::vector<Group>& groups, int32_t dtype, CallTables& ct, GraphEntry* e) {
+  hipStream_t is = nullptr;
+  if (int r = internal_stream(&is)) return r;
+  if (int r = e->tables.ensure(ct.blob.bytes.size())) return r;
+  patch_tables(ct, static_cast<char*>(e->tables.p));
+  HIP_TRY(hipMemcpy(e->tables.p, ct.blob.bytes.data(), ct.blob.bytes.size(), hipMemcpyHostToDevice));
+  CaptureRec rec;
+  g_capture = &rec;
+  hipError_t be = hipStreamBeginCapture(is, hipStreamCaptureModeThreadLocal);
+  if (be != hipSuccess) {
+    g_capture = nullptr;
+    return fail(TT_E_DEVICE, "hipStreamBeginCapture failed: %s", hipGetErrorString(be));
+  }
+  const int r = enqueue_launches(ct, static_cast<const char*>(e->tables.p), groups[0].dc, dtype, is);
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(is, &graph);
+  g_capture = nullptr;
+  for (const ProfRec& pr : rec.events) {
+    e->owned.push_back(pr.a);
+    e->owned.push_back(pr.b);
+  }
+  if (r) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return r;
+  }
+  if (ee != hipSuccess) return fail(TT_E_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+  e->graph = graph;
+  HIP_TRY(hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0));
+  HIP_TRY(hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming));
+  if (!rec.events.empty()) {
+    size_t nn = 0;
+    HIP_TRY(hipGraphGetNodes(graph, nullptr, &nn));
+    std::vector<hipGraphNode_t> nodes(nn);
+    HIP_TRY(hipGraphGetNodes(graph, nodes.data(), &nn));
+    std::map<hipEvent_t, hipGraphNode_t> by_event;
+    for (hipGraphNode_t nd : nodes) {
+      hipGraphNodeType ty;
+      HIP_TRY(hipGraphNodeGetType(nd, &ty));
+      if (ty != hipGraphNodeTypeEventRecord) continue;
+      hipEvent_t ev = nullptr;
+      HIP_TRY(hipGraphEventRecordNodeGetEvent(nd, &ev));
+      by_event[ev] = nd;
+    }
+    for (const ProfRec& pr : rec.events) {
+      auto ia = by_event.find(pr.a), ib = by_event.find(pr.b);
+      if (ia == by_event.end() || ib == by_event.end()) return fail(TT_E_DEVICE, "graph lost a timing event");
+      e->prof.push_back({pr.name, {ia->second, ib->second}});
+    }
+  }
+  return 0;
+}
+
+int replay(GraphEntry* e, hipStream_t s) {
+  hipStream_t is = nullptr;
+  if (int r = internal_stream(&is)) return r;
+  HIP_TRY(hipEventRecord(e->ev_in, s));
+  HIP_TRY(hipStreamWaitEvent(is, e->ev_in, 0));
+  if (g_prof_on) {
+    for (auto& pr : e->prof) {
+      hipEvent_t a = pool_get(), b = pool_get();
+      if (!a || !b) return fail(TT_E_DEVICE, "event pool exhausted");
+      HIP_TRY(hipGraphExecEventRecordNodeSetEvent(e->exec, pr.second.first, a));
+      HIP_TRY(hipGraphExecEventRecordNodeSetEvent(e->exec, pr.second.second, b));
+      std::lock_guard<std::mutex> g(g_prof_mu);
+      g_prof_pending.push_back({pr.first, a, b});
+    }
+  }
+  HIP_TRY(hipGraphLaunch(e->exec, is));
+  HIP_TRY(hipEventRecord(e->ev_out, is));
+  HIP_TRY(hipStreamWaitEvent(s, e->ev_out, 0));
+  return 0;
+}
+
+// Forward passes (one launch per pass index across groups), the final
+// reduction and, with `backward`, the argmax-routing walk.
+int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStream_t s) {
+  for (Group& g : groups)
+    if (int r = prepare_group(g, backward)) return r;
+  CallTables ct;
+  build_tables(groups, dtype, backward, ct);
+  DevCache* dc0 = groups[0].dc;
+  if (int r = dc0->part_v.ensure((size_t)ct.chunks * sizeof(float))) return r;
+  if (int r = dc0->part_i.ensure((size_t)ct.chunks * sizeof(uint64_t))) return r;
+  if (g_graphs_on) {
+    const std::vector<uint64_t> key = call_key(groups, dtype, backward);
+    for (size_t i = 0; i < dc0->graphs.size(); ++i) {
+      if (dc0->graphs[i]->key != key) continue;
+      GraphEntry* e = dc0->graphs[i];
+      dc0->graphs.erase(dc0->graphs.begin() + i);
+      dc0->graphs.push_back(e);   // most recently used last
+      return replay(e, s);
+    }
+    auto seen = std::find(dc0->seen.begin(), dc0->seen.end(), key);
+    if (seen != dc0->seen.end()) {
+      dc0->seen.erase(seen);
+      std::unique_ptr<GraphEntry> e(new GraphEntry());
+      e->key = key;
+      if (int r = capture(groups, dtype, ct, e.get())) return r;
+      if (dc0->graphs.size() >= 8) {
+        delete dc0->graphs.front();
+        dc0->graphs.erase(dc0->graphs.begin());
+      }
+      dc0->graphs.push_back(e.release());
+      return replay(dc0->graphs.back(), s);
+    }
+    dc0->seen.push_back(key);
+    if (dc0->seen.size() > 16) dc0->seen.erase(dc0->seen.begin());
+  }
+  char* host = nullptr;
+  char* dev = nullptr;
+  int slot = 0;
+  if (int r = stage_reserve(ct.blob.bytes.size(), &host, &dev, &slot)) return r;
+  patch_tables(ct, dev);
+  std::memcpy(host, ct.blob.bytes.data(), ct.blob.bytes.size());
+  if (int r = stage_commit(slot, ct.blob.bytes.size(), s)) return r;
+  if (int r = enqueue_launches(ct, dev, dc0, dtype, s)) return r;
   return stage_release(slot, s);
 }
 
@@ -572,7 +776,9 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
       if (a < 0 || b >= n_spins || a >= b) return fail(TT_E_INVAL, "edge %lld = (%d, %d) needs 0 <= i < j < n", (long long)k, a, b);
       if (!seen.insert({a, b}).second) return fail(TT_E_INVAL, "duplicate edge (%d, %d)", a, b);
     }
+    static std::atomic<uint64_t> next_serial{1};
     std::unique_ptr<Plan> p(new Plan());
+    p->serial = next_serial.fetch_add(1);
     p->n = n_spins;
     p->m = n_edges;
     p->edges.assign(edges, edges + 2 * n_edges);
@@ -909,6 +1115,11 @@ int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype, con
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
   }
+}
+
+int tt_graphs_enable(int32_t on) {
+  g_graphs_on = on != 0;
+  return TT_OK;
 }
 
 int tt_prof_enable(int32_t on) {

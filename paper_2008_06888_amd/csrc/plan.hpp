@@ -101,6 +101,7 @@ struct Plan {
   double reduce_terms = 0;           // of which the final reduction
   int64_t max_bytes = 0;
   void* dev = nullptr;               // device-side cache (owned, see capi)
+  uint64_t serial = 0;               // unique over the process lifetime (never reused)
 };
 
 // Builds ops from a spin order; returns "" or an error message.

@@ -252,3 +252,44 @@ def test_uneven_matches_per_instance_calls():
         assert E1[0].item() == E[b].item()
         assert torch.equal(s1[0], sig[b]) and torch.equal(dJ1[0], dJ[b])
     del insts
+
+
+def test_graph_replays_match_eager():
+    insts = I.config_instances(1, batch=16, L=8)
+    plan = B.Plan(64, insts[0].edges, order=list(range(64)), has_field=True, tile_bits=7)
+    J, h = dev(stack(insts, "J")), dev(stack(insts, "h"))
+    say("graph replays")
+    B.graphs_enable(False)
+    ref = [t.clone() for t in B.backward(plan, J, h)]
+    B.graphs_enable(True)
+    E = torch.empty(16, dtype=torch.float64, device=DEV)
+    sig = torch.empty(16, 64, dtype=torch.int8, device=DEV)
+    dJ = torch.empty(16, plan.m, dtype=torch.float32, device=DEV)
+    dh = torch.empty(16, 64, dtype=torch.float32, device=DEV)
+    lib = B.lib()
+    import ctypes as C
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for rep in range(6):                       # 1st eager, 2nd captured, then replays
+        E.zero_()
+        sig.zero_()
+        rc = lib.tt_backward(plan.handle, 16, B.TT_F32, C.c_void_p(J.data_ptr()), C.c_void_p(h.data_ptr()),
+                             C.c_void_p(E.data_ptr()), C.c_void_p(sig.data_ptr()), C.c_void_p(dJ.data_ptr()),
+                             C.c_void_p(dh.data_ptr()), st)
+        assert rc == 0
+        x = torch.randn(256, 256, device=DEV) @ torch.randn(256, 256, device=DEV)   # eager work between
+        torch.cuda.synchronize()
+        assert torch.equal(E, ref[0]) and torch.equal(sig, ref[1]) and torch.equal(dJ, ref[2])
+        assert torch.equal(dh, ref[3])
+        del x
+    # a replay reads the current inputs: change J in place and compare to eager
+    J.mul_(-1.0)
+    for rep in range(2):
+        rc = lib.tt_backward(plan.handle, 16, B.TT_F32, C.c_void_p(J.data_ptr()), C.c_void_p(h.data_ptr()),
+                             C.c_void_p(E.data_ptr()), C.c_void_p(sig.data_ptr()), C.c_void_p(dJ.data_ptr()),
+                             C.c_void_p(dh.data_ptr()), st)
+        assert rc == 0
+    torch.cuda.synchronize()
+    B.graphs_enable(False)
+    ref2 = B.backward(plan, J, h)
+    B.graphs_enable(True)
+    assert torch.equal(E, ref2[0]) and torch.equal(sig, ref2[1])
