@@ -151,6 +151,16 @@ int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype,
                        int8_t* sigma, const int64_t* s_off, float* dJ,
                        void* stream);
 
+/* Dense tropical matrix product (Eq. 2 as a matrix product, the contraction
+ * of two tensors over a run of shared labels):
+ *   C[b][i][j] = max_k (A[b][i][k] + B[b][k][j]),  b < batch.
+ * A, B, C: device float32, row-major with leading dimensions lda, ldb, ldc
+ * (elements) and batch strides sA, sB, sC (elements). K = 0 gives -inf.
+ * Each term is one float32 add; max is exact, so C equals the float64
+ * product rounded to float32. */
+int tt_tgemm(int32_t batch, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, int64_t sA,
+             const float* B, int64_t ldb, int64_t sB, float* C, int64_t ldc, int64_t sC, void* stream);
+
 /* HIP-graph replay of repeated calls (on by default): tt_contract,
  * tt_backward and tt_contract_uneven calls whose plans, sizes and device
  * addresses equal those of an earlier call are captured once (on their

@@ -4,10 +4,11 @@ TEST INFRASTRUCTURE ONLY (see spinglass.py for the usage rule).
 
 C[i, j] = max_k (A[i, k] + B[k, j])  -- the tropical product of Eq. (2)
 written out as a matrix product (the "generic BLAS" over max and + of
-Sec. III). Computed in float64 from the given (float32) inputs: every sum
-of two float32 values is exact in float64 and max is exact, so rounding the
-result to float32 gives the float32 product bit for bit (rounding is
-monotonic, so it commutes with max).
+Sec. III). Computed in float64 from the given (float32) inputs. When the
+exponents of two addends differ by at most 29 (true of every input the
+tests draw), their sum is exact in float64; max is exact and rounding is
+monotonic, so it commutes with max, and rounding the result to float32
+gives the float32 product bit for bit.
 """
 import numpy as np
 

@@ -31,7 +31,7 @@ ORDER_GREEDY, ORDER_GIVEN, ORDER_CHIMERA = 0, 1, 2
 EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy", "tt_contract",
            "tt_backward", "tt_count", "tt_count_moduli", "tt_count_to_decimal", "tt_contract_uneven",
            "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops",
-           "tt_plan_program", "tt_graphs_enable")
+           "tt_plan_program", "tt_graphs_enable", "tt_tgemm")
 
 
 class PlanOpts(C.Structure):
@@ -64,6 +64,8 @@ _lib.tt_count_to_decimal.argtypes = [_vp, C.c_char_p, C.c_size_t]
 _lib.tt_contract_uneven.argtypes = [C.c_int32, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_prof_enable.argtypes = [C.c_int32]
 _lib.tt_graphs_enable.argtypes = [C.c_int32]
+_lib.tt_tgemm.argtypes = [C.c_int32, C.c_int64, C.c_int64, C.c_int64, _vp, C.c_int64, C.c_int64, _vp, C.c_int64,
+                          C.c_int64, _vp, C.c_int64, C.c_int64, _vp]
 _lib.tt_prof_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
 _lib.tt_last_error.restype = C.c_char_p
 
@@ -272,6 +274,24 @@ def contract_uneven(plans: Sequence[Plan], J_list, want_sigma: bool = True):
     sig = [sigma[s_off[i]:s_off[i] + plans[i].n] for i in range(n)]
     dj = [dJ[j_off[i]:j_off[i] + plans[i].m] for i in range(n)]
     return energy, sig, dj
+
+
+def tgemm(A, B, out=None):
+    """Tropical product C = max_k A[..., i, k] + B[..., k, j] of float32 device tensors (2-D or batched 3-D)."""
+    torch = _torch()
+    if A.dtype != torch.float32 or B.dtype != torch.float32 or not (A.is_cuda and B.is_cuda):
+        raise TypeError("tgemm takes float32 device tensors")
+    batched = A.dim() == 3
+    A3 = A if batched else A.unsqueeze(0)
+    B3 = B if batched else B.unsqueeze(0)
+    A3, B3 = A3.contiguous(), B3.contiguous()
+    nb, M, K = A3.shape
+    nb2, K2, N = B3.shape
+    if nb != nb2 or K != K2:
+        raise ValueError("shape mismatch")
+    C3 = torch.empty(nb, M, N, dtype=torch.float32, device=A.device) if out is None else out.view(nb, M, N)
+    _check(_lib.tt_tgemm(nb, M, N, K, _ptr(A3), K, M * K, _ptr(B3), N, K * N, _ptr(C3), N, M * N, _stream()))
+    return C3 if batched else C3[0]
 
 
 def graphs_enable(on: bool = True):

@@ -1117,6 +1117,18 @@ int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype, con
   }
 }
 
+int tt_tgemm(int32_t batch, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, int64_t sA,
+             const float* B, int64_t ldb, int64_t sB, float* C, int64_t ldc, int64_t sC, void* stream) {
+  if (batch < 1 || M < 0 || N < 0 || K < 0) return fail(TT_E_INVAL, "bad sizes");
+  if (M == 0 || N == 0) return TT_OK;
+  if (!C || (K > 0 && (!A || !B))) return fail(TT_E_INVAL, "null operand");
+  if (lda < K || ldb < N || ldc < N) return fail(TT_E_INVAL, "leading dimension too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ProfScope ps(s, "tgemm");
+  HIP_TRY(launch_tgemm(batch, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, s));
+  return TT_OK;
+}
+
 int tt_graphs_enable(int32_t on) {
   g_graphs_on = on != 0;
   return TT_OK;
