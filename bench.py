@@ -39,16 +39,68 @@ def cpu_baseline(insts, seconds=15.0):
                       f"with traceback, single thread, {dt:.1f} s"}
 
 
+def bench_tgemm(args):
+    """Dense tropical product C = max_k A + B, float32, square S x S x S."""
+    import torch
+
+    from paper_2008_06888_amd import binding as B
+    S = args.tgemm
+    g = torch.Generator(device="cuda:0").manual_seed(0)
+    A = torch.randn(S, S, device="cuda:0", generator=g)
+    Bm = torch.randn(S, S, device="cuda:0", generator=g)
+    C = torch.empty(S, S, device="cuda:0")
+    for _ in range(args.warmup):
+        B.tgemm(A, Bm, out=C)
+    torch.cuda.synchronize()
+    B.prof_reset()
+    B.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.tgemm(A, Bm, out=C)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    B.prof_enable(False)
+    ms, n = B.prof_read("tgemm")
+    ops = 2.0 * S * S * S        # one add and one max per term
+    achieved = ops * n / (ms * 1e-3) if ms > 0 else 0.0
+    print(json.dumps({"metric": "tropical GEMM max-plus TFLOP/s", "value": ops * args.steps / dt / 1e12,
+                      "unit": "TFLOP/s", "steps": args.steps, "warmup": args.warmup, "dtype": "f32",
+                      "config": {"workload": f"tgemm_{S}x{S}x{S}"},
+                      "roofline": {"kernel": "k_tgemm", "bound": "alu", "achieved": achieved / 1e12,
+                                   "peak": VALU_PEAK_OPS / 1e12, "unit": "TFLOP/s",
+                                   "frac": achieved / VALU_PEAK_OPS, "avg_launch_ms": ms / max(n, 1)}}))
+
+
+def copy_calibration(args):
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale the counters."""
+    import torch
+    n = args.copy_calibration * (1 << 20) // 4
+    src = torch.ones(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(max(args.steps, 1)):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": 4 * n, "launches": max(args.steps, 1)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tgemm", type=int, default=0, metavar="S",
+                    help="instead: time the dense tropical product at M = N = K = S")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="instead: run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.tgemm:
+        return bench_tgemm(args)
+    if args.copy_calibration:
+        return copy_calibration(args)
 
     import numpy as np
     import torch

@@ -99,7 +99,8 @@ int tt_plan_order(const tt_plan* plan, int32_t* order_out);
 void tt_plan_destroy(tt_plan* plan);
 /* The encoded energy program the kernels execute, for host-side checks:
  * which = 0 pass descriptors, 1 stages, 2 fused ops, 3 backward candidates,
- * 4 backward terms, 5 final bit layout. Copies at most cap bytes into out
+ * 4 backward terms, 5 final bit layout, 6 per pass the chimera row whose
+ * chain step follows it (int32, -1 = none). Copies at most cap bytes into out
  * (may be NULL) and returns the total size in bytes (or a negative
  * tt_status). The record layouts are those of the library's device.hpp. */
 int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t cap);

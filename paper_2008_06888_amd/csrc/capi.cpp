@@ -158,6 +158,8 @@ struct DevCache {
   Encoded cen;
   DevBuf d_passes, d_stages, d_fops, d_cands, d_terms, d_final_pos, d_final_slot, d_edges, d_chunks;
   DevBuf d_cops;
+  DevBuf d_chim_rows, d_chim_vert;
+  std::vector<int> chain_after, count_chain_after;   // pass -> chimera row whose chain follows, -1
   DevBuf state, ckpt, arg, part_v, part_i;
   DevBuf cx, cn, cpart;
 };
@@ -262,6 +264,35 @@ int ensure_device(Plan& p, DevCache*& dc) {
   if (int r = upload(dc->d_final_slot, p.final_slot_spin)) return r;
   if (int r = upload(dc->d_edges, p.edges)) return r;
   if (int r = upload(dc->d_cops, dc->cen.ops)) return r;
+  if (p.is_chimera) {
+    if (int r = upload(dc->d_chim_rows, p.chim.row)) return r;
+    if (int r = upload(dc->d_chim_vert, p.chim.vert)) return r;
+    auto after = [&](const std::vector<Pass>& ps, std::vector<int>& out) -> int {
+      out.assign(ps.size(), -1);
+      for (int r = 1; r < p.chim.rows; ++r) {
+        int q = -1;
+        for (size_t k = 0; k < ps.size(); ++k)
+          if (ps[k].op_end == p.chim.row_end_op[r]) q = (int)k;
+        if (q < 0) return fail(TT_E_INVAL, "internal: chimera row %d does not end a pass", r);
+        out[q] = r;
+      }
+      return 0;
+    };
+    if (int r = after(p.passes, dc->chain_after)) return r;
+    if (int r = after(p.count_passes, dc->count_chain_after)) return r;
+    // the chain reads slot s at index bit s: identity order at every row boundary
+    const int w = p.width;
+    for (size_t q = 0; q < dc->ep.passes.size(); ++q) {
+      const DevPass2& P = dc->ep.passes[q];
+      const bool first = q == 0 || dc->chain_after[q - 1] >= 0;
+      const bool last = dc->chain_after[q] >= 0;
+      for (int sl = 0; sl < w; ++sl)
+        if ((first && P.in_pos[sl] != sl) || (last && P.out_pos[sl] != sl))
+          return fail(TT_E_INVAL, "internal: chimera row boundary is not in slot order");
+    }
+    for (int sl = 0; sl < w; ++sl)
+      if (dc->ep.final_pos[sl] != sl) return fail(TT_E_INVAL, "internal: chimera final layout is not in slot order");
+  }
   return 0;
 }
 
@@ -480,6 +511,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
     const int np = (int)g.dc->ep.passes.size();
     for (int b = 0; b < g.batch; ++b) {
       RedItem r;
+      std::memset(&r, 0, sizeof(r));
       r.st = g.bufs[np] + (int64_t)b * g.strides[np];
       r.chunk_begin = ct.chunks;
       r.energy = g.energy ? g.energy + b : nullptr;
@@ -751,6 +783,166 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
   return stage_release(slot, s);
 }
 
+// Chimera plans: row 0's state is written by its chain; every later row
+// runs its relabel passes and then its chain in place; the final maximum
+// selects the last row's groups. With `backward`, the state after every row
+// but the last is kept, and each earlier row's groups are selected (last row
+// first) by a maximum over that stored state with the vertical couplers to
+// the already selected row added; the finish kernel then walks each row's
+// horizontal chain. Launched eagerly (no graph capture).
+int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
+  Plan& p = *g.p;
+  if (int r = ensure_device(p, g.dc)) return r;
+  DevCache* dc = g.dc;
+  const ChimeraInfo& ch = p.chim;
+  const int np = (int)dc->ep.passes.size();
+  const int w = p.width, rows = ch.rows;
+  const int64_t sst = (int64_t)1 << w;
+  const size_t per = ((size_t)g.batch * (size_t)sst * sizeof(float) + 255) & ~size_t(255);
+  const int nck = backward ? rows - 1 : 0;
+  const size_t need = (size_t)(2 + nck) * per;
+  DevBuf& buf = dc->state;
+  if ((int64_t)need > (int64_t)buf.cap && (int64_t)need > budget_bytes(p) + (int64_t)buf.cap)
+    return fail(TT_E_TOOBIG, "plan needs %lld bytes of device state (budget %lld)", (long long)need,
+                (long long)budget_bytes(p));
+  if (int r = buf.ensure(need)) return r;
+  char* base = static_cast<char*>(buf.p);
+  float* work[2] = {reinterpret_cast<float*>(base), reinterpret_cast<float*>(base + per)};
+  auto kept = [&](int r) -> float* {
+    return (backward && r < rows - 1) ? reinterpret_cast<float*>(base + (size_t)(2 + r) * per) : nullptr;
+  };
+  // buffers: bufs[q] = input of pass q; a row's last pass writes the row's kept state
+  g.bufs.assign(np + 1, nullptr);
+  g.strides.assign(np + 1, sst);
+  std::vector<float*> row_state(rows, nullptr);
+  float* cur = kept(0) ? kept(0) : work[0];
+  row_state[0] = cur;
+  int q = 0;
+  for (int r = 1; r < rows; ++r) {
+    for (;;) {
+      if (q >= np) return fail(TT_E_INVAL, "internal: chimera passes out of step");
+      const bool last = dc->chain_after[q] == r;
+      float* out = (last && kept(r)) ? kept(r) : (cur == work[0] ? work[1] : work[0]);
+      g.bufs[q] = cur;
+      g.bufs[q + 1] = out;
+      cur = out;
+      ++q;
+      if (last) break;
+    }
+    row_state[r] = cur;
+  }
+  g.bufs[np] = cur;
+  if (int r = dc->arg.ensure((size_t)rows * g.batch * sizeof(uint64_t))) return r;
+  uint64_t* args = static_cast<uint64_t*>(dc->arg.p);   // [rows][batch]
+  g.arg = args + (size_t)(rows - 1) * g.batch;
+  std::vector<Group> gs(1, g);
+  CallTables ct;
+  build_tables(gs, dtype, false, ct);
+  const int lc = reduce_log2_chunks(w);
+  const int64_t row_chunks = (int64_t)g.batch << lc;
+  if (int r = dc->part_v.ensure((size_t)std::max<int64_t>(ct.chunks, row_chunks) * sizeof(float))) return r;
+  if (int r = dc->part_i.ensure((size_t)std::max<int64_t>(ct.chunks, row_chunks) * sizeof(uint64_t))) return r;
+  const ChimeraRow* drows = static_cast<const ChimeraRow*>(dc->d_chim_rows.p);
+  const int lblk = w > 16 ? w - 16 : 0;
+  std::vector<size_t> chain_off(rows);
+  for (int r = 0; r < rows; ++r) {
+    ChainItem ci;
+    std::memset(&ci, 0, sizeof(ci));
+    ci.row = drows + r;
+    ci.J = g.J;
+    ci.h = p.has_field ? g.h : nullptr;
+    ci.jst = p.m;
+    ci.hst = p.n;
+    ci.x = row_state[r];
+    ci.sst = sst;
+    ci.w = w;
+    ci.cols = ch.cols;
+    ci.batch = g.batch;
+    ci.init = r == 0 ? 1 : 0;
+    ci.log2_blocks = lblk;
+    ci.dtype = dtype;
+    chain_off[r] = ct.blob.add(&ci, 1);
+  }
+  std::vector<size_t> walk_off(rows, 0);
+  size_t fin_off = 0;
+  if (backward) {
+    const int32_t* vert = static_cast<const int32_t*>(dc->d_chim_vert.p);
+    for (int r = rows - 1; r >= 1; --r) {
+      std::vector<RedItem> items(g.batch);
+      for (int b = 0; b < g.batch; ++b) {
+        RedItem& it = items[b];
+        std::memset(&it, 0, sizeof(it));
+        it.st = row_state[r - 1] + (int64_t)b * sst;
+        it.chunk_begin = (int64_t)b << lc;
+        it.arg = args + (size_t)(r - 1) * g.batch + b;
+        it.w = w;
+        it.log2_chunks = lc;
+        it.bJ = static_cast<const char*>(g.J) + (size_t)b * p.m * sizeof(float);
+        it.bedge = vert + (size_t)(r - 1) * w;
+        it.bref = args + (size_t)r * g.batch + b;
+        it.bdtype = dtype;
+      }
+      walk_off[r] = ct.blob.add(items.data(), items.size());
+    }
+    ChimFinishItem fi;
+    std::memset(&fi, 0, sizeof(fi));
+    fi.rows = drows;
+    fi.edges = static_cast<const int32_t*>(dc->d_edges.p);
+    fi.args = args;
+    fi.J = g.J;
+    fi.h = p.has_field ? g.h : nullptr;
+    fi.jst = p.m;
+    fi.hst = p.n;
+    fi.m = p.m;
+    fi.sigma = g.sigma;
+    fi.dJ = g.dJ;
+    fi.dh = g.dh;
+    fi.n = p.n;
+    fi.n_rows = rows;
+    fi.cols = ch.cols;
+    fi.batch = g.batch;
+    fi.dtype = dtype;
+    fin_off = ct.blob.add(&fi, 1);
+  }
+  char* host = nullptr;
+  char* dev = nullptr;
+  int slot = 0;
+  if (int r = stage_reserve(ct.blob.bytes.size(), &host, &dev, &slot)) return r;
+  std::memcpy(host, ct.blob.bytes.data(), ct.blob.bytes.size());
+  if (int r = stage_commit(slot, ct.blob.bytes.size(), s)) return r;
+  const int64_t chain_blocks = (int64_t)g.batch << lblk;
+  auto chain = [&](int r) -> int {
+    ProfScope ps(s, "chain");
+    HIP_TRY(launch_chain(reinterpret_cast<const ChainItem*>(dev + chain_off[r]), chain_blocks, dtype, false, s));
+    return 0;
+  };
+  if (int r = chain(0)) return r;
+  for (int k = 0; k < np; ++k) {
+    const CallTables::Launch& L = ct.levels[k];
+    {
+      ProfScope ps(s, "sweep_pass");
+      HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, dtype, s));
+    }
+    if (dc->chain_after[k] >= 0)
+      if (int r = chain(dc->chain_after[k])) return r;
+  }
+  float* pv = static_cast<float*>(dc->part_v.p);
+  uint64_t* pi = static_cast<uint64_t*>(dc->part_i.p);
+  {
+    ProfScope ps(s, "final_reduce");
+    HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks, pv, pi, s));
+  }
+  if (backward) {
+    for (int r = rows - 1; r >= 1; --r) {
+      ProfScope ps(s, "row_argmax");
+      HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + walk_off[r]), g.batch, row_chunks, pv, pi, s));
+    }
+    ProfScope ps(s, "chimera_finish");
+    HIP_TRY(launch_chim_finish(reinterpret_cast<const ChimFinishItem*>(dev + fin_off), g.batch, dtype, s));
+  }
+  return stage_release(slot, s);
+}
+
 }  // namespace
 
 // ============================================================================
@@ -804,8 +996,18 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
     if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
     if (p->width > 40) return fail(TT_E_TOOBIG, "plan width %d exceeds 40 bits", p->width);
     p->max_dec = 16;
-    p->passes = partition_passes(*p, p->tile_bits, p->max_dec, false, 0);
-    p->count_passes = partition_passes(*p, p->count_tile_bits, 1 << 20, false, 6);
+    if (p->is_chimera) {
+      // two cells (eight relabels) per pass: every pass boundary then keeps
+      // six shared resident slots and the row boundaries the identity order
+      const int per_pass = p->width <= p->tile_bits ? 16 : 8;
+      p->passes = partition_passes(*p, p->tile_bits, per_pass, false, 0);
+      p->count_passes = partition_passes(*p, p->count_tile_bits, 1 << 20, false, 6);
+      for (Pass& q : p->passes) q.init = false;        // row 0 is written by the chain
+      for (Pass& q : p->count_passes) q.init = false;
+    } else {
+      p->passes = partition_passes(*p, p->tile_bits, p->max_dec, false, 0);
+      p->count_passes = partition_passes(*p, p->count_tile_bits, 1 << 20, false, 6);
+    }
     *out = reinterpret_cast<tt_plan*>(p.release());
     return TT_OK;
   } catch (const std::bad_alloc&) {
@@ -869,6 +1071,14 @@ int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t c
   if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
   const void* src = nullptr;
   int64_t bytes = 0;
+  std::vector<int32_t> after;   // chimera: row whose chain follows each pass, -1
+  if (which == 6) {
+    after.assign(p.passes.size(), -1);
+    if (p.is_chimera)
+      for (size_t q = 0; q < p.passes.size(); ++q)
+        for (int r = 1; r < p.chim.rows; ++r)
+          if (p.passes[q].op_end == p.chim.row_end_op[r]) after[q] = r;
+  }
   switch (which) {
     case 0: src = ep.passes.data(); bytes = (int64_t)(ep.passes.size() * sizeof(DevPass2)); break;
     case 1: src = ep.stages.data(); bytes = (int64_t)(ep.stages.size() * sizeof(DevStage)); break;
@@ -876,6 +1086,7 @@ int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t c
     case 3: src = ep.cands.data(); bytes = (int64_t)(ep.cands.size() * sizeof(BCand)); break;
     case 4: src = ep.terms.data(); bytes = (int64_t)(ep.terms.size() * sizeof(BTerm)); break;
     case 5: src = ep.final_pos.data(); bytes = (int64_t)ep.final_pos.size(); break;
+    case 6: src = after.data(); bytes = (int64_t)(after.size() * sizeof(int32_t)); break;
     default: return fail(TT_E_INVAL, "unknown program part %d", which);
   }
   if (out && bytes) std::memcpy(out, src, (size_t)std::min(bytes, cap));
@@ -900,6 +1111,7 @@ int tt_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
     g[0].J = J;
     g[0].h = h;
     g[0].energy = energy;
+    if (g[0].p->is_chimera) return run_chimera(g[0], dtype, false, static_cast<hipStream_t>(stream));
     return run_groups(g, dtype, false, static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
@@ -923,6 +1135,7 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
     g[0].sigma = sigma;
     g[0].dJ = dJ;
     g[0].dh = dh;
+    if (p.is_chimera) return run_chimera(g[0], dtype, true, static_cast<hipStream_t>(stream));
     return run_groups(g, dtype, true, static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
@@ -979,13 +1192,59 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
     uint64_t* nb[2] = {static_cast<uint64_t*>(dc->cn.p),
                        reinterpret_cast<uint64_t*>(static_cast<char*>(dc->cn.p) + (nb2 - 1) * nper)};
     int cur = 0;
-    for (const DevPass& P : dc->cen.passes) {
-      ProfScope ps(s, "count_pass");
-      const int dst = in_place_ok(P) ? cur : (cur ^ 1);
-      HIP_TRY(launch_count_pass(P, static_cast<const DevOp*>(dc->d_cops.p), J, h, p.m, p.n, xb[cur], nb[cur],
-                                xb[dst], nb[dst], sst, batch, s));
-      cur = dst;
+    // chimera: the row chains between the count passes (row 0 writes the state)
+    std::vector<ChainItem> chain_items;
+    char* chain_dev = nullptr;
+    int chain_slot = -1;
+    const int lblk = p.width > 16 ? p.width - 16 : 0;
+    if (p.is_chimera) {
+      if (!all_in_place) return fail(TT_E_INVAL, "internal: chimera count passes must run in place");
+      for (int r = 0; r < p.chim.rows; ++r) {
+        ChainItem ci;
+        std::memset(&ci, 0, sizeof(ci));
+        ci.row = static_cast<const ChimeraRow*>(dc->d_chim_rows.p) + r;
+        ci.J = J;
+        ci.h = p.has_field ? h : nullptr;
+        ci.jst = p.m;
+        ci.hst = p.n;
+        ci.x = xb[0];
+        ci.n = nb[0];
+        ci.sst = sst;
+        ci.w = p.width;
+        ci.cols = p.chim.cols;
+        ci.batch = batch;
+        ci.init = r == 0 ? 1 : 0;
+        ci.log2_blocks = lblk;
+        ci.dtype = TT_I32;
+        chain_items.push_back(ci);
+      }
+      char* host = nullptr;
+      const size_t bytes = chain_items.size() * sizeof(ChainItem);
+      if (int r = stage_reserve(bytes, &host, &chain_dev, &chain_slot)) return r;
+      std::memcpy(host, chain_items.data(), bytes);
+      if (int r = stage_commit(chain_slot, bytes, s)) return r;
     }
+    auto count_chain = [&](int r) -> int {
+      ProfScope ps(s, "count_chain");
+      HIP_TRY(launch_chain(reinterpret_cast<const ChainItem*>(chain_dev) + r, (int64_t)batch << lblk, TT_I32, true, s));
+      return 0;
+    };
+    if (p.is_chimera)
+      if (int r = count_chain(0)) return r;
+    for (size_t qi = 0; qi < dc->cen.passes.size(); ++qi) {
+      const DevPass& P = dc->cen.passes[qi];
+      {
+        ProfScope ps(s, "count_pass");
+        const int dst = in_place_ok(P) ? cur : (cur ^ 1);
+        HIP_TRY(launch_count_pass(P, static_cast<const DevOp*>(dc->d_cops.p), J, h, p.m, p.n, xb[cur], nb[cur],
+                                  xb[dst], nb[dst], sst, batch, s));
+        cur = dst;
+      }
+      if (p.is_chimera && dc->count_chain_after[qi] >= 0)
+        if (int r = count_chain(dc->count_chain_after[qi])) return r;
+    }
+    if (chain_slot >= 0)
+      if (int r = stage_release(chain_slot, s)) return r;
     const int lc = count_reduce_log2_chunks(p.final_w);
     const size_t nparts = (size_t)batch << lc;
     const size_t bytes = nparts * sizeof(float) + nparts * 3 * sizeof(uint64_t) + (size_t)batch * 4 * sizeof(uint64_t) + 64;
@@ -1099,6 +1358,7 @@ int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype, con
       Plan& p = *reinterpret_cast<Plan*>(plans[i]);
       if (p.has_field) return fail(TT_E_INVAL, "uneven batches take no fields");
       if (p.n_regs != 1) return fail(TT_E_INVAL, "multi-register plans are not supported here");
+      if (p.is_chimera) return fail(TT_E_INVAL, "chimera plans are solved with tt_contract / tt_backward");
       for (int k = 0; k < i; ++k)
         if (plans[k] == plans[i]) return fail(TT_E_INVAL, "each instance needs its own plan object");
       Group& g = groups[i];

@@ -2,6 +2,8 @@
 #pragma once
 #include <cstdint>
 
+#include "plan.hpp"
+
 namespace tt {
 
 // Slot operands are encoded as a tile bit (0..31) when the slot is resident
@@ -137,13 +139,49 @@ struct PassItem {
   int32_t batch, xcd_group;
 };
 
-// Final reduction of one instance's state (2^w entries).
+// Final reduction of one instance's state (2^w entries): maximum and its
+// first address. With `bedge` set, entry a scores x[a] + sum over slots s of
+// J[bedge[s]] sigma(a_s) sigma(ref_s), ref = *bref (a chimera row's vertical
+// couplers to the already selected next row).
 struct RedItem {
   const float* st;
   int64_t chunk_begin;   // first partial of the instance
   double* energy;        // may be NULL
   uint64_t* arg;         // may be NULL
   int32_t w, log2_chunks;
+  const void* bJ;        // couplings of the instance (bonus), or NULL
+  const int32_t* bedge;  // [w] edge per slot, -1 = none
+  const uint64_t* bref;  // selected address of the next row
+  int32_t bdtype, pad;
+};
+
+// Chimera row chain (see ChimeraRow): adds (init: writes) to every entry of
+// one row's state the maximum over the row's horizontal groups; with `n` set
+// (counting) multiplies the residues by the number of maximisers.
+struct ChainItem {
+  const ChimeraRow* row;
+  const void* J;         // couplings / fields of the first instance
+  const void* h;         // (NULL without fields)
+  int64_t jst, hst;
+  float* x;              // state of the first instance
+  uint64_t* n;           // residue planes (counting), else NULL
+  int64_t sst;           // entries per instance (2^w)
+  int32_t w, cols, batch, init, log2_blocks, dtype;
+};
+
+// Chimera backward finish: spins of every row from the selected addresses,
+// horizontal groups by a Viterbi walk along each row, then sigma, dE/dJ, dE/dh.
+struct ChimFinishItem {
+  const ChimeraRow* rows;
+  const int32_t* edges;
+  const uint64_t* args;  // [rows][batch] selected address per row
+  const void* J;
+  const void* h;
+  int64_t jst, hst, m;
+  int8_t* sigma;
+  float* dJ;
+  float* dh;
+  int32_t n, n_rows, cols, batch, dtype, pad;
 };
 
 // Backward walk of one instance.

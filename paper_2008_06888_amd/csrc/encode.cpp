@@ -40,10 +40,19 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
   out = EnergyProgram();
   const int np = (int)passes.size();
   const int tmax = p.tile_bits;
+  if (np == 0) {   // nothing to sweep (a one-row chimera plan): identity layout
+    for (int s = 0; s < p.final_w; ++s) out.final_pos.push_back((uint8_t)s);
+    return "";
+  }
   // slot -> spin before every op (replay of the op list)
   std::vector<std::vector<int>> slot_spin_at(p.ops.size() + 1);
   {
     std::vector<int> cur;
+    if (p.is_chimera) {   // the sweep starts from row 0's vertical groups
+      cur.assign(p.width, -1);
+      for (int c = 0; c < p.chim.cols; ++c)
+        for (int k = 0; k < 4; ++k) cur[4 * c + k] = p.chim.row[0].vspin[c][k];
+    }
     for (size_t o = 0; o < p.ops.size(); ++o) {
       slot_spin_at[o] = cur;
       const SweepOp& op = p.ops[o];
@@ -51,6 +60,7 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
         if ((int)cur.size() <= op.slot_a) cur.resize(op.slot_a + 1, -1);
         cur[op.slot_a] = op.new_spin;
       } else if (op.kind == OP_CUT) {
+        if ((int)cur.size() <= op.slot_a) cur.resize(op.slot_a + 1, -1);
         cur[op.slot_a] = -1;
       }
     }
@@ -72,6 +82,8 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
       };
       if (q + 1 < np)
         for (int s : G[q + 1]) add(s);
+      else if (p.is_chimera)   // the final state is stored in slot order
+        for (int s = 0; s < LOW_BITS; ++s) add(s);
       if (q > 0)
         for (int s : G[q - 1]) add(s);
       for (int s = 0; s < ps.w_max; ++s) add(s);
@@ -82,12 +94,20 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
     std::sort(r.begin(), r.end());
     R[q] = r;
   }
-  // layouts at the pass boundaries: pos[b][slot], b = 0..np
+  // layouts at the pass boundaries: pos[b][slot], b = 0..np; a chimera
+  // plan's row boundaries keep slot order (its chain step reads slot s at
+  // index bit s)
+  auto row_boundary = [&](int b) {
+    if (!p.is_chimera) return false;
+    if (b == 0 || b == np) return true;
+    const int e = passes[b - 1].op_end;
+    return std::find(p.chim.row_end_op.begin(), p.chim.row_end_op.end(), e) != p.chim.row_end_op.end();
+  };
   std::vector<std::vector<int>> pos(np + 1);
   for (int b = 0; b <= np; ++b) {
     const int w = b < np ? passes[b].in_w : passes[np - 1].out_w;
     std::vector<int> low;
-    if (b > 0) {
+    if (b > 0 && !row_boundary(b)) {
       for (int s : R[b - 1]) {
         if (s >= w) continue;
         if (b < np && std::find(R[b].begin(), R[b].end(), s) == R[b].end()) continue;

@@ -18,6 +18,10 @@ hipError_t launch_tgemm(int batch, int64_t M, int64_t N, int64_t K, const float*
                         const float* B, int64_t ldb, int64_t sB, float* C, int64_t ldc, int64_t sC,
                         hipStream_t stream);
 
+// chimera row chain (energy or counting) and backward finish
+hipError_t launch_chain(const ChainItem* item, int64_t n_blocks, int dtype, bool count, hipStream_t stream);
+hipError_t launch_chim_finish(const ChimFinishItem* item, int batch, int dtype, hipStream_t stream);
+
 // counting path: state entries (x, n mod p_r), r = 0, 1, 2
 hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h,
                              int64_t jst, int64_t hst, const float* xin, const uint64_t* nin, float* xout,

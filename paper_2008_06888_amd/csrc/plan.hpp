@@ -80,6 +80,29 @@ struct GroupMatrix {
   int32_t n_edges = 0;
 };
 
+// Chimera graph of rows x cols K_{4,4} unit cells (Sec. V): spin
+// 8 (r cols + c) + k of cell (r, c); k < 4 the group coupled vertically,
+// k >= 4 the group coupled horizontally. The sweep state holds the vertical
+// group of every cell of the current row (slot 4 c + k, 16^cols entries).
+// Per row, one-to-one vertical couplers relabel the previous row's group into
+// the current one (GATE ops); then the row's horizontal chain (the intra-cell
+// 16 x 16 matrices and the horizontal couplers, with the horizontal groups
+// maximised out) is added to every entry as a function of the whole state
+// index ("chain" step, a kernel of its own between passes).
+struct ChimeraRow {
+  int32_t intra[8][16];   // edge of (v_k, h_l), index 4 k + l; -1 = no coupler
+  int32_t horz[8][4];     // edge of h_l of cell c and h_l of cell c + 1; -1 = none
+  int32_t vspin[8][4];    // spin of v_k of cell c
+  int32_t hspin[8][4];    // spin of h_l of cell c
+};
+
+struct ChimeraInfo {
+  int32_t rows = 0, cols = 0;
+  std::vector<ChimeraRow> row;        // per row
+  std::vector<int32_t> vert;          // [rows][cols][4] edge to the cell below, -1 = none
+  std::vector<int32_t> row_end_op;    // op index after the last op of row r (row 0: 0)
+};
+
 struct Plan {
   int32_t n = 0;
   int64_t m = 0;
@@ -100,6 +123,9 @@ struct Plan {
   double terms = 0;                  // algorithmic max-plus terms per instance
   double reduce_terms = 0;           // of which the final reduction
   int64_t max_bytes = 0;
+  std::vector<int32_t> breaks;       // op indices where a pass must begin
+  bool is_chimera = false;
+  ChimeraInfo chim;
   void* dev = nullptr;               // device-side cache (owned, see capi)
   uint64_t serial = 0;               // unique over the process lifetime (never reused)
 };
@@ -109,7 +135,7 @@ std::string build_sweep_ops(Plan& p);
 // Greedy order search with restarts.
 std::vector<int32_t> greedy_order(int32_t n, const std::vector<int32_t>& edges, uint64_t seed,
                                   int trials);
-// Chimera row-chain plan (two state registers); returns "" or an error.
+// Chimera row-by-row plan (see ChimeraInfo); returns "" or an error.
 std::string build_chimera_ops(Plan& p, int rows, int cols);
 // Splits ops into passes of at most `t` resident bits and `max_dec` gated
 // slots; `separable` adds the conditions of the one-argmax backward walk.

@@ -310,6 +310,9 @@ std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separ
   std::vector<Pass> out;
   const int n_ops = (int)p.ops.size();
   const int LOW = low;   // lowest slots always resident (consecutive entries per load)
+  std::vector<char> brk(n_ops + 1, 0);
+  for (int b : p.breaks)
+    if (b >= 0 && b <= n_ops) brk[b] = 1;
   int i = 0;
   while (i < n_ops) {
     const int start = i;
@@ -320,7 +323,7 @@ std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separ
     int merge_src = -1;
     while (i < n_ops) {
       const SweepOp& op = p.ops[i];
-      if (op.reg != reg) break;
+      if (op.reg != reg || (i > start && brk[i])) break;
       std::set<int> need2 = need;
       int ndec2 = ndec;
       bool sep_ok = true;
@@ -385,10 +388,93 @@ std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separ
 }
 
 std::string build_chimera_ops(Plan& p, int rows, int cols) {
-  (void)p;
-  (void)rows;
-  (void)cols;
-  return "chimera plans are not available in this build";
+  if (rows < 1 || cols < 1 || rows > 64) return "chimera plans need 1 <= rows <= 64 and cols >= 1";
+  if (cols > 8) return "chimera plans hold at most 8 cells per row (a 2^32-entry state)";
+  if ((int64_t)p.n != 8ll * rows * cols) return "chimera plan: n_spins must be 8 * rows * cols";
+  ChimeraInfo& ch = p.chim;
+  ch.rows = rows;
+  ch.cols = cols;
+  ch.row.assign(rows, ChimeraRow());
+  for (ChimeraRow& R : ch.row) {
+    std::memset(&R, 0xff, sizeof(R));   // -1 everywhere
+  }
+  ch.vert.assign((size_t)rows * cols * 4, -1);
+  auto id = [&](int r, int c, int k) { return 8 * (r * cols + c) + k; };
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c)
+      for (int k = 0; k < 4; ++k) {
+        ch.row[r].vspin[c][k] = id(r, c, k);
+        ch.row[r].hspin[c][k] = id(r, c, 4 + k);
+      }
+  // classify every edge as an intra-cell, vertical or horizontal coupler
+  for (int64_t e = 0; e < p.m; ++e) {
+    const int a = p.edges[2 * e], b = p.edges[2 * e + 1];
+    const int ca = a / 8, cb = b / 8, ka = a % 8, kb = b % 8;
+    const int ra = ca / cols, ma = ca % cols, rb = cb / cols, mb = cb % cols;
+    int32_t* slot = nullptr;
+    if (ca == cb && ka < 4 && kb >= 4) {
+      slot = &ch.row[ra].intra[ma][4 * ka + (kb - 4)];
+    } else if (ka == kb && ka < 4 && mb == ma && rb == ra + 1) {
+      slot = &ch.vert[((size_t)ra * cols + ma) * 4 + ka];
+    } else if (ka == kb && ka >= 4 && rb == ra && mb == ma + 1) {
+      slot = &ch.row[ra].horz[ma][ka - 4];
+    }
+    if (!slot) return "edge (" + std::to_string(a) + ", " + std::to_string(b) + ") is not a chimera coupler";
+    *slot = (int32_t)e;
+  }
+  // ops: per row r >= 1, relabel the vertical group of every cell (one-to-one
+  // couplers; a missing coupler eliminates the old spin and frees the slot)
+  const int w = 4 * cols;
+  p.ops.clear();
+  p.order.clear();
+  ch.row_end_op.assign(rows, 0);
+  for (int r = 0; r < rows; ++r) {
+    for (int c = 0; c < cols; ++c)
+      for (int k = 0; k < 8; ++k) p.order.push_back(id(r, c, k));
+    if (r > 0) {
+      for (int c = 0; c < cols; ++c)
+        for (int k = 0; k < 4; ++k) {
+          const int slot = 4 * c + k;
+          const int e = ch.vert[((size_t)(r - 1) * cols + c) * 4 + k];
+          SweepOp op;
+          op.slot_a = (int16_t)slot;
+          op.old_spin = id(r - 1, c, k);
+          op.live = w;
+          op.w_before = op.w_after = w;
+          if (e >= 0) {
+            op.kind = OP_GATE;
+            op.param = e;
+            op.new_spin = id(r, c, k);
+            p.ops.push_back(op);
+          } else {
+            op.kind = OP_CUT;
+            p.ops.push_back(op);
+            SweepOp in;
+            in.kind = OP_INTRO;
+            in.slot_a = (int16_t)slot;
+            in.new_spin = id(r, c, k);
+            in.live = w;
+            in.w_before = in.w_after = w;
+            p.ops.push_back(in);
+          }
+        }
+    }
+    ch.row_end_op[r] = (int32_t)p.ops.size();
+  }
+  p.breaks.assign(ch.row_end_op.begin(), ch.row_end_op.end());
+  p.is_chimera = true;
+  p.width = w;
+  p.final_w = w;
+  p.final_slot_spin.assign(w, -1);
+  for (int c = 0; c < cols; ++c)
+    for (int k = 0; k < 4; ++k) p.final_slot_spin[4 * c + k] = id(rows - 1, c, k);
+  // algorithmic terms: two per relabelled entry, sixteen per entry for the
+  // chain of every row (one 16-way maximum per entry), one per entry for the
+  // final maximum
+  const double W = std::ldexp(1.0, w);
+  p.reduce_terms = W;
+  p.terms = (double)(rows - 1) * 4 * cols * 2.0 * W + (double)rows * 16.0 * W + W;
+  return "";
 }
 
 }  // namespace tt

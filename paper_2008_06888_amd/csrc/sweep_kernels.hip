@@ -401,17 +401,66 @@ __device__ VI block_best(VI x) {
 
 __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict__ items, int n_items,
                                                        float* __restrict__ pv, uint64_t* __restrict__ pi) {
+  __shared__ float bt[5][256];   // bonus of each index byte (chimera row walk)
   const int64_t wg = blockIdx.x;
   int it = 0;
   while (it + 1 < n_items && wg >= items[it + 1].chunk_begin) ++it;
   const RedItem& I = items[it];
   const uint64_t chunk = (uint64_t)(wg - I.chunk_begin);
   const uint64_t len = 1ull << (I.w - I.log2_chunks);
+  const uint64_t base = chunk * len;
   const float* s = I.st;
+  const bool bonus = I.bedge != nullptr;
+  if (bonus) {
+    const uint64_t ref = *I.bref;
+    for (int j = threadIdx.x; j < 5 * 256; j += NTR) {
+      const int b = j >> 8, v = j & 255;
+      float t = 0.f;
+      for (int q = 0; q < 8; ++q) {
+        const int sl = 8 * b + q;
+        if (sl >= I.w) break;
+        const int e = I.bedge[sl];
+        if (e < 0) continue;
+        const float Jv = I.bdtype == 0 ? static_cast<const float*>(I.bJ)[e]
+                                       : (float)static_cast<const int32_t*>(I.bJ)[e];
+        t += (((ref >> sl) ^ (uint64_t)(v >> q)) & 1ull) ? -Jv : Jv;
+      }
+      bt[b][v] = t;
+    }
+    __syncthreads();
+  }
   VI best{-INFINITY, ~0ull};
-  for (uint64_t k = threadIdx.x; k < len; k += NTR) {
-    const uint64_t idx = chunk * len + k;
-    best = vi_best(best, VI{s[idx], idx});
+  if (len >= 4) {
+    // four consecutive entries per load; ties keep the smaller address
+    const float4* s4 = reinterpret_cast<const float4*>(s + base);
+#pragma unroll 4
+    for (uint64_t k = threadIdx.x; k < len / 4; k += NTR) {
+      const float4 v = s4[k];
+      const uint64_t i0 = base + 4 * k;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+      if (bonus) {
+        const float hi = bt[1][(i0 >> 8) & 255] + bt[2][(i0 >> 16) & 255] + bt[3][(i0 >> 24) & 255] +
+                         bt[4][(i0 >> 32) & 255];
+        const uint32_t lo = (uint32_t)(i0 & 255);
+        a0 = bt[0][lo] + hi;
+        a1 = bt[0][lo + 1] + hi;
+        a2 = bt[0][lo + 2] + hi;
+        a3 = bt[0][lo + 3] + hi;
+      }
+      best = vi_best(best, VI{v.x + a0, i0});
+      best = vi_best(best, VI{v.y + a1, i0 + 1});
+      best = vi_best(best, VI{v.z + a2, i0 + 2});
+      best = vi_best(best, VI{v.w + a3, i0 + 3});
+    }
+  } else {
+    for (uint64_t k = threadIdx.x; k < len; k += NTR) {
+      const uint64_t idx = base + k;
+      float a = 0.f;
+      if (bonus)
+        a = bt[0][idx & 255] + bt[1][(idx >> 8) & 255] + bt[2][(idx >> 16) & 255] + bt[3][(idx >> 24) & 255] +
+            bt[4][(idx >> 32) & 255];
+      best = vi_best(best, VI{s[idx] + a, idx});
+    }
   }
   best = block_best<NTR>(best);
   if (threadIdx.x == 0) {

@@ -62,6 +62,7 @@ def load_program(plan):
         "cands": _records(plan.program(3), BCand),
         "terms": _records(plan.program(4), BTerm),
         "final_pos": list(plan.program(5)),
+        "chain_after": list(np.frombuffer(plan.program(6), dtype=np.int32)),
     }
 
 
@@ -73,11 +74,14 @@ def _ebit(enc, i, bs):
     return (i >> enc) & 1 if enc < SLOT_FIXED else (bs >> (enc - SLOT_FIXED)) & 1
 
 
-def forward(prog, width, J, h):
-    """Runs every pass; returns the list of pass inputs and the final state."""
+def forward(prog, width, J, h, x0=None, after_pass=None):
+    """Runs every pass; returns the list of pass inputs and the final state.
+
+    x0: initial state (default zeros); after_pass(q, state): called on each
+    pass's output state (may modify it in place)."""
     size = 1 << width
-    states = [np.zeros(size)]
-    for P in prog["passes"]:
+    states = [np.zeros(size) if x0 is None else np.array(x0, dtype=np.float64)]
+    for qi, P in enumerate(prog["passes"]):
         src = states[-1]
         dst = np.full(size, np.nan)
         t = P.t
@@ -161,6 +165,8 @@ def forward(prog, width, J, h):
                 ti |= P.st_hti[hi]
                 a |= P.st_had[hi]
                 dst[out_base | a] = tile[ti]
+        if after_pass is not None:
+            after_pass(qi, dst)
         states.append(dst)
     return states
 
