@@ -71,6 +71,112 @@ def bench_tgemm(args):
                                    "frac": achieved / VALU_PEAK_OPS, "avg_launch_ms": ms / max(n, 1)}}))
 
 
+def _timed(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_chimera(args):
+    """Chimera graph of 8 x 8 K_{4,4} cells (512 spins), J = +-1, h = 0: ground-state
+    energy and configuration, and separately the exact degeneracy count."""
+    import numpy as np
+    import torch
+
+    from paper_2008_06888_amd import binding as B
+    from paper_2008_06888_amd import instances as I
+    x = I.config_instances(4)[0]
+    J = torch.tensor(x.J[None], device="cuda:0")
+    plan = B.Plan(512, x.edges, chimera=(8, 8))
+    steps = max(1, min(args.steps, 5))
+    for _ in range(min(args.warmup, 1)):
+        B.backward(plan, J)
+    B.prof_reset()
+    B.prof_enable(True)
+    t_solve = _timed(lambda: B.backward(plan, J), steps)
+    B.prof_enable(False)
+    kern = {k: B.prof_read(k) for k in ("sweep_pass", "chain", "final_reduce", "row_argmax", "chimera_finish")}
+    E, sig, _, _ = B.backward(plan, J)
+    plan.close()
+    cplan = B.Plan(512, x.edges, chimera=(8, 8))
+    t0 = time.perf_counter()
+    Ec, res, g = B.count(cplan, J)
+    t_count = time.perf_counter() - t0
+    cplan.close()
+    print(json.dumps({"metric": "chimera 8x8 ground state (energy + configuration) wall time", "value": t_solve,
+                      "unit": "s", "higher_is_better": False, "steps": steps, "dtype": "f32 (integer-valued)",
+                      "config": {"workload": "chimera8x8_pm1", "spins": 512, "couplers": int(len(x.edges))},
+                      "energy": float(E[0].item()), "count_s": t_count, "count_energy": int(Ec[0]),
+                      "degeneracy": str(g[0]), "entropy_per_spin": float(np.log(g[0]) / 512),
+                      "kernel_ms_per_solve": {k: v[0] / steps for k, v in kern.items()}}))
+
+
+def bench_square32(args):
+    """32 x 32 open square lattice, J = +-1: ground-state energy and exact degeneracy."""
+    import numpy as np
+    import torch
+
+    from paper_2008_06888_amd import binding as B
+    from paper_2008_06888_amd import instances as I
+    x = I.config_instances(2)[0]
+    J = torch.tensor(x.J[None], device="cuda:0")
+    plan = B.Plan(1024, x.edges, order=list(range(1024)))
+    B.count(plan, J)
+    B.prof_reset()
+    B.prof_enable(True)
+    t0 = time.perf_counter()
+    Ec, res, g = B.count(plan, J)
+    dt = time.perf_counter() - t0
+    B.prof_enable(False)
+    kern = {k: B.prof_read(k) for k in ("count_pass", "count_reduce")}
+    t_e = _timed(lambda: B.contract(plan, J), max(1, min(args.steps, 5)))
+    print(json.dumps({"metric": "32x32 +-J ground-state energy and degeneracy wall time", "value": dt, "unit": "s",
+                      "higher_is_better": False, "dtype": "f32 (integer-valued) + 3 x u64 residues",
+                      "config": {"workload": "square32_pm1_count", "spins": 1024},
+                      "energy": int(Ec[0]), "degeneracy": str(g[0]), "entropy_per_spin": float(np.log(g[0]) / 1024),
+                      "energy_only_s": t_e, "kernel_ms": {k: v[0] for k, v in kern.items()}}))
+
+
+def bench_uneven(args):
+    """16 random 3-regular graphs, N = 100 + 20 (i mod 7), J ~ N(0, 1), h = 0, greedy
+    orders, tile sizes autotuned per plan: energy + configuration of all 16 in one
+    call (grouped launches) against one call per instance."""
+    import torch
+
+    from paper_2008_06888_amd import binding as B
+    from paper_2008_06888_amd import instances as I
+    insts = I.config_instances(3)
+    t0 = time.perf_counter()
+    plans = [B.Plan(x.n, x.edges, seed=i) for i, x in enumerate(insts)]
+    t_plan = time.perf_counter() - t0
+    Js = [torch.tensor(x.J, device="cuda:0") for x in insts]
+    t0 = time.perf_counter()
+    tiles = [B.autotune(p, j[None])[0] for p, j in zip(plans, Js)]
+    t_tune = time.perf_counter() - t0
+    steps = max(1, min(args.steps, 3))
+    for _ in range(2):
+        B.contract_uneven(plans, Js)
+        for p, j in zip(plans, Js):
+            B.backward(p, j[None])
+    t_batched = _timed(lambda: B.contract_uneven(plans, Js), steps)
+
+    def one_by_one():
+        for p, j in zip(plans, Js):
+            B.backward(p, j[None])
+    t_single = _timed(one_by_one, steps)
+    widths = [p.info()["width"] for p in plans]
+    print(json.dumps({"metric": "uneven batch ground states (energy + configuration) solves/s",
+                      "value": len(insts) / t_batched, "unit": "solves/s", "higher_is_better": True,
+                      "steps": steps, "dtype": "f32",
+                      "config": {"workload": "reg3_uneven_b16", "n": [x.n for x in insts], "widths": widths},
+                      "one_call_per_instance_solves_s": len(insts) / t_single, "planning_s": t_plan,
+                      "tile_bits": tiles, "autotune_s": t_tune}))
+
+
 def copy_calibration(args):
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale the counters."""
     import torch
@@ -93,6 +199,9 @@ def main():
                     help="instead: time the dense tropical product at M = N = K = S")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead: run a plain device copy of MIB MiB (scale for HBM byte counters)")
+    ap.add_argument("--workload", default="square16_gauss_b64",
+                    choices=["square16_gauss_b64", "chimera8x8_pm1", "square32_pm1_count", "reg3_uneven_b16"],
+                    help="the headline workload (default) or one of the other measured cases")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -101,6 +210,12 @@ def main():
         return bench_tgemm(args)
     if args.copy_calibration:
         return copy_calibration(args)
+    if args.workload == "chimera8x8_pm1":
+        return bench_chimera(args)
+    if args.workload == "square32_pm1_count":
+        return bench_square32(args)
+    if args.workload == "reg3_uneven_b16":
+        return bench_uneven(args)
 
     import numpy as np
     import torch
@@ -166,6 +281,24 @@ def main():
                                "final_reduce": ms_red / args.steps},
         "plan": {"width": info["width"], "passes": info["n_passes"], "terms_per_instance": info["terms"]},
     }
+    # context, outside the timed region: the same shape with J = +-1 (the metric's
+    # name), and the batch solved as 64 one-instance calls
+    extra_steps = max(1, min(args.steps, 10))
+    pm1 = I.config_instances(0, batch=batch, L=L)
+    Jp = torch.tensor(np.stack([x.J for x in pm1]), device=dev)
+    pplan = B.Plan(n, pm1[0].edges, order=list(range(n)))
+    B.backward(pplan, Jp)
+    B.backward(pplan, Jp)
+    t_pm1 = _timed(lambda: B.backward(pplan, Jp), extra_steps)
+    rows = [(J[b:b + 1].contiguous(), h[b:b + 1].contiguous()) for b in range(batch)]
+
+    def one_by_one():
+        for jb, hb in rows:
+            B.backward(plan, jb, hb)
+    one_by_one()
+    one_by_one()
+    t_single = _timed(one_by_one, extra_steps)
+    out["context"] = {"pm1_int32_h0_solves_s": batch / t_pm1, "one_instance_per_call_solves_s": batch / t_single}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts)
     print(json.dumps(out))

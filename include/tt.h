@@ -170,6 +170,17 @@ int tt_tgemm(int32_t batch, int64_t M, int64_t N, int64_t K, const float* A, int
  * current contents of the inputs, so it is equivalent to the eager call. */
 int tt_graphs_enable(int32_t on);
 
+/* Tile-size autotuner (batched execution, tiles chosen per plan): times the
+ * forward contraction (count = 0; tiles of up to 14 bits) or the counting
+ * sweep (count = 1; up to 12 bits) of `batch` instances given as for
+ * tt_contract / tt_count, on `stream`, and keeps the fastest tile size in
+ * the plan for later calls. Candidates: the five sizes below the largest
+ * useful one (min(maximum, state width)), never under 7 bits. Blocks until the timing is done; allocates a small output buffer.
+ * chosen_bits and best_ms (milliseconds per call) may be NULL. Captured
+ * graphs and device buffers of the plan are released. */
+int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, int32_t count,
+                     int32_t* chosen_bits, double* best_ms, void* stream);
+
 /* Per-kernel timing on the call's stream, for measurement tools: when on,
  * every pass launch is bracketed by HIP events; tt_prof_read returns the
  * summed milliseconds and launch count of the named kernel family

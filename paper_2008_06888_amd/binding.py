@@ -31,7 +31,7 @@ ORDER_GREEDY, ORDER_GIVEN, ORDER_CHIMERA = 0, 1, 2
 EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy", "tt_contract",
            "tt_backward", "tt_count", "tt_count_moduli", "tt_count_to_decimal", "tt_contract_uneven",
            "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops",
-           "tt_plan_program", "tt_graphs_enable", "tt_tgemm")
+           "tt_plan_program", "tt_graphs_enable", "tt_tgemm", "tt_plan_autotune")
 
 
 class PlanOpts(C.Structure):
@@ -66,6 +66,7 @@ _lib.tt_prof_enable.argtypes = [C.c_int32]
 _lib.tt_graphs_enable.argtypes = [C.c_int32]
 _lib.tt_tgemm.argtypes = [C.c_int32, C.c_int64, C.c_int64, C.c_int64, _vp, C.c_int64, C.c_int64, _vp, C.c_int64,
                           C.c_int64, _vp, C.c_int64, C.c_int64, _vp]
+_lib.tt_plan_autotune.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, C.c_int32, _vp, _vp, _vp]
 _lib.tt_prof_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
 _lib.tt_last_error.restype = C.c_char_p
 
@@ -292,6 +293,18 @@ def tgemm(A, B, out=None):
     C3 = torch.empty(nb, M, N, dtype=torch.float32, device=A.device) if out is None else out.view(nb, M, N)
     _check(_lib.tt_tgemm(nb, M, N, K, _ptr(A3), K, M * K, _ptr(B3), N, K * N, _ptr(C3), N, M * N, _stream()))
     return C3 if batched else C3[0]
+
+
+def autotune(plan: Plan, J, h=None, count: bool = False):
+    """Times every tile size on these instances and keeps the fastest in the plan; returns (bits, ms per call)."""
+    _check_inputs(plan, J, h)
+    if count and J.dtype != _torch().int32:
+        raise TypeError("counting needs int32 couplings")
+    bits = C.c_int32(0)
+    ms = C.c_double(0.0)
+    _check(_lib.tt_plan_autotune(plan.handle, J.shape[0], _dtype_code(J), _ptr(J), _ptr(h), int(bool(count)),
+                                 C.byref(bits), C.byref(ms), _stream()))
+    return bits.value, ms.value
 
 
 def graphs_enable(on: bool = True):

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -301,6 +302,22 @@ int64_t budget_bytes(const Plan& p) {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return INT64_MAX;
   return (int64_t)(fr / 8 * 7);
+}
+
+// Passes of the energy and counting sweeps at the plan's tile sizes.
+void partition_plan(Plan& p) {
+  if (p.is_chimera) {
+    // two cells (eight relabels) per pass: every pass boundary then keeps
+    // six shared resident slots and the row boundaries the identity order
+    const int per_pass = p.width <= p.tile_bits ? 16 : 8;
+    p.passes = partition_passes(p, p.tile_bits, per_pass, false, 0);
+    p.count_passes = partition_passes(p, p.count_tile_bits, 1 << 20, false, 6);
+    for (Pass& q : p.passes) q.init = false;        // row 0 is written by the chain
+    for (Pass& q : p.count_passes) q.init = false;
+  } else {
+    p.passes = partition_passes(p, p.tile_bits, p.max_dec, false, 0);
+    p.count_passes = partition_passes(p, p.count_tile_bits, 1 << 20, false, 6);
+  }
 }
 
 int check_common(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h) {
@@ -996,18 +1013,7 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
     if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
     if (p->width > 40) return fail(TT_E_TOOBIG, "plan width %d exceeds 40 bits", p->width);
     p->max_dec = 16;
-    if (p->is_chimera) {
-      // two cells (eight relabels) per pass: every pass boundary then keeps
-      // six shared resident slots and the row boundaries the identity order
-      const int per_pass = p->width <= p->tile_bits ? 16 : 8;
-      p->passes = partition_passes(*p, p->tile_bits, per_pass, false, 0);
-      p->count_passes = partition_passes(*p, p->count_tile_bits, 1 << 20, false, 6);
-      for (Pass& q : p->passes) q.init = false;        // row 0 is written by the chain
-      for (Pass& q : p->count_passes) q.init = false;
-    } else {
-      p->passes = partition_passes(*p, p->tile_bits, p->max_dec, false, 0);
-      p->count_passes = partition_passes(*p, p->count_tile_bits, 1 << 20, false, 6);
-    }
+    partition_plan(*p);
     *out = reinterpret_cast<tt_plan*>(p.release());
     return TT_OK;
   } catch (const std::bad_alloc&) {
@@ -1387,6 +1393,60 @@ int tt_tgemm(int32_t batch, int64_t M, int64_t N, int64_t K, const float* A, int
   ProfScope ps(s, "tgemm");
   HIP_TRY(launch_tgemm(batch, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, s));
   return TT_OK;
+}
+
+int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, int32_t count,
+                     int32_t* chosen_bits, double* best_ms, void* stream) {
+  try {
+    if (int r = check_common(plan, batch, count ? TT_I32 : dtype, J, h)) return r;
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int hi = count ? 12 : 14;
+    const int top = std::min(hi, std::max(7, p.width));   // tiles at least as wide as the state are all alike
+    const int lo = std::max(7, top - 4);                   // five candidates at most
+    DevBuf out;
+    if (int r = out.ensure((size_t)batch * 4 * sizeof(double))) return r;
+    std::vector<int64_t> en((size_t)batch);
+    std::vector<uint64_t> res((size_t)batch * 3);
+    const bool graphs = g_graphs_on;
+    g_graphs_on = false;   // timing of eager launches; no capture of discarded plans
+    auto run_once = [&]() -> int {
+      if (count) return tt_count(plan, batch, static_cast<const int32_t*>(J), static_cast<const int32_t*>(h),
+                                 en.data(), res.data(), stream);
+      if (int r = tt_contract(plan, batch, dtype, J, h, static_cast<double*>(out.p), stream)) return r;
+      HIP_TRY(hipStreamSynchronize(s));
+      return 0;
+    };
+    const int keep = count ? p.count_tile_bits : p.tile_bits;
+    int best_t = keep;
+    double best = 1e300;
+    int rc = 0;
+    for (int t = lo; t <= top && rc == 0; ++t) {
+      (count ? p.count_tile_bits : p.tile_bits) = t;
+      delete static_cast<DevCache*>(p.dev);
+      p.dev = nullptr;
+      partition_plan(p);
+      if ((rc = run_once())) break;   // warm-up (encodes and uploads the plan)
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int k = 0; k < 2 && rc == 0; ++k) rc = run_once();
+      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / 2;
+      if (rc == 0 && ms < best) {
+        best = ms;
+        best_t = t;
+      }
+    }
+    g_graphs_on = graphs;
+    (count ? p.count_tile_bits : p.tile_bits) = best_t;
+    delete static_cast<DevCache*>(p.dev);
+    p.dev = nullptr;
+    partition_plan(p);
+    if (rc) return rc;
+    if (chosen_bits) *chosen_bits = best_t;
+    if (best_ms) *best_ms = best;
+    return TT_OK;
+  } catch (...) {
+    return fail(TT_E_INVAL, "unexpected failure");
+  }
 }
 
 int tt_graphs_enable(int32_t on) {

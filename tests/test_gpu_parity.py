@@ -293,3 +293,29 @@ def test_graph_replays_match_eager():
     ref2 = B.backward(plan, J, h)
     B.graphs_enable(True)
     assert torch.equal(E, ref2[0]) and torch.equal(sig, ref2[1])
+
+
+# ----------------------------------------------------------------------------
+# tile-size autotuner: the chosen tiles give the same results
+# ----------------------------------------------------------------------------
+def test_autotune_keeps_results():
+    insts = I.config_instances(1, batch=8, L=10)
+    say("autotune square10 gauss batch 8")
+    plan = B.Plan(100, insts[0].edges, order=list(range(100)), has_field=True)
+    J = dev(np.stack([x.J for x in insts]))
+    h = dev(np.stack([x.h for x in insts]))
+    E0 = B.contract(plan, J, h).cpu().numpy()
+    bits, ms = B.autotune(plan, J, h)
+    assert 7 <= bits <= 14 and ms > 0
+    E1, sig, _, _ = B.backward(plan, J, h)
+    assert np.array_equal(E0, E1.cpu().numpy())
+    say("autotune count reg3 n=24")
+    rng = np.random.default_rng(5)
+    e = I.random_regular(24, 3, rng)
+    Jp = I.pm1(len(e), rng)
+    cplan = B.Plan(24, e, seed=1)
+    Ec0, res0, _ = B.count(cplan, dev(Jp[None]))
+    cbits, _ = B.autotune(cplan, dev(Jp[None]), count=True)
+    assert 7 <= cbits <= 12
+    Ec1, res1, _ = B.count(cplan, dev(Jp[None]))
+    assert Ec0[0] == Ec1[0] and np.array_equal(res0, res1)
