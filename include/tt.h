@@ -182,10 +182,12 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
                      int32_t* chosen_bits, double* best_ms, void* stream);
 
 /* Per-kernel timing on the call's stream, for measurement tools: when on,
- * every pass launch is bracketed by HIP events; tt_prof_read returns the
- * summed milliseconds and launch count of the named kernel family
- * ("sweep_pass", "sweep_backward", "final_reduce", "count_pass") since the
- * last reset. Timing adds no work to the launches themselves. */
+ * every launch is bracketed by HIP events and calls run eagerly (no graph
+ * capture or replay); tt_prof_read returns the summed milliseconds and
+ * launch count of the named kernel family ("sweep_pass", "sweep_backward",
+ * "final_reduce", "count_pass", "count_reduce", "count_chain", "chain",
+ * "row_argmax", "chimera_finish", "tgemm") since the last reset. Timing adds
+ * no work to the launches themselves. */
 int tt_prof_enable(int32_t on);
 int tt_prof_reset(void);
 int tt_prof_read(const char* name, double* total_ms, int64_t* launches);

@@ -12,6 +12,11 @@ import os
 from typing import List, Optional, Sequence
 
 import numpy as np
+# torch first: its HIP and HSA runtime libraries then satisfy the library's
+# dependencies, so the process holds one runtime. Loading the library first
+# would bring in a second HIP/HSA runtime beside torch's, and the second one
+# to initialise finds no device.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtt.so")

@@ -72,11 +72,9 @@ hipEvent_t pool_get() {
 
 // Events recorded while a graph is being captured become event-record nodes
 // of that graph; they are registered with the capture instead of drained.
-struct CaptureRec {
-  std::vector<ProfRec> events;
-};
-thread_local CaptureRec* g_capture = nullptr;
-
+// Kernel timing brackets a launch with two pooled events on its stream.
+// Timed calls always run eagerly (a call is never captured while timing is
+// on), so every bracket times exactly one launch.
 struct ProfScope {
   hipStream_t s;
   const char* name;
@@ -84,22 +82,13 @@ struct ProfScope {
   bool on;
   ProfScope(hipStream_t s_, const char* n) : s(s_), name(n), on(g_prof_on) {
     if (!on) return;
-    if (g_capture) {
-      on = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
-    } else {
-      a = pool_get();
-      b = pool_get();
-      on = a && b;
-    }
-    on = on && hipEventRecord(a, s) == hipSuccess;
+    a = pool_get();
+    b = pool_get();
+    on = a && b && hipEventRecord(a, s) == hipSuccess;
   }
   ~ProfScope() {
     if (!on) return;
     if (hipEventRecord(b, s) != hipSuccess) return;
-    if (g_capture) {
-      g_capture->events.push_back({name, a, b});
-      return;
-    }
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof_pending.push_back({name, a, b});
   }
@@ -473,6 +462,8 @@ struct CallTables {
     size_t off;
     int n;
     int64_t n_wg;
+    int threads;   // the largest tile's thread count among the items
+    size_t lds;    // the largest tile's bytes among the items
   };
   std::vector<Launch> levels;
   size_t red_off = 0, bwd_off = 0, ckpt_off = 0;
@@ -488,16 +479,22 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
   for (int q = 0; q < max_np; ++q) {
     std::vector<PassItem> items;
     int64_t wg = 0;
+    int threads = 64;
+    size_t lds = 0;
     auto flush = [&]() {
       if (items.empty()) return;
-      ct.levels.push_back({ct.blob.add(items.data(), items.size()), (int)items.size(), wg});
+      ct.levels.push_back({ct.blob.add(items.data(), items.size()), (int)items.size(), wg, threads, lds});
       items.clear();
       wg = 0;
+      threads = 64;
+      lds = 0;
     };
     for (Group& g : groups) {
       const EnergyProgram& ep = g.dc->ep;
       if (q >= (int)ep.passes.size()) continue;
       const DevPass2& P = ep.passes[q];
+      threads = std::max(threads, 1 << P.tb);
+      lds = std::max(lds, sizeof(float) << P.t);
       PassItem it;
       std::memset(&it, 0, sizeof(it));
       it.P = static_cast<const DevPass2*>(g.dc->d_passes.p) + q;
@@ -595,7 +592,7 @@ void patch_tables(CallTables& ct, char* dev) {
 int enqueue_launches(const CallTables& ct, const char* dev, DevCache* dc0, int32_t dtype, hipStream_t s) {
   for (const CallTables::Launch& L : ct.levels) {
     ProfScope ps(s, "sweep_pass");
-    HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, dtype, s));
+    HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s));
   }
   {
     ProfScope ps(s, "final_reduce");
@@ -624,14 +621,11 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   DevBuf tables;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  std::vector<std::pair<std::string, std::pair<hipGraphNode_t, hipGraphNode_t>>> prof;
-  std::vector<hipEvent_t> owned;
   ~GraphEntry() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
-    for (hipEvent_t e : owned) (void)hipEventDestroy(e);
   }
 };
 
@@ -659,7 +653,7 @@ int internal_stream(hipStream_t* out) {
 uint64_t plan_serial(const Plan* p) { return p->serial; }
 
 std::vector<uint64_t> call_key(const std::vector<Group>& groups, int32_t dtype, bool backward) {
-  std::vector<uint64_t> k = {(uint64_t)dtype, (uint64_t)backward, (uint64_t)g_prof_on, groups.size()};
+  std::vector<uint64_t> k = {(uint64_t)dtype, (uint64_t)backward, groups.size()};
   auto P = [&](const void* x) { k.push_back((uint64_t)(uintptr_t)x); };
   for (const Group& g : groups) {
     k.push_back(plan_serial(g.p));
@@ -686,21 +680,10 @@ int capture(std::vector<Group>& groups, int32_t dtype, CallTables& ct, GraphEntr
   if (int r = e->tables.ensure(ct.blob.bytes.size())) return r;
   patch_tables(ct, static_cast<char*>(e->tables.p));
   HIP_TRY(hipMemcpy(e->tables.p, ct.blob.bytes.data(), ct.blob.bytes.size(), hipMemcpyHostToDevice));
-  CaptureRec rec;
-  g_capture = &rec;
-  hipError_t be = hipStreamBeginCapture(is, hipStreamCaptureModeThreadLocal);
-  if (be != hipSuccess) {
-    g_capture = nullptr;
-    return fail(TT_E_DEVICE, "hipStreamBeginCapture failed: %s", hipGetErrorString(be));
-  }
+  HIP_TRY(hipStreamBeginCapture(is, hipStreamCaptureModeThreadLocal));
   const int r = enqueue_launches(ct, static_cast<const char*>(e->tables.p), groups[0].dc, dtype, is);
   hipGraph_t graph = nullptr;
   const hipError_t ee = hipStreamEndCapture(is, &graph);
-  g_capture = nullptr;
-  for (const ProfRec& pr : rec.events) {
-    e->owned.push_back(pr.a);
-    e->owned.push_back(pr.b);
-  }
   if (r) {
     if (graph) (void)hipGraphDestroy(graph);
     return r;
@@ -710,26 +693,6 @@ int capture(std::vector<Group>& groups, int32_t dtype, CallTables& ct, GraphEntr
   HIP_TRY(hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0));
   HIP_TRY(hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming));
-  if (!rec.events.empty()) {
-    size_t nn = 0;
-    HIP_TRY(hipGraphGetNodes(graph, nullptr, &nn));
-    std::vector<hipGraphNode_t> nodes(nn);
-    HIP_TRY(hipGraphGetNodes(graph, nodes.data(), &nn));
-    std::map<hipEvent_t, hipGraphNode_t> by_event;
-    for (hipGraphNode_t nd : nodes) {
-      hipGraphNodeType ty;
-      HIP_TRY(hipGraphNodeGetType(nd, &ty));
-      if (ty != hipGraphNodeTypeEventRecord) continue;
-      hipEvent_t ev = nullptr;
-      HIP_TRY(hipGraphEventRecordNodeGetEvent(nd, &ev));
-      by_event[ev] = nd;
-    }
-    for (const ProfRec& pr : rec.events) {
-      auto ia = by_event.find(pr.a), ib = by_event.find(pr.b);
-      if (ia == by_event.end() || ib == by_event.end()) return fail(TT_E_DEVICE, "graph lost a timing event");
-      e->prof.push_back({pr.name, {ia->second, ib->second}});
-    }
-  }
   return 0;
 }
 
@@ -738,16 +701,6 @@ int replay(GraphEntry* e, hipStream_t s) {
   if (int r = internal_stream(&is)) return r;
   HIP_TRY(hipEventRecord(e->ev_in, s));
   HIP_TRY(hipStreamWaitEvent(is, e->ev_in, 0));
-  if (g_prof_on) {
-    for (auto& pr : e->prof) {
-      hipEvent_t a = pool_get(), b = pool_get();
-      if (!a || !b) return fail(TT_E_DEVICE, "event pool exhausted");
-      HIP_TRY(hipGraphExecEventRecordNodeSetEvent(e->exec, pr.second.first, a));
-      HIP_TRY(hipGraphExecEventRecordNodeSetEvent(e->exec, pr.second.second, b));
-      std::lock_guard<std::mutex> g(g_prof_mu);
-      g_prof_pending.push_back({pr.first, a, b});
-    }
-  }
   HIP_TRY(hipGraphLaunch(e->exec, is));
   HIP_TRY(hipEventRecord(e->ev_out, is));
   HIP_TRY(hipStreamWaitEvent(s, e->ev_out, 0));
@@ -764,7 +717,7 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
   DevCache* dc0 = groups[0].dc;
   if (int r = dc0->part_v.ensure((size_t)ct.chunks * sizeof(float))) return r;
   if (int r = dc0->part_i.ensure((size_t)ct.chunks * sizeof(uint64_t))) return r;
-  if (g_graphs_on) {
+  if (g_graphs_on && !g_prof_on) {   // timed calls run eagerly
     const std::vector<uint64_t> key = call_key(groups, dtype, backward);
     for (size_t i = 0; i < dc0->graphs.size(); ++i) {
       if (dc0->graphs[i]->key != key) continue;
@@ -938,7 +891,7 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
     const CallTables::Launch& L = ct.levels[k];
     {
       ProfScope ps(s, "sweep_pass");
-      HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, dtype, s));
+      HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s));
     }
     if (dc->chain_after[k] >= 0)
       if (int r = chain(dc->chain_after[k])) return r;

@@ -79,9 +79,13 @@ struct DevPass2 {
   // bit q of the load (store) enumeration index -> tile-index bit, address bit
   uint16_t ld_bti[16], st_bti[16];
   uint64_t ld_bad[16], st_bad[16];
-  // the same maps for the index bits above 10 (k = u >> 10), all 16 combinations
+  // the same maps for the index bits from tb up (k = u >> tb), all 16 combinations
   uint16_t ld_hti[16], st_hti[16];
   uint64_t ld_had[16], st_had[16];
+  int32_t tb;            // log2 of the threads a tile uses (max(6, t - 4), at most 10)
+  int32_t pad_tb;
+  uint8_t fin[48];       // fre[k] -> input address bit (NO_POS if none)
+  uint8_t fout[48];      // fre[k] -> output address bit (NO_POS if none)
 };
 
 // An op with its constants resolved for one instance and one tile (built in

@@ -149,6 +149,12 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
     std::memset(d.out_pos, NO_POS, sizeof(d.out_pos));
     for (int s = 0; s < ps.in_w; ++s) d.in_pos[s] = (uint8_t)pos[q][s];
     for (int s = 0; s < ps.out_w; ++s) d.out_pos[s] = (uint8_t)pos[q + 1][s];
+    for (int k = 0; k < nf; ++k) {
+      d.fin[k] = d.in_pos[d.fre[k]];
+      d.fout[k] = d.out_pos[d.fre[k]];
+    }
+    // threads per tile: 16 entries each, one wave at least, 1024 at most
+    d.tb = std::min(10, std::max(6, d.t - 4));
     // enumeration orders of the load and the store
     std::vector<int> ld, st, ld_rest, st_rest;
     for (int k = 0; k < d.t; ++k) {
@@ -175,13 +181,13 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
       uint64_t la = 0, sa = 0;
       for (int b = 0; b < 4; ++b) {
         if (!((kk >> b) & 1)) continue;
-        if (10 + b < d.t) {
-          lt |= d.ld_bti[10 + b];
-          la |= d.ld_bad[10 + b];
+        if (d.tb + b < d.t) {
+          lt |= d.ld_bti[d.tb + b];
+          la |= d.ld_bad[d.tb + b];
         }
-        if (10 + b < d.n_st) {
-          stt |= d.st_bti[10 + b];
-          sa |= d.st_bad[10 + b];
+        if (d.tb + b < d.n_st) {
+          stt |= d.st_bti[d.tb + b];
+          sa |= d.st_bad[d.tb + b];
         }
       }
       d.ld_hti[kk] = (uint16_t)lt;

@@ -8,7 +8,9 @@
 
 namespace tt {
 
-hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int dtype, hipStream_t stream);
+// threads: at least 2^tb of every item's pass; lds: at least 4 * 2^t bytes of every item's pass
+hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int threads, size_t lds, int dtype,
+                       hipStream_t stream);
 int reduce_log2_chunks(int w);
 hipError_t launch_reduce(const RedItem* items, int n_items, int64_t n_chunks, float* pv, uint64_t* pi,
                          hipStream_t stream);

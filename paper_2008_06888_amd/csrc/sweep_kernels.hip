@@ -56,6 +56,19 @@ __device__ __forceinline__ bool wg_to_tile(uint64_t b, int log2_tiles, int batch
   return *inst < batch;
 }
 
+// OR over the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
+  for (int off = 32; off > 0; off >>= 1) x |= __shfl_xor(x, off, 64);
+  return x;
+}
+
+// A value every lane of the wave holds, moved to scalar registers.
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Value (0/1) of tile bit w of an entry index.
 __device__ __forceinline__ uint32_t tbit(uint32_t ix, uint32_t w) { return __builtin_amdgcn_ubfe(ix, w, 1); }
 
@@ -126,6 +139,37 @@ __device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, c
   }
 }
 
+// The fields of an op descriptor (read from LDS) that every lane shares,
+// made wave-uniform: they live in scalar registers, so the dispatch on the
+// op's kind and bits is a scalar branch and its coefficients are scalar
+// operands. The rarely used extra partners stay in LDS.
+struct UOp {
+  float J2, p0, m0, p1, m1;
+  uint32_t kind, lidx, wf, nx, sbit, wl, sl;
+};
+
+__device__ __forceinline__ float ufl(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ uint32_t uin(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
+__device__ __forceinline__ UOp uniform_op(const ROp& r) {
+  UOp u;
+  u.J2 = ufl(r.J2);
+  u.p0 = ufl(r.p0);
+  u.m0 = ufl(r.m0);
+  u.p1 = ufl(r.p1);
+  u.m1 = ufl(r.m1);
+  u.kind = uin(r.kind);
+  u.lidx = uin(r.lidx);
+  u.wf = uin(r.wf);
+  u.nx = uin(r.nx);
+  u.sbit = uin(r.sbit);
+  u.wl = uin(r.wl);
+  u.sl = uin(r.sl);
+  return u;
+}
+
 // Bit (0/1) of register entry J (a compile-time index) for a slot that is
 // stage bit l (< 4) or the non-stage tile bit w (from the group base gb).
 template <int J>
@@ -158,12 +202,12 @@ __device__ __forceinline__ void gate_extra(float (&e0)[8], float (&e1)[8], const
 // W < 4: the first partner is stage bit W, so its sign per pair is known at
 // compile time; W == 4: the partner is constant over the group (or absent).
 template <int L, int W>
-__device__ __forceinline__ void gate_lw(float (&v)[16], uint32_t gb, const ROp& r) {
-  const float J2 = r.J2;
+__device__ __forceinline__ void gate_lw(float (&v)[16], uint32_t gb, const UOp& u, const ROp& r) {
+  const float J2 = u.J2;
   float e0[8], e1[8];
   if (W == 4) {
-    const bool b = r.wf != 255 && tbit(gb, r.wf);
-    const float c0 = b ? r.m0 : r.p0, c1 = b ? r.m1 : r.p1;
+    const bool b = u.wf != 255 && tbit(gb, u.wf);
+    const float c0 = b ? u.m0 : u.p0, c1 = b ? u.m1 : u.p1;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       e0[p] = c0;
@@ -174,11 +218,11 @@ __device__ __forceinline__ void gate_lw(float (&v)[16], uint32_t gb, const ROp& 
     for (int p = 0; p < 8; ++p) {
       const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
       const bool b = (j0 >> W) & 1;
-      e0[p] = b ? r.m0 : r.p0;
-      e1[p] = b ? r.m1 : r.p1;
+      e0[p] = b ? u.m0 : u.p0;
+      e1[p] = b ? u.m1 : u.p1;
     }
   }
-  if (r.nx) gate_extra<L>(e0, e1, r, gb);
+  if (u.nx) gate_extra<L>(e0, e1, r, gb);
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
     const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
@@ -202,13 +246,13 @@ __device__ __forceinline__ void cut_l(float (&v)[16]) {
 }
 
 // Star of a spin that entered without a gate: x += sigma(spin) * sw.
-__device__ __forceinline__ void star16(float (&v)[16], uint32_t gb, const ROp& r) {
-  const uint32_t wl = r.wl, wf = r.wf, sl = r.sl, sbit = r.sbit;
+__device__ __forceinline__ void star16(float (&v)[16], uint32_t gb, const UOp& u, const ROp& r) {
+  const uint32_t wl = u.wl, wf = u.wf, sl = u.sl, sbit = u.sbit;
 #define TT_STAR(J)                                                              \
   {                                                                            \
-    float sw = r.p0;                                                           \
-    if (wf != 255) sw += rbit<J>(wl, wf, gb) ? -r.m0 : r.m0;                   \
-    for (int k = 0; k < r.nx; ++k) sw += rbit<J>(r.xl[k], r.xw[k], gb) ? -r.xJ[k] : r.xJ[k]; \
+    float sw = u.p0;                                                           \
+    if (wf != 255) sw += rbit<J>(wl, wf, gb) ? -u.m0 : u.m0;                   \
+    for (uint32_t k = 0; k < u.nx; ++k) sw += rbit<J>(r.xl[k], r.xw[k], gb) ? -r.xJ[k] : r.xJ[k]; \
     v[J] += (sbit != 255 && rbit<J>(sl, sbit, gb)) ? -sw : sw;                \
   }
   TT_STAR(0) TT_STAR(1) TT_STAR(2) TT_STAR(3) TT_STAR(4) TT_STAR(5) TT_STAR(6) TT_STAR(7)
@@ -217,13 +261,13 @@ __device__ __forceinline__ void star16(float (&v)[16], uint32_t gb, const ROp& r
 }
 
 template <int L>
-__device__ __forceinline__ void gate_dispatch_w(float (&v)[16], uint32_t gb, const ROp& r) {
-  switch (r.wl) {
-    case 0: gate_lw<L, 0>(v, gb, r); break;
-    case 1: gate_lw<L, 1>(v, gb, r); break;
-    case 2: gate_lw<L, 2>(v, gb, r); break;
-    case 3: gate_lw<L, 3>(v, gb, r); break;
-    default: gate_lw<L, 4>(v, gb, r); break;
+__device__ __forceinline__ void gate_dispatch_w(float (&v)[16], uint32_t gb, const UOp& u, const ROp& r) {
+  switch (u.wl) {
+    case 0: gate_lw<L, 0>(v, gb, u, r); break;
+    case 1: gate_lw<L, 1>(v, gb, u, r); break;
+    case 2: gate_lw<L, 2>(v, gb, u, r); break;
+    case 3: gate_lw<L, 3>(v, gb, u, r); break;
+    default: gate_lw<L, 4>(v, gb, u, r); break;
   }
 }
 
@@ -243,53 +287,67 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   if (!wg_to_tile((uint64_t)(wg - I.wg_begin), P.n_free, I.batch, I.xcd_group, &inst, &tid_bits)) return;
   const int tid = threadIdx.x;
   const int t = P.t;
+  const int tb = P.tb;              // this tile uses threads 0 .. 2^tb - 1
   const uint32_t size = 1u << t;
-  // fixed (non-resident) slots of this tile, in slot space and in both layouts
-  uint64_t bs = 0, in_base = 0, out_base = 0;
-  bool stored = true;
-  for (int k = 0; k < P.n_free; ++k) {
-    const uint64_t b = (tid_bits >> k) & 1ull;
-    const int slot = P.fre[k];
-    bs |= b << slot;
-    if (P.in_pos[slot] != NO_POS) in_base |= b << P.in_pos[slot];
-    if (P.out_pos[slot] != NO_POS) out_base |= b << P.out_pos[slot];
-    else if (b) stored = false;   // only the copy with a dropped slot at 0 is kept
+  // fixed (non-resident) slots of this tile, in slot space and in both
+  // layouts: lane k of every wave takes tile-id bit k (n_free <= 48), then
+  // an OR across the wave; no serial loop over dependent loads
+  uint64_t bs = 0, in_base = 0, out_base = 0, dropped = 0;
+  {
+    const int lane = tid & 63;
+    if (lane < P.n_free) {
+      const uint64_t b = (tid_bits >> lane) & 1ull;
+      const uint32_t fi = P.fin[lane], fo = P.fout[lane];
+      bs = b << P.fre[lane];
+      in_base = fi != NO_POS ? b << fi : 0ull;
+      out_base = fo != NO_POS ? b << fo : 0ull;
+      dropped = fo == NO_POS ? b : 0ull;
+    }
+    bs = uni64(wave_or(bs));
+    in_base = uni64(wave_or(in_base));
+    out_base = uni64(wave_or(out_base));
+    dropped = uni64(wave_or(dropped));
   }
+  const bool stored = dropped == 0;   // only the copy with dropped slots at 0 is kept
   const IT* Jrow = static_cast<const IT*>(I.J) + inst * I.jst;
   const IT* hrow = I.h ? static_cast<const IT*>(I.h) + inst * I.hst : nullptr;
   const float* in = I.in + inst * I.in_st;
   float* out = I.out + inst * I.out_st;
+  // load: enumeration index u = tid + 2^tb k; bit q of u -> tile bit / address
+  // bit. The tile's global loads are issued first and stay in flight while
+  // the pass's ops are resolved; then they are written to LDS.
+  const int nb_ld = t < tb ? t : tb;
+  const bool loader = tid < (1 << nb_ld);
+  const int nk_ld = 1 << (t - nb_ld);
+  uint32_t ti_ld = 0;
+  float vals[16];
+  {
+    uint64_t ad_lo = 0;
+    for (int q = 0; q < nb_ld; ++q)
+      if ((tid >> q) & 1) {
+        ti_ld |= P.ld_bti[q];
+        ad_lo |= P.ld_bad[q];
+      }
+    const float* src = in + in_base;
+    if (loader) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk_ld) vals[k] = P.init ? 0.f : src[ad_lo | P.ld_had[k]];
+    }
+  }
   // resolve the pass's ops for this instance and tile
   const int op0 = P.n_stages ? stages[P.stage_begin].op_begin : 0;
   const int n_ops = P.n_stages ? stages[P.stage_begin + P.n_stages - 1].op_end - op0 : 0;
-  for (int o = tid; o < n_ops; o += NT) {
+  for (int o = tid; o < n_ops; o += (int)blockDim.x) {
     // the stage of op o (for the stage indices of its bits)
     int si = 0;
     while (si + 1 < P.n_stages && stages[P.stage_begin + si + 1].op_begin <= op0 + o) ++si;
     resolve_op<IT>(fops + op0 + o, rops + o, Jrow, hrow, bs, stages[P.stage_begin + si].sb);
   }
-  // load: enumeration index u = tid + 1024 k; bit q of u -> tile bit / address
-  // bit. All loads of a thread are issued before any is consumed.
-  {
-    uint32_t ti_lo = 0;
-    uint64_t ad_lo = 0;
-    const int nb = t < 10 ? t : 10;
-    for (int q = 0; q < nb; ++q)
-      if ((tid >> q) & 1) {
-        ti_lo |= P.ld_bti[q];
-        ad_lo |= P.ld_bad[q];
-      }
-    const float* src = in + in_base;
-    if (tid < (int)size) {
-      const int nk = t > 10 ? (1 << (t - 10)) : 1;
-      float vals[16];
+  if (loader) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k < nk) vals[k] = P.init ? 0.f : src[ad_lo | P.ld_had[k]];
-#pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k < nk) tile[swz(ti_lo | P.ld_hti[k])] = vals[k];
-    }
+    for (int k = 0; k < 16; ++k)
+      if (k < nk_ld) tile[swz(ti_ld | P.ld_hti[k])] = vals[k];
   }
   __syncthreads();
   const int n_stages = P.n_stages;
@@ -300,7 +358,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
     uint32_t so[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) so[j] = ST->soff[j];
-    for (uint32_t g = tid; g < groups; g += NT) {
+    for (uint32_t g = tid; g < groups; g += 1u << tb) {
       const uint32_t gb = (uint32_t)ST->g_lo[g & 31u] | (uint32_t)ST->g_hi[g >> 5];
       const uint32_t sg = (uint32_t)ST->sg_lo[g & 31u] ^ (uint32_t)ST->sg_hi[g >> 5];
       float v[16];
@@ -308,21 +366,22 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
       for (int j = 0; j < 16; ++j) v[j] = tile[sg ^ so[j]];
       for (int o = ob; o < oe; ++o) {
         const ROp& r = rops[o];
-        if (r.kind == FK_STAR) {
-          star16(v, gb, r);
-        } else if (r.kind == FK_CUT) {
-          switch (r.lidx) {
+        const UOp u = uniform_op(r);
+        if (u.kind == FK_STAR) {
+          star16(v, gb, u, r);
+        } else if (u.kind == FK_CUT) {
+          switch (u.lidx) {
             case 0: cut_l<0>(v); break;
             case 1: cut_l<1>(v); break;
             case 2: cut_l<2>(v); break;
             default: cut_l<3>(v); break;
           }
         } else {
-          switch (r.lidx) {
-            case 0: gate_dispatch_w<0>(v, gb, r); break;
-            case 1: gate_dispatch_w<1>(v, gb, r); break;
-            case 2: gate_dispatch_w<2>(v, gb, r); break;
-            default: gate_dispatch_w<3>(v, gb, r); break;
+          switch (u.lidx) {
+            case 0: gate_dispatch_w<0>(v, gb, u, r); break;
+            case 1: gate_dispatch_w<1>(v, gb, u, r); break;
+            case 2: gate_dispatch_w<2>(v, gb, u, r); break;
+            default: gate_dispatch_w<3>(v, gb, u, r); break;
           }
         }
       }
@@ -337,7 +396,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
     const int ns = P.n_st;
     uint32_t ti_lo = 0;
     uint64_t ad_lo = 0;
-    const int nb = ns < 10 ? ns : 10;
+    const int nb = ns < tb ? ns : tb;
     for (int q = 0; q < nb; ++q)
       if ((tid >> q) & 1) {
         ti_lo |= P.st_bti[q];
@@ -345,7 +404,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
       }
     float* dst = out + out_base;
     if (tid < (1 << nb)) {
-      const int nk = ns > 10 ? (1 << (ns - 10)) : 1;
+      const int nk = 1 << (ns - nb);
       float vals[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k)
@@ -519,10 +578,6 @@ struct LPass {
   int32_t in_w, init, cand_off, term_off;   // offsets inside the chunk
 };
 
-__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
-  for (int off = 32; off > 0; off >>= 1) x |= __shfl_xor(x, off, 64);
-  return x;
-}
 
 template <typename IT>
 __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ items) {
@@ -701,17 +756,17 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
   return e;
 }
 
-hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int dtype, hipStream_t stream) {
-  const size_t lds = 65536;
-  if (n_wg >= (1ll << 31)) return hipErrorInvalidConfiguration;
+hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int threads, size_t lds, int dtype,
+                       hipStream_t stream) {
+  if (n_wg >= (1ll << 31) || threads < 64 || threads > NT || lds > 65536) return hipErrorInvalidConfiguration;
   if (dtype == 0) {
-    hipError_t e = allow_lds(k_pass<float>, lds);
+    hipError_t e = allow_lds(k_pass<float>, 65536);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pass<float>, dim3((uint32_t)n_wg), dim3(NT), lds, stream, items, n_items);
+    hipLaunchKernelGGL(k_pass<float>, dim3((uint32_t)n_wg), dim3(threads), lds, stream, items, n_items);
   } else {
-    hipError_t e = allow_lds(k_pass<int32_t>, lds);
+    hipError_t e = allow_lds(k_pass<int32_t>, 65536);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pass<int32_t>, dim3((uint32_t)n_wg), dim3(NT), lds, stream, items, n_items);
+    hipLaunchKernelGGL(k_pass<int32_t>, dim3((uint32_t)n_wg), dim3(threads), lds, stream, items, n_items);
   }
   return hipGetLastError();
 }

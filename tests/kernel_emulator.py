@@ -22,7 +22,8 @@ class DevPass2(C.Structure):
                 ("out_pos", C.c_uint8 * 64), ("ld_order", C.c_uint8 * 16), ("st_order", C.c_uint8 * 16),
                 ("n_ld", C.c_int32), ("n_st", C.c_int32), ("ld_bti", C.c_uint16 * 16), ("st_bti", C.c_uint16 * 16),
                 ("ld_bad", C.c_uint64 * 16), ("st_bad", C.c_uint64 * 16), ("ld_hti", C.c_uint16 * 16),
-                ("st_hti", C.c_uint16 * 16), ("ld_had", C.c_uint64 * 16), ("st_had", C.c_uint64 * 16)]
+                ("st_hti", C.c_uint16 * 16), ("ld_had", C.c_uint64 * 16), ("st_had", C.c_uint64 * 16),
+                ("tb", C.c_int32), ("pad_tb", C.c_int32), ("fin", C.c_uint8 * 48), ("fout", C.c_uint8 * 48)]
 
 
 class DevStage(C.Structure):
@@ -85,6 +86,10 @@ def forward(prog, width, J, h, x0=None, after_pass=None):
         src = states[-1]
         dst = np.full(size, np.nan)
         t = P.t
+        tb = P.tb
+        assert tb == min(10, max(6, t - 4))
+        for k in range(P.n_free):
+            assert P.fin[k] == P.in_pos[P.fre[k]] and P.fout[k] == P.out_pos[P.fre[k]]
         for tid in range(1 << P.n_free):
             bs = in_base = out_base = 0
             stored = True
@@ -100,9 +105,9 @@ def forward(prog, width, J, h, x0=None, after_pass=None):
                     stored = False
             tile = np.full(1 << t, np.nan)
             for u in range(1 << t):
-                lo, hi = u & 1023, u >> 10
+                lo, hi = u & ((1 << tb) - 1), u >> tb
                 ti = a = 0
-                for k in range(min(t, 10)):
+                for k in range(min(t, tb)):
                     if (lo >> k) & 1:
                         ti |= P.ld_bti[k]
                         a |= P.ld_bad[k]
@@ -156,9 +161,9 @@ def forward(prog, width, J, h, x0=None, after_pass=None):
             if not stored:
                 continue
             for u in range(1 << P.n_st):
-                lo, hi = u & 1023, u >> 10
+                lo, hi = u & ((1 << tb) - 1), u >> tb
                 ti = a = 0
-                for k in range(min(P.n_st, 10)):
+                for k in range(min(P.n_st, tb)):
                     if (lo >> k) & 1:
                         ti |= P.st_bti[k]
                         a |= P.st_bad[k]

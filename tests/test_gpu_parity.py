@@ -295,6 +295,31 @@ def test_graph_replays_match_eager():
     assert torch.equal(E, ref2[0]) and torch.equal(sig, ref2[1])
 
 
+def test_kernel_timing_with_graphs_enabled():
+    """Kernel timing on: repeated calls run eagerly, every launch is timed, results are exact."""
+    insts = I.config_instances(1, batch=8, L=8)
+    plan = B.Plan(64, insts[0].edges, order=list(range(64)), has_field=True, tile_bits=7)
+    J, h = dev(stack(insts, "J")), dev(stack(insts, "h"))
+    say("graph replays with kernel timing")
+    B.graphs_enable(False)
+    ref = [t.clone() for t in B.backward(plan, J, h)]
+    B.graphs_enable(True)
+    B.prof_enable(True)
+    try:
+        B.prof_reset()
+        for rep in range(5):                   # never captured while timing is on
+            out = B.backward(plan, J, h)
+            torch.cuda.synchronize()
+            assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]) and torch.equal(out[2], ref[2])
+        ms, n = B.prof_read("sweep_pass")
+        nb = plan.info()["n_passes"]
+        assert n == 5 * nb and ms > 0
+        msb, nbw = B.prof_read("sweep_backward")
+        assert nbw == 5 and msb > 0
+    finally:
+        B.prof_enable(False)
+
+
 # ----------------------------------------------------------------------------
 # tile-size autotuner: the chosen tiles give the same results
 # ----------------------------------------------------------------------------
@@ -319,3 +344,26 @@ def test_autotune_keeps_results():
     assert 7 <= cbits <= 12
     Ec1, res1, _ = B.count(cplan, dev(Jp[None]))
     assert Ec0[0] == Ec1[0] and np.array_equal(res0, res1)
+
+
+# ----------------------------------------------------------------------------
+# full size: 32 x 32 random +-J (the counting workload) -- properties that
+# hold at any size: forward energy = counting energy, g even (spin flip at
+# h = 0), E* and the residues unchanged by a gauge transform
+# ----------------------------------------------------------------------------
+def test_square32_random_pm1_count_properties():
+    x = I.config_instances(2)[0]
+    L = 32
+    tau = (2 * np.random.default_rng(78).integers(0, 2, L * L) - 1).astype(np.int8)
+    xg = I.gauge(x, tau)
+    plan = B.Plan(L * L, x.edges, order=list(range(L * L)))
+    say("square32 pm1: contract")
+    E = B.contract(plan, dev(x.J[None])).cpu().numpy()[0]
+    say("square32 pm1: count")
+    Ec, res, g = B.count(plan, dev(x.J[None]))
+    say("square32 pm1: count gauged")
+    Eg, resg, gg = B.count(plan, dev(xg.J[None]))
+    plan.close()
+    assert Ec[0] == E and Eg[0] == E
+    assert np.array_equal(res, resg) and g[0] == gg[0]
+    assert g[0] % 2 == 0 and g[0] >= 2
