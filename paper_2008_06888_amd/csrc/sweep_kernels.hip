@@ -195,79 +195,134 @@ __device__ __forceinline__ void gate_extra(float (&e0)[8], float (&e1)[8], const
   }
 }
 
-// One relabelling gate on stage bit L of the 16 register entries, with the
-// star of the entering spin, sw = h + sum_k J_k sigma(partner_k):
+// Every op of a stage reads the 16 register entries from one array and writes
+// all 16 to the other (the stage alternates between two arrays), so no op
+// needs register copies to put its results back in place.
+//
+// One relabelling gate on stage bit L, with the star of the entering spin,
+// sw = h + sum_k J_k sigma(partner_k):
 //   new[0] = max(a0 + J, a1 - J) + sw = max(a0, a1 - 2J) + (J + sw)
 //   new[1] = max(a0 - J, a1 + J) - sw = max(a0 - 2J, a1) + (J - sw).
-// W < 4: the first partner is stage bit W, so its sign per pair is known at
-// compile time; W == 4: the partner is constant over the group (or absent).
-template <int L, int W>
-__device__ __forceinline__ void gate_lw(float (&v)[16], uint32_t gb, const UOp& u, const ROp& r) {
+// WS: the first partner is stage bit u.wl, so its sign per pair is a scalar
+// select; otherwise the partner is constant over the group (or absent). A
+// gate with further partners (rare) takes gate_x.
+template <int L, bool WS>
+__device__ __forceinline__ void gate_l(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u) {
   const float J2 = u.J2;
-  float e0[8], e1[8];
-  if (W == 4) {
+  float c0 = 0.f, c1 = 0.f;
+  if (!WS) {
     const bool b = u.wf != 255 && tbit(gb, u.wf);
-    const float c0 = b ? u.m0 : u.p0, c1 = b ? u.m1 : u.p1;
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      e0[p] = c0;
-      e1[p] = c1;
-    }
-  } else {
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-      const bool b = (j0 >> W) & 1;
-      e0[p] = b ? u.m0 : u.p0;
-      e1[p] = b ? u.m1 : u.p1;
-    }
+    c0 = b ? u.m0 : u.p0;
+    c1 = b ? u.m1 : u.p1;
   }
-  if (u.nx) gate_extra<L>(e0, e1, r, gb);
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
     const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
     const int j1 = j0 | (1 << L);
-    const float a0 = v[j0], a1 = v[j1];
-    v[j0] = fmaxf(a0, a1 - J2) + e0[p];
-    v[j1] = fmaxf(a0 - J2, a1) + e1[p];
+    float e0 = c0, e1 = c1;
+    if (WS) {
+      const bool b = ((uint32_t)j0 >> u.wl) & 1u;
+      e0 = b ? u.m0 : u.p0;
+      e1 = b ? u.m1 : u.p1;
+    }
+    o[j0] = fmaxf(a[j0], a[j1] - J2) + e0;
+    o[j1] = fmaxf(a[j0] - J2, a[j1]) + e1;
   }
 }
 
 template <int L>
-__device__ __forceinline__ void cut_l(float (&v)[16]) {
+__device__ __forceinline__ void gate_x(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u,
+                                       const ROp& r) {
+  const float J2 = u.J2;
+  float e0[8], e1[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    e0[p] = u.p0;
+    e1[p] = u.p1;
+  }
+  if (u.wf != 255) {
+#define TT_FIRST(P)                                                            \
+  {                                                                           \
+    constexpr int j0 = ((P >> L) << (L + 1)) | (P & ((1 << L) - 1));         \
+    if (rbit<j0>(u.wl, u.wf, gb)) {                                           \
+      e0[P] = u.m0;                                                           \
+      e1[P] = u.m1;                                                           \
+    }                                                                         \
+  }
+    TT_FIRST(0) TT_FIRST(1) TT_FIRST(2) TT_FIRST(3) TT_FIRST(4) TT_FIRST(5) TT_FIRST(6) TT_FIRST(7)
+#undef TT_FIRST
+  }
+  gate_extra<L>(e0, e1, r, gb);
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
     const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
     const int j1 = j0 | (1 << L);
-    const float m = fmaxf(v[j0], v[j1]);
-    v[j0] = m;
-    v[j1] = m;
+    o[j0] = fmaxf(a[j0], a[j1] - J2) + e0[p];
+    o[j1] = fmaxf(a[j0] - J2, a[j1]) + e1[p];
+  }
+}
+
+template <int L>
+__device__ __forceinline__ void cut_l(const float (&a)[16], float (&o)[16]) {
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+    const int j1 = j0 | (1 << L);
+    const float m = fmaxf(a[j0], a[j1]);
+    o[j0] = m;
+    o[j1] = m;
   }
 }
 
 // Star of a spin that entered without a gate: x += sigma(spin) * sw.
-__device__ __forceinline__ void star16(float (&v)[16], uint32_t gb, const UOp& u, const ROp& r) {
+__device__ __forceinline__ void star16(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u,
+                                       const ROp& r) {
   const uint32_t wl = u.wl, wf = u.wf, sl = u.sl, sbit = u.sbit;
 #define TT_STAR(J)                                                              \
   {                                                                            \
     float sw = u.p0;                                                           \
     if (wf != 255) sw += rbit<J>(wl, wf, gb) ? -u.m0 : u.m0;                   \
     for (uint32_t k = 0; k < u.nx; ++k) sw += rbit<J>(r.xl[k], r.xw[k], gb) ? -r.xJ[k] : r.xJ[k]; \
-    v[J] += (sbit != 255 && rbit<J>(sl, sbit, gb)) ? -sw : sw;                \
+    o[J] = a[J] + ((sbit != 255 && rbit<J>(sl, sbit, gb)) ? -sw : sw);         \
   }
   TT_STAR(0) TT_STAR(1) TT_STAR(2) TT_STAR(3) TT_STAR(4) TT_STAR(5) TT_STAR(6) TT_STAR(7)
   TT_STAR(8) TT_STAR(9) TT_STAR(10) TT_STAR(11) TT_STAR(12) TT_STAR(13) TT_STAR(14) TT_STAR(15)
 #undef TT_STAR
 }
 
-template <int L>
-__device__ __forceinline__ void gate_dispatch_w(float (&v)[16], uint32_t gb, const UOp& u, const ROp& r) {
-  switch (u.wl) {
-    case 0: gate_lw<L, 0>(v, gb, u, r); break;
-    case 1: gate_lw<L, 1>(v, gb, u, r); break;
-    case 2: gate_lw<L, 2>(v, gb, u, r); break;
-    case 3: gate_lw<L, 3>(v, gb, u, r); break;
-    default: gate_lw<L, 4>(v, gb, u, r); break;
+// One op of a stage: reads a, writes every entry of o.
+__device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], uint32_t gb, const ROp& r) {
+  const UOp u = uniform_op(r);
+  if (u.kind == FK_STAR) {
+    star16(a, o, gb, u, r);
+  } else if (u.kind == FK_CUT) {
+    switch (u.lidx) {
+      case 0: cut_l<0>(a, o); break;
+      case 1: cut_l<1>(a, o); break;
+      case 2: cut_l<2>(a, o); break;
+      default: cut_l<3>(a, o); break;
+    }
+  } else if (u.nx) {
+    switch (u.lidx) {
+      case 0: gate_x<0>(a, o, gb, u, r); break;
+      case 1: gate_x<1>(a, o, gb, u, r); break;
+      case 2: gate_x<2>(a, o, gb, u, r); break;
+      default: gate_x<3>(a, o, gb, u, r); break;
+    }
+  } else if (u.wl < 4) {
+    switch (u.lidx) {
+      case 0: gate_l<0, true>(a, o, gb, u); break;
+      case 1: gate_l<1, true>(a, o, gb, u); break;
+      case 2: gate_l<2, true>(a, o, gb, u); break;
+      default: gate_l<3, true>(a, o, gb, u); break;
+    }
+  } else {
+    switch (u.lidx) {
+      case 0: gate_l<0, false>(a, o, gb, u); break;
+      case 1: gate_l<1, false>(a, o, gb, u); break;
+      case 2: gate_l<2, false>(a, o, gb, u); break;
+      default: gate_l<3, false>(a, o, gb, u); break;
+    }
   }
 }
 
@@ -361,32 +416,21 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
     for (uint32_t g = tid; g < groups; g += 1u << tb) {
       const uint32_t gb = (uint32_t)ST->g_lo[g & 31u] | (uint32_t)ST->g_hi[g >> 5];
       const uint32_t sg = (uint32_t)ST->sg_lo[g & 31u] ^ (uint32_t)ST->sg_hi[g >> 5];
-      float v[16];
+      float va[16], vb[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) v[j] = tile[sg ^ so[j]];
-      for (int o = ob; o < oe; ++o) {
-        const ROp& r = rops[o];
-        const UOp u = uniform_op(r);
-        if (u.kind == FK_STAR) {
-          star16(v, gb, u, r);
-        } else if (u.kind == FK_CUT) {
-          switch (u.lidx) {
-            case 0: cut_l<0>(v); break;
-            case 1: cut_l<1>(v); break;
-            case 2: cut_l<2>(v); break;
-            default: cut_l<3>(v); break;
-          }
+      for (int j = 0; j < 16; ++j) va[j] = tile[sg ^ so[j]];
+      // ops in pairs: va -> vb -> va; an odd last op copies its result back
+      for (int o = ob; o < oe; o += 2) {
+        apply_op(va, vb, gb, rops[o]);
+        if (o + 1 < oe) {
+          apply_op(vb, va, gb, rops[o + 1]);
         } else {
-          switch (u.lidx) {
-            case 0: gate_dispatch_w<0>(v, gb, u, r); break;
-            case 1: gate_dispatch_w<1>(v, gb, u, r); break;
-            case 2: gate_dispatch_w<2>(v, gb, u, r); break;
-            default: gate_dispatch_w<3>(v, gb, u, r); break;
-          }
+#pragma unroll
+          for (int j = 0; j < 16; ++j) va[j] = vb[j];
         }
       }
 #pragma unroll
-      for (int j = 0; j < 16; ++j) tile[sg ^ so[j]] = v[j];
+      for (int j = 0; j < 16; ++j) tile[sg ^ so[j]] = va[j];
     }
     __syncthreads();
   }
