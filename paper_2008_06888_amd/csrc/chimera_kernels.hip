@@ -29,6 +29,7 @@
 #include <cstdint>
 
 #include "device.hpp"
+#include "device_mem.hpp"
 
 namespace tt {
 
@@ -49,7 +50,7 @@ __device__ __forceinline__ uint64_t mulmod_small(uint64_t a, uint64_t b, int r) 
 __device__ __forceinline__ float sgn4(int v, int bit) { return ((v >> bit) & 1) ? -1.f : 1.f; }
 
 template <typename IT>
-__device__ __forceinline__ float coup(const IT* J, int e) {
+__device__ __forceinline__ float coup(cptr<IT> J, int e) {
   return e >= 0 ? (float)J[e] : 0.f;
 }
 
@@ -66,8 +67,8 @@ __device__ __forceinline__ void vc_acc(float& m, uint32_t& n, float v, uint32_t 
 // K[c][16 w + h]: cell c with vertical group w and horizontal group h;
 // L[c][16 a + b]: horizontal couplers of cell c (group a) and cell c + 1 (group b).
 template <typename IT>
-__device__ void chain_tables(const ChimeraRow* __restrict__ R, int cols, const IT* J, const IT* h,
-                             float (*K)[256], float (*L)[256]) {
+__device__ void chain_tables(cptr<ChimeraRow> R, int cols, cptr<IT> J, cptr<IT> h, float (*K)[256],
+                             float (*L)[256]) {
   for (int j = threadIdx.x; j < cols * 256; j += blockDim.x) {
     const int c = j >> 8, wv = (j >> 4) & 15, hv = j & 15;
     float s = 0.f;
@@ -95,7 +96,7 @@ __device__ void chain_tables(const ChimeraRow* __restrict__ R, int cols, const I
 
 template <typename IT, bool COUNT>
 __global__ __launch_bounds__(CH_T) void k_chain(const ChainItem* __restrict__ item) {
-  const ChainItem& I = *item;
+  const auto& I = *as_const(item);
   __shared__ float K[8][256], L[8][256];
   __shared__ float S[256][17];
   __shared__ __align__(16) float B2[256][16];
@@ -105,10 +106,10 @@ __global__ __launch_bounds__(CH_T) void k_chain(const ChainItem* __restrict__ it
 
   const int64_t inst = (int64_t)(blockIdx.x >> I.log2_blocks);
   const uint64_t blk = blockIdx.x & ((1u << I.log2_blocks) - 1u);
-  const IT* J = static_cast<const IT*>(I.J) + inst * I.jst;
-  const IT* h = I.h ? static_cast<const IT*>(I.h) + inst * I.hst : nullptr;
+  const cptr<IT> J = as_const(static_cast<const IT*>(I.J)) + inst * I.jst;
+  const cptr<IT> h = I.h ? as_const(static_cast<const IT*>(I.h)) + inst * I.hst : nullptr;
   const int cols = I.cols, tid = threadIdx.x;
-  chain_tables<IT>(I.row, cols, J, h, K, L);
+  chain_tables<IT>(as_const(I.row), cols, J, h, K, L);
   __syncthreads();
   // A0[16 w0 + h1] = max over h0 of K_0(w0, h0) + L_0(h0, h1)
   if (cols >= 2 && tid < 256) {
@@ -196,14 +197,16 @@ __global__ __launch_bounds__(CH_T) void k_chain(const ChainItem* __restrict__ it
   const int lb = I.w < 16 ? I.w : 16;
   const uint32_t E = 1u << lb;
   const int64_t off = inst * I.sst + (int64_t)(blk << 16);
-  float* x = I.x + off;
-  uint64_t* nres = COUNT ? I.n + inst * 3 * I.sst + (int64_t)(blk << 16) : nullptr;
+  const gptr<float> x = as_global(I.x) + off;
+  const gptr<uint64_t> nres = COUNT ? as_global(I.n) + inst * 3 * I.sst + (int64_t)(blk << 16) : nullptr;
+  const bool init = I.init != 0;
+  const int64_t sst = I.sst;
   auto update = [&](uint32_t e, float g, uint64_t gc) {
-    x[e] = I.init ? g : x[e] + g;
+    x[e] = init ? g : x[e] + g;
     if (COUNT) {
       for (int r = 0; r < 3; ++r) {
-        uint64_t* pr = nres + (int64_t)r * I.sst + e;
-        *pr = I.init ? gc : mulmod_small(*pr, gc, r);
+        const gptr<uint64_t> pr = nres + (int64_t)r * sst + e;
+        *pr = init ? gc : mulmod_small(*pr, gc, r);
       }
     }
   };
@@ -247,26 +250,29 @@ __global__ __launch_bounds__(CH_T) void k_chain(const ChainItem* __restrict__ it
 // Backward finish of a chimera plan: one workgroup per instance.
 template <typename IT>
 __global__ __launch_bounds__(CH_T) void k_chim_finish(const ChimFinishItem* __restrict__ item) {
-  const ChimFinishItem& I = *item;
+  const auto& I = *as_const(item);
   __shared__ int8_t sig[8192];
   __shared__ float D[2][64][16];
   __shared__ uint8_t bp[64][8][16];
   const int64_t inst = blockIdx.x;
-  const IT* J = static_cast<const IT*>(I.J) + inst * I.jst;
-  const IT* h = I.h ? static_cast<const IT*>(I.h) + inst * I.hst : nullptr;
+  const cptr<IT> J = as_const(static_cast<const IT*>(I.J)) + inst * I.jst;
+  const cptr<IT> h = I.h ? as_const(static_cast<const IT*>(I.h)) + inst * I.hst : nullptr;
   const int rows = I.n_rows, cols = I.cols, tid = threadIdx.x;
+  const cptr<ChimeraRow> rows_d = as_const(I.rows);
+  const cptr<uint64_t> args = as_const(I.args);
+  const cptr<int32_t> edges = as_const(I.edges);
   // vertical groups: the selected address of each row
   for (int j = tid; j < rows * cols * 4; j += CH_T) {
     const int r = j / (4 * cols), s = j % (4 * cols);
-    const uint64_t a = I.args[(int64_t)r * I.batch + inst];
-    sig[I.rows[r].vspin[s >> 2][s & 3]] = ((a >> s) & 1ull) ? -1 : 1;
+    const uint64_t a = args[(int64_t)r * I.batch + inst];
+    sig[rows_d[r].vspin[s >> 2][s & 3]] = ((a >> s) & 1ull) ? -1 : 1;
   }
   // horizontal groups: Viterbi along each row given its vertical groups;
   // thread (r, hh) holds the best chain value ending in h_c = hh
   const int r = tid >> 4, hh = tid & 15;
   const bool act = r < rows;
-  const uint64_t a = act ? I.args[(int64_t)r * I.batch + inst] : 0ull;
-  const ChimeraRow* R = act ? I.rows + r : I.rows;
+  const uint64_t a = act ? args[(int64_t)r * I.batch + inst] : 0ull;
+  const cptr<ChimeraRow> R = act ? rows_d + r : rows_d;
   int cur = 0;
   for (int c = 0; c < cols; ++c) {
     if (act) {
@@ -318,14 +324,16 @@ __global__ __launch_bounds__(CH_T) void k_chim_finish(const ChimFinishItem* __re
     }
   }
   __syncthreads();
+  const gptr<int8_t> sigma = as_global(I.sigma);
+  const gptr<float> dh = as_global(I.dh), dJ = as_global(I.dJ);
   for (int j = tid; j < I.n; j += CH_T) {
-    I.sigma[inst * I.n + j] = sig[j];
-    if (I.dh) I.dh[inst * I.n + j] = -(float)sig[j];
+    sigma[inst * I.n + j] = sig[j];
+    if (dh) dh[inst * I.n + j] = -(float)sig[j];
   }
-  if (I.dJ)
+  if (dJ)
     for (int64_t e = tid; e < I.m; e += CH_T) {
-      const int u = I.edges[2 * e], v = I.edges[2 * e + 1];
-      I.dJ[inst * I.m + e] = -(float)(sig[u] * sig[v]);
+      const int u = edges[2 * e], v = edges[2 * e + 1];
+      dJ[inst * I.m + e] = -(float)(sig[u] * sig[v]);
     }
 }
 

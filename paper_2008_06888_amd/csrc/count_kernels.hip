@@ -15,7 +15,8 @@
 
 namespace tt {
 
-constexpr int CNT = 256;
+constexpr int CNT = 256;        // reductions
+constexpr int CNT_PASS = 1024;  // count passes: 16 waves hide the LDS latency of the per-op sweeps
 constexpr int NRES = 3;
 
 __device__ __constant__ uint64_t c_mod[NRES] = {(1ull << 61) - 1, (1ull << 61) - 31, (1ull << 61) - 45};
@@ -43,7 +44,7 @@ __device__ __forceinline__ void cbuild_deposit(const uint8_t* R, int t, uint64_t
 
 // State layout per instance: x plane [2^W] float, then residue planes
 // n[r][2^W] uint64 (sst = 2^W entries per plane).
-__global__ __launch_bounds__(CNT) void k_count_pass(DevPass P, const DevOp* __restrict__ ops,
+__global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp* __restrict__ ops,
                                                     const int32_t* __restrict__ J, const int32_t* __restrict__ h,
                                                     int64_t jst, int64_t hst, const float* __restrict__ xin,
                                                     const uint64_t* __restrict__ nin, float* __restrict__ xout,
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(CNT) void k_count_pass(DevPass P, const DevOp* __re
   const uint64_t in_mask = (1ull << P.in_w) - 1ull;
   const float* xs = xin + inst * sst;
   const uint64_t* ns = nin + inst * sst * NRES;
-  for (uint32_t i = threadIdx.x; i < size; i += CNT) {
+  for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) {
     const uint64_t idx = (base | dep_lo[i & 255u] | dep_hi[i >> 8]) & in_mask;
     if (P.init) {
       tx[i] = 0.f;
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(CNT) void k_count_pass(DevPass P, const DevOp* __re
       const float Jv = op.kind == OP_GATE ? (float)Jrow[op.param] : 0.f;
       const int b = op.a;
       const uint32_t lowmask = (1u << b) - 1u;
-      for (uint32_t p = threadIdx.x; p < (size >> 1); p += CNT) {
+      for (uint32_t p = threadIdx.x; p < (size >> 1); p += CNT_PASS) {
         const uint32_t i0 = ((p & ~lowmask) << 1) | (p & lowmask);
         const uint32_t i1 = i0 | (1u << b);
         const float a0 = tx[i0], a1 = tx[i1];
@@ -99,18 +100,18 @@ __global__ __launch_bounds__(CNT) void k_count_pass(DevPass P, const DevOp* __re
       __syncthreads();
     } else if (op.kind == OP_DIAG) {
       const float Jv = (float)Jrow[op.param];
-      for (uint32_t i = threadIdx.x; i < size; i += CNT)
+      for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS)
         tx[i] += (cbit(op.a, i, base) ^ cbit(op.b, i, base)) ? -Jv : Jv;
       __syncthreads();
     } else if (op.kind == OP_FIELD) {
       const float hv = (float)hrow[op.param];
-      for (uint32_t i = threadIdx.x; i < size; i += CNT) tx[i] += cbit(op.a, i, base) ? -hv : hv;
+      for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) tx[i] += cbit(op.a, i, base) ? -hv : hv;
       __syncthreads();
     }
   }
   float* xd = xout + inst * sst;
   uint64_t* nd = nout + inst * sst * NRES;
-  for (uint32_t i = threadIdx.x; i < size; i += CNT) {
+  for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) {
     const uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
     if ((idx >> P.out_w) != 0) continue;
     xd[idx] = tx[i];
@@ -202,7 +203,7 @@ hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* 
   }
   const uint64_t grid = (uint64_t)batch << P.n_free;
   if (grid >= (1ull << 31)) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_count_pass, dim3((uint32_t)grid), dim3(CNT), lds, stream, P, ops, J, h, jst, hst, xin, nin,
+  hipLaunchKernelGGL(k_count_pass, dim3((uint32_t)grid), dim3(CNT_PASS), lds, stream, P, ops, J, h, jst, hst, xin, nin,
                      xout, nout, sst, P.n_free);
   return hipGetLastError();
 }

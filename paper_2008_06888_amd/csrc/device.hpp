@@ -61,7 +61,7 @@ struct DevStage {
   uint16_t g_hi[32];
   uint16_t sg_lo[32]; // the same, LDS-swizzled (the swizzle is linear over GF(2))
   uint16_t sg_hi[32];
-  uint16_t soff[16];  // swizzled LDS offset of register entry j (stage bits of j)
+  uint32_t soff[16];  // swizzled LDS offset of register entry j (stage bits of j)
 };
 
 struct DevPass2 {
@@ -77,10 +77,10 @@ struct DevPass2 {
   uint8_t st_order[16];  // tile bits with an output position, ascending by position
   int32_t n_ld, n_st;
   // bit q of the load (store) enumeration index -> tile-index bit, address bit
-  uint16_t ld_bti[16], st_bti[16];
+  uint32_t ld_bti[16], st_bti[16];
   uint64_t ld_bad[16], st_bad[16];
   // the same maps for the index bits from tb up (k = u >> tb), all 16 combinations
-  uint16_t ld_hti[16], st_hti[16];
+  uint32_t ld_hti[16], st_hti[16];
   uint64_t ld_had[16], st_had[16];
   int32_t tb;            // log2 of the threads a tile uses (max(6, t - 4), at most 10)
   int32_t pad_tb;

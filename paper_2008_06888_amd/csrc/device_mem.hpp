@@ -1,0 +1,44 @@
+// Address spaces for device code (HIP kernels only).
+#pragma once
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace tt {
+
+// Launch tables, encoded programs and inputs are read-only while a kernel
+// runs: read through the constant address space, so uniform fields come in
+// by scalar loads (through the scalar cache) and the rest by global loads.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
+
+// A whole record read from the constant address space, word by word.
+template <typename T>
+__device__ __forceinline__ T ldc(cptr<T> p) {
+  static_assert(sizeof(T) % 4 == 0, "records are read as 32-bit words");
+  T r;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&r);
+  const cptr<uint32_t> w = (cptr<uint32_t>)(p);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = w[k];
+  return r;
+}
+
+// Device memory written by a kernel: the global address space (no flat
+// accesses, whose completion also holds back LDS waits).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)(p);
+}
+
+// LDS records reached through pointers: the local address space (ds_*
+// accesses instead of flat ones).
+using LROp = __attribute__((address_space(3))) ROp;
+
+}  // namespace tt

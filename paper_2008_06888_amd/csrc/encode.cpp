@@ -171,8 +171,8 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
     for (int k = 0; k < d.t; ++k) {
       d.ld_order[k] = (uint8_t)ld[k];
       d.st_order[k] = (uint8_t)st[k];
-      d.ld_bti[k] = (uint16_t)(1u << ld[k]);
-      d.st_bti[k] = (uint16_t)(1u << st[k]);
+      d.ld_bti[k] = 1u << ld[k];
+      d.st_bti[k] = 1u << st[k];
       d.ld_bad[k] = k < d.n_ld ? (1ull << d.in_pos[R[q][ld[k]]]) : 0ull;
       d.st_bad[k] = k < d.n_st ? (1ull << d.out_pos[R[q][st[k]]]) : 0ull;
     }
@@ -190,9 +190,9 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
           sa |= d.st_bad[d.tb + b];
         }
       }
-      d.ld_hti[kk] = (uint16_t)lt;
+      d.ld_hti[kk] = lt;
       d.ld_had[kk] = la;
-      d.st_hti[kk] = (uint16_t)stt;
+      d.st_hti[kk] = stt;
       d.st_had[kk] = sa;
     }
     auto enc = [&](int slot) -> uint8_t {
@@ -293,7 +293,7 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
         uint32_t sj = 0;
         for (int l = 0; l < 4; ++l)
           if ((j >> l) & 1) sj |= 1u << S[l];
-        st2.soff[j] = (uint16_t)swz(sj);
+        st2.soff[j] = swz(sj);
       }
       st2.op_begin = (int)out.fops.size();
       for (size_t k = b0; k < e; ++k) {

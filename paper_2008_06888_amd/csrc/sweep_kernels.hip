@@ -19,6 +19,7 @@
 #include <cstdint>
 
 #include "device.hpp"
+#include "device_mem.hpp"
 #include "plan.hpp"
 
 namespace tt {
@@ -26,8 +27,9 @@ namespace tt {
 constexpr int NT = 1024;   // threads per workgroup (energy pass, backward)
 constexpr int NTR = 256;   // threads per workgroup (final reduction)
 
+
 template <typename IT>
-__device__ __forceinline__ float ldv(const IT* p, int64_t k) {
+__device__ __forceinline__ float ldv(cptr<IT> p, int64_t k) {
   return (float)p[k];
 }
 
@@ -77,8 +79,8 @@ constexpr int MAX_PASS_OPS = 256;   // fused ops of one pass held in LDS (the pl
 // Resolves one op of a pass for this instance and tile into its LDS record
 // (see ROp). Fields are written in place: no private arrays.
 template <typename IT>
-__device__ void resolve_op(const FOp* __restrict__ op, ROp* r, const IT* Jrow, const IT* hrow, uint64_t bs,
-                           const uint8_t* sb) {
+__device__ __forceinline__ void resolve_op(cptr<FOp> op, LROp* r, cptr<IT> Jrow, cptr<IT> hrow, uint64_t bs,
+                                           cptr<uint8_t> sb) {
   float cst = op->hspin >= 0 ? ldv(hrow, op->hspin) : 0.f;
   const uint8_t kind = op->kind;
   const int nt = op->nt;
@@ -153,7 +155,7 @@ __device__ __forceinline__ float ufl(float x) {
 }
 __device__ __forceinline__ uint32_t uin(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
 
-__device__ __forceinline__ UOp uniform_op(const ROp& r) {
+__device__ __forceinline__ UOp uniform_op(const LROp& r) {
   UOp u;
   u.J2 = ufl(r.J2);
   u.p0 = ufl(r.p0);
@@ -179,7 +181,7 @@ __device__ __forceinline__ uint32_t rbit(uint32_t l, uint32_t w, uint32_t gb) {
 
 // Extra star terms of a gate (rare: more than one resident partner).
 template <int L>
-__device__ __forceinline__ void gate_extra(float (&e0)[8], float (&e1)[8], const ROp& r, uint32_t gb) {
+__device__ __forceinline__ void gate_extra(float (&e0)[8], float (&e1)[8], const LROp& r, uint32_t gb) {
   for (int k = 0; k < r.nx; ++k) {
     const uint32_t w = r.xw[k], l = r.xl[k];
     const float Jk = r.xJ[k];
@@ -203,36 +205,60 @@ __device__ __forceinline__ void gate_extra(float (&e0)[8], float (&e1)[8], const
 // sw = h + sum_k J_k sigma(partner_k):
 //   new[0] = max(a0 + J, a1 - J) + sw = max(a0, a1 - 2J) + (J + sw)
 //   new[1] = max(a0 - J, a1 + J) - sw = max(a0 - 2J, a1) + (J - sw).
-// WS: the first partner is stage bit u.wl, so its sign per pair is a scalar
-// select; otherwise the partner is constant over the group (or absent). A
-// gate with further partners (rare) takes gate_x.
-template <int L, bool WS>
+// The core of a gate pair, max(a0, a1 - J2) + e, with J2 and e scalar
+// operands; written as one asm unit per output so that the compiler cannot
+// merge the variants below into one body that first copies every pair's
+// constant to a vector register.
+__device__ __forceinline__ float gate_out_s(float a_keep, float a_move, float J2, float e) {
+  float r;
+  asm("v_subrev_f32 %0, %3, %2\n\tv_max_f32 %0, %1, %0\n\tv_add_f32 %0, %4, %0"
+      : "=&v"(r)
+      : "v"(a_keep), "v"(a_move), "s"(J2), "s"(e));
+  return r;
+}
+
+// W < 4: the first partner is stage bit W, so its sign per pair is known at
+// compile time (scalar constants); W == 4: the partner is constant over the
+// group (or absent). A gate with further partners (rare) takes gate_x.
+template <int L, int W>
 __device__ __forceinline__ void gate_l(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u) {
   const float J2 = u.J2;
-  float c0 = 0.f, c1 = 0.f;
-  if (!WS) {
+  if constexpr (W == 4) {
     const bool b = u.wf != 255 && tbit(gb, u.wf);
-    c0 = b ? u.m0 : u.p0;
-    c1 = b ? u.m1 : u.p1;
-  }
+    const float c0 = b ? u.m0 : u.p0, c1 = b ? u.m1 : u.p1;
 #pragma unroll
-  for (int p = 0; p < 8; ++p) {
-    const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
-    const int j1 = j0 | (1 << L);
-    float e0 = c0, e1 = c1;
-    if (WS) {
-      const bool b = ((uint32_t)j0 >> u.wl) & 1u;
-      e0 = b ? u.m0 : u.p0;
-      e1 = b ? u.m1 : u.p1;
+    for (int p = 0; p < 8; ++p) {
+      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+      const int j1 = j0 | (1 << L);
+      o[j0] = fmaxf(a[j0], a[j1] - J2) + c0;
+      o[j1] = fmaxf(a[j0] - J2, a[j1]) + c1;
     }
-    o[j0] = fmaxf(a[j0], a[j1] - J2) + e0;
-    o[j1] = fmaxf(a[j0] - J2, a[j1]) + e1;
+  } else {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+      const int j1 = j0 | (1 << L);
+      const bool b = (j0 >> W) & 1;
+      o[j0] = gate_out_s(a[j0], a[j1], J2, b ? u.m0 : u.p0);
+      o[j1] = gate_out_s(a[j1], a[j0], J2, b ? u.m1 : u.p1);
+    }
+  }
+}
+
+template <int L>
+__device__ __forceinline__ void gate_lw(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u) {
+  switch (u.wl) {
+    case 0: gate_l<L, 0>(a, o, gb, u); break;
+    case 1: gate_l<L, 1>(a, o, gb, u); break;
+    case 2: gate_l<L, 2>(a, o, gb, u); break;
+    case 3: gate_l<L, 3>(a, o, gb, u); break;
+    default: gate_l<L, 4>(a, o, gb, u); break;
   }
 }
 
 template <int L>
 __device__ __forceinline__ void gate_x(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u,
-                                       const ROp& r) {
+                                       const LROp& r) {
   const float J2 = u.J2;
   float e0[8], e1[8];
 #pragma unroll
@@ -276,7 +302,7 @@ __device__ __forceinline__ void cut_l(const float (&a)[16], float (&o)[16]) {
 
 // Star of a spin that entered without a gate: x += sigma(spin) * sw.
 __device__ __forceinline__ void star16(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u,
-                                       const ROp& r) {
+                                       const LROp& r) {
   const uint32_t wl = u.wl, wf = u.wf, sl = u.sl, sbit = u.sbit;
 #define TT_STAR(J)                                                              \
   {                                                                            \
@@ -291,7 +317,7 @@ __device__ __forceinline__ void star16(const float (&a)[16], float (&o)[16], uin
 }
 
 // One op of a stage: reads a, writes every entry of o.
-__device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], uint32_t gb, const ROp& r) {
+__device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], uint32_t gb, const LROp& r) {
   const UOp u = uniform_op(r);
   if (u.kind == FK_STAR) {
     star16(a, o, gb, u, r);
@@ -309,19 +335,12 @@ __device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], u
       case 2: gate_x<2>(a, o, gb, u, r); break;
       default: gate_x<3>(a, o, gb, u, r); break;
     }
-  } else if (u.wl < 4) {
-    switch (u.lidx) {
-      case 0: gate_l<0, true>(a, o, gb, u); break;
-      case 1: gate_l<1, true>(a, o, gb, u); break;
-      case 2: gate_l<2, true>(a, o, gb, u); break;
-      default: gate_l<3, true>(a, o, gb, u); break;
-    }
   } else {
     switch (u.lidx) {
-      case 0: gate_l<0, false>(a, o, gb, u); break;
-      case 1: gate_l<1, false>(a, o, gb, u); break;
-      case 2: gate_l<2, false>(a, o, gb, u); break;
-      default: gate_l<3, false>(a, o, gb, u); break;
+      case 0: gate_lw<0>(a, o, gb, u); break;
+      case 1: gate_lw<1>(a, o, gb, u); break;
+      case 2: gate_lw<2>(a, o, gb, u); break;
+      default: gate_lw<3>(a, o, gb, u); break;
     }
   }
 }
@@ -329,14 +348,16 @@ __device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], u
 template <typename IT>
 __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items, int n_items) {
   extern __shared__ float tile[];
-  __shared__ ROp rops[MAX_PASS_OPS];
+  __shared__ ROp rops_sh[MAX_PASS_OPS];
+  LROp* const rops = (LROp*)(rops_sh);
   const int64_t wg = blockIdx.x;
   int it = 0;
-  while (it + 1 < n_items && wg >= items[it + 1].wg_begin) ++it;
-  const PassItem& I = items[it];
-  const DevPass2& P = *I.P;
-  const DevStage* __restrict__ stages = I.stages;
-  const FOp* __restrict__ fops = I.fops;
+  const cptr<PassItem> citems = as_const(items);
+  while (it + 1 < n_items && wg >= citems[it + 1].wg_begin) ++it;
+  const auto& I = citems[it];
+  const auto& P = *as_const(I.P);
+  const cptr<DevStage> stages = as_const(I.stages);
+  const cptr<FOp> fops = as_const(I.fops);
   int64_t inst;
   uint64_t tid_bits;
   if (!wg_to_tile((uint64_t)(wg - I.wg_begin), P.n_free, I.batch, I.xcd_group, &inst, &tid_bits)) return;
@@ -364,10 +385,10 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
     dropped = uni64(wave_or(dropped));
   }
   const bool stored = dropped == 0;   // only the copy with dropped slots at 0 is kept
-  const IT* Jrow = static_cast<const IT*>(I.J) + inst * I.jst;
-  const IT* hrow = I.h ? static_cast<const IT*>(I.h) + inst * I.hst : nullptr;
-  const float* in = I.in + inst * I.in_st;
-  float* out = I.out + inst * I.out_st;
+  const cptr<IT> Jrow = as_const(static_cast<const IT*>(I.J)) + inst * I.jst;
+  const cptr<IT> hrow = I.h ? as_const(static_cast<const IT*>(I.h)) + inst * I.hst : nullptr;
+  const cptr<float> in = as_const(I.in) + inst * I.in_st;     // read-only in this pass (in != out)
+  const gptr<float> out = as_global(I.out) + inst * I.out_st;
   // load: enumeration index u = tid + 2^tb k; bit q of u -> tile bit / address
   // bit. The tile's global loads are issued first and stay in flight while
   // the pass's ops are resolved; then they are written to LDS.
@@ -383,7 +404,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
         ti_ld |= P.ld_bti[q];
         ad_lo |= P.ld_bad[q];
       }
-    const float* src = in + in_base;
+    const cptr<float> src = in + in_base;
     if (loader) {
 #pragma unroll
       for (int k = 0; k < 16; ++k)
@@ -407,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   __syncthreads();
   const int n_stages = P.n_stages;
   for (int s = 0; s < n_stages; ++s) {
-    const DevStage* __restrict__ ST = stages + P.stage_begin + s;
+    const cptr<DevStage> ST = stages + P.stage_begin + s;
     const uint32_t groups = size >> 4;
     const int ob = ST->op_begin - op0, oe = ST->op_end - op0;
     uint32_t so[16];
@@ -446,7 +467,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
         ti_lo |= P.st_bti[q];
         ad_lo |= P.st_bad[q];
       }
-    float* dst = out + out_base;
+    const gptr<float> dst = out + out_base;
     if (tid < (1 << nb)) {
       const int nk = 1 << (ns - nb);
       float vals[16];
@@ -507,25 +528,27 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict
   __shared__ float bt[5][256];   // bonus of each index byte (chimera row walk)
   const int64_t wg = blockIdx.x;
   int it = 0;
-  while (it + 1 < n_items && wg >= items[it + 1].chunk_begin) ++it;
-  const RedItem& I = items[it];
+  const cptr<RedItem> citems = as_const(items);
+  while (it + 1 < n_items && wg >= citems[it + 1].chunk_begin) ++it;
+  const auto& I = citems[it];
   const uint64_t chunk = (uint64_t)(wg - I.chunk_begin);
   const uint64_t len = 1ull << (I.w - I.log2_chunks);
   const uint64_t base = chunk * len;
-  const float* s = I.st;
+  const cptr<float> s = as_const(I.st);
   const bool bonus = I.bedge != nullptr;
   if (bonus) {
-    const uint64_t ref = *I.bref;
+    const uint64_t ref = *as_const(I.bref);
+    const cptr<int32_t> bedge = as_const(I.bedge);
     for (int j = threadIdx.x; j < 5 * 256; j += NTR) {
       const int b = j >> 8, v = j & 255;
       float t = 0.f;
       for (int q = 0; q < 8; ++q) {
         const int sl = 8 * b + q;
         if (sl >= I.w) break;
-        const int e = I.bedge[sl];
+        const int e = bedge[sl];
         if (e < 0) continue;
-        const float Jv = I.bdtype == 0 ? static_cast<const float*>(I.bJ)[e]
-                                       : (float)static_cast<const int32_t*>(I.bJ)[e];
+        const float Jv = I.bdtype == 0 ? as_const(static_cast<const float*>(I.bJ))[e]
+                                       : (float)as_const(static_cast<const int32_t*>(I.bJ))[e];
         t += (((ref >> sl) ^ (uint64_t)(v >> q)) & 1ull) ? -Jv : Jv;
       }
       bt[b][v] = t;
@@ -535,10 +558,10 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict
   VI best{-INFINITY, ~0ull};
   if (len >= 4) {
     // four consecutive entries per load; ties keep the smaller address
-    const float4* s4 = reinterpret_cast<const float4*>(s + base);
+    const cptr<float4> s4 = (cptr<float4>)(s + base);
 #pragma unroll 4
     for (uint64_t k = threadIdx.x; k < len / 4; k += NTR) {
-      const float4 v = s4[k];
+      const float4 v = ldc(s4 + k);
       const uint64_t i0 = base + 4 * k;
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
       if (bonus) {
@@ -575,14 +598,14 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict
 __global__ __launch_bounds__(NTR) void k_reduce_stage2(const RedItem* __restrict__ items,
                                                        const float* __restrict__ pv,
                                                        const uint64_t* __restrict__ pi) {
-  const RedItem& I = items[blockIdx.x];
+  const auto& I = as_const(items)[blockIdx.x];
   const int64_t nc = 1ll << I.log2_chunks;
   VI best{-INFINITY, ~0ull};
   for (int64_t k = threadIdx.x; k < nc; k += NTR) best = vi_best(best, VI{pv[I.chunk_begin + k], pi[I.chunk_begin + k]});
   best = block_best<NTR>(best);
   if (threadIdx.x == 0) {
-    if (I.energy) *I.energy = -(double)best.v;
-    if (I.arg) *I.arg = best.i;
+    if (I.energy) *as_global(I.energy) = -(double)best.v;
+    if (I.arg) *as_global(I.arg) = best.i;
   }
 }
 
@@ -633,23 +656,30 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   __shared__ BCand lc[BCH_CANDS];
   __shared__ LPass lp[BCH_PASSES];
   __shared__ uint8_t lpos[BCH_PASSES][64];
-  const BwdItem& I = items[blockIdx.x];
+  const auto& I = as_const(items)[blockIdx.x];
   const int tid = threadIdx.x;
-  const IT* Jrow = static_cast<const IT*>(I.J);
-  const IT* hrow = static_cast<const IT*>(I.h);
-  const DevPass2* __restrict__ passes = I.passes;
+  const cptr<IT> Jrow = as_const(static_cast<const IT*>(I.J));
+  const cptr<IT> hrow = as_const(static_cast<const IT*>(I.h));
+  const cptr<DevPass2> passes = as_const(I.passes);
+  const cptr<uint8_t> final_pos = as_const(I.final_pos);
+  const cptr<int32_t> final_slot_spin = as_const(I.final_slot_spin);
+  const cptr<BChunk> chunks = as_const(I.chunks);
+  const cptr<BCand> cands = as_const(I.cands);
+  const cptr<BTerm> terms = as_const(I.terms);
+  const cptr<int32_t> edges = as_const(I.edges);
+  const cptr<const float*> ckpt = as_const(I.ckpt);
   const int final_w = I.final_w, n = I.n;
   const int64_t m = I.m;
   for (int v = tid; v < n; v += NT) s_sh[v] = 0;
   __syncthreads();
   if (tid < 64) {
     // final state: address -> slot index; spins still in a slot take its bit
-    const uint64_t addr = *I.final_addr;
+    const uint64_t addr = *as_const(I.final_addr);
     uint64_t tb = 0;
     if (tid < final_w) {
-      const uint64_t b = (addr >> I.final_pos[tid]) & 1ull;
+      const uint64_t b = (addr >> final_pos[tid]) & 1ull;
       tb = b << tid;
-      const int sp = I.final_slot_spin[tid];
+      const int sp = final_slot_spin[tid];
       if (sp >= 0) s_sh[sp] = (int8_t)b;
     }
     tb = wave_or(tb);
@@ -657,10 +687,10 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   }
   __syncthreads();
   for (int ci = 0; ci < I.n_chunks; ++ci) {
-    const BChunk CH = I.chunks[ci];
+    const BChunk CH = ldc(chunks + ci);
     // stage the chunk: pass fields and layouts, candidates, terms (coefficients resolved)
     for (int q = tid; q <= CH.p_hi - CH.p_lo; q += NT) {
-      const DevPass2* P = passes + CH.p_lo + q;
+      const cptr<DevPass2> P = passes + CH.p_lo + q;
       LPass x;
       x.surv = P->surv_mask;
       x.n_cand = P->n_cand;
@@ -675,9 +705,9 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
     }
     for (int k = tid; k < (CH.p_hi - CH.p_lo + 1) * 64; k += NT)
       lpos[k >> 6][k & 63] = passes[CH.p_lo + (k >> 6)].in_pos[k & 63];
-    for (int k = tid; k < CH.n_cand; k += NT) lc[k] = I.cands[CH.cand_begin + k];
+    for (int k = tid; k < CH.n_cand; k += NT) lc[k] = ldc(cands + CH.cand_begin + k);
     for (int k = tid; k < CH.n_term; k += NT) {
-      const BTerm b = I.terms[CH.term_begin + k];
+      const BTerm b = ldc(terms + CH.term_begin + k);
       LTerm x;
       x.c = b.is_field ? ldv(hrow, b.coef) : ldv(Jrow, b.coef);
       x.a = b.a;
@@ -735,7 +765,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
         if (c == 0) sh_base = b;
       }
       __syncthreads();
-      const float* src = P.init ? nullptr : I.ckpt[p] + sh_base;
+      const cptr<float> src = P.init ? nullptr : as_const(ckpt[p]) + sh_base;
       VI best{-INFINITY, ~0ull};
       const uint32_t na = 1u << nc;
       const int cross_b = n_lo + n_hi;
@@ -771,14 +801,16 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       __syncthreads();
     }
   }
+  const gptr<int8_t> sigma = as_global(I.sigma);
+  const gptr<float> dh = as_global(I.dh), dJ = as_global(I.dJ);
   for (int v = tid; v < n; v += NT) {
-    I.sigma[v] = (int8_t)(s_sh[v] ? -1 : 1);
-    if (I.dh) I.dh[v] = s_sh[v] ? 1.f : -1.f;           // -sigma_v
+    sigma[v] = (int8_t)(s_sh[v] ? -1 : 1);
+    if (dh) dh[v] = s_sh[v] ? 1.f : -1.f;           // -sigma_v
   }
-  if (I.dJ) {
+  if (dJ) {
     for (int64_t e = tid; e < m; e += NT) {
-      const int a = I.edges[2 * e], c = I.edges[2 * e + 1];
-      I.dJ[e] = (s_sh[a] ^ s_sh[c]) ? 1.f : -1.f;   // -sigma_a sigma_c
+      const int a = edges[2 * e], c = edges[2 * e + 1];
+      dJ[e] = (s_sh[a] ^ s_sh[c]) ? 1.f : -1.f;   // -sigma_a sigma_c
     }
   }
 }

@@ -20,9 +20,9 @@ class DevPass2(C.Structure):
                 ("n_hi", C.c_int32), ("n_cross", C.c_int32), ("surv_mask", C.c_uint64),
                 ("R", C.c_uint8 * 16), ("fre", C.c_uint8 * 48), ("in_pos", C.c_uint8 * 64),
                 ("out_pos", C.c_uint8 * 64), ("ld_order", C.c_uint8 * 16), ("st_order", C.c_uint8 * 16),
-                ("n_ld", C.c_int32), ("n_st", C.c_int32), ("ld_bti", C.c_uint16 * 16), ("st_bti", C.c_uint16 * 16),
-                ("ld_bad", C.c_uint64 * 16), ("st_bad", C.c_uint64 * 16), ("ld_hti", C.c_uint16 * 16),
-                ("st_hti", C.c_uint16 * 16), ("ld_had", C.c_uint64 * 16), ("st_had", C.c_uint64 * 16),
+                ("n_ld", C.c_int32), ("n_st", C.c_int32), ("ld_bti", C.c_uint32 * 16), ("st_bti", C.c_uint32 * 16),
+                ("ld_bad", C.c_uint64 * 16), ("st_bad", C.c_uint64 * 16), ("ld_hti", C.c_uint32 * 16),
+                ("st_hti", C.c_uint32 * 16), ("ld_had", C.c_uint64 * 16), ("st_had", C.c_uint64 * 16),
                 ("tb", C.c_int32), ("pad_tb", C.c_int32), ("fin", C.c_uint8 * 48), ("fout", C.c_uint8 * 48)]
 
 
@@ -30,7 +30,7 @@ class DevStage(C.Structure):
     _fields_ = [("sb", C.c_uint8 * 4), ("nns", C.c_uint8), ("ns", C.c_uint8 * 15), ("op_begin", C.c_int32),
                 ("op_end", C.c_int32), ("pad", C.c_int32 * 2), ("g_lo", C.c_uint16 * 32),
                 ("g_hi", C.c_uint16 * 32), ("sg_lo", C.c_uint16 * 32), ("sg_hi", C.c_uint16 * 32),
-                ("soff", C.c_uint16 * 16)]
+                ("soff", C.c_uint32 * 16)]
 
 
 class FOp(C.Structure):
