@@ -304,7 +304,7 @@ void partition_plan(Plan& p) {
     for (Pass& q : p.passes) q.init = false;        // row 0 is written by the chain
     for (Pass& q : p.count_passes) q.init = false;
   } else {
-    p.passes = partition_passes(p, p.tile_bits, p.max_dec, false, 0);
+    p.passes = partition_passes(p, p.tile_bits, p.max_dec, false, 0, 6);
     p.count_passes = partition_passes(p, p.count_tile_bits, 1 << 20, false, 6);
   }
 }
@@ -489,10 +489,22 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
       threads = 64;
       lds = 0;
     };
-    for (Group& g : groups) {
+    // one launch per tile size: a launch's workgroups are all as large as
+    // its largest tile needs, so tiles of different sizes go separately
+    std::vector<std::pair<int, Group*>> order;
+    for (Group& g : groups)
+      if (q < (int)g.dc->ep.passes.size()) order.push_back({g.dc->ep.passes[q].t, &g});
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<int, Group*>& a, const std::pair<int, Group*>& b) { return a.first < b.first; });
+    int cur_t = -1;
+    for (auto& og : order) {
+      Group& g = *og.second;
       const EnergyProgram& ep = g.dc->ep;
-      if (q >= (int)ep.passes.size()) continue;
       const DevPass2& P = ep.passes[q];
+      if (P.t != cur_t) {
+        flush();
+        cur_t = P.t;
+      }
       threads = std::max(threads, 1 << P.tb);
       lds = std::max(lds, sizeof(float) << P.t);
       PassItem it;

@@ -114,9 +114,21 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
         if ((int)low.size() < LOW_BITS) low.push_back(s);
       }
     }
+    // above the shared bits: the rest of the next tile (so a tile loads one
+    // contiguous block), then the rest of the previous tile (so a tile's
+    // stores stay inside a region of 2^(t + 8) entries), then slot order;
+    // both keep the pages a workgroup touches few
     std::vector<int> ps(w, -1);
     int k = 0;
     for (int s : low) ps[s] = k++;
+    if (!row_boundary(b)) {
+      if (b < np)
+        for (int s : R[b])
+          if (s < w && ps[s] < 0) ps[s] = k++;
+      if (b > 0)
+        for (int s : R[b - 1])
+          if (s < w && ps[s] < 0) ps[s] = k++;
+    }
     for (int s = 0; s < w; ++s)
       if (ps[s] < 0) ps[s] = k++;
     pos[b] = ps;

@@ -140,6 +140,8 @@ std::string build_chimera_ops(Plan& p, int rows, int cols);
 // Splits ops into passes of at most `t` resident bits and `max_dec` gated
 // slots; `separable` adds the conditions of the one-argmax backward walk.
 // `low` lowest slots are kept resident in every tile (identity bit order).
-std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separable, int low);
+// `reserve` tile bits stay free for slots shared with the next pass (when
+// the state is at least that much wider than the tile).
+std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separable, int low, int reserve = 0);
 
 }  // namespace tt

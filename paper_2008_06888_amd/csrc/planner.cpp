@@ -303,7 +303,7 @@ std::vector<int32_t> greedy_order(int32_t n, const std::vector<int32_t>& edges, 
   return best;
 }
 
-std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separable, int low) {
+std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separable, int low, int reserve) {
   // separable: every pass can be walked back by one argmax over its gated
   // slots (see the backward kernel): no slot gated twice, no gate on a slot
   // that a diagonal term or an INTRO already touched in the same pass.
@@ -342,7 +342,12 @@ std::vector<Pass> partition_passes(const Plan& p, int t, int max_dec, bool separ
       const int wmax2 = std::max(wmax, std::max(op.w_before, op.w_after));
       std::set<int> with_low = need2;
       for (int s = 0; s < std::min(LOW, wmax2); ++s) with_low.insert(s);
-      bool ok = (wmax2 <= t) || ((int)with_low.size() <= t);
+      // keep `reserve` tile bits for slots shared with the next pass when at
+      // least that many slots lie outside the tile (else the neighbours'
+      // tiles overlap anyway): consecutive tiles then share the low address
+      // bits and both the store and the next load stream whole runs
+      const int rsv = (wmax2 - t >= reserve) ? reserve : 0;
+      bool ok = (wmax2 <= t) || ((int)with_low.size() + rsv <= t);
       ok = ok && ndec2 <= max_dec && (!separable || sep_ok) && (i - start) < MAX_OPS_PER_PASS;
       if (!ok && i > start) break;
       need.swap(need2);
