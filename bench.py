@@ -21,6 +21,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "max-plus Gop/s & % VALU peak; ground-state solves/s (energy+config), 16x16 ±J"
 VALU_PEAK_OPS = 256 * 64 * 2.4e9 * 2      # max-plus ops/s: one term (add + max) per lane per cycle
+# HBM bytes per k_pass launch of the headline workload, from rocprofv3 counter
+# passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain 256 MiB
+# device copy reads for the same counters); profiles/k_pass_square16x16_gauss_b64.txt.
+# Set to None whenever the pass kernel changes until the counters are taken again.
+K_PASS_TRAFFIC_BYTES = 33.36e6
 
 
 def cpu_baseline(insts, seconds=15.0):
@@ -286,7 +291,7 @@ def main():
         "valu_frac": ops_step * args.steps / dt / VALU_PEAK_OPS,
         "roofline": {"kernel": "k_pass", "bound": "alu", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK_OPS / 1e12, "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": None,
+                     "traffic": K_PASS_TRAFFIC_BYTES,
                      "avg_launch_ms": ms_pass / max(n_pass, 1), "launches": n_pass},
         "kernel_ms_per_step": {"sweep_pass": ms_pass / args.steps, "sweep_backward": ms_bwd / args.steps,
                                "final_reduce": ms_red / args.steps},

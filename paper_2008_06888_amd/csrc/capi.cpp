@@ -70,8 +70,6 @@ hipEvent_t pool_get() {
   return e;
 }
 
-// Events recorded while a graph is being captured become event-record nodes
-// of that graph; they are registered with the capture instead of drained.
 // Kernel timing brackets a launch with two pooled events on its stream.
 // Timed calls always run eagerly (a call is never captured while timing is
 // on), so every bracket times exactly one launch.
@@ -1392,9 +1390,29 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
       p.dev = nullptr;
       partition_plan(p);
       if ((rc = run_once())) break;   // warm-up (encodes and uploads the plan)
-      const auto t0 = std::chrono::steady_clock::now();
-      for (int k = 0; k < 2 && rc == 0; ++k) rc = run_once();
-      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / 2;
+      // the summed device time of the call's kernels (HIP events around each
+      // launch, so host launch gaps do not count), the least of three calls
+      double ms = 1e300;
+      for (int k = 0; k < 3 && rc == 0; ++k) {
+        prof_drain();
+        const auto before = g_prof_acc;
+        const bool was_on = g_prof_on;
+        g_prof_on = true;
+        rc = run_once();
+        g_prof_on = was_on;
+        HIP_TRY(hipStreamSynchronize(s));
+        prof_drain();
+        double sum = 0;
+        {
+          std::lock_guard<std::mutex> g(g_prof_mu);
+          for (const auto& kv : g_prof_acc) {
+            auto it = before.find(kv.first);
+            sum += kv.second.first - (it == before.end() ? 0.0 : it->second.first);
+          }
+          g_prof_acc = before;   // the caller's own timing totals are left as they were
+        }
+        if (rc == 0) ms = std::min(ms, sum);
+      }
       if (rc == 0 && ms < best) {
         best = ms;
         best_t = t;
