@@ -25,7 +25,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9 * 2      # max-plus ops/s: one term (add + max)
 # passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain 256 MiB
 # device copy reads for the same counters); profiles/k_pass_square16x16_gauss_b64.txt.
 # Set to None whenever the pass kernel changes until the counters are taken again.
-K_PASS_TRAFFIC_BYTES = 33.36e6
+K_PASS_TRAFFIC_BYTES = None
 
 
 def cpu_baseline(insts, seconds=15.0):
@@ -98,7 +98,7 @@ def bench_chimera(args):
     x = I.config_instances(4)[0]
     J = torch.tensor(x.J[None], device="cuda:0")
     plan = B.Plan(512, x.edges, chimera=(8, 8))
-    tile_bits, _ = B.autotune(plan, J)
+    tile_bits, _ = B.autotune(plan, J, config=True)
     steps = max(1, min(args.steps, 5))
     for _ in range(min(args.warmup, 1)):
         B.backward(plan, J)
@@ -162,7 +162,7 @@ def bench_uneven(args):
     t_plan = time.perf_counter() - t0
     Js = [torch.tensor(x.J, device="cuda:0") for x in insts]
     t0 = time.perf_counter()
-    tiles = [B.autotune(p, j[None])[0] for p, j in zip(plans, Js)]
+    tiles = [B.autotune(p, j[None], config=True)[0] for p, j in zip(plans, Js)]
     t_tune = time.perf_counter() - t0
     steps = max(1, min(args.steps, 3))
     for _ in range(2):
@@ -242,7 +242,7 @@ def main():
     h = torch.tensor(np.stack([x.h for x in insts]), device=dev)
 
     # tile size chosen by the autotuner on this batch (outside the timed region)
-    tile_bits, _ = B.autotune(plan, J, h)
+    tile_bits, _ = B.autotune(plan, J, h, config=True)
     info = plan.info()
     # warm-up: the second call is captured as a HIP graph, later calls replay it
     for _ in range(max(args.warmup, 2)):

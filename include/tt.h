@@ -171,14 +171,21 @@ int tt_tgemm(int32_t batch, int64_t M, int64_t N, int64_t K, const float* A, int
 int tt_graphs_enable(int32_t on);
 
 /* Tile-size autotuner (batched execution, tiles chosen per plan): times the
- * forward contraction (count = 0; tiles of up to 14 bits) or the counting
- * sweep (count = 1; up to 12 bits) of `batch` instances given as for
- * tt_contract / tt_count, on `stream`, and keeps the fastest tile size in
- * the plan for later calls. Candidates: the five sizes below the largest
- * useful one (min(maximum, state width)), never under 7 bits. Blocks until the timing is done; allocates a small output buffer.
- * chosen_bits and best_ms (milliseconds per call) may be NULL. Captured
- * graphs and device buffers of the plan are released. */
-int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, int32_t count,
+ * call the tiles will serve, on `batch` instances given as for that call, on
+ * `stream`, and keeps the fastest tile size in the plan for later calls.
+ * mode: TT_TUNE_ENERGY times tt_contract (tiles of up to 14 bits),
+ * TT_TUNE_COUNT tt_count (up to 12 bits; int32 couplings), TT_TUNE_BACKWARD
+ * tt_backward (energy, one configuration and both gradients; the backward
+ * sweep's cost grows with the spins a pass eliminates, so it can prefer
+ * smaller tiles than the energy alone). Candidates: the five sizes below the
+ * largest useful one (min(maximum, state width)), never under 7 bits. The
+ * score is the summed device time of the call's kernels, the least of three
+ * calls. Blocks until the timing is done; allocates the timed calls' outputs
+ * (freed before it returns). chosen_bits and best_ms (milliseconds per call)
+ * may be NULL. Captured graphs and device buffers of the plan are released.
+ * TT_E_INVAL for an unknown mode. */
+enum { TT_TUNE_ENERGY = 0, TT_TUNE_COUNT = 1, TT_TUNE_BACKWARD = 2 };
+int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, int32_t mode,
                      int32_t* chosen_bits, double* best_ms, void* stream);
 
 /* Per-kernel timing on the call's stream, for measurement tools: when on,

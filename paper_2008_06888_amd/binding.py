@@ -300,14 +300,23 @@ def tgemm(A, B, out=None):
     return C3 if batched else C3[0]
 
 
-def autotune(plan: Plan, J, h=None, count: bool = False):
-    """Times every tile size on these instances and keeps the fastest in the plan; returns (bits, ms per call)."""
+TUNE_ENERGY, TUNE_COUNT, TUNE_BACKWARD = 0, 1, 2
+
+
+def autotune(plan: Plan, J, h=None, count: bool = False, config: bool = False):
+    """Times every tile size on these instances and keeps the fastest in the plan; returns (bits, ms per call).
+
+    Times the call the tiles are for: contract (default), count (count=True)
+    or backward (config=True: energy, configuration and gradients)."""
     _check_inputs(plan, J, h)
+    if count and config:
+        raise ValueError("count and config exclude each other")
     if count and J.dtype != _torch().int32:
         raise TypeError("counting needs int32 couplings")
+    mode = TUNE_COUNT if count else (TUNE_BACKWARD if config else TUNE_ENERGY)
     bits = C.c_int32(0)
     ms = C.c_double(0.0)
-    _check(_lib.tt_plan_autotune(plan.handle, J.shape[0], _dtype_code(J), _ptr(J), _ptr(h), int(bool(count)),
+    _check(_lib.tt_plan_autotune(plan.handle, J.shape[0], _dtype_code(J), _ptr(J), _ptr(h), mode,
                                  C.byref(bits), C.byref(ms), _stream()))
     return bits.value, ms.value
 

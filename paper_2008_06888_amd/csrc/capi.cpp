@@ -504,7 +504,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
         cur_t = P.t;
       }
       threads = std::max(threads, 1 << P.tb);
-      lds = std::max(lds, sizeof(float) << P.t);
+      lds = std::max(lds, pass_lds_bytes(P.t));
       PassItem it;
       std::memset(&it, 0, sizeof(it));
       it.P = static_cast<const DevPass2*>(g.dc->d_passes.p) + q;
@@ -1358,25 +1358,41 @@ int tt_tgemm(int32_t batch, int64_t M, int64_t N, int64_t K, const float* A, int
   return TT_OK;
 }
 
-int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, int32_t count,
+int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, int32_t mode,
                      int32_t* chosen_bits, double* best_ms, void* stream) {
   try {
+    if (mode < TT_TUNE_ENERGY || mode > TT_TUNE_BACKWARD) return fail(TT_E_INVAL, "unknown autotune mode");
+    const bool count = mode == TT_TUNE_COUNT;
     if (int r = check_common(plan, batch, count ? TT_I32 : dtype, J, h)) return r;
     Plan& p = *reinterpret_cast<Plan*>(plan);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int hi = count ? 12 : 14;
     const int top = std::min(hi, std::max(7, p.width));   // tiles at least as wide as the state are all alike
     const int lo = std::max(7, top - 4);                   // five candidates at most
+    // outputs of the timed calls: energies, and for the backward sweep one
+    // configuration with both gradients
+    const size_t nb = (size_t)batch;
+    const size_t o_en = 0, o_dJ = o_en + nb * sizeof(double), o_dh = o_dJ + nb * (size_t)p.m * sizeof(float),
+                 o_sg = o_dh + nb * (size_t)p.n * sizeof(float);
+    const size_t out_bytes = mode == TT_TUNE_BACKWARD ? o_sg + nb * (size_t)p.n : nb * sizeof(double);
     DevBuf out;
-    if (int r = out.ensure((size_t)batch * 4 * sizeof(double))) return r;
-    std::vector<int64_t> en((size_t)batch);
-    std::vector<uint64_t> res((size_t)batch * 3);
+    if (int r = out.ensure(out_bytes)) return r;
+    char* const ob = static_cast<char*>(out.p);
+    std::vector<int64_t> en(nb);
+    std::vector<uint64_t> res(nb * 3);
     const bool graphs = g_graphs_on;
     g_graphs_on = false;   // timing of eager launches; no capture of discarded plans
     auto run_once = [&]() -> int {
       if (count) return tt_count(plan, batch, static_cast<const int32_t*>(J), static_cast<const int32_t*>(h),
                                  en.data(), res.data(), stream);
-      if (int r = tt_contract(plan, batch, dtype, J, h, static_cast<double*>(out.p), stream)) return r;
+      if (mode == TT_TUNE_BACKWARD) {
+        if (int r = tt_backward(plan, batch, dtype, J, h, reinterpret_cast<double*>(ob + o_en),
+                                reinterpret_cast<int8_t*>(ob + o_sg), reinterpret_cast<float*>(ob + o_dJ),
+                                reinterpret_cast<float*>(ob + o_dh), stream))
+          return r;
+      } else if (int r = tt_contract(plan, batch, dtype, J, h, reinterpret_cast<double*>(ob + o_en), stream)) {
+        return r;
+      }
       HIP_TRY(hipStreamSynchronize(s));
       return 0;
     };

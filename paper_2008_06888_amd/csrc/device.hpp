@@ -48,6 +48,7 @@ struct FOp {
   int32_t te[STAR_TERMS];   // star edges
   uint8_t wl[STAR_TERMS];   // partner's index among the stage bits (255: not a stage bit)
 };
+// (STAR: lidx is the index of `bit` among the stage bits, 4 if it is not one.)
 
 // A stage: up to four gate bits applied in registers, each thread owning
 // groups of 16 entries that span the stage bits.
@@ -86,22 +87,16 @@ struct DevPass2 {
   int32_t pad_tb;
   uint8_t fin[48];       // fre[k] -> input address bit (NO_POS if none)
   uint8_t fout[48];      // fre[k] -> output address bit (NO_POS if none)
+  int32_t op_begin, n_ops;   // the pass's fused ops (all its stages)
 };
 
-// An op with its constants resolved for one instance and one tile (built in
-// LDS at the start of a pass): GATE keeps 2J and the four constants J +- cst
-// +- J_first; STAR keeps cst; extra star terms on resident slots follow.
-struct ROp {
-  float J2, p0, m0, p1, m1;
-  uint8_t kind, lidx, wf, nx;   // wf: first resident partner bit (255: none)
-  uint8_t xw[3];                // further resident partners
-  uint8_t sbit;                 // STAR: tile bit of the spin (255: fixed slot, sign folded)
-  float xJ[3];
-  uint8_t wl;                   // wf's index among the stage bits (4: not a stage bit)
-  uint8_t sl;                   // STAR: sbit's index among the stage bits (4: not a stage bit)
-  uint8_t xl[3];                // xw's indices among the stage bits (4: not a stage bit)
-  uint8_t pad[3];
-};
+// Fused ops of one pass: the pass kernel resolves them one per lane of a
+// wave (the planner keeps passes within this).
+constexpr int MAX_PASS_OPS = 64;
+
+// Dynamic LDS of a pass launch: the tile of 2^t floats.
+inline size_t pass_lds_bytes(int t) { return sizeof(float) << t; }
+constexpr size_t PASS_LDS_MAX = sizeof(float) << 14;
 
 // Backward walk: a spin eliminated in a pass (candidate bit k) and the slot it
 // held when the pass started (-1 if it entered during the pass).

@@ -39,6 +39,13 @@ __device__ __forceinline__ gptr<T> as_global(T* p) {
 
 // LDS records reached through pointers: the local address space (ds_*
 // accesses instead of flat ones).
-using LROp = __attribute__((address_space(3))) ROp;
+using LFloat = __attribute__((address_space(3))) float;
+using LByte = __attribute__((address_space(3))) char;
+
+// The float at an LDS byte address. Only for kernels without static LDS,
+// whose dynamic region starts at address 0 (their launchers check it).
+__device__ __forceinline__ LFloat& lds_at(uint32_t addr) {
+  return *(LFloat*)(uintptr_t)(addr);
+}
 
 }  // namespace tt

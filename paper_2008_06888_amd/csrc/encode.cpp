@@ -310,7 +310,7 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
       st2.op_begin = (int)out.fops.size();
       for (size_t k = b0; k < e; ++k) {
         FOp x = f[k];
-        if (x.kind != FK_STAR) x.lidx = (uint8_t)(std::find(S.begin(), S.end(), (int)x.bit) - S.begin());
+        x.lidx = (uint8_t)(std::find(S.begin(), S.end(), (int)x.bit) - S.begin());   // 4 if absent
         for (int q = 0; q < STAR_TERMS; ++q) {
           x.wl[q] = 255;
           if (q < x.nt && x.w[q] < SLOT_FIXED) {
@@ -325,6 +325,9 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
       b0 = e;
     }
     d.n_stages = (int)out.stages.size() - d.stage_begin;
+    d.op_begin = d.n_stages ? out.stages[d.stage_begin].op_begin : (int)out.fops.size();
+    d.n_ops = d.n_stages ? out.stages.back().op_end - d.op_begin : 0;
+    if (d.n_ops > MAX_PASS_OPS) return "a pass holds more ops than the pass kernel resolves (one per lane)";
     // backward tables
     const std::vector<int>& start = slot_spin_at[ps.op_begin];
     const std::vector<int>& end = slot_spin_at[ps.op_end];

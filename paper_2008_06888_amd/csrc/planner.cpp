@@ -20,7 +20,7 @@ namespace tt {
 
 namespace {
 
-constexpr int MAX_OPS_PER_PASS = 256;   // the energy kernel holds a pass's ops in LDS
+constexpr int MAX_OPS_PER_PASS = 64;   // the energy kernel resolves a pass's ops one per lane of a wave
 
 struct Adj {
   std::vector<std::vector<std::pair<int, int>>> nb;  // (neighbour, edge)

@@ -71,105 +71,161 @@ __device__ __forceinline__ uint64_t uni64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// A lane value the compiler may not re-derive (keeps a pre-shifted LDS
+// address part from being folded back into a shift after the XOR).
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Raw buffer resource over up to 4 GiB from p (offsets checked by the
+// caller to stay below 2^32 bytes).
+template <typename P>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(P p) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)p, 0, 0x7fffffff, 0x00020000);
+}
+
 // Value (0/1) of tile bit w of an entry index.
 __device__ __forceinline__ uint32_t tbit(uint32_t ix, uint32_t w) { return __builtin_amdgcn_ubfe(ix, w, 1); }
 
-constexpr int MAX_PASS_OPS = 256;   // fused ops of one pass held in LDS (the planner keeps passes below)
 
-// Resolves one op of a pass for this instance and tile into its LDS record
-// (see ROp). Fields are written in place: no private arrays.
+// The pass's ops resolved for this instance and tile, one op per lane (lane
+// o holds op o of the pass; a pass has at most 64): GATE keeps 2J and the
+// four constants J +- cst +- J_first; STAR keeps cst; up to three further
+// resident partners follow. Every wave resolves the ops itself, in
+// registers, while its tile loads are in flight.
+struct OpLanes {
+  float J2, p0, m0, p1, m1;
+  // kind | lidx << 4 | wf << 8 | sbit << 16 | wl << 24 | sl << 27 | nx << 30
+  // (wf: first resident partner bit, 255 none; sbit: STAR spin's tile bit,
+  // 255 fixed slot with its sign folded; wl / sl: their stage-bit indices,
+  // 4 if not a stage bit; nx: further partners)
+  uint32_t pk;
+  float x0, x1, x2;   // further partners' couplings (STAR: with the spin's sign)
+  uint32_t xwl;       // partner k: tile bit at 7k, stage-bit index at 7k + 4
+};
+
+// An op's record and the couplings and field it reads, loaded as soon as the
+// pass is known (they do not depend on the tile).
+struct OpIn {
+  FOp f;
+  float hv, Je, Jt[STAR_TERMS];
+};
+
 template <typename IT>
-__device__ __forceinline__ void resolve_op(cptr<FOp> op, LROp* r, cptr<IT> Jrow, cptr<IT> hrow, uint64_t bs,
-                                           cptr<uint8_t> sb) {
-  float cst = op->hspin >= 0 ? ldv(hrow, op->hspin) : 0.f;
-  const uint8_t kind = op->kind;
-  const int nt = op->nt;
-  for (int k = 0; k < nt; ++k) {
-    const uint8_t w = op->w[k];
-    if (w >= SLOT_FIXED) cst += ((bs >> (w - SLOT_FIXED)) & 1ull) ? -ldv(Jrow, op->te[k]) : ldv(Jrow, op->te[k]);
-  }
-  r->kind = kind;
-  r->lidx = op->lidx;
-  r->nx = 0;
-  r->sbit = 255;
-  r->sl = 4;
-  r->wf = 255;
-  r->wl = 4;
-  r->J2 = r->p0 = r->m0 = r->p1 = r->m1 = 0.f;
-  float sg = 1.f;
-  float J = 0.f;
-  if (kind == FK_STAR) {
-    if (op->bit >= SLOT_FIXED) {
-      if ((bs >> (op->bit - SLOT_FIXED)) & 1ull) sg = -1.f;
-    } else {
-      r->sbit = op->bit;
-      for (int l = 0; l < 4; ++l)
-        if (sb[l] == op->bit) r->sl = (uint8_t)l;
-    }
-    r->p0 = sg * cst;
-  } else if (kind == FK_GATE) {
-    J = ldv(Jrow, op->edge);
-    r->J2 = J + J;
-    r->p0 = r->m0 = J + cst;
-    r->p1 = r->m1 = J - cst;
-  } else {
-    return;
-  }
-  for (int k = 0; k < nt; ++k) {
-    const uint8_t w = op->w[k];
-    if (w >= SLOT_FIXED) continue;
-    const float Jk = ldv(Jrow, op->te[k]);
-    const uint8_t wl = op->wl[k] < 4 ? op->wl[k] : 4;
-    if (r->wf == 255) {
-      r->wf = w;
-      r->wl = wl;
-      if (kind == FK_STAR) {
-        r->m0 = sg * Jk;
-      } else {
-        r->p0 = J + cst + Jk;
-        r->m0 = J + cst - Jk;
-        r->p1 = J - cst - Jk;
-        r->m1 = J - cst + Jk;
-      }
-    } else {
-      const int x = r->nx;
-      r->xw[x] = w;
-      r->xl[x] = wl;
-      r->xJ[x] = kind == FK_STAR ? sg * Jk : Jk;
-      r->nx = (uint8_t)(x + 1);
-    }
-  }
+__device__ __forceinline__ OpIn load_op(cptr<FOp> op, cptr<IT> Jrow, cptr<IT> hrow) {
+  OpIn x;
+  x.f = ldc(op);
+  x.hv = x.f.hspin >= 0 ? ldv(hrow, x.f.hspin) : 0.f;
+  x.Je = x.f.kind == FK_GATE ? ldv(Jrow, x.f.edge) : 0.f;
+#pragma unroll
+  for (int k = 0; k < STAR_TERMS; ++k) x.Jt[k] = k < x.f.nt ? ldv(Jrow, x.f.te[k]) : 0.f;
+  return x;
 }
 
-// The fields of an op descriptor (read from LDS) that every lane shares,
-// made wave-uniform: they live in scalar registers, so the dispatch on the
-// op's kind and bits is a scalar branch and its coefficients are scalar
-// operands. The rarely used extra partners stay in LDS.
+// The op resolved for the tile whose fixed slots hold the bits bs.
+__device__ __forceinline__ OpLanes resolve_lane(const OpIn& x, uint64_t bs) {
+  const FOp& op = x.f;
+  OpLanes r{0.f, 0.f, 0.f, 0.f, 0.f, 0u, 0.f, 0.f, 0.f, 0u};
+  float cst = x.hv;
+  const uint32_t kind = op.kind, lidx = op.lidx;
+  const int nt = op.nt;
+#pragma unroll
+  for (int k = 0; k < STAR_TERMS; ++k) {
+    const uint8_t w = op.w[k];
+    if (k < nt && w >= SLOT_FIXED) cst += ((bs >> (w - SLOT_FIXED)) & 1ull) ? -x.Jt[k] : x.Jt[k];
+  }
+  uint32_t nx = 0, sbit = 255, sl = 4, wf = 255, wl = 4;
+  float sg = 1.f;
+  const float J = x.Je;
+  if (kind == FK_STAR) {
+    if (op.bit >= SLOT_FIXED) {
+      if ((bs >> (op.bit - SLOT_FIXED)) & 1ull) sg = -1.f;
+    } else {
+      sbit = op.bit;
+      sl = lidx;
+    }
+    r.p0 = sg * cst;
+  } else if (kind == FK_GATE) {
+    r.J2 = J + J;
+    r.p0 = r.m0 = J + cst;
+    r.p1 = r.m1 = J - cst;
+  }
+  if (kind == FK_STAR || kind == FK_GATE) {
+#pragma unroll
+    for (int k = 0; k < STAR_TERMS; ++k) {
+      const uint8_t w = op.w[k];
+      if (k >= nt || w >= SLOT_FIXED) continue;
+      const float Jk = x.Jt[k];
+      const uint32_t l = op.wl[k] < 4 ? op.wl[k] : 4;
+      if (wf == 255) {
+        wf = w;
+        wl = l;
+        if (kind == FK_STAR) {
+          r.m0 = sg * Jk;
+        } else {
+          r.p0 = J + cst + Jk;
+          r.m0 = J + cst - Jk;
+          r.p1 = J - cst - Jk;
+          r.m1 = J - cst + Jk;
+        }
+      } else {
+        const float xj = kind == FK_STAR ? sg * Jk : Jk;
+        if (nx == 0) r.x0 = xj;
+        else if (nx == 1) r.x1 = xj;
+        else r.x2 = xj;
+        r.xwl |= ((uint32_t)w | (l << 4)) << (7 * nx);
+        ++nx;
+      }
+    }
+  }
+  r.pk = kind | (lidx << 4) | (wf << 8) | (sbit << 16) | (wl << 24) | (sl << 27) | (nx << 30);
+  return r;
+}
+
+// The fields of an op that every lane shares, made wave-uniform: they live in
+// scalar registers, so the dispatch on the op's kind and bits is a scalar
+// branch and its coefficients are scalar operands.
 struct UOp {
   float J2, p0, m0, p1, m1;
   uint32_t kind, lidx, wf, nx, sbit, wl, sl;
 };
 
-__device__ __forceinline__ float ufl(float x) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
-}
-__device__ __forceinline__ uint32_t uin(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+// Further resident partners of an op (rare), also wave-uniform.
+struct XOp {
+  float xJ[3];
+  uint32_t xwl;
+};
 
-__device__ __forceinline__ UOp uniform_op(const LROp& r) {
+__device__ __forceinline__ float rl_f(float x, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
+}
+
+__device__ __forceinline__ UOp op_at(const OpLanes& R, int k) {
   UOp u;
-  u.J2 = ufl(r.J2);
-  u.p0 = ufl(r.p0);
-  u.m0 = ufl(r.m0);
-  u.p1 = ufl(r.p1);
-  u.m1 = ufl(r.m1);
-  u.kind = uin(r.kind);
-  u.lidx = uin(r.lidx);
-  u.wf = uin(r.wf);
-  u.nx = uin(r.nx);
-  u.sbit = uin(r.sbit);
-  u.wl = uin(r.wl);
-  u.sl = uin(r.sl);
+  u.J2 = rl_f(R.J2, k);
+  u.p0 = rl_f(R.p0, k);
+  u.m0 = rl_f(R.m0, k);
+  u.p1 = rl_f(R.p1, k);
+  u.m1 = rl_f(R.m1, k);
+  const uint32_t pk = (uint32_t)__builtin_amdgcn_readlane((int)R.pk, k);
+  u.kind = pk & 15u;
+  u.lidx = (pk >> 4) & 15u;
+  u.wf = (pk >> 8) & 255u;
+  u.sbit = (pk >> 16) & 255u;
+  u.wl = (pk >> 24) & 7u;
+  u.sl = (pk >> 27) & 7u;
+  u.nx = pk >> 30;
   return u;
+}
+
+__device__ __forceinline__ XOp xop_at(const OpLanes& R, int k) {
+  XOp x;
+  x.xJ[0] = rl_f(R.x0, k);
+  x.xJ[1] = rl_f(R.x1, k);
+  x.xJ[2] = rl_f(R.x2, k);
+  x.xwl = (uint32_t)__builtin_amdgcn_readlane((int)R.xwl, k);
+  return x;
 }
 
 // Bit (0/1) of register entry J (a compile-time index) for a slot that is
@@ -181,10 +237,11 @@ __device__ __forceinline__ uint32_t rbit(uint32_t l, uint32_t w, uint32_t gb) {
 
 // Extra star terms of a gate (rare: more than one resident partner).
 template <int L>
-__device__ __forceinline__ void gate_extra(float (&e0)[8], float (&e1)[8], const LROp& r, uint32_t gb) {
-  for (int k = 0; k < r.nx; ++k) {
-    const uint32_t w = r.xw[k], l = r.xl[k];
-    const float Jk = r.xJ[k];
+__device__ __forceinline__ void gate_extra(float (&e0)[8], float (&e1)[8], const XOp& x, uint32_t nx, uint32_t gb) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint32_t w = (x.xwl >> (7 * k)) & 15u, l = (x.xwl >> (7 * k + 4)) & 7u;
+    const float Jk = (uint32_t)k < nx ? x.xJ[k] : 0.f;
 #define TT_EXTRA(P)                                                            \
   {                                                                           \
     constexpr int j0 = ((P >> L) << (L + 1)) | (P & ((1 << L) - 1));         \
@@ -258,7 +315,7 @@ __device__ __forceinline__ void gate_lw(const float (&a)[16], float (&o)[16], ui
 
 template <int L>
 __device__ __forceinline__ void gate_x(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u,
-                                       const LROp& r) {
+                                       const XOp& x) {
   const float J2 = u.J2;
   float e0[8], e1[8];
 #pragma unroll
@@ -278,7 +335,7 @@ __device__ __forceinline__ void gate_x(const float (&a)[16], float (&o)[16], uin
     TT_FIRST(0) TT_FIRST(1) TT_FIRST(2) TT_FIRST(3) TT_FIRST(4) TT_FIRST(5) TT_FIRST(6) TT_FIRST(7)
 #undef TT_FIRST
   }
-  gate_extra<L>(e0, e1, r, gb);
+  gate_extra<L>(e0, e1, x, u.nx, gb);
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
     const int j0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
@@ -300,15 +357,24 @@ __device__ __forceinline__ void cut_l(const float (&a)[16], float (&o)[16]) {
   }
 }
 
+// Signed coupling of further partner K for register entry J.
+template <int J, int K>
+__device__ __forceinline__ float xterm(const XOp& x, uint32_t gb) {
+  const uint32_t xw = (x.xwl >> (7 * K)) & 15u, xl = (x.xwl >> (7 * K + 4)) & 7u;
+  return rbit<J>(xl, xw, gb) ? -x.xJ[K] : x.xJ[K];
+}
+
 // Star of a spin that entered without a gate: x += sigma(spin) * sw.
 __device__ __forceinline__ void star16(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u,
-                                       const LROp& r) {
+                                       const XOp& x) {
   const uint32_t wl = u.wl, wf = u.wf, sl = u.sl, sbit = u.sbit;
 #define TT_STAR(J)                                                              \
   {                                                                            \
     float sw = u.p0;                                                           \
     if (wf != 255) sw += rbit<J>(wl, wf, gb) ? -u.m0 : u.m0;                   \
-    for (uint32_t k = 0; k < u.nx; ++k) sw += rbit<J>(r.xl[k], r.xw[k], gb) ? -r.xJ[k] : r.xJ[k]; \
+    if (u.nx > 0) sw += xterm<J, 0>(x, gb);                                     \
+    if (u.nx > 1) sw += xterm<J, 1>(x, gb);                                     \
+    if (u.nx > 2) sw += xterm<J, 2>(x, gb);                                     \
     o[J] = a[J] + ((sbit != 255 && rbit<J>(sl, sbit, gb)) ? -sw : sw);         \
   }
   TT_STAR(0) TT_STAR(1) TT_STAR(2) TT_STAR(3) TT_STAR(4) TT_STAR(5) TT_STAR(6) TT_STAR(7)
@@ -317,10 +383,13 @@ __device__ __forceinline__ void star16(const float (&a)[16], float (&o)[16], uin
 }
 
 // One op of a stage: reads a, writes every entry of o.
-__device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], uint32_t gb, const LROp& r) {
-  const UOp u = uniform_op(r);
+__device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], uint32_t gb, const OpLanes& R,
+                                         int k) {
+  const UOp u = op_at(R, k);
   if (u.kind == FK_STAR) {
-    star16(a, o, gb, u, r);
+    XOp x{{0.f, 0.f, 0.f}, 0u};
+    if (u.nx) x = xop_at(R, k);
+    star16(a, o, gb, u, x);
   } else if (u.kind == FK_CUT) {
     switch (u.lidx) {
       case 0: cut_l<0>(a, o); break;
@@ -329,11 +398,12 @@ __device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], u
       default: cut_l<3>(a, o); break;
     }
   } else if (u.nx) {
+    const XOp x = xop_at(R, k);
     switch (u.lidx) {
-      case 0: gate_x<0>(a, o, gb, u, r); break;
-      case 1: gate_x<1>(a, o, gb, u, r); break;
-      case 2: gate_x<2>(a, o, gb, u, r); break;
-      default: gate_x<3>(a, o, gb, u, r); break;
+      case 0: gate_x<0>(a, o, gb, u, x); break;
+      case 1: gate_x<1>(a, o, gb, u, x); break;
+      case 2: gate_x<2>(a, o, gb, u, x); break;
+      default: gate_x<3>(a, o, gb, u, x); break;
     }
   } else {
     switch (u.lidx) {
@@ -347,9 +417,10 @@ __device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], u
 
 template <typename IT>
 __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items, int n_items) {
-  extern __shared__ float tile[];
-  __shared__ ROp rops_sh[MAX_PASS_OPS];
-  LROp* const rops = (LROp*)(rops_sh);
+  // LDS holds the tile only (2^t floats, dynamic, so it starts at address
+  // 0). The byte address of a tile entry is the XOR of a lane's part and a
+  // scalar part (the swizzle is linear over GF(2) and the two parts have
+  // disjoint bits): one VALU op per access.
   const int64_t wg = blockIdx.x;
   int it = 0;
   const cptr<PassItem> citems = as_const(items);
@@ -362,6 +433,14 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   uint64_t tid_bits;
   if (!wg_to_tile((uint64_t)(wg - I.wg_begin), P.n_free, I.batch, I.xcd_group, &inst, &tid_bits)) return;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const cptr<IT> Jrow = as_const(static_cast<const IT*>(I.J)) + inst * I.jst;
+  const cptr<IT> hrow = I.h ? as_const(static_cast<const IT*>(I.h)) + inst * I.hst : nullptr;
+  // the pass's ops: lane o of every wave takes op o; their records and
+  // couplings are read first, so these loads overlap the tile set-up below
+  const int n_ops = P.n_ops;
+  OpIn opin;
+  if (lane < n_ops) opin = load_op<IT>(fops + P.op_begin + lane, Jrow, hrow);
   const int t = P.t;
   const int tb = P.tb;              // this tile uses threads 0 .. 2^tb - 1
   const uint32_t size = 1u << t;
@@ -370,7 +449,6 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   // an OR across the wave; no serial loop over dependent loads
   uint64_t bs = 0, in_base = 0, out_base = 0, dropped = 0;
   {
-    const int lane = tid & 63;
     if (lane < P.n_free) {
       const uint64_t b = (tid_bits >> lane) & 1ull;
       const uint32_t fi = P.fin[lane], fo = P.fout[lane];
@@ -385,8 +463,6 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
     dropped = uni64(wave_or(dropped));
   }
   const bool stored = dropped == 0;   // only the copy with dropped slots at 0 is kept
-  const cptr<IT> Jrow = as_const(static_cast<const IT*>(I.J)) + inst * I.jst;
-  const cptr<IT> hrow = I.h ? as_const(static_cast<const IT*>(I.h)) + inst * I.hst : nullptr;
   const cptr<float> in = as_const(I.in) + inst * I.in_st;     // read-only in this pass (in != out)
   const gptr<float> out = as_global(I.out) + inst * I.out_st;
   // load: enumeration index u = tid + 2^tb k; bit q of u -> tile bit / address
@@ -397,61 +473,102 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   const int nk_ld = 1 << (t - nb_ld);
   uint32_t ti_ld = 0;
   float vals[16];
+  const bool init = P.init != 0;   // first pass: the state starts at zero, nothing is read
   {
-    uint64_t ad_lo = 0;
-    for (int q = 0; q < nb_ld; ++q)
-      if ((tid >> q) & 1) {
-        ti_ld |= P.ld_bti[q];
-        ad_lo |= P.ld_bad[q];
-      }
-    const cptr<float> src = in + in_base;
-    if (loader) {
+    // the pass's tables are read unconditionally, so their scalar loads
+    // issue together instead of one dependent round trip per element
+    uint32_t bti[10];
+    uint64_t bad[10], had[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k < nk_ld) vals[k] = P.init ? 0.f : src[ad_lo | P.ld_had[k]];
+    for (int q = 0; q < 10; ++q) {   // tb <= 10
+      bti[q] = P.ld_bti[q];
+      bad[q] = P.ld_bad[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) had[k] = P.ld_had[k];
+    uint64_t ad_lo = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const uint32_t m = (q < nb_ld) ? (uint32_t)0 - (((uint32_t)tid >> q) & 1u) : 0u;
+      ti_ld |= bti[q] & m;
+      ad_lo |= bad[q] & (uint64_t)(int64_t)(int32_t)m;
+      if (q < nb_ld) all |= bad[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) all |= had[k];
+    const cptr<float> src = in + in_base;
+    if (init) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) vals[k] = 0.f;
+    } else if (loader) {
+      if (nk_ld == 16 && all < (1ull << 30)) {
+        // every offset in the tile fits 32 bits: buffer loads with the
+        // lane's offset in a VGPR and each k's in an SGPR, no per-load
+        // address arithmetic
+        const __amdgpu_buffer_rsrc_t rs = raw_rsrc(src);
+        const uint32_t off = (uint32_t)ad_lo << 2;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          vals[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)(had[k] << 2), 0));
+      } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < nk_ld) vals[k] = src[ad_lo | had[k]];
+      }
     }
   }
-  // resolve the pass's ops for this instance and tile
-  const int op0 = P.n_stages ? stages[P.stage_begin].op_begin : 0;
-  const int n_ops = P.n_stages ? stages[P.stage_begin + P.n_stages - 1].op_end - op0 : 0;
-  for (int o = tid; o < n_ops; o += (int)blockDim.x) {
-    // the stage of op o (for the stage indices of its bits)
-    int si = 0;
-    while (si + 1 < P.n_stages && stages[P.stage_begin + si + 1].op_begin <= op0 + o) ++si;
-    resolve_op<IT>(fops + op0 + o, rops + o, Jrow, hrow, bs, stages[P.stage_begin + si].sb);
-  }
+  // resolve the ops for this tile (the signs of its fixed slots)
+  OpLanes R{0.f, 0.f, 0.f, 0.f, 0.f, 0u, 0.f, 0.f, 0.f, 0u};
+  if (lane < n_ops) R = resolve_lane(opin, bs);
   if (loader) {
+    uint32_t hs[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-      if (k < nk_ld) tile[swz(ti_ld | P.ld_hti[k])] = vals[k];
+    for (int k = 0; k < 16; ++k) hs[k] = swz(P.ld_hti[k]) << 2;
+    const uint32_t ls = opaque(swz(ti_ld) << 2);
+    if (nk_ld == 16) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lds_at(ls ^ hs[k]) = vals[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk_ld) lds_at(ls ^ hs[k]) = vals[k];
+    }
   }
   __syncthreads();
   const int n_stages = P.n_stages;
+  const uint32_t groups = size >> 4;   // 16 entries each; 1 <= groups <= 2^tb
+  // one group per thread. With fewer than 64 groups (t < 10) the first wave
+  // does them all, its lanes repeating groups: lanes of one wave read before
+  // any of them writes and write the same values, and every lane stays
+  // active, so op words can be read from any lane. With 64 or more, whole
+  // waves beyond the groups (a launch with more threads than this tile uses)
+  // sit the stages out.
+  const bool active = (uint32_t)tid < (groups > 64u ? groups : 64u);
+  const uint32_t g = (uint32_t)tid & (groups - 1);
   for (int s = 0; s < n_stages; ++s) {
-    const cptr<DevStage> ST = stages + P.stage_begin + s;
-    const uint32_t groups = size >> 4;
-    const int ob = ST->op_begin - op0, oe = ST->op_end - op0;
-    uint32_t so[16];
+    if (active) {
+      const cptr<DevStage> ST = stages + P.stage_begin + s;
+      const int ob = ST->op_begin - P.op_begin, oe = ST->op_end - P.op_begin;
+      uint32_t so[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) so[j] = ST->soff[j];
-    for (uint32_t g = tid; g < groups; g += 1u << tb) {
+      for (int j = 0; j < 16; ++j) so[j] = ST->soff[j] << 2;
       const uint32_t gb = (uint32_t)ST->g_lo[g & 31u] | (uint32_t)ST->g_hi[g >> 5];
-      const uint32_t sg = (uint32_t)ST->sg_lo[g & 31u] ^ (uint32_t)ST->sg_hi[g >> 5];
+      const uint32_t sg = opaque(((uint32_t)ST->sg_lo[g & 31u] ^ (uint32_t)ST->sg_hi[g >> 5]) << 2);
       float va[16], vb[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) va[j] = tile[sg ^ so[j]];
+      for (int j = 0; j < 16; ++j) va[j] = lds_at(sg ^ so[j]);
       // ops in pairs: va -> vb -> va; an odd last op copies its result back
       for (int o = ob; o < oe; o += 2) {
-        apply_op(va, vb, gb, rops[o]);
+        apply_op(va, vb, gb, R, o);
         if (o + 1 < oe) {
-          apply_op(vb, va, gb, rops[o + 1]);
+          apply_op(vb, va, gb, R, o + 1);
         } else {
 #pragma unroll
           for (int j = 0; j < 16; ++j) va[j] = vb[j];
         }
       }
 #pragma unroll
-      for (int j = 0; j < 16; ++j) tile[sg ^ so[j]] = va[j];
+      for (int j = 0; j < 16; ++j) lds_at(sg ^ so[j]) = va[j];
     }
     __syncthreads();
   }
@@ -459,24 +576,52 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   // store, enumerating the tile in the order of the output layout
   {
     const int ns = P.n_st;
+    uint32_t bti[10], hs[16];
+    uint64_t bad[10], had[16];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {   // tb <= 10
+      bti[q] = P.st_bti[q];
+      bad[q] = P.st_bad[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      hs[k] = swz(P.st_hti[k]) << 2;
+      had[k] = P.st_had[k];
+    }
     uint32_t ti_lo = 0;
-    uint64_t ad_lo = 0;
+    uint64_t ad_lo = 0, all = 0;
     const int nb = ns < tb ? ns : tb;
-    for (int q = 0; q < nb; ++q)
-      if ((tid >> q) & 1) {
-        ti_lo |= P.st_bti[q];
-        ad_lo |= P.st_bad[q];
-      }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const uint32_t m = (q < nb) ? (uint32_t)0 - (((uint32_t)tid >> q) & 1u) : 0u;
+      ti_lo |= bti[q] & m;
+      ad_lo |= bad[q] & (uint64_t)(int64_t)(int32_t)m;
+      if (q < nb) all |= bad[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) all |= had[k];
     const gptr<float> dst = out + out_base;
     if (tid < (1 << nb)) {
       const int nk = 1 << (ns - nb);
+      const uint32_t ls = opaque(swz(ti_lo) << 2);
       float vals[16];
+      if (nk == 16 && all < (1ull << 30)) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k < nk) vals[k] = tile[swz(ti_lo | P.st_hti[k])];
+        for (int k = 0; k < 16; ++k) vals[k] = lds_at(ls ^ hs[k]);
+        const __amdgpu_buffer_rsrc_t rs = raw_rsrc(dst);
+        const uint32_t off = (uint32_t)ad_lo << 2;
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k < nk) dst[ad_lo | P.st_had[k]] = vals[k];
+        for (int k = 0; k < 16; ++k)
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, vals[k]), rs, (int)off,
+                                                (int)(had[k] << 2), 0);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < nk) vals[k] = lds_at(ls ^ hs[k]);
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < nk) dst[ad_lo | had[k]] = vals[k];
+      }
     }
   }
 }
@@ -822,12 +967,16 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
 // Raises the dynamic LDS limit of a kernel once (static tables come on top).
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t bytes) {
-  if (bytes < 32768) return hipSuccess;
   static int done[2] = {0, 0};
   const int slot = (reinterpret_cast<const void*>(kernel) == reinterpret_cast<const void*>(k_pass<float>)) ? 0 : 1;
   if (done[slot]) return hipSuccess;
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+  // the pass kernel addresses LDS from 0: it must have no static LDS
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel));
+  if (e != hipSuccess) return e;
+  if (fa.sharedSizeBytes != 0) return hipErrorInvalidConfiguration;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)bytes);
   if (e == hipSuccess) done[slot] = 1;
   return e;
 }
@@ -836,11 +985,11 @@ hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int thr
                        hipStream_t stream) {
   if (n_wg >= (1ll << 31) || threads < 64 || threads > NT || lds > 65536) return hipErrorInvalidConfiguration;
   if (dtype == 0) {
-    hipError_t e = allow_lds(k_pass<float>, 65536);
+    hipError_t e = allow_lds(k_pass<float>, PASS_LDS_MAX);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pass<float>, dim3((uint32_t)n_wg), dim3(threads), lds, stream, items, n_items);
   } else {
-    hipError_t e = allow_lds(k_pass<int32_t>, 65536);
+    hipError_t e = allow_lds(k_pass<int32_t>, PASS_LDS_MAX);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pass<int32_t>, dim3((uint32_t)n_wg), dim3(threads), lds, stream, items, n_items);
   }

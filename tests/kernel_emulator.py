@@ -23,7 +23,8 @@ class DevPass2(C.Structure):
                 ("n_ld", C.c_int32), ("n_st", C.c_int32), ("ld_bti", C.c_uint32 * 16), ("st_bti", C.c_uint32 * 16),
                 ("ld_bad", C.c_uint64 * 16), ("st_bad", C.c_uint64 * 16), ("ld_hti", C.c_uint32 * 16),
                 ("st_hti", C.c_uint32 * 16), ("ld_had", C.c_uint64 * 16), ("st_had", C.c_uint64 * 16),
-                ("tb", C.c_int32), ("pad_tb", C.c_int32), ("fin", C.c_uint8 * 48), ("fout", C.c_uint8 * 48)]
+                ("tb", C.c_int32), ("pad_tb", C.c_int32), ("fin", C.c_uint8 * 48), ("fout", C.c_uint8 * 48),
+                ("op_begin", C.c_int32), ("n_ops", C.c_int32)]
 
 
 class DevStage(C.Structure):
@@ -115,6 +116,12 @@ def forward(prog, width, J, h, x0=None, after_pass=None):
                 a |= P.ld_had[hi]
                 tile[ti] = 0.0 if P.init else src[in_base | a]
             assert not np.any(np.isnan(tile))
+            if P.n_stages:
+                stg = prog["stages"]
+                assert P.op_begin == stg[P.stage_begin].op_begin
+                assert P.n_ops == stg[P.stage_begin + P.n_stages - 1].op_end - P.op_begin <= 64
+            else:
+                assert P.n_ops == 0
             for si in range(P.n_stages):
                 ST = prog["stages"][P.stage_begin + si]
                 sb = [ST.sb[l] for l in range(4)]
@@ -125,6 +132,8 @@ def forward(prog, width, J, h, x0=None, after_pass=None):
                     assert ST.soff[j] == _swz(sum((1 << sb[l]) for l in range(4) if (j >> l) & 1))
                 for o in range(ST.op_begin, ST.op_end):
                     op = prog["fops"][o]
+                    # the op's bit among the stage bits (4: not a stage bit, or a fixed slot)
+                    assert op.lidx == (sb.index(op.bit) if op.bit in sb else 4)
                     for k in range(op.nt):
                         if op.w[k] < SLOT_FIXED and op.w[k] in sb:
                             assert op.wl[k] == sb.index(op.w[k])

@@ -62,3 +62,10 @@ def test_invalid_order_rejected():
 def test_tile_bits_option_validated():
     with pytest.raises(B.TTError):
         B.Plan(16, I.square_lattice(4), order=list(range(16)), tile_bits=20)
+
+
+def test_autotune_mode_validated_before_any_device_work():
+    p = B.Plan(16, I.square_lattice(4), order=list(range(16)))
+    for mode in (-1, 3):
+        assert B.lib().tt_plan_autotune(p.handle, 1, 0, None, None, mode, None, None, None) == B.TT_E_INVAL
+    assert B.TUNE_ENERGY == 0 and B.TUNE_COUNT == 1 and B.TUNE_BACKWARD == 2

@@ -334,6 +334,13 @@ def test_autotune_keeps_results():
     assert 7 <= bits <= 14 and ms > 0
     E1, sig, _, _ = B.backward(plan, J, h)
     assert np.array_equal(E0, E1.cpu().numpy())
+    say("autotune backward square10 gauss batch 8")
+    bits2, ms2 = B.autotune(plan, J, h, config=True)
+    assert 7 <= bits2 <= 14 and ms2 > 0
+    E2, sig2, _, _ = B.backward(plan, J, h)
+    assert np.array_equal(E0, E2.cpu().numpy())
+    with pytest.raises(ValueError):
+        B.autotune(plan, J, h, count=True, config=True)
     say("autotune count reg3 n=24")
     rng = np.random.default_rng(5)
     e = I.random_regular(24, 3, rng)
