@@ -202,11 +202,12 @@ __global__ __launch_bounds__(CH_T) void k_chain(const ChainItem* __restrict__ it
   const bool init = I.init != 0;
   const int64_t sst = I.sst;
   auto update = [&](uint32_t e, float g, uint64_t gc) {
-    x[e] = init ? g : x[e] + g;
+    // non-temporal stores: the next launch reads the state from memory
+    __builtin_nontemporal_store(init ? g : x[e] + g, &x[e]);
     if (COUNT) {
       for (int r = 0; r < 3; ++r) {
         const gptr<uint64_t> pr = nres + (int64_t)r * sst + e;
-        *pr = init ? gc : mulmod_small(*pr, gc, r);
+        __builtin_nontemporal_store(init ? gc : mulmod_small(*pr, gc, r), pr);
       }
     }
   };

@@ -114,8 +114,9 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
   for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) {
     const uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
     if ((idx >> P.out_w) != 0) continue;
-    xd[idx] = tx[i];
-    for (int r = 0; r < NRES; ++r) nd[r * sst + idx] = tn[r * size + i];
+    // non-temporal: the next pass reads the state from memory
+    __builtin_nontemporal_store(tx[i], &xd[idx]);
+    for (int r = 0; r < NRES; ++r) __builtin_nontemporal_store(tn[r * size + i], &nd[r * sst + idx]);
   }
 }
 

@@ -78,6 +78,9 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
   return x;
 }
 
+// Cache-policy operand of the raw buffer intrinsics: non-temporal.
+constexpr int AUX_NT = 2;
+
 // Raw buffer resource over up to 4 GiB from p (offsets checked by the
 // caller to stay below 2^32 bytes).
 template <typename P>
@@ -610,17 +613,20 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
         for (int k = 0; k < 16; ++k) vals[k] = lds_at(ls ^ hs[k]);
         const __amdgpu_buffer_rsrc_t rs = raw_rsrc(dst);
         const uint32_t off = (uint32_t)ad_lo << 2;
+        // non-temporal: the next pass reads the state from memory on any XCD,
+        // so it is not kept dirty in this XCD's L2 (which the end of the
+        // launch would otherwise write back)
 #pragma unroll
         for (int k = 0; k < 16; ++k)
           __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, vals[k]), rs, (int)off,
-                                                (int)(had[k] << 2), 0);
+                                                (int)(had[k] << 2), AUX_NT);
       } else {
 #pragma unroll
         for (int k = 0; k < 16; ++k)
           if (k < nk) vals[k] = lds_at(ls ^ hs[k]);
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-          if (k < nk) dst[ad_lo | had[k]] = vals[k];
+          if (k < nk) __builtin_nontemporal_store(vals[k], &dst[ad_lo | had[k]]);
       }
     }
   }
@@ -801,6 +807,9 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   __shared__ BCand lc[BCH_CANDS];
   __shared__ LPass lp[BCH_PASSES];
   __shared__ uint8_t lpos[BCH_PASSES][64];
+  __shared__ uint64_t lcad[BCH_CANDS];   // input address bit of each candidate (0: none)
+  __shared__ float part_v[NT / 64];
+  __shared__ uint32_t part_i[NT / 64];
   const auto& I = as_const(items)[blockIdx.x];
   const int tid = threadIdx.x;
   const cptr<IT> Jrow = as_const(static_cast<const IT*>(I.J));
@@ -861,6 +870,16 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       lt[k] = x;
     }
     __syncthreads();
+    {
+      // the input address bit of each candidate's starting slot: thread
+      // 16 q + k takes candidate k of the chunk's pass q (<= 16 per pass)
+      const int q = tid >> 4, k = tid & 15;
+      if (q <= CH.p_hi - CH.p_lo && k < lp[q].n_cand) {
+        const int ss = lc[lp[q].cand_off + k].start_slot;
+        lcad[lp[q].cand_off + k] = (ss >= 0 && lpos[q][ss] != NO_POS) ? 1ull << lpos[q][ss] : 0ull;
+      }
+    }
+    __syncthreads();
     for (int p = CH.p_hi; p >= CH.p_lo; --p) {
       const LPass& P = lp[p - CH.p_lo];
       const uint8_t* ipos = lpos[p - CH.p_lo];
@@ -874,6 +893,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
         continue;
       }
       const BCand* C = lc + P.cand_off;
+      const uint64_t* cad = lcad + P.cand_off;
       const LTerm* T = lt + P.term_off;
       const int n_lo = P.n_lo, n_hi = P.n_hi;
       const int nterm = n_lo + n_hi + P.n_cross;
@@ -887,13 +907,20 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
           const uint32_t full = hi ? (x << 8) : x;
           float acc = 0.f;
           const int tb = hi ? n_lo : 0, te = hi ? n_lo + n_hi : n_lo;
-          for (int k = tb; k < te; ++k) acc += lterm_val(T[k], full, t);
+          // terms four at a time: their LDS reads issue together
+          for (int k0 = tb; k0 < te; k0 += 4) {
+            LTerm tt[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tt[j] = T[k0 + j < te ? k0 + j : te - 1];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (k0 + j < te) acc += lterm_val(tt[j], full, t);
+          }
           uint64_t ad = 0;
           const int kb = hi ? 8 : 0, ke = hi ? nc : nlo;
-          for (int k = kb; k < ke; ++k) {
-            const int ss = C[k].start_slot;
-            if (ss >= 0 && ipos[ss] != NO_POS && ((full >> k) & 1u)) ad |= 1ull << ipos[ss];
-          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (kb + k < ke && ((full >> (kb + k)) & 1u)) ad |= cad[kb + k];
           if (hi) {
             lut_hi[x] = acc;
             ad_hi[x] = ad;
@@ -911,29 +938,65 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       }
       __syncthreads();
       const cptr<float> src = P.init ? nullptr : as_const(ckpt[p]) + sh_base;
-      VI best{-INFINITY, ~0ull};
       const uint32_t na = 1u << nc;
       const int cross_b = n_lo + n_hi;
-      // candidates in batches of 8 per thread: all loads of a batch in flight together
+      // candidates in batches of 8 per thread: all loads of a batch in flight
+      // together; the cross terms (both halves) are read once per batch
+      float bv = -INFINITY;
+      uint32_t bi = ~0u;
       for (uint32_t a0 = tid; a0 < na; a0 += 8u * NT) {
-        float x[8];
+        float val[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const uint32_t a = a0 + (uint32_t)j * NT;
-          x[j] = (src && a < na) ? src[ad_lo[a & 255u] | ad_hi[a >> 8]] : 0.f;
+          val[j] = (src && a < na) ? src[ad_lo[a & 255u] | ad_hi[a >> 8]] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t a = (a0 + (uint32_t)j * NT) & (na - 1u);
+          val[j] += lut_lo[a & 255u] + lut_hi[a >> 8];
+        }
+        for (int k = cross_b; k < nterm; ++k) {
+          const LTerm tk = T[k];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) val[j] += lterm_val(tk, a0 + (uint32_t)j * NT, t);
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const uint32_t a = a0 + (uint32_t)j * NT;
-          if (a >= na) break;
-          float val = lut_lo[a & 255u] + lut_hi[a >> 8] + x[j];
-          for (int k = cross_b; k < nterm; ++k) val += lterm_val(T[k], a, t);
-          best = vi_best(best, VI{val, (uint64_t)a});
+          if (a < na && (val[j] > bv || (val[j] == bv && a < bi))) {
+            bv = val[j];
+            bi = a;
+          }
         }
       }
-      best = block_best<NT>(best);
+      // the best (value, lowest index) of the workgroup: waves, then wave 0
+      // over the wave results; wave 0 also records the choice
+      for (int off = 32; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(bv, off, 64);
+        const uint32_t oi = (uint32_t)__shfl_xor((int)bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if ((tid & 63) == 0) {
+        part_v[tid >> 6] = bv;
+        part_i[tid >> 6] = bi;
+      }
+      __syncthreads();
       if (tid < 64) {
-        const uint32_t a = (uint32_t)best.i;
+        bv = tid < NT / 64 ? part_v[tid] : -INFINITY;
+        bi = tid < NT / 64 ? part_i[tid] : ~0u;
+        for (int off = 32; off > 0; off >>= 1) {
+          const float ov = __shfl_xor(bv, off, 64);
+          const uint32_t oi = (uint32_t)__shfl_xor((int)bi, off, 64);
+          if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+          }
+        }
+        const uint32_t a = bi;
         uint64_t b = 0;
         if (tid < nc) {
           const uint32_t bit = (a >> tid) & 1u;
