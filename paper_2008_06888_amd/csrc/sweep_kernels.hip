@@ -512,7 +512,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
         const uint32_t off = (uint32_t)ad_lo << 2;
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-          vals[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)(had[k] << 2), 0));
+          vals[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)(had[k] << 2), AUX_NT));
       } else {
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -789,6 +789,50 @@ __device__ __forceinline__ float lterm_val(const LTerm& tm, uint32_t a, uint64_t
   return tm.c * s;
 }
 
+// Wave reductions over DPP lane moves (no LDS traffic). The row steps pair
+// lanes within a row of 16 (quad swaps, then half-row and row mirrors); the
+// broadcasts of lanes 15 and 31 then combine the four rows, so lane 63 ends
+// with the result of the whole wave.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void best_step(float& v, uint32_t& i) {
+  const float ov =
+      __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+  const uint32_t oi = (uint32_t)__builtin_amdgcn_update_dpp((int)i, (int)i, CTRL, ROW_MASK, 0xF, false);
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+
+// (value, lowest index) maximum of the wave, in lane 63.
+__device__ __forceinline__ void wave_best_dpp(float& v, uint32_t& i) {
+  best_step<0xB1, 0xF>(v, i);    // quad_perm [1,0,3,2]
+  best_step<0x4E, 0xF>(v, i);    // quad_perm [2,3,0,1]
+  best_step<0x141, 0xF>(v, i);   // row_half_mirror
+  best_step<0x140, 0xF>(v, i);   // row_mirror
+  best_step<0x142, 0xA>(v, i);   // row_bcast:15 into rows 1 and 3
+  best_step<0x143, 0xC>(v, i);   // row_bcast:31 into rows 2 and 3
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t or_step(uint32_t x) {
+  return x | (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xF, 0xF, false);
+}
+
+// OR over the 16 lanes of each row, in every lane of the row.
+__device__ __forceinline__ uint64_t row_or_dpp(uint64_t x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  lo = or_step<0xB1>(lo);
+  hi = or_step<0xB1>(hi);
+  lo = or_step<0x4E>(lo);
+  hi = or_step<0x4E>(hi);
+  lo = or_step<0x141>(lo);
+  hi = or_step<0x141>(hi);
+  lo = or_step<0x140>(lo);
+  hi = or_step<0x140>(hi);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Per-pass backward data held in LDS for a chunk of passes.
 struct LPass {
   uint64_t surv;
@@ -972,15 +1016,8 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       }
       // the best (value, lowest index) of the workgroup: waves, then wave 0
       // over the wave results; wave 0 also records the choice
-      for (int off = 32; off > 0; off >>= 1) {
-        const float ov = __shfl_xor(bv, off, 64);
-        const uint32_t oi = (uint32_t)__shfl_xor((int)bi, off, 64);
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
-      if ((tid & 63) == 0) {
+      wave_best_dpp(bv, bi);
+      if ((tid & 63) == 63) {
         part_v[tid >> 6] = bv;
         part_i[tid >> 6] = bi;
       }
@@ -988,22 +1025,15 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       if (tid < 64) {
         bv = tid < NT / 64 ? part_v[tid] : -INFINITY;
         bi = tid < NT / 64 ? part_i[tid] : ~0u;
-        for (int off = 32; off > 0; off >>= 1) {
-          const float ov = __shfl_xor(bv, off, 64);
-          const uint32_t oi = (uint32_t)__shfl_xor((int)bi, off, 64);
-          if (ov > bv || (ov == bv && oi < bi)) {
-            bv = ov;
-            bi = oi;
-          }
-        }
-        const uint32_t a = bi;
+        wave_best_dpp(bv, bi);
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)bi, 63);
         uint64_t b = 0;
-        if (tid < nc) {
+        if (tid < nc) {   // nc <= 16: the first row of lanes
           const uint32_t bit = (a >> tid) & 1u;
           s_sh[C[tid].spin] = (int8_t)bit;
           if (C[tid].start_slot >= 0) b = (uint64_t)bit << C[tid].start_slot;
         }
-        b = wave_or(b);
+        b = row_or_dpp(b);
         if (tid == 0) sh_t = (t & surv) | b;
       }
       __syncthreads();
