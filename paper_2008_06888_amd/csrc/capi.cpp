@@ -466,13 +466,47 @@ struct CallTables {
   std::vector<Launch> levels;
   size_t red_off = 0, bwd_off = 0, ckpt_off = 0;
   int n_red = 0, n_bwd = 0;
+  bool fused = false;   // partials written by the last passes: only the second reduction stage runs
   int64_t chunks = 0;
   std::vector<size_t> ckpt_first;
 };
 
-void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, CallTables& ct) {
+// Partials of the final maximum per instance: with the reduction fused into
+// the last pass, one per tile of that pass, else one per fixed-size chunk.
+int red_log2_parts(const Group& g, bool fused) {
+  return fused ? g.dc->ep.passes.back().n_free : reduce_log2_chunks(g.p->final_w);
+}
+
+// The final maximum can be taken inside the last pass when every group has
+// one (chimera plans run their own final stages) with at most 2^12 tiles per
+// instance (the partials stay small and one workgroup per instance ranks them).
+bool can_fuse_reduce(const std::vector<Group>& groups) {
+  for (const Group& g : groups)
+    if (g.dc->ep.passes.empty() || g.p->is_chimera || g.dc->ep.passes.back().n_free > 12) return false;
+  return true;
+}
+
+int64_t red_parts_needed(const std::vector<Group>& groups, bool fused) {
+  int64_t n = 0;
+  for (const Group& g : groups) n += (int64_t)g.batch << red_log2_parts(g, fused);
+  return n;
+}
+
+// pv / pi: the partial buffers, needed when `fuse` (the last passes write them).
+void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, CallTables& ct, bool fuse,
+                  float* pv, uint64_t* pi) {
+  ct.fused = fuse;
   int max_np = 0;
   for (Group& g : groups) max_np = std::max(max_np, (int)g.dc->ep.passes.size());
+  // partial of each group's first instance
+  std::vector<int64_t> part_base;
+  {
+    int64_t b = 0;
+    for (Group& g : groups) {
+      part_base.push_back(b);
+      b += (int64_t)g.batch << red_log2_parts(g, fuse);
+    }
+  }
   const size_t MAXI = 32;   // items per launch
   for (int q = 0; q < max_np; ++q) {
     std::vector<PassItem> items;
@@ -497,6 +531,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
     int cur_t = -1;
     for (auto& og : order) {
       Group& g = *og.second;
+      const size_t gi = (size_t)(og.second - groups.data());
       const EnergyProgram& ep = g.dc->ep;
       const DevPass2& P = ep.passes[q];
       if (P.t != cur_t) {
@@ -521,6 +556,11 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
       it.batch = g.batch;
       it.xcd_group = (g.batch % 8 == 0) ? 1 : 0;
       it.wg_begin = wg;
+      if (fuse && q == (int)ep.passes.size() - 1) {
+        it.red_v = pv;
+        it.red_i = pi;
+        it.red_base = part_base[gi];
+      }
       const int64_t n_wg = ((int64_t)g.batch << P.n_free);
       wg += (n_wg + 7) & ~int64_t(7);
       items.push_back(it);
@@ -531,12 +571,12 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
   std::vector<RedItem> red;
   for (Group& g : groups) {
     const int fw = g.p->final_w;
-    const int lc = reduce_log2_chunks(fw);
+    const int lc = red_log2_parts(g, fuse);
     const int np = (int)g.dc->ep.passes.size();
     for (int b = 0; b < g.batch; ++b) {
       RedItem r;
       std::memset(&r, 0, sizeof(r));
-      r.st = g.bufs[np] + (int64_t)b * g.strides[np];
+      r.st = fuse ? nullptr : g.bufs[np] + (int64_t)b * g.strides[np];
       r.chunk_begin = ct.chunks;
       r.energy = g.energy ? g.energy + b : nullptr;
       r.arg = g.arg + b;
@@ -607,7 +647,8 @@ int enqueue_launches(const CallTables& ct, const char* dev, DevCache* dc0, int32
   {
     ProfScope ps(s, "final_reduce");
     HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks,
-                          static_cast<float*>(dc0->part_v.p), static_cast<uint64_t*>(dc0->part_i.p), s));
+                          static_cast<float*>(dc0->part_v.p), static_cast<uint64_t*>(dc0->part_i.p), s,
+                          ct.fused));
   }
   if (ct.n_bwd) {
     ProfScope ps(s, "sweep_backward");
@@ -723,10 +764,13 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
   for (Group& g : groups)
     if (int r = prepare_group(g, backward)) return r;
   CallTables ct;
-  build_tables(groups, dtype, backward, ct);
   DevCache* dc0 = groups[0].dc;
-  if (int r = dc0->part_v.ensure((size_t)ct.chunks * sizeof(float))) return r;
-  if (int r = dc0->part_i.ensure((size_t)ct.chunks * sizeof(uint64_t))) return r;
+  const bool fuse = can_fuse_reduce(groups);
+  const int64_t parts = red_parts_needed(groups, fuse);
+  if (int r = dc0->part_v.ensure((size_t)parts * sizeof(float))) return r;
+  if (int r = dc0->part_i.ensure((size_t)parts * sizeof(uint64_t))) return r;
+  build_tables(groups, dtype, backward, ct, fuse, static_cast<float*>(dc0->part_v.p),
+               static_cast<uint64_t*>(dc0->part_i.p));
   if (g_graphs_on && !g_prof_on) {   // timed calls run eagerly
     const std::vector<uint64_t> key = call_key(groups, dtype, backward);
     for (size_t i = 0; i < dc0->graphs.size(); ++i) {
@@ -817,7 +861,7 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   g.arg = args + (size_t)(rows - 1) * g.batch;
   std::vector<Group> gs(1, g);
   CallTables ct;
-  build_tables(gs, dtype, false, ct);
+  build_tables(gs, dtype, false, ct, false, nullptr, nullptr);
   const int lc = reduce_log2_chunks(w);
   const int64_t row_chunks = (int64_t)g.batch << lc;
   if (int r = dc->part_v.ensure((size_t)std::max<int64_t>(ct.chunks, row_chunks) * sizeof(float))) return r;

@@ -136,6 +136,13 @@ struct PassItem {
   int64_t in_st, out_st; // state strides between instances (2^in_w, 2^out_w)
   int64_t wg_begin;      // first workgroup of the item in the launch
   int32_t batch, xcd_group;
+  // Last pass of a plan whose final state only feeds the final maximum: each
+  // tile writes its maximum and first address (in the output layout) to
+  // red_v / red_i[red_base + instance * 2^n_free + tile] instead of storing
+  // the state (NULL: store).
+  float* red_v;
+  uint64_t* red_i;
+  int64_t red_base;
 };
 
 // Final reduction of one instance's state (2^w entries): maximum and its

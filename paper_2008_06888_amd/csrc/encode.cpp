@@ -434,6 +434,12 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
     out.chunks.push_back(ch);
     hi = lo - 1;
   }
+  // a record past the last pass's ops: every lane of the pass kernel reads a
+  // valid record (lanes beyond a pass's ops read one and ignore it)
+  FOp pad;
+  std::memset(&pad, 0, sizeof(pad));
+  pad.hspin = -1;
+  out.fops.push_back(pad);
   return "";
 }
 

@@ -13,7 +13,7 @@ hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int thr
                        hipStream_t stream);
 int reduce_log2_chunks(int w);
 hipError_t launch_reduce(const RedItem* items, int n_items, int64_t n_chunks, float* pv, uint64_t* pi,
-                         hipStream_t stream);
+                         hipStream_t stream, bool partials_ready = false);
 hipError_t launch_backward(const BwdItem* items, int n_items, int dtype, hipStream_t stream);
 
 hipError_t launch_tgemm(int batch, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, int64_t sA,

@@ -81,16 +81,69 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
 // Cache-policy operand of the raw buffer intrinsics: non-temporal.
 constexpr int AUX_NT = 2;
 
-// Raw buffer resource over up to 4 GiB from p (offsets checked by the
-// caller to stay below 2^32 bytes).
+// Raw buffer resource over `records` bytes from p (offsets checked by the
+// caller to stay below 2^32 bytes; with 0 records every access is out of
+// range: loads return zero and touch no memory).
 template <typename P>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(P p) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)p, 0, 0x7fffffff, 0x00020000);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(P p, int records = 0x7fffffff) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)p, 0, records, 0x00020000);
 }
 
 // Value (0/1) of tile bit w of an entry index.
 __device__ __forceinline__ uint32_t tbit(uint32_t ix, uint32_t w) { return __builtin_amdgcn_ubfe(ix, w, 1); }
 
+
+// (value, lowest 64-bit index) maximum of a wave by DPP lane moves, in lane
+// 63: quad swaps, half-row and row mirrors, then the broadcasts of lanes 15
+// and 31 across rows.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void best64_step(float& v, uint64_t& i) {
+  const float ov =
+      __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)i, (int)(uint32_t)i, CTRL, ROW_MASK, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(i >> 32), (int)(uint32_t)(i >> 32), CTRL, ROW_MASK, 0xF, false);
+  const uint64_t oi = ((uint64_t)hi << 32) | lo;
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+
+__device__ __forceinline__ void wave_best64_dpp(float& v, uint64_t& i) {
+  best64_step<0xB1, 0xF>(v, i);    // quad_perm [1,0,3,2]
+  best64_step<0x4E, 0xF>(v, i);    // quad_perm [2,3,0,1]
+  best64_step<0x141, 0xF>(v, i);   // row_half_mirror
+  best64_step<0x140, 0xF>(v, i);   // row_mirror
+  best64_step<0x142, 0xA>(v, i);   // row_bcast:15 into rows 1 and 3
+  best64_step<0x143, 0xC>(v, i);   // row_bcast:31 into rows 2 and 3
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t or_dpp(uint32_t x) {
+  return x | (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xF, false);
+}
+
+// OR over the whole wave by DPP lane moves (as for the maxima above), made
+// uniform from lane 63.
+__device__ __forceinline__ uint64_t wave_or_dpp(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = or_dpp<0xB1, 0xF>(lo);
+  hi = or_dpp<0xB1, 0xF>(hi);
+  lo = or_dpp<0x4E, 0xF>(lo);
+  hi = or_dpp<0x4E, 0xF>(hi);
+  lo = or_dpp<0x141, 0xF>(lo);
+  hi = or_dpp<0x141, 0xF>(hi);
+  lo = or_dpp<0x140, 0xF>(lo);
+  hi = or_dpp<0x140, 0xF>(hi);
+  lo = or_dpp<0x142, 0xA>(lo);
+  hi = or_dpp<0x142, 0xA>(hi);
+  lo = or_dpp<0x143, 0xC>(lo);
+  hi = or_dpp<0x143, 0xC>(hi);
+  lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
+  hi = (uint32_t)__builtin_amdgcn_readlane((int)hi, 63);
+  return ((uint64_t)hi << 32) | lo;
+}
 
 // The pass's ops resolved for this instance and tile, one op per lane (lane
 // o holds op o of the pass; a pass has at most 64): GATE keeps 2J and the
@@ -115,15 +168,19 @@ struct OpIn {
   float hv, Je, Jt[STAR_TERMS];
 };
 
+// Zero words: what an op reads in place of a coupling or field it does not
+// have, so that every lane loads unconditionally (no branch, no early wait).
+__device__ const int32_t g_zero_words[4] = {0, 0, 0, 0};
+
+// The couplings and field an op record refers to.
 template <typename IT>
-__device__ __forceinline__ OpIn load_op(cptr<FOp> op, cptr<IT> Jrow, cptr<IT> hrow) {
-  OpIn x;
-  x.f = ldc(op);
-  x.hv = x.f.hspin >= 0 ? ldv(hrow, x.f.hspin) : 0.f;
-  x.Je = x.f.kind == FK_GATE ? ldv(Jrow, x.f.edge) : 0.f;
+__device__ __forceinline__ void load_op_values(OpIn& x, cptr<IT> Jrow, cptr<IT> hrow) {
+  const cptr<IT> zero = as_const(reinterpret_cast<const IT*>(g_zero_words));
+  const bool hf = x.f.hspin >= 0, ge = x.f.kind == FK_GATE;
+  x.hv = ldv(hf ? hrow : zero, hf ? x.f.hspin : 0);
+  x.Je = ldv(ge ? Jrow : zero, ge ? x.f.edge : 0);
 #pragma unroll
-  for (int k = 0; k < STAR_TERMS; ++k) x.Jt[k] = k < x.f.nt ? ldv(Jrow, x.f.te[k]) : 0.f;
-  return x;
+  for (int k = 0; k < STAR_TERMS; ++k) x.Jt[k] = ldv(k < x.f.nt ? Jrow : zero, k < x.f.nt ? x.f.te[k] : 0);
 }
 
 // The op resolved for the tile whose fixed slots hold the bits bs.
@@ -439,11 +496,17 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   const int lane = tid & 63;
   const cptr<IT> Jrow = as_const(static_cast<const IT*>(I.J)) + inst * I.jst;
   const cptr<IT> hrow = I.h ? as_const(static_cast<const IT*>(I.h)) + inst * I.hst : nullptr;
-  // the pass's ops: lane o of every wave takes op o; their records and
-  // couplings are read first, so these loads overlap the tile set-up below
+  // Set-up in two rounds of loads: first the per-lane tables of the fixed
+  // slots and the op records (lane o of every wave takes op o), then the
+  // tile itself together with the couplings the ops refer to.
+  // Both reads are unconditional (clamped indices: the encoder leaves a
+  // record past the last pass's ops), so no wait is forced before the tile's
+  // addresses are known.
   const int n_ops = P.n_ops;
+  const int li = lane < 48 ? lane : 47;
+  const uint32_t fi = P.fin[li], fo = P.fout[li], fr = P.fre[li];
   OpIn opin;
-  if (lane < n_ops) opin = load_op<IT>(fops + P.op_begin + lane, Jrow, hrow);
+  opin.f = ldc(fops + P.op_begin + (lane < n_ops ? lane : 0));
   const int t = P.t;
   const int tb = P.tb;              // this tile uses threads 0 .. 2^tb - 1
   const uint32_t size = 1u << t;
@@ -454,16 +517,15 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   {
     if (lane < P.n_free) {
       const uint64_t b = (tid_bits >> lane) & 1ull;
-      const uint32_t fi = P.fin[lane], fo = P.fout[lane];
-      bs = b << P.fre[lane];
+      bs = b << fr;
       in_base = fi != NO_POS ? b << fi : 0ull;
       out_base = fo != NO_POS ? b << fo : 0ull;
       dropped = fo == NO_POS ? b : 0ull;
     }
-    bs = uni64(wave_or(bs));
-    in_base = uni64(wave_or(in_base));
-    out_base = uni64(wave_or(out_base));
-    dropped = uni64(wave_or(dropped));
+    bs = wave_or_dpp(bs);
+    in_base = wave_or_dpp(in_base);
+    out_base = wave_or_dpp(out_base);
+    dropped = wave_or_dpp(dropped);
   }
   const bool stored = dropped == 0;   // only the copy with dropped slots at 0 is kept
   const cptr<float> in = as_const(I.in) + inst * I.in_st;     // read-only in this pass (in != out)
@@ -476,6 +538,9 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
   const int nk_ld = 1 << (t - nb_ld);
   uint32_t ti_ld = 0;
   float vals[16];
+  bool fast_ld = false;
+  cptr<float> src;
+  uint64_t ad_lo_ld, had_ld[16];
   const bool init = P.init != 0;   // first pass: the state starts at zero, nothing is read
   {
     // the pass's tables are read unconditionally, so their scalar loads
@@ -499,30 +564,41 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) all |= had[k];
-    const cptr<float> src = in + in_base;
-    if (init) {
+    src = in + in_base;
+    // the ops' couplings first: they depend only on the op records, and a
+    // wait for them below then leaves the tile's loads in flight
+    load_op_values<IT>(opin, Jrow, hrow);
+    __builtin_amdgcn_sched_barrier(0);   // keep them issued before the tile's loads
+    // When every offset in the tile fits 32 bits and each thread takes 16
+    // entries (t = tb + 4: every thread of the workgroup loads), the tile
+    // is read by buffer loads with the lane's offset in a VGPR and each k's
+    // in an SGPR, no per-load address arithmetic. The loads are issued
+    // without a branch: otherwise (and in the first pass, whose state
+    // starts at zero) the resource has no records and they return zeros
+    // without touching memory.
+    fast_ld = !init && nk_ld == 16 && all < (1ull << 30);
+    const __amdgpu_buffer_rsrc_t rs = raw_rsrc(src, fast_ld ? 0x7fffffff : 0);
+    const uint32_t off = (uint32_t)ad_lo << 2;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) vals[k] = 0.f;
-    } else if (loader) {
-      if (nk_ld == 16 && all < (1ull << 30)) {
-        // every offset in the tile fits 32 bits: buffer loads with the
-        // lane's offset in a VGPR and each k's in an SGPR, no per-load
-        // address arithmetic
-        const __amdgpu_buffer_rsrc_t rs = raw_rsrc(src);
-        const uint32_t off = (uint32_t)ad_lo << 2;
+    for (int k = 0; k < 16; ++k)
+      vals[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)(had[k] << 2), AUX_NT));
+    ad_lo_ld = ad_lo;
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          vals[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)(had[k] << 2), AUX_NT));
-      } else {
-#pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (k < nk_ld) vals[k] = src[ad_lo | had[k]];
-      }
-    }
+    for (int k = 0; k < 16; ++k) had_ld[k] = had[k];
   }
-  // resolve the ops for this tile (the signs of its fixed slots)
-  OpLanes R{0.f, 0.f, 0.f, 0.f, 0.f, 0u, 0.f, 0.f, 0.f, 0u};
-  if (lane < n_ops) R = resolve_lane(opin, bs);
+  // the ops resolved for this tile (the signs of its fixed slots) while the
+  // tile's loads are in flight
+  // (every lane resolves a valid record; lanes beyond the pass's ops are
+  // never read)
+  const OpLanes R = resolve_lane(opin, bs);
+  if (loader && !init && !fast_ld) {
+    // the general load (64-bit addresses or fewer than 16 entries per
+    // thread), after the resolve so that its branch does not hold back the
+    // loads above
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k < nk_ld) vals[k] = src[ad_lo_ld | had_ld[k]];
+  }
   if (loader) {
     uint32_t hs[16];
 #pragma unroll
@@ -575,7 +651,15 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
     }
     __syncthreads();
   }
-  if (!stored) return;
+  const int64_t red_at = I.red_base + (inst << P.n_free) + (int64_t)tid_bits;
+  if (!stored) {
+    // a duplicate tile (a dropped slot at 1): nothing to store or rank
+    if (I.red_v && tid == 0) {
+      as_global(I.red_v)[red_at] = -INFINITY;
+      as_global(I.red_i)[red_at] = ~0ull;
+    }
+    return;
+  }
   // store, enumerating the tile in the order of the output layout
   {
     const int ns = P.n_st;
@@ -604,6 +688,52 @@ __global__ __launch_bounds__(NT) void k_pass(const PassItem* __restrict__ items,
 #pragma unroll
     for (int k = 0; k < 16; ++k) all |= had[k];
     const gptr<float> dst = out + out_base;
+    if (I.red_v) {
+      // fused final reduction: the tile's maximum over the entries it would
+      // store, ties to the lowest output address (as a scan of the stored
+      // state would give); the state itself is not stored
+      float bv = -INFINITY;
+      uint64_t bi = ~0ull;
+      if (tid < (1 << nb)) {
+        const int nk = 1 << (ns - nb);
+        const uint32_t ls = opaque(swz(ti_lo) << 2);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          if (k < nk) {
+            const float v = lds_at(ls ^ hs[k]);
+            const uint64_t a = out_base | ad_lo | had[k];
+            if (v > bv || (v == bv && a < bi)) {
+              bv = v;
+              bi = a;
+            }
+          }
+        }
+      }
+      wave_best64_dpp(bv, bi);
+      __syncthreads();   // every tile read is done: LDS is reused below
+      const int wv = tid >> 6;
+      if ((tid & 63) == 63) {
+        lds_at(16 * wv) = bv;
+        lds_at(16 * wv + 4) = __uint_as_float((uint32_t)bi);
+        lds_at(16 * wv + 8) = __uint_as_float((uint32_t)(bi >> 32));
+      }
+      __syncthreads();
+      if (tid < 64) {
+        const int nw = (int)(blockDim.x >> 6);
+        bv = -INFINITY;
+        bi = ~0ull;
+        if (tid < nw) {
+          bv = lds_at(16 * tid);
+          bi = ((uint64_t)__float_as_uint(lds_at(16 * tid + 8)) << 32) | __float_as_uint(lds_at(16 * tid + 4));
+        }
+        wave_best64_dpp(bv, bi);
+        if (tid == 63) {
+          as_global(I.red_v)[red_at] = bv;
+          as_global(I.red_i)[red_at] = bi;
+        }
+      }
+      return;
+    }
     if (tid < (1 << nb)) {
       const int nk = 1 << (ns - nb);
       const uint32_t ls = opaque(swz(ti_lo) << 2);
@@ -1098,8 +1228,9 @@ int reduce_log2_chunks(int w) {
 }
 
 hipError_t launch_reduce(const RedItem* items, int n_items, int64_t n_chunks, float* pv, uint64_t* pi,
-                         hipStream_t stream) {
-  hipLaunchKernelGGL(k_reduce_stage1, dim3((uint32_t)n_chunks), dim3(NTR), 0, stream, items, n_items, pv, pi);
+                         hipStream_t stream, bool partials_ready) {
+  if (!partials_ready)
+    hipLaunchKernelGGL(k_reduce_stage1, dim3((uint32_t)n_chunks), dim3(NTR), 0, stream, items, n_items, pv, pi);
   hipLaunchKernelGGL(k_reduce_stage2, dim3((uint32_t)n_items), dim3(NTR), 0, stream, items, pv, pi);
   return hipGetLastError();
 }
