@@ -639,15 +639,14 @@ void patch_tables(CallTables& ct, char* dev) {
     bi[k].ckpt = reinterpret_cast<const float* const*>(dev + ct.ckpt_off + ct.ckpt_first[k] * sizeof(float*));
 }
 
-int enqueue_launches(const CallTables& ct, const char* dev, DevCache* dc0, int32_t dtype, hipStream_t s) {
+int enqueue_launches(const CallTables& ct, const char* dev, float* pv, uint64_t* pi, int32_t dtype, hipStream_t s) {
   for (const CallTables::Launch& L : ct.levels) {
     ProfScope ps(s, "sweep_pass");
     HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s));
   }
   {
     ProfScope ps(s, "final_reduce");
-    HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks,
-                          static_cast<float*>(dc0->part_v.p), static_cast<uint64_t*>(dc0->part_i.p), s,
+    HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks, pv, pi, s,
                           ct.fused));
   }
   if (ct.n_bwd) {
@@ -732,7 +731,8 @@ int capture(std::vector<Group>& groups, int32_t dtype, CallTables& ct, GraphEntr
   patch_tables(ct, static_cast<char*>(e->tables.p));
   HIP_TRY(hipMemcpy(e->tables.p, ct.blob.bytes.data(), ct.blob.bytes.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipStreamBeginCapture(is, hipStreamCaptureModeThreadLocal));
-  const int r = enqueue_launches(ct, static_cast<const char*>(e->tables.p), groups[0].dc, dtype, is);
+  const int r = enqueue_launches(ct, static_cast<const char*>(e->tables.p), static_cast<float*>(groups[0].dc->part_v.p),
+                                 static_cast<uint64_t*>(groups[0].dc->part_i.p), dtype, is);
   hipGraph_t graph = nullptr;
   const hipError_t ee = hipStreamEndCapture(is, &graph);
   if (r) {
@@ -758,11 +758,103 @@ int replay(GraphEntry* e, hipStream_t s) {
   return 0;
 }
 
+// A second stream per device (default priority, non-blocking) with its
+// fork and join events: the two halves of a large same-graph batch run on
+// the caller's stream and on this one, so the launches of one half fill the
+// gaps between and the latency-bound phases of the other's.
+struct AuxStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_aux_mu;
+std::map<int, AuxStream> g_aux;
+
+int aux_stream(AuxStream** out) {
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  std::lock_guard<std::mutex> g(g_aux_mu);
+  AuxStream& a = g_aux[device];
+  if (!a.s) {
+    HIP_TRY(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&a.join, hipEventDisableTiming));
+  }
+  *out = &a;
+  return 0;
+}
+
+// Instances b0 .. b0 + nb - 1 of a prepared group (inputs, outputs and
+// state buffers are all instance-major).
+Group sub_group(const Group& g, int b0, int nb) {
+  Group h = g;
+  const int64_t n = g.p->n, m = g.p->m;
+  h.batch = nb;
+  h.J = g.J ? static_cast<const char*>(g.J) + (size_t)b0 * (size_t)m * 4 : nullptr;   // fp32 or int32
+  h.h = g.h ? static_cast<const char*>(g.h) + (size_t)b0 * (size_t)n * 4 : nullptr;
+  h.energy = g.energy ? g.energy + b0 : nullptr;
+  h.sigma = g.sigma ? g.sigma + (size_t)b0 * (size_t)n : nullptr;
+  h.dJ = g.dJ ? g.dJ + (size_t)b0 * (size_t)m : nullptr;
+  h.dh = g.dh ? g.dh + (size_t)b0 * (size_t)n : nullptr;
+  for (size_t q = 0; q < g.bufs.size(); ++q) h.bufs[q] = g.bufs[q] + (size_t)b0 * (size_t)g.strides[q];
+  h.arg = g.arg + b0;
+  return h;
+}
+
+// Stages one call's tables and enqueues its launches on stream s.
+int stage_and_enqueue(CallTables& ct, float* pv, uint64_t* pi, int32_t dtype, hipStream_t s) {
+  char* host = nullptr;
+  char* dev = nullptr;
+  int slot = 0;
+  if (int r = stage_reserve(ct.blob.bytes.size(), &host, &dev, &slot)) return r;
+  patch_tables(ct, dev);
+  std::memcpy(host, ct.blob.bytes.data(), ct.blob.bytes.size());
+  if (int r = stage_commit(slot, ct.blob.bytes.size(), s)) return r;
+  if (int r = enqueue_launches(ct, dev, pv, pi, dtype, s)) return r;
+  return stage_release(slot, s);
+}
+
+// A same-graph batch whose state per pass has at least 2^20 entries is large:
+// it runs eagerly (its kernels are long enough that replaying a captured
+// graph saves nothing) and, with two instances or more, as two halves on two
+// streams.
+bool large_call(const std::vector<Group>& groups) {
+  return groups.size() == 1 && ((int64_t)groups[0].batch << groups[0].p->width) >= ((int64_t)1 << 20);
+}
+
+std::mutex g_split_mu;   // one split call at a time shares the fork / join events
+
+int run_split(Group& g, int32_t dtype, bool backward, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_split_mu);
+  AuxStream* aux = nullptr;
+  if (int r = aux_stream(&aux)) return r;
+  const int na = g.batch / 2;
+  std::vector<Group> ga(1, sub_group(g, 0, na)), gb(1, sub_group(g, na, g.batch - na));
+  DevCache* dc = g.dc;
+  const bool fuse = can_fuse_reduce(ga);
+  const int64_t pa = red_parts_needed(ga, fuse), pb = red_parts_needed(gb, fuse);
+  if (int r = dc->part_v.ensure((size_t)(pa + pb) * sizeof(float))) return r;
+  if (int r = dc->part_i.ensure((size_t)(pa + pb) * sizeof(uint64_t))) return r;
+  float* pv = static_cast<float*>(dc->part_v.p);
+  uint64_t* pi = static_cast<uint64_t*>(dc->part_i.p);
+  CallTables ca, cb;
+  build_tables(ga, dtype, backward, ca, fuse, pv, pi);
+  build_tables(gb, dtype, backward, cb, fuse, pv + pa, pi + pa);
+  HIP_TRY(hipEventRecord(aux->fork, s));
+  HIP_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
+  if (int r = stage_and_enqueue(ca, pv, pi, dtype, s)) return r;
+  if (int r = stage_and_enqueue(cb, pv + pa, pi + pa, dtype, aux->s)) return r;
+  HIP_TRY(hipEventRecord(aux->join, aux->s));
+  HIP_TRY(hipStreamWaitEvent(s, aux->join, 0));
+  return 0;
+}
+
 // Forward passes (one launch per pass index across groups), the final
 // reduction and, with `backward`, the argmax-routing walk.
 int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStream_t s) {
   for (Group& g : groups)
     if (int r = prepare_group(g, backward)) return r;
+  const bool large = large_call(groups);
+  if (large && groups[0].batch >= 2) return run_split(groups[0], dtype, backward, s);
   CallTables ct;
   DevCache* dc0 = groups[0].dc;
   const bool fuse = can_fuse_reduce(groups);
@@ -771,7 +863,7 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
   if (int r = dc0->part_i.ensure((size_t)parts * sizeof(uint64_t))) return r;
   build_tables(groups, dtype, backward, ct, fuse, static_cast<float*>(dc0->part_v.p),
                static_cast<uint64_t*>(dc0->part_i.p));
-  if (g_graphs_on && !g_prof_on) {   // timed calls run eagerly
+  if (g_graphs_on && !g_prof_on && !large) {   // timed calls run eagerly
     const std::vector<uint64_t> key = call_key(groups, dtype, backward);
     for (size_t i = 0; i < dc0->graphs.size(); ++i) {
       if (dc0->graphs[i]->key != key) continue;
@@ -796,15 +888,7 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
     dc0->seen.push_back(key);
     if (dc0->seen.size() > 16) dc0->seen.erase(dc0->seen.begin());
   }
-  char* host = nullptr;
-  char* dev = nullptr;
-  int slot = 0;
-  if (int r = stage_reserve(ct.blob.bytes.size(), &host, &dev, &slot)) return r;
-  patch_tables(ct, dev);
-  std::memcpy(host, ct.blob.bytes.data(), ct.blob.bytes.size());
-  if (int r = stage_commit(slot, ct.blob.bytes.size(), s)) return r;
-  if (int r = enqueue_launches(ct, dev, dc0, dtype, s)) return r;
-  return stage_release(slot, s);
+  return stage_and_enqueue(ct, static_cast<float*>(dc0->part_v.p), static_cast<uint64_t*>(dc0->part_i.p), dtype, s);
 }
 
 // Chimera plans: row 0's state is written by its chain; every later row
