@@ -292,7 +292,10 @@ def main():
         "roofline": {"kernel": "k_pass", "bound": "alu", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK_OPS / 1e12, "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_OPS,
                      "traffic": K_PASS_TRAFFIC_BYTES,
-                     "avg_launch_ms": ms_pass / max(n_pass, 1), "launches": n_pass},
+                     "avg_launch_ms": ms_pass / max(n_pass, 1), "launches": n_pass,
+                     # the batch runs in parts on concurrent streams: each launch does its part's
+                     # work, so the whole-step rate (valu_frac) exceeds the per-launch one
+                     "concurrent_parts": round(n_pass / max(args.steps, 1) / max(info["n_passes"], 1))},
         "kernel_ms_per_step": {"sweep_pass": ms_pass / args.steps, "sweep_backward": ms_bwd / args.steps,
                                "final_reduce": ms_red / args.steps},
         "plan": {"width": info["width"], "passes": info["n_passes"], "terms_per_instance": info["terms"],

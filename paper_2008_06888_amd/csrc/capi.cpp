@@ -337,7 +337,7 @@ struct Blob {
   }
 };
 
-constexpr int N_SLOTS = 4;   // calls that may be in flight per device
+constexpr int N_SLOTS = 8;   // table uploads that may be in flight per device (a split call takes one per part)
 struct Stager {
   char* host[N_SLOTS] = {};
   char* dev[N_SLOTS] = {};
@@ -758,26 +758,29 @@ int replay(GraphEntry* e, hipStream_t s) {
   return 0;
 }
 
-// A second stream per device (default priority, non-blocking) with its
-// fork and join events: the two halves of a large same-graph batch run on
-// the caller's stream and on this one, so the launches of one half fill the
-// gaps between and the latency-bound phases of the other's.
-struct AuxStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+// Extra streams per device (default priority, non-blocking) with fork and
+// join events: the parts of a large same-graph batch run on the caller's
+// stream and on these, so the launches of one part fill the gaps between and
+// the latency-bound phases of the others'.
+constexpr int SPLIT_PARTS = 2;
+struct AuxStreams {
+  hipStream_t s[SPLIT_PARTS - 1] = {};
+  hipEvent_t fork = nullptr, join[SPLIT_PARTS - 1] = {};
 };
 std::mutex g_aux_mu;
-std::map<int, AuxStream> g_aux;
+std::map<int, AuxStreams> g_aux;
 
-int aux_stream(AuxStream** out) {
+int aux_streams(AuxStreams** out) {
   int device = 0;
   HIP_TRY(hipGetDevice(&device));
   std::lock_guard<std::mutex> g(g_aux_mu);
-  AuxStream& a = g_aux[device];
-  if (!a.s) {
-    HIP_TRY(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+  AuxStreams& a = g_aux[device];
+  if (!a.fork) {
     HIP_TRY(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&a.join, hipEventDisableTiming));
+    for (int k = 0; k < SPLIT_PARTS - 1; ++k) {
+      HIP_TRY(hipStreamCreateWithFlags(&a.s[k], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&a.join[k], hipEventDisableTiming));
+    }
   }
   *out = &a;
   return 0;
@@ -815,8 +818,8 @@ int stage_and_enqueue(CallTables& ct, float* pv, uint64_t* pi, int32_t dtype, hi
 
 // A same-graph batch whose state per pass has at least 2^20 entries is large:
 // it runs eagerly (its kernels are long enough that replaying a captured
-// graph saves nothing) and, with two instances or more, as two halves on two
-// streams.
+// graph saves nothing) and, with two instances or more, in parts on
+// several streams.
 bool large_call(const std::vector<Group>& groups) {
   return groups.size() == 1 && ((int64_t)groups[0].batch << groups[0].p->width) >= ((int64_t)1 << 20);
 }
@@ -825,26 +828,34 @@ std::mutex g_split_mu;   // one split call at a time shares the fork / join even
 
 int run_split(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   std::lock_guard<std::mutex> lock(g_split_mu);
-  AuxStream* aux = nullptr;
-  if (int r = aux_stream(&aux)) return r;
-  const int na = g.batch / 2;
-  std::vector<Group> ga(1, sub_group(g, 0, na)), gb(1, sub_group(g, na, g.batch - na));
+  AuxStreams* aux = nullptr;
+  if (int r = aux_streams(&aux)) return r;
+  const int parts = std::min(SPLIT_PARTS, (int)g.batch);
+  std::vector<std::vector<Group>> gp(parts);
+  for (int k = 0; k < parts; ++k) {
+    const int b0 = (int)((int64_t)g.batch * k / parts), b1 = (int)((int64_t)g.batch * (k + 1) / parts);
+    gp[k].push_back(sub_group(g, b0, b1 - b0));
+  }
   DevCache* dc = g.dc;
-  const bool fuse = can_fuse_reduce(ga);
-  const int64_t pa = red_parts_needed(ga, fuse), pb = red_parts_needed(gb, fuse);
-  if (int r = dc->part_v.ensure((size_t)(pa + pb) * sizeof(float))) return r;
-  if (int r = dc->part_i.ensure((size_t)(pa + pb) * sizeof(uint64_t))) return r;
+  const bool fuse = can_fuse_reduce(gp[0]);
+  std::vector<int64_t> first(parts + 1, 0);
+  for (int k = 0; k < parts; ++k) first[k + 1] = first[k] + red_parts_needed(gp[k], fuse);
+  if (int r = dc->part_v.ensure((size_t)first[parts] * sizeof(float))) return r;
+  if (int r = dc->part_i.ensure((size_t)first[parts] * sizeof(uint64_t))) return r;
   float* pv = static_cast<float*>(dc->part_v.p);
   uint64_t* pi = static_cast<uint64_t*>(dc->part_i.p);
-  CallTables ca, cb;
-  build_tables(ga, dtype, backward, ca, fuse, pv, pi);
-  build_tables(gb, dtype, backward, cb, fuse, pv + pa, pi + pa);
   HIP_TRY(hipEventRecord(aux->fork, s));
-  HIP_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
-  if (int r = stage_and_enqueue(ca, pv, pi, dtype, s)) return r;
-  if (int r = stage_and_enqueue(cb, pv + pa, pi + pa, dtype, aux->s)) return r;
-  HIP_TRY(hipEventRecord(aux->join, aux->s));
-  HIP_TRY(hipStreamWaitEvent(s, aux->join, 0));
+  for (int k = 0; k < parts; ++k) {
+    hipStream_t sk = k == 0 ? s : aux->s[k - 1];
+    if (k > 0) HIP_TRY(hipStreamWaitEvent(sk, aux->fork, 0));
+    CallTables ct;
+    build_tables(gp[k], dtype, backward, ct, fuse, pv + first[k], pi + first[k]);
+    if (int r = stage_and_enqueue(ct, pv + first[k], pi + first[k], dtype, sk)) return r;
+  }
+  for (int k = 1; k < parts; ++k) {
+    HIP_TRY(hipEventRecord(aux->join[k - 1], aux->s[k - 1]));
+    HIP_TRY(hipStreamWaitEvent(s, aux->join[k - 1], 0));
+  }
   return 0;
 }
 
