@@ -167,7 +167,11 @@ int tt_tgemm(int32_t batch, int64_t M, int64_t N, int64_t K, const float* A, int
  * addresses equal those of an earlier call are captured once (on their
  * second occurrence) and then replayed as one graph launch on an internal
  * stream, ordered after and before `stream` by events. A replay reads the
- * current contents of the inputs, so it is equivalent to the eager call. */
+ * current contents of the inputs, so it is equivalent to the eager call.
+ * Large same-graph batches (batch * 2^width >= 2^20 state entries) are never
+ * captured: they run eagerly in two parts, the first on `stream` and the
+ * second on an internal stream forked from and joined to `stream` by events
+ * (the call is ordered on `stream` like any other). */
 int tt_graphs_enable(int32_t on);
 
 /* Tile-size autotuner (batched execution, tiles chosen per plan): times the
@@ -180,7 +184,9 @@ int tt_graphs_enable(int32_t on);
  * smaller tiles than the energy alone). Candidates: the five sizes below the
  * largest useful one (min(maximum, state width)), never under 7 bits. The
  * score is the summed device time of the call's kernels, the least of three
- * calls. Blocks until the timing is done; allocates the timed calls' outputs
+ * calls; for a same-graph batch of at least 2^20 state entries (which runs in
+ * parts on concurrent streams) it is the device time from before to after the
+ * call instead. Blocks until the timing is done; allocates the timed calls' outputs
  * (freed before it returns). chosen_bits and best_ms (milliseconds per call)
  * may be NULL. Captured graphs and device buffers of the plan are released.
  * TT_E_INVAL for an unknown mode. */

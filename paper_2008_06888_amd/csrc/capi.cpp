@@ -467,6 +467,7 @@ struct CallTables {
   size_t red_off = 0, bwd_off = 0, ckpt_off = 0;
   int n_red = 0, n_bwd = 0;
   bool fused = false;   // partials written by the last passes: only the second reduction stage runs
+  bool bwd_ranks = false;   // ... and the backward kernel ranks them itself (no reduction launch)
   int64_t chunks = 0;
   std::vector<size_t> ckpt_first;
 };
@@ -624,9 +625,17 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
       it.n_passes = np;
       it.final_w = g.p->final_w;
       it.n = g.p->n;
+      if (fuse) {
+        const RedItem& r = red[bwd.size()];
+        it.red_v = pv + r.chunk_begin;
+        it.red_i = pi + r.chunk_begin;
+        it.red_n = (int64_t)1 << r.log2_chunks;
+        it.energy = r.energy;
+      }
       bwd.push_back(it);
     }
   }
+  ct.bwd_ranks = fuse;
   ct.bwd_off = ct.blob.add(bwd.data(), bwd.size());
   ct.n_bwd = (int)bwd.size();
 }
@@ -644,7 +653,7 @@ int enqueue_launches(const CallTables& ct, const char* dev, float* pv, uint64_t*
     ProfScope ps(s, "sweep_pass");
     HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s));
   }
-  {
+  if (!ct.bwd_ranks) {
     ProfScope ps(s, "final_reduce");
     HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks, pv, pi, s,
                           ct.fused));
@@ -820,8 +829,10 @@ int stage_and_enqueue(CallTables& ct, float* pv, uint64_t* pi, int32_t dtype, hi
 // it runs eagerly (its kernels are long enough that replaying a captured
 // graph saves nothing) and, with two instances or more, in parts on
 // several streams.
+bool large_batch(const Plan& p, int64_t batch) { return (batch << p.width) >= ((int64_t)1 << 20); }
+
 bool large_call(const std::vector<Group>& groups) {
-  return groups.size() == 1 && ((int64_t)groups[0].batch << groups[0].p->width) >= ((int64_t)1 << 20);
+  return groups.size() == 1 && large_batch(*groups[0].p, groups[0].batch);
 }
 
 std::mutex g_split_mu;   // one split call at a time shares the fork / join events
@@ -1521,20 +1532,36 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
     std::vector<uint64_t> res(nb * 3);
     const bool graphs = g_graphs_on;
     g_graphs_on = false;   // timing of eager launches; no capture of discarded plans
+    // one call, left running on the stream (energy / backward modes)
+    auto run_call = [&]() -> int {
+      if (mode == TT_TUNE_BACKWARD)
+        return tt_backward(plan, batch, dtype, J, h, reinterpret_cast<double*>(ob + o_en),
+                           reinterpret_cast<int8_t*>(ob + o_sg), reinterpret_cast<float*>(ob + o_dJ),
+                           reinterpret_cast<float*>(ob + o_dh), stream);
+      return tt_contract(plan, batch, dtype, J, h, reinterpret_cast<double*>(ob + o_en), stream);
+    };
     auto run_once = [&]() -> int {
       if (count) return tt_count(plan, batch, static_cast<const int32_t*>(J), static_cast<const int32_t*>(h),
                                  en.data(), res.data(), stream);
-      if (mode == TT_TUNE_BACKWARD) {
-        if (int r = tt_backward(plan, batch, dtype, J, h, reinterpret_cast<double*>(ob + o_en),
-                                reinterpret_cast<int8_t*>(ob + o_sg), reinterpret_cast<float*>(ob + o_dJ),
-                                reinterpret_cast<float*>(ob + o_dh), stream))
-          return r;
-      } else if (int r = tt_contract(plan, batch, dtype, J, h, reinterpret_cast<double*>(ob + o_en), stream)) {
-        return r;
-      }
+      if (int r = run_call()) return r;
       HIP_TRY(hipStreamSynchronize(s));
       return 0;
     };
+    // a large same-graph batch runs in parts on concurrent streams (see
+    // run_split), so summed kernel times would count overlapping work twice
+    const bool split = !count && !p.is_chimera && batch >= 2 && large_batch(p, batch);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (split) {
+      HIP_TRY(hipEventCreate(&ev0));
+      HIP_TRY(hipEventCreate(&ev1));
+    }
+    struct EvFree {
+      hipEvent_t a, b;
+      ~EvFree() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+      }
+    } ev_free{ev0, ev1};
     const int keep = count ? p.count_tile_bits : p.tile_bits;
     int best_t = keep;
     double best = 1e300;
@@ -1545,10 +1572,25 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
       p.dev = nullptr;
       partition_plan(p);
       if ((rc = run_once())) break;   // warm-up (encodes and uploads the plan)
-      // the summed device time of the call's kernels (HIP events around each
-      // launch, so host launch gaps do not count), the least of three calls
       double ms = 1e300;
-      for (int k = 0; k < 3 && rc == 0; ++k) {
+      if (split) {
+        // parts on concurrent streams: the device time from before the first
+        // to after the last of two back-to-back calls (the host enqueues the
+        // second while the first runs), the least of three
+        for (int k = 0; k < 3 && rc == 0; ++k) {
+          HIP_TRY(hipEventRecord(ev0, s));
+          if ((rc = run_call()) || (rc = run_call())) break;
+          HIP_TRY(hipEventRecord(ev1, s));
+          HIP_TRY(hipEventSynchronize(ev1));
+          float f = 0.f;
+          HIP_TRY(hipEventElapsedTime(&f, ev0, ev1));
+          ms = std::min(ms, 0.5 * (double)f);
+        }
+      }
+      // otherwise the summed device time of the call's kernels (HIP events
+      // around each launch, so host launch gaps do not count), the least of
+      // three calls
+      for (int k = 0; k < 3 && rc == 0 && !split; ++k) {
         prof_drain();
         const auto before = g_prof_acc;
         const bool was_on = g_prof_on;

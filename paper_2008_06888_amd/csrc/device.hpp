@@ -209,6 +209,13 @@ struct BwdItem {
   float* dh;
   int64_t m;
   int32_t n_passes, final_w, n, pad;
+  // With red_v set, the selected final address is not read from final_addr:
+  // the kernel ranks the instance's red_n partials of the final maximum
+  // itself (ties to the lowest address) and writes -max to energy.
+  const float* red_v;
+  const uint64_t* red_i;
+  int64_t red_n;
+  double* energy;
 };
 
 }  // namespace tt

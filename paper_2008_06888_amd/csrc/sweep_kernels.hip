@@ -984,6 +984,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   __shared__ uint64_t lcad[BCH_CANDS];   // input address bit of each candidate (0: none)
   __shared__ float part_v[NT / 64];
   __shared__ uint32_t part_i[NT / 64];
+  __shared__ uint64_t part_a[NT / 64];
   const auto& I = as_const(items)[blockIdx.x];
   const int tid = threadIdx.x;
   const cptr<IT> Jrow = as_const(static_cast<const IT*>(I.J));
@@ -999,10 +1000,41 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   const int final_w = I.final_w, n = I.n;
   const int64_t m = I.m;
   for (int v = tid; v < n; v += NT) s_sh[v] = 0;
+  if (I.red_v) {
+    // the final maximum over the last pass's per-tile partials: the largest
+    // value, ties to the lowest address
+    float bv = -INFINITY;
+    uint64_t bi = ~0ull;
+    const cptr<float> rv = as_const(I.red_v);
+    const cptr<uint64_t> ri = as_const(I.red_i);
+    for (int64_t k = tid; k < I.red_n; k += NT) {
+      const float v = rv[k];
+      const uint64_t a = ri[k];
+      if (v > bv || (v == bv && a < bi)) {
+        bv = v;
+        bi = a;
+      }
+    }
+    wave_best64_dpp(bv, bi);
+    if ((tid & 63) == 63) {
+      part_v[tid >> 6] = bv;
+      part_a[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      bv = tid < NT / 64 ? part_v[tid] : -INFINITY;
+      bi = tid < NT / 64 ? part_a[tid] : ~0ull;
+      wave_best64_dpp(bv, bi);
+      if (tid == 63) {
+        sh_base = bi;   // the selected final address (sh_base is free until the passes)
+        if (I.energy) *as_global(I.energy) = -(double)bv;
+      }
+    }
+  }
   __syncthreads();
   if (tid < 64) {
     // final state: address -> slot index; spins still in a slot take its bit
-    const uint64_t addr = *as_const(I.final_addr);
+    const uint64_t addr = I.red_v ? sh_base : *as_const(I.final_addr);
     uint64_t tb = 0;
     if (tid < final_w) {
       const uint64_t b = (addr >> final_pos[tid]) & 1ull;

@@ -166,6 +166,26 @@ def test_square16_gauss_b64_sampled():
         assert np.array_equal(sig[b], ref["sigma"])
 
 
+def test_split_batch_odd_size_matches_single_calls():
+    # 17 x 2^16 state entries: the call runs as two parts (8 and 9 instances)
+    # on two streams; every instance must equal its own single-instance call
+    insts = I.config_instances(1, batch=17)
+    say("square16 gauss b17 split")
+    plan = B.Plan(256, insts[0].edges, order=list(range(256)), has_field=True)
+    J, h = dev(stack(insts, "J")), dev(stack(insts, "h"))
+    E, sig, dJ, dh = B.backward(plan, J, h)
+    Ec = B.contract(plan, J, h)
+    E, sig, Ec = E.cpu().numpy(), sig.cpu().numpy(), Ec.cpu().numpy()
+    assert np.array_equal(E, Ec)
+    for b in (0, 7, 8, 16):
+        E1, sig1, _, _ = B.backward(plan, J[b:b + 1].contiguous(), h[b:b + 1].contiguous())
+        assert E1.cpu().numpy()[0] == E[b]
+        assert np.array_equal(sig1.cpu().numpy()[0], sig[b])
+    x = insts[8]
+    ref = O.eliminate(256, x.edges, x.J, x.h, order=list(range(256)))
+    assert abs(E[8] - ref["energy"]) <= tol(256) and np.array_equal(sig[8], ref["sigma"])
+
+
 def test_square16_gradient_finite_differences():
     insts = I.config_instances(1, batch=2)
     plan = B.Plan(256, insts[0].edges, order=list(range(256)), has_field=True)
