@@ -21,11 +21,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "max-plus Gop/s & % VALU peak; ground-state solves/s (energy+config), 16x16 ±J"
 VALU_PEAK_OPS = 256 * 64 * 2.4e9 * 2      # max-plus ops/s: one term (add + max) per lane per cycle
-# HBM bytes per k_pass launch of the headline workload, from rocprofv3 counter
-# passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain 256 MiB
-# device copy reads for the same counters); profiles/k_pass_square16x16_gauss_b64.txt.
-# Set to None whenever the pass kernel changes until the counters are taken again.
-K_PASS_TRAFFIC_BYTES = None
+# HBM bytes per k_pass launch of the headline workload (one of the two
+# concurrent half-batch launches of a pass), by tile size, from rocprofv3
+# counter passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain
+# 256 MiB device copy reads for the same counters);
+# profiles/k_pass_square16x16_gauss_b64.txt. Emptied whenever the pass
+# kernel changes, until the counters are taken again.
+K_PASS_TRAFFIC_BYTES = {11: 16.54e6, 12: 16.47e6, 13: 16.39e6, 14: 16.34e6}
 
 
 def cpu_baseline(insts, seconds=15.0):
@@ -291,7 +293,7 @@ def main():
         "valu_frac": ops_step * args.steps / dt / VALU_PEAK_OPS,
         "roofline": {"kernel": "k_pass", "bound": "alu", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK_OPS / 1e12, "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": K_PASS_TRAFFIC_BYTES,
+                     "traffic": K_PASS_TRAFFIC_BYTES.get(tile_bits),
                      "avg_launch_ms": ms_pass / max(n_pass, 1), "launches": n_pass,
                      # the batch runs in parts on concurrent streams: each launch does its part's
                      # work, so the whole-step rate (valu_frac) exceeds the per-launch one
