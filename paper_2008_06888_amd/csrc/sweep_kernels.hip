@@ -58,18 +58,7 @@ __device__ __forceinline__ bool wg_to_tile(uint64_t b, int log2_tiles, int batch
   return *inst < batch;
 }
 
-// OR over the 64 lanes of a wave.
-__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
-  for (int off = 32; off > 0; off >>= 1) x |= __shfl_xor(x, off, 64);
-  return x;
-}
 
-// A value every lane of the wave holds, moved to scalar registers.
-__device__ __forceinline__ uint64_t uni64(uint64_t x) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
 
 // A lane value the compiler may not re-derive (keeps a pre-shifted LDS
 // address part from being folded back into a shift after the XOR).
@@ -1042,7 +1031,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       const int sp = final_slot_spin[tid];
       if (sp >= 0) s_sh[sp] = (int8_t)b;
     }
-    tb = wave_or(tb);
+    tb = wave_or_dpp(tb);
     if (tid == 0) sh_t = tb;
   }
   __syncthreads();
@@ -1139,7 +1128,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
         const int c = tid - 512;
         uint64_t b = 0;
         if (c < P.in_w && ((surv >> c) & 1ull) && ((t >> c) & 1ull)) b = 1ull << ipos[c];
-        b = wave_or(b);
+        b = wave_or_dpp(b);
         if (c == 0) sh_base = b;
       }
       __syncthreads();
