@@ -115,22 +115,79 @@ struct Encoded {
   int max_t = 0, max_dec = 0;
 };
 
+// Large device blocks released by the library (plans destroyed, tile sizes
+// re-partitioned by the autotuner, buffers grown) are kept per device and
+// handed out again: memory a kernel has already touched comes back at full
+// speed, while fresh allocations measured slower for their first tens of
+// milliseconds. Releasing a block waits for the device, as hipFree does.
+constexpr size_t POOL_MIN = size_t(1) << 20;     // smaller blocks are freed at once
+constexpr size_t POOL_MAX = size_t(8) << 30;     // at most this much kept per device
+struct BlockPool {
+  std::multimap<size_t, void*> free;
+  size_t bytes = 0;
+};
+std::mutex g_pool_mu;
+std::map<int, BlockPool> g_pool;
+
+void* pool_take(int device, size_t bytes, size_t* got) {
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  BlockPool& bp = g_pool[device];
+  auto it = bp.free.lower_bound(bytes);
+  if (it == bp.free.end() || it->first > 2 * bytes) return nullptr;   // no block, or one far too large
+  void* p = it->second;
+  *got = it->first;
+  bp.bytes -= it->first;
+  bp.free.erase(it);
+  return p;
+}
+
+void pool_give(int device, void* p, size_t cap) {
+  if (!p) return;
+  if (cap < POOL_MIN) {
+    (void)hipFree(p);
+    return;
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != device) (void)hipSetDevice(device);
+  (void)hipDeviceSynchronize();   // kernels of earlier calls may still use the block
+  if (cur != device) (void)hipSetDevice(cur);
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  BlockPool& bp = g_pool[device];
+  bp.free.emplace(cap, p);
+  bp.bytes += cap;
+  while (bp.bytes > POOL_MAX && !bp.free.empty()) {   // drop the largest kept blocks
+    auto last = std::prev(bp.free.end());
+    bp.bytes -= last->first;
+    (void)hipFree(last->second);
+    bp.free.erase(last);
+  }
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
+  int device = 0;
+  ~DevBuf() { pool_give(device, p, cap); }
   int ensure(size_t bytes) {
     if (bytes <= cap) return 0;
     if (p) {
-      (void)hipFree(p);
+      pool_give(device, p, cap);
       p = nullptr;
       cap = 0;
+    }
+    HIP_TRY(hipGetDevice(&device));
+    size_t got = 0;
+    if (bytes >= POOL_MIN && (p = pool_take(device, bytes, &got))) {
+      cap = got;
+      return 0;
     }
     hipError_t e = hipMalloc(&p, bytes == 0 ? 1 : bytes);
     if (e != hipSuccess) return fail(TT_E_DEVICE, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     cap = bytes;
+    // touch a large fresh block once, at allocation (synchronous, outside
+    // any captured graph), so that its first use by the kernels is not slow
+    if (bytes >= POOL_MIN) HIP_TRY(hipMemset(p, 0, bytes));
     return 0;
   }
 };
