@@ -27,7 +27,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9 * 2      # max-plus ops/s: one term (add + max)
 # 256 MiB device copy reads for the same counters);
 # profiles/k_pass_square16x16_gauss_b64.txt. Emptied whenever the pass
 # kernel changes, until the counters are taken again.
-K_PASS_TRAFFIC_BYTES = {}
+K_PASS_TRAFFIC_BYTES = {11: 16.53e6, 12: 16.47e6, 13: 16.39e6, 14: 16.34e6}
 
 
 def cpu_baseline(insts, seconds=15.0):

@@ -117,9 +117,8 @@ struct Encoded {
 
 // Large device blocks released by the library (plans destroyed, tile sizes
 // re-partitioned by the autotuner, buffers grown) are kept per device and
-// handed out again: memory a kernel has already touched comes back at full
-// speed, while fresh allocations measured slower for their first tens of
-// milliseconds. Releasing a block waits for the device, as hipFree does.
+// handed out again instead of going back through hipFree / hipMalloc.
+// Releasing a block waits for the device, as hipFree does.
 constexpr size_t POOL_MIN = size_t(1) << 20;     // smaller blocks are freed at once
 constexpr size_t POOL_MAX = size_t(8) << 30;     // at most this much kept per device
 struct BlockPool {
@@ -185,9 +184,6 @@ struct DevBuf {
     hipError_t e = hipMalloc(&p, bytes == 0 ? 1 : bytes);
     if (e != hipSuccess) return fail(TT_E_DEVICE, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     cap = bytes;
-    // touch a large fresh block once, at allocation (synchronous, outside
-    // any captured graph), so that its first use by the kernels is not slow
-    if (bytes >= POOL_MIN) HIP_TRY(hipMemset(p, 0, bytes));
     return 0;
   }
 };
@@ -424,7 +420,7 @@ int stage_reserve(size_t n, char** host, char** dev, int* slot) {
     st.host[k] = nullptr;
     st.dev[k] = nullptr;
     st.cap[k] = 0;
-    const size_t c = std::max<size_t>(n * 2, 1 << 16);
+    const size_t c = std::max<size_t>(n * 4, size_t(1) << 20);   // rare growth: each one waits for the device
     HIP_TRY(hipHostMalloc((void**)&st.host[k], c, hipHostMallocDefault));
     HIP_TRY(hipMalloc((void**)&st.dev[k], c));
     st.cap[k] = c;
