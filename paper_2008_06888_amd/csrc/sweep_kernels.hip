@@ -70,9 +70,11 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
 // Cache-policy operand of the raw buffer intrinsics: non-temporal.
 constexpr int AUX_NT = 2;
 
-// Raw buffer resource over `records` bytes from p (offsets checked by the
-// caller to stay below 2^32 bytes; with 0 records every access is out of
-// range: loads return zero and touch no memory).
+// Raw buffer resource over `records` bytes from p (with 0 records every
+// access is out of range: loads return zero and touch no memory). Callers
+// keep every offset (lane part plus scalar part, disjoint bits) below
+// BUF_MAX_ENTRIES floats, i.e. below 2^31 bytes, inside the records.
+constexpr uint64_t BUF_MAX_ENTRIES = 1ull << 29;
 template <typename P>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(P p, int records = 0x7fffffff) {
   return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)p, 0, records, 0x00020000);
@@ -562,14 +564,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
     // wait for them below then leaves the tile's loads in flight
     load_op_values<IT>(opin, Jrow, hrow);
     __builtin_amdgcn_sched_barrier(0);   // keep them issued before the tile's loads
-    // When every offset in the tile fits 32 bits and each thread takes 16
+    // When every offset in the tile fits the buffer range and each thread takes 16
     // entries (t = tb + 4: every thread of the workgroup loads), the tile
     // is read by buffer loads with the lane's offset in a VGPR and each k's
     // in an SGPR, no per-load address arithmetic. The loads are issued
     // without a branch: otherwise (and in the first pass, whose state
     // starts at zero) the resource has no records and they return zeros
     // without touching memory.
-    fast_ld = !init && nk_ld == 16 && all < (1ull << 30);
+    fast_ld = !init && nk_ld == 16 && all < BUF_MAX_ENTRIES;
     const __amdgpu_buffer_rsrc_t rs = raw_rsrc(src, fast_ld ? 0x7fffffff : 0);
     const uint32_t off = (uint32_t)ad_lo << 2;
 #pragma unroll
@@ -731,7 +733,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
       const int nk = 1 << (ns - nb);
       const uint32_t ls = opaque(swz(ti_lo) << 2);
       float vals[16];
-      if (nk == 16 && all < (1ull << 30)) {
+      if (nk == 16 && all < BUF_MAX_ENTRIES) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) vals[k] = lds_at(ls ^ hs[k]);
         const __amdgpu_buffer_rsrc_t rs = raw_rsrc(dst);
