@@ -966,11 +966,48 @@ struct LPass {
 };
 
 
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int k) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), k);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Address tables of a pass (they depend only on the pass, not on the
+// selected entry): entry x of the low / high table is the OR of the input
+// address bits of the candidates set in x, over candidate bits 0..7 / 8..15.
+// Called by 512 threads, x_tid = 0..511.
+__device__ __forceinline__ void bwd_address_tables(const LPass& Q, const uint64_t* lcad, uint64_t* tlo, uint64_t* thi,
+                                                   int x_tid) {
+  const int nc = Q.n_cand;
+  const int nlo = nc < 8 ? nc : 8, nhi = nc - nlo;
+  const int hi = x_tid >= 256;
+  const uint32_t x = hi ? (uint32_t)(x_tid - 256) : (uint32_t)x_tid;
+  if (nc == 0 || x >= (1u << (hi ? nhi : nlo))) return;
+  const uint64_t* cad = lcad + Q.cand_off;
+  const int kb = hi ? 8 : 0, ke = hi ? nc : nlo;
+  uint64_t ad = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (kb + k < ke && ((x >> k) & 1u)) ad |= cad[kb + k];
+  (hi ? thi : tlo)[x] = ad;
+}
+
+// The input address of a pass's surviving slots under the selected output
+// entry t: lane c takes slot c, then an OR across the wave (one whole wave
+// calls it, lane = 0..63); lane 0 stores it.
+__device__ __forceinline__ void bwd_surviving_base(const LPass& Q, const uint8_t* ipos, uint64_t t, int lane,
+                                                   uint64_t* out) {
+  uint64_t b = 0;
+  if (lane < Q.in_w && ((Q.surv >> lane) & 1ull) && ((t >> lane) & 1ull)) b = 1ull << ipos[lane];
+  b = wave_or_dpp(b);
+  if (lane == 0) *out = b;
+}
+
 template <typename IT>
 __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ items) {
   __shared__ int8_t s_sh[MAX_SPINS];
   __shared__ float lut_lo[256], lut_hi[256];
-  __shared__ uint64_t ad_lo[256], ad_hi[256];
+  __shared__ uint64_t ad_lo[2][256], ad_hi[2][256];   // by pass parity
   __shared__ uint64_t sh_t, sh_base;
   __shared__ LTerm lt[BCH_TERMS];
   __shared__ BCand lc[BCH_CANDS];
@@ -1081,26 +1118,63 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       }
     }
     __syncthreads();
+    // the chunk's last pass: its address tables, and the address of its
+    // surviving slots under the selected output entry
+    bwd_address_tables(lp[CH.p_hi - CH.p_lo], lcad, ad_lo[CH.p_hi & 1], ad_hi[CH.p_hi & 1], tid);
+    if (tid >= 960) bwd_surviving_base(lp[CH.p_hi - CH.p_lo], lpos[CH.p_hi - CH.p_lo], sh_t, tid - 960, &sh_base);
+    __syncthreads();
     for (int p = CH.p_hi; p >= CH.p_lo; --p) {
       const LPass& P = lp[p - CH.p_lo];
-      const uint8_t* ipos = lpos[p - CH.p_lo];
       const int nc = P.n_cand;
       const uint64_t surv = P.surv;
       const uint64_t t = sh_t;
+      const bool has_next = p > CH.p_lo;
       if (nc == 0) {
         __syncthreads();
-        if (tid == 0) sh_t = t & surv;
+        if (tid < 64) {
+          const uint64_t nt = t & surv;
+          if (has_next) bwd_surviving_base(lp[p - 1 - CH.p_lo], lpos[p - 1 - CH.p_lo], nt, tid, &sh_base);
+          if (tid == 0) sh_t = nt;
+        } else if (has_next && tid >= 512) {
+          bwd_address_tables(lp[p - 1 - CH.p_lo], lcad, ad_lo[(p - 1) & 1], ad_hi[(p - 1) & 1], tid - 512);
+        }
         __syncthreads();
         continue;
       }
       const BCand* C = lc + P.cand_off;
-      const uint64_t* cad = lcad + P.cand_off;
       const LTerm* T = lt + P.term_off;
       const int n_lo = P.n_lo, n_hi = P.n_hi;
       const int nterm = n_lo + n_hi + P.n_cross;
       const int nlo = nc < 8 ? nc : 8, nhi = nc - nlo;
-      // tables over the low / high halves of the candidate bits (threads 0..511);
-      // the address of the surviving slots (one wave of threads 512..575)
+      const uint32_t na = 1u << nc;
+      // the candidates' entries of the pass's input, in batches of 8 per
+      // thread; their addresses come from tables built during the pass
+      // before, so the loads are issued first and stay in flight while the
+      // term tables are built (the last batch's loads are the ones kept in
+      // flight; with NT = 1024 and at most 2^16 candidates there are at
+      // most eight batches)
+      // The loads are unconditional (a branch around each would make every
+      // one wait for the one before): a candidate beyond the last, or any
+      // candidate of the first pass (whose input is all zero), reads a valid
+      // word instead (offset 0, or the zero word) and its value is zeroed.
+      const bool have_src = !P.init;
+      const cptr<float> src =
+          have_src ? as_const(ckpt[p]) + sh_base : as_const(reinterpret_cast<const float*>(g_zero_words));
+      const uint64_t* AL = ad_lo[p & 1];
+      const uint64_t* AH = ad_hi[p & 1];
+      const uint32_t nb = (na + 8u * NT - 1u) / (8u * NT);
+      float val[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t a = (uint32_t)tid + (uint32_t)j * NT;
+        const bool ok = have_src && a < na;
+        const uint64_t off = AL[a & 255u] | AH[(a >> 8) & 255u];
+        const float v = src[ok ? off : 0ull];
+        val[j] = ok ? v : 0.f;
+      }
+      // tables of the terms over the low / high halves of the candidate
+      // bits (threads 0..511); the next pass's address tables (threads
+      // 512..1023)
       if (tid < 512) {
         const int hi = tid >= 256;
         const uint32_t x = hi ? (uint32_t)(tid - 256) : (uint32_t)tid;
@@ -1117,40 +1191,29 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
             for (int j = 0; j < 4; ++j)
               if (k0 + j < te) acc += lterm_val(tt[j], full, t);
           }
-          uint64_t ad = 0;
-          const int kb = hi ? 8 : 0, ke = hi ? nc : nlo;
-#pragma unroll
-          for (int k = 0; k < 8; ++k)
-            if (kb + k < ke && ((full >> (kb + k)) & 1u)) ad |= cad[kb + k];
-          if (hi) {
+          if (hi)
             lut_hi[x] = acc;
-            ad_hi[x] = ad;
-          } else {
+          else
             lut_lo[x] = acc;
-            ad_lo[x] = ad;
-          }
         }
-      } else if (tid < 576) {
-        const int c = tid - 512;
-        uint64_t b = 0;
-        if (c < P.in_w && ((surv >> c) & 1ull) && ((t >> c) & 1ull)) b = 1ull << ipos[c];
-        b = wave_or_dpp(b);
-        if (c == 0) sh_base = b;
+      } else if (has_next) {
+        bwd_address_tables(lp[p - 1 - CH.p_lo], lcad, ad_lo[(p - 1) & 1], ad_hi[(p - 1) & 1], tid - 512);
       }
       __syncthreads();
-      const cptr<float> src = P.init ? nullptr : as_const(ckpt[p]) + sh_base;
-      const uint32_t na = 1u << nc;
       const int cross_b = n_lo + n_hi;
-      // candidates in batches of 8 per thread: all loads of a batch in flight
-      // together; the cross terms (both halves) are read once per batch
       float bv = -INFINITY;
       uint32_t bi = ~0u;
-      for (uint32_t a0 = tid; a0 < na; a0 += 8u * NT) {
-        float val[8];
+      for (uint32_t bt = 0; bt < nb; ++bt) {
+        const uint32_t a0 = (uint32_t)tid + bt * 8u * NT;
+        if (bt > 0) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const uint32_t a = a0 + (uint32_t)j * NT;
-          val[j] = (src && a < na) ? src[ad_lo[a & 255u] | ad_hi[a >> 8]] : 0.f;
+          for (int j = 0; j < 8; ++j) {
+            const uint32_t a = a0 + (uint32_t)j * NT;
+            const bool ok = have_src && a < na;
+            const uint64_t off = AL[a & 255u] | AH[(a >> 8) & 255u];
+            const float v = src[ok ? off : 0ull];
+            val[j] = ok ? v : 0.f;
+          }
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -1172,7 +1235,8 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
         }
       }
       // the best (value, lowest index) of the workgroup: waves, then wave 0
-      // over the wave results; wave 0 also records the choice
+      // over the wave results; wave 0 also records the choice and finds the
+      // next pass's surviving address
       wave_best_dpp(bv, bi);
       if ((tid & 63) == 63) {
         part_v[tid >> 6] = bv;
@@ -1191,7 +1255,9 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
           if (C[tid].start_slot >= 0) b = (uint64_t)bit << C[tid].start_slot;
         }
         b = row_or_dpp(b);
-        if (tid == 0) sh_t = (t & surv) | b;
+        const uint64_t nt = (t & surv) | readlane64(b, 0);
+        if (has_next) bwd_surviving_base(lp[p - 1 - CH.p_lo], lpos[p - 1 - CH.p_lo], nt, tid, &sh_base);
+        if (tid == 0) sh_t = nt;
       }
       __syncthreads();
     }
