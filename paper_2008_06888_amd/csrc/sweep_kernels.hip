@@ -993,14 +993,12 @@ __device__ __forceinline__ void bwd_address_tables(const LPass& Q, const uint64_
 }
 
 // The input address of a pass's surviving slots under the selected output
-// entry t: lane c takes slot c, then an OR across the wave (one whole wave
-// calls it, lane = 0..63); lane 0 stores it.
-__device__ __forceinline__ void bwd_surviving_base(const LPass& Q, const uint8_t* ipos, uint64_t t, int lane,
-                                                   uint64_t* out) {
+// entry t: lane c takes slot c, then an OR across the wave (a whole wave
+// calls it, lane = 0..63); the result is the same in every lane.
+__device__ __forceinline__ uint64_t bwd_surviving_base(const LPass& Q, const uint8_t* ipos, uint64_t t, int lane) {
   uint64_t b = 0;
   if (lane < Q.in_w && ((Q.surv >> lane) & 1ull) && ((t >> lane) & 1ull)) b = 1ull << ipos[lane];
-  b = wave_or_dpp(b);
-  if (lane == 0) *out = b;
+  return wave_or_dpp(b);
 }
 
 template <typename IT>
@@ -1014,8 +1012,8 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   __shared__ LPass lp[BCH_PASSES];
   __shared__ uint8_t lpos[BCH_PASSES][64];
   __shared__ uint64_t lcad[BCH_CANDS];   // input address bit of each candidate (0: none)
-  __shared__ float part_v[NT / 64];
-  __shared__ uint32_t part_i[NT / 64];
+  __shared__ float part_v[2][NT / 64];   // by pass parity
+  __shared__ uint32_t part_i[2][NT / 64];
   __shared__ uint64_t part_a[NT / 64];
   const auto& I = as_const(items)[blockIdx.x];
   const int tid = threadIdx.x;
@@ -1049,12 +1047,12 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
     }
     wave_best64_dpp(bv, bi);
     if ((tid & 63) == 63) {
-      part_v[tid >> 6] = bv;
+      part_v[0][tid >> 6] = bv;
       part_a[tid >> 6] = bi;
     }
     __syncthreads();
     if (tid < 64) {
-      bv = tid < NT / 64 ? part_v[tid] : -INFINITY;
+      bv = tid < NT / 64 ? part_v[0][tid] : -INFINITY;
       bi = tid < NT / 64 ? part_a[tid] : ~0ull;
       wave_best64_dpp(bv, bi);
       if (tid == 63) {
@@ -1078,6 +1076,11 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
     if (tid == 0) sh_t = tb;
   }
   __syncthreads();
+  // the selected output entry of the pass being walked and the input address
+  // of its surviving slots: wave-uniform, and every wave follows the choices
+  // itself (no exchange through LDS)
+  uint64_t t_cur = sh_t, base_cur = 0;
+  const int lane = tid & 63;
   for (int ci = 0; ci < I.n_chunks; ++ci) {
     const BChunk CH = ldc(chunks + ci);
     // stage the chunk: pass fields and layouts, candidates, terms (coefficients resolved)
@@ -1121,22 +1124,20 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
     // the chunk's last pass: its address tables, and the address of its
     // surviving slots under the selected output entry
     bwd_address_tables(lp[CH.p_hi - CH.p_lo], lcad, ad_lo[CH.p_hi & 1], ad_hi[CH.p_hi & 1], tid);
-    if (tid >= 960) bwd_surviving_base(lp[CH.p_hi - CH.p_lo], lpos[CH.p_hi - CH.p_lo], sh_t, tid - 960, &sh_base);
+    base_cur = bwd_surviving_base(lp[CH.p_hi - CH.p_lo], lpos[CH.p_hi - CH.p_lo], t_cur, lane);
     __syncthreads();
     for (int p = CH.p_hi; p >= CH.p_lo; --p) {
       const LPass& P = lp[p - CH.p_lo];
       const int nc = P.n_cand;
       const uint64_t surv = P.surv;
-      const uint64_t t = sh_t;
+      const uint64_t t = t_cur;
       const bool has_next = p > CH.p_lo;
       if (nc == 0) {
-        __syncthreads();
-        if (tid < 64) {
-          const uint64_t nt = t & surv;
-          if (has_next) bwd_surviving_base(lp[p - 1 - CH.p_lo], lpos[p - 1 - CH.p_lo], nt, tid, &sh_base);
-          if (tid == 0) sh_t = nt;
-        } else if (has_next && tid >= 512) {
-          bwd_address_tables(lp[p - 1 - CH.p_lo], lcad, ad_lo[(p - 1) & 1], ad_hi[(p - 1) & 1], tid - 512);
+        t_cur = t & surv;
+        if (has_next) {
+          base_cur = bwd_surviving_base(lp[p - 1 - CH.p_lo], lpos[p - 1 - CH.p_lo], t_cur, lane);
+          if (tid >= 512)
+            bwd_address_tables(lp[p - 1 - CH.p_lo], lcad, ad_lo[(p - 1) & 1], ad_hi[(p - 1) & 1], tid - 512);
         }
         __syncthreads();
         continue;
@@ -1159,7 +1160,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       // word instead (offset 0, or the zero word) and its value is zeroed.
       const bool have_src = !P.init;
       const cptr<float> src =
-          have_src ? as_const(ckpt[p]) + sh_base : as_const(reinterpret_cast<const float*>(g_zero_words));
+          have_src ? as_const(ckpt[p]) + base_cur : as_const(reinterpret_cast<const float*>(g_zero_words));
       const uint64_t* AL = ad_lo[p & 1];
       const uint64_t* AH = ad_hi[p & 1];
       const uint32_t nb = (na + 8u * NT - 1u) / (8u * NT);
@@ -1234,33 +1235,32 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
           }
         }
       }
-      // the best (value, lowest index) of the workgroup: waves, then wave 0
-      // over the wave results; wave 0 also records the choice and finds the
-      // next pass's surviving address
+      // the best (value, lowest index) of the workgroup: each wave's, then
+      // every wave ranks the wave results and follows the choice (wave 0
+      // records the spins)
       wave_best_dpp(bv, bi);
-      if ((tid & 63) == 63) {
-        part_v[tid >> 6] = bv;
-        part_i[tid >> 6] = bi;
+      float* pv = part_v[p & 1];
+      uint32_t* pi = part_i[p & 1];
+      if (lane == 63) {
+        pv[tid >> 6] = bv;
+        pi[tid >> 6] = bi;
       }
       __syncthreads();
-      if (tid < 64) {
-        bv = tid < NT / 64 ? part_v[tid] : -INFINITY;
-        bi = tid < NT / 64 ? part_i[tid] : ~0u;
-        wave_best_dpp(bv, bi);
-        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)bi, 63);
-        uint64_t b = 0;
-        if (tid < nc) {   // nc <= 16: the first row of lanes
-          const uint32_t bit = (a >> tid) & 1u;
-          s_sh[C[tid].spin] = (int8_t)bit;
-          if (C[tid].start_slot >= 0) b = (uint64_t)bit << C[tid].start_slot;
-        }
-        b = row_or_dpp(b);
-        const uint64_t nt = (t & surv) | readlane64(b, 0);
-        if (has_next) bwd_surviving_base(lp[p - 1 - CH.p_lo], lpos[p - 1 - CH.p_lo], nt, tid, &sh_base);
-        if (tid == 0) sh_t = nt;
+      bv = lane < NT / 64 ? pv[lane] : -INFINITY;
+      bi = lane < NT / 64 ? pi[lane] : ~0u;
+      wave_best_dpp(bv, bi);
+      const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)bi, 63);
+      uint64_t b = 0;
+      if (lane < nc) {   // nc <= 16: the first row of lanes
+        const uint32_t bit = (a >> lane) & 1u;
+        if (tid < 64) s_sh[C[lane].spin] = (int8_t)bit;
+        if (C[lane].start_slot >= 0) b = (uint64_t)bit << C[lane].start_slot;
       }
-      __syncthreads();
+      b = row_or_dpp(b);
+      t_cur = (t & surv) | readlane64(b, 0);
+      if (has_next) base_cur = bwd_surviving_base(lp[p - 1 - CH.p_lo], lpos[p - 1 - CH.p_lo], t_cur, lane);
     }
+    __syncthreads();   // the chunk's LDS data is replaced next
   }
   const gptr<int8_t> sigma = as_global(I.sigma);
   const gptr<float> dh = as_global(I.dh), dJ = as_global(I.dJ);
