@@ -166,6 +166,28 @@ def test_square16_gauss_b64_sampled():
         assert np.array_equal(sig[b], ref["sigma"])
 
 
+@pytest.mark.parametrize("tile_bits", [13, 14])
+def test_square16_wide_tiles_backward(tile_bits):
+    """Tiles of 2^13 / 2^14: the passes eliminate 13 / 14 spins, so the
+    backward scores exactly one / two full batches of 8 x 1024 candidates per
+    pass (the second batch is loaded inside the scoring loop)."""
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    import kernel_emulator as KE
+    insts = I.config_instances(1, batch=3)
+    say("square16 gauss tile_bits", tile_bits, "batch 3")
+    plan = B.Plan(256, insts[0].edges, order=list(range(256)), has_field=True, tile_bits=tile_bits)
+    assert max(p.n_cand for p in KE.load_program(plan)["passes"]) == tile_bits
+    J, h = dev(stack(insts, "J")), dev(stack(insts, "h"))
+    E, sig, dJ, dh = B.backward(plan, J, h)
+    E, sig, dJ, dh = E.cpu().numpy(), sig.cpu().numpy(), dJ.cpu().numpy(), dh.cpu().numpy()
+    for b, x in enumerate(insts):
+        ref = O.eliminate(256, x.edges, x.J, x.h, order=list(range(256)))
+        assert abs(E[b] - ref["energy"]) <= tol(256)
+        assert np.array_equal(sig[b], ref["sigma"])
+        gJ, gh = O.ground_state_gradient(x.edges, ref["sigma"])
+        assert np.array_equal(dJ[b], gJ.astype(np.float32)) and np.array_equal(dh[b], gh.astype(np.float32))
+
+
 def test_split_batch_odd_size_matches_single_calls():
     # 17 x 2^16 state entries: the call runs as two parts (8 and 9 instances)
     # on two streams; every instance must equal its own single-instance call
