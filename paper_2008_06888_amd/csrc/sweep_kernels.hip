@@ -1001,6 +1001,77 @@ __device__ __forceinline__ uint64_t bwd_surviving_base(const LPass& Q, const uin
   return wave_or_dpp(b);
 }
 
+// A 64-bit lane value the compiler may not re-derive (so that it cannot
+// turn a load whose offset it could prove uniform into a separate scalar
+// path).
+__device__ __forceinline__ uint64_t opaque64(uint64_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Where a pass's candidates read their input entries: the checkpoint at the
+// surviving-slot address (or the zero word in the first pass, whose input is
+// all zero) and the two address tables.
+struct BwdSrc {
+  bool have;
+  cptr<float> src;
+  const uint64_t* AL;
+  const uint64_t* AH;
+  uint32_t na;
+};
+
+__device__ __forceinline__ bool have_src_of(const LPass& P) { return !P.init; }
+
+// Loads of the input entries of candidates a0 + j NT, j < W. The loads are
+// unconditional (a branch around each would make every one wait for the one
+// before) and nothing here uses their values, so they stay in flight until
+// the scoring: a candidate beyond the last reads a valid word instead
+// (offset 0; the scoring skips it), and in the first pass every candidate
+// reads the zero word.
+template <int W>
+__device__ __forceinline__ void bwd_issue(float (&val)[8], const BwdSrc& S, uint32_t a0) {
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const uint32_t a = a0 + (uint32_t)j * NT;
+    const uint64_t off = S.AL[a & 255u] | S.AH[(a >> 8) & 255u];
+    val[j] = S.src[opaque64((S.have && a < S.na) ? off : 0ull)];
+  }
+}
+
+// The terms of a pass that are not in the two tables (they touch a low and a
+// high candidate bit) and the selected output entry t.
+struct BwdTerms {
+  const LTerm* T;
+  int cross_b, nterm;
+  uint64_t t;
+  uint32_t na;
+};
+
+// Scores candidates a0 + j NT, j < W (input entry + table terms + cross
+// terms) into the thread's best (value, lowest index).
+template <int W>
+__device__ __forceinline__ void bwd_score(float (&val)[8], const BwdTerms& X, const float* lut_lo, const float* lut_hi,
+                                          uint32_t a0, float& bv, uint32_t& bi) {
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const uint32_t a = (a0 + (uint32_t)j * NT) & (X.na - 1u);
+    val[j] += lut_lo[a & 255u] + lut_hi[a >> 8];
+  }
+  for (int k = X.cross_b; k < X.nterm; ++k) {
+    const LTerm tk = X.T[k];
+#pragma unroll
+    for (int j = 0; j < W; ++j) val[j] += lterm_val(tk, a0 + (uint32_t)j * NT, X.t);
+  }
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const uint32_t a = a0 + (uint32_t)j * NT;
+    if (a < X.na && (val[j] > bv || (val[j] == bv && a < bi))) {
+      bv = val[j];
+      bi = a;
+    }
+  }
+}
+
 template <typename IT>
 __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ items) {
   __shared__ int8_t s_sh[MAX_SPINS];
@@ -1149,30 +1220,18 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       const int nlo = nc < 8 ? nc : 8, nhi = nc - nlo;
       const uint32_t na = 1u << nc;
       // the candidates' entries of the pass's input, in batches of 8 per
-      // thread; their addresses come from tables built during the pass
-      // before, so the loads are issued first and stay in flight while the
-      // term tables are built (the last batch's loads are the ones kept in
-      // flight; with NT = 1024 and at most 2^16 candidates there are at
-      // most eight batches)
-      // The loads are unconditional (a branch around each would make every
-      // one wait for the one before): a candidate beyond the last, or any
-      // candidate of the first pass (whose input is all zero), reads a valid
-      // word instead (offset 0, or the zero word) and its value is zeroed.
-      const bool have_src = !P.init;
-      const cptr<float> src =
-          have_src ? as_const(ckpt[p]) + base_cur : as_const(reinterpret_cast<const float*>(g_zero_words));
-      const uint64_t* AL = ad_lo[p & 1];
-      const uint64_t* AH = ad_hi[p & 1];
+      // thread (with NT = 1024 and at most 2^16 candidates, at most eight
+      // batches); their addresses come from tables built during the pass
+      // before, so the first batch's loads are issued here, without a
+      // branch, and stay in flight while the term tables are built. Only
+      // the W = 1, 2, 4 or 8 of them that cover the candidates are scored.
+      const BwdSrc S{have_src_of(P), have_src_of(P) ? as_const(ckpt[p]) + base_cur
+                                                    : as_const(reinterpret_cast<const float*>(g_zero_words)),
+                     ad_lo[p & 1], ad_hi[p & 1], na};
+      const int wsel = na <= (uint32_t)NT ? 1 : na <= 2u * NT ? 2 : na <= 4u * NT ? 4 : 8;
       const uint32_t nb = (na + 8u * NT - 1u) / (8u * NT);
       float val[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t a = (uint32_t)tid + (uint32_t)j * NT;
-        const bool ok = have_src && a < na;
-        const uint64_t off = AL[a & 255u] | AH[(a >> 8) & 255u];
-        const float v = src[ok ? off : 0ull];
-        val[j] = ok ? v : 0.f;
-      }
+      bwd_issue<8>(val, S, (uint32_t)tid);
       // tables of the terms over the low / high halves of the candidate
       // bits (threads 0..511); the next pass's address tables (threads
       // 512..1023)
@@ -1204,36 +1263,18 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       const int cross_b = n_lo + n_hi;
       float bv = -INFINITY;
       uint32_t bi = ~0u;
-      for (uint32_t bt = 0; bt < nb; ++bt) {
-        const uint32_t a0 = (uint32_t)tid + bt * 8u * NT;
-        if (bt > 0) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const uint32_t a = a0 + (uint32_t)j * NT;
-            const bool ok = have_src && a < na;
-            const uint64_t off = AL[a & 255u] | AH[(a >> 8) & 255u];
-            const float v = src[ok ? off : 0ull];
-            val[j] = ok ? v : 0.f;
+      const BwdTerms TT{T, cross_b, nterm, t, na};
+      switch (wsel) {
+        case 1: bwd_score<1>(val, TT, lut_lo, lut_hi, (uint32_t)tid, bv, bi); break;
+        case 2: bwd_score<2>(val, TT, lut_lo, lut_hi, (uint32_t)tid, bv, bi); break;
+        case 4: bwd_score<4>(val, TT, lut_lo, lut_hi, (uint32_t)tid, bv, bi); break;
+        default:
+          for (uint32_t bt = 0; bt < nb; ++bt) {
+            const uint32_t a0 = (uint32_t)tid + bt * 8u * NT;
+            if (bt > 0) bwd_issue<8>(val, S, a0);
+            bwd_score<8>(val, TT, lut_lo, lut_hi, a0, bv, bi);
           }
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const uint32_t a = (a0 + (uint32_t)j * NT) & (na - 1u);
-          val[j] += lut_lo[a & 255u] + lut_hi[a >> 8];
-        }
-        for (int k = cross_b; k < nterm; ++k) {
-          const LTerm tk = T[k];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) val[j] += lterm_val(tk, a0 + (uint32_t)j * NT, t);
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const uint32_t a = a0 + (uint32_t)j * NT;
-          if (a < na && (val[j] > bv || (val[j] == bv && a < bi))) {
-            bv = val[j];
-            bi = a;
-          }
-        }
+          break;
       }
       // the best (value, lowest index) of the workgroup: each wave's, then
       // every wave ranks the wave results and follows the choice (wave 0
