@@ -195,7 +195,9 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
                      int32_t* chosen_bits, double* best_ms, void* stream);
 
 /* Per-kernel timing on the call's stream, for measurement tools: when on,
- * every launch is bracketed by HIP events and calls run eagerly (no graph
+ * every launch is bracketed by HIP events (the pass kernel's two events are
+ * handed to its launch, which stamps them with the kernel's own start and
+ * end, dispatch excluded) and calls run eagerly (no graph
  * capture or replay); tt_prof_read returns the summed milliseconds and
  * launch count of the named kernel family ("sweep_pass", "sweep_backward",
  * "final_reduce", "count_pass", "count_reduce", "count_chain", "chain",

@@ -72,21 +72,33 @@ hipEvent_t pool_get() {
 
 // Kernel timing brackets a launch with two pooled events on its stream.
 // Timed calls always run eagerly (a call is never captured while timing is
-// on), so every bracket times exactly one launch.
+// on), so every bracket times exactly one launch. In the attached form the
+// two events are handed to the launch itself (start() / stop()), which
+// stamps them with the kernel's own start and end, dispatch excluded; the
+// record counts only once the launch has taken them (launched()).
 struct ProfScope {
   hipStream_t s;
   const char* name;
   hipEvent_t a = nullptr, b = nullptr;
-  bool on;
-  ProfScope(hipStream_t s_, const char* n) : s(s_), name(n), on(g_prof_on) {
+  bool on, attached, fired = false;
+  ProfScope(hipStream_t s_, const char* n, bool attached_ = false)
+      : s(s_), name(n), on(g_prof_on), attached(attached_) {
     if (!on) return;
     a = pool_get();
     b = pool_get();
-    on = a && b && hipEventRecord(a, s) == hipSuccess;
+    on = a && b && (attached || hipEventRecord(a, s) == hipSuccess);
   }
+  hipEvent_t start() const { return on && attached ? a : nullptr; }
+  hipEvent_t stop() const { return on && attached ? b : nullptr; }
+  void launched() { fired = true; }
   ~ProfScope() {
     if (!on) return;
-    if (hipEventRecord(b, s) != hipSuccess) return;
+    if (attached ? !fired : hipEventRecord(b, s) != hipSuccess) {
+      std::lock_guard<std::mutex> g(g_prof_mu);
+      g_event_pool.push_back(a);
+      g_event_pool.push_back(b);
+      return;
+    }
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof_pending.push_back({name, a, b});
   }
@@ -703,8 +715,10 @@ void patch_tables(CallTables& ct, char* dev) {
 
 int enqueue_launches(const CallTables& ct, const char* dev, float* pv, uint64_t* pi, int32_t dtype, hipStream_t s) {
   for (const CallTables::Launch& L : ct.levels) {
-    ProfScope ps(s, "sweep_pass");
-    HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s));
+    ProfScope ps(s, "sweep_pass", true);
+    HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s,
+                        ps.start(), ps.stop()));
+    ps.launched();
   }
   if (!ct.bwd_ranks) {
     ProfScope ps(s, "final_reduce");
@@ -1103,8 +1117,10 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   for (int k = 0; k < np; ++k) {
     const CallTables::Launch& L = ct.levels[k];
     {
-      ProfScope ps(s, "sweep_pass");
-      HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s));
+      ProfScope ps(s, "sweep_pass", true);
+      HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s,
+                          ps.start(), ps.stop()));
+      ps.launched();
     }
     if (dc->chain_after[k] >= 0)
       if (int r = chain(dc->chain_after[k])) return r;

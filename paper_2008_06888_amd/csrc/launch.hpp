@@ -8,9 +8,10 @@
 
 namespace tt {
 
-// threads: at least 2^tb of every item's pass; lds: at least 4 * 2^t bytes of every item's pass
+// threads: at least 2^tb of every item's pass; lds: at least 4 * 2^t bytes of every item's pass.
+// t0 / t1 (optional, created events): receive the kernel's own start and end times.
 hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int threads, size_t lds, int dtype,
-                       hipStream_t stream);
+                       hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 int reduce_log2_chunks(int w);
 hipError_t launch_reduce(const RedItem* items, int n_items, int64_t n_chunks, float* pv, uint64_t* pi,
                          hipStream_t stream, bool partials_ready = false);

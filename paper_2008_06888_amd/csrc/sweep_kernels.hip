@@ -14,6 +14,7 @@
 // float add, the tropical sum a float max. Bond entries follow Sec. II: the
 // bond matrix is [[J, -J], [-J, J]] with index 0 <-> sigma = +1, so the
 // state holds negative energies and its final maximum is -E*.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -1339,16 +1340,23 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 }
 
 hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int threads, size_t lds, int dtype,
-                       hipStream_t stream) {
+                       hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
   if (n_wg >= (1ll << 31) || threads < 64 || threads > NT || lds > 65536) return hipErrorInvalidConfiguration;
+  const dim3 grid((uint32_t)n_wg), block(threads);
   if (dtype == 0) {
     hipError_t e = allow_lds(k_pass<float>, PASS_LDS_MAX);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pass<float>, dim3((uint32_t)n_wg), dim3(threads), lds, stream, items, n_items);
+    if (t0 || t1)
+      hipExtLaunchKernelGGL(k_pass<float>, grid, block, (uint32_t)lds, stream, t0, t1, 0u, items, n_items);
+    else
+      hipLaunchKernelGGL(k_pass<float>, grid, block, lds, stream, items, n_items);
   } else {
     hipError_t e = allow_lds(k_pass<int32_t>, PASS_LDS_MAX);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pass<int32_t>, dim3((uint32_t)n_wg), dim3(threads), lds, stream, items, n_items);
+    if (t0 || t1)
+      hipExtLaunchKernelGGL(k_pass<int32_t>, grid, block, (uint32_t)lds, stream, t0, t1, 0u, items, n_items);
+    else
+      hipLaunchKernelGGL(k_pass<int32_t>, grid, block, lds, stream, items, n_items);
   }
   return hipGetLastError();
 }
