@@ -1078,7 +1078,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   __shared__ int8_t s_sh[MAX_SPINS];
   __shared__ float lut_lo[256], lut_hi[256];
   __shared__ uint64_t ad_lo[2][256], ad_hi[2][256];   // by pass parity
-  __shared__ uint64_t sh_t, sh_base;
+  __shared__ uint64_t sh_t, sh_final;   // the first selected entry, the final address
   __shared__ LTerm lt[BCH_TERMS];
   __shared__ BCand lc[BCH_CANDS];
   __shared__ LPass lp[BCH_PASSES];
@@ -1128,7 +1128,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       bi = tid < NT / 64 ? part_a[tid] : ~0ull;
       wave_best64_dpp(bv, bi);
       if (tid == 63) {
-        sh_base = bi;   // the selected final address (sh_base is free until the passes)
+        sh_final = bi;   // the selected final address
         if (I.energy) *as_global(I.energy) = -(double)bv;
       }
     }
@@ -1136,7 +1136,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   __syncthreads();
   if (tid < 64) {
     // final state: address -> slot index; spins still in a slot take its bit
-    const uint64_t addr = I.red_v ? sh_base : *as_const(I.final_addr);
+    const uint64_t addr = I.red_v ? sh_final : *as_const(I.final_addr);
     uint64_t tb = 0;
     if (tid < final_w) {
       const uint64_t b = (addr >> final_pos[tid]) & 1ull;
