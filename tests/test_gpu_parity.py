@@ -188,6 +188,29 @@ def test_square16_wide_tiles_backward(tile_bits):
         assert np.array_equal(dJ[b], gJ.astype(np.float32)) and np.array_equal(dh[b], gh.astype(np.float32))
 
 
+@pytest.mark.parametrize("tile_bits", [7, 8])
+def test_square14_many_passes_backward(tile_bits):
+    """14x14 at tiles 2^7 / 2^8: 182 / 91 passes, more than the 64 a chunk of
+    the backward stages in LDS at once, so the walk crosses chunk boundaries."""
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    import kernel_emulator as KE
+    L = 14
+    e = I.square_lattice(L)
+    insts = [I.make(e, L * L, np.random.default_rng([11, b]), "gauss", field_std=0.3) for b in range(3)]
+    say("square14 gauss tile_bits", tile_bits, "batch 3")
+    plan = B.Plan(L * L, e, order=list(range(L * L)), has_field=True, tile_bits=tile_bits)
+    assert len(KE.load_program(plan)["passes"]) > 64
+    J, h = dev(stack(insts, "J")), dev(stack(insts, "h"))
+    E, sig, dJ, dh = B.backward(plan, J, h)
+    E, sig, dJ, dh = E.cpu().numpy(), sig.cpu().numpy(), dJ.cpu().numpy(), dh.cpu().numpy()
+    for b, x in enumerate(insts):
+        ref = O.eliminate(L * L, e, x.J, x.h, order=list(range(L * L)))
+        assert abs(E[b] - ref["energy"]) <= tol(L * L)
+        assert np.array_equal(sig[b], ref["sigma"])
+        gJ, gh = O.ground_state_gradient(e, ref["sigma"])
+        assert np.array_equal(dJ[b], gJ.astype(np.float32)) and np.array_equal(dh[b], gh.astype(np.float32))
+
+
 def test_split_batch_odd_size_matches_single_calls():
     # 17 x 2^16 state entries: the call runs as two parts (8 and 9 instances)
     # on two streams; every instance must equal its own single-instance call
