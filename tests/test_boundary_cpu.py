@@ -69,3 +69,14 @@ def test_autotune_mode_validated_before_any_device_work():
     for mode in (-1, 3):
         assert B.lib().tt_plan_autotune(p.handle, 1, 0, None, None, mode, None, None, None) == B.TT_E_INVAL
     assert B.TUNE_ENERGY == 0 and B.TUNE_COUNT == 1 and B.TUNE_BACKWARD == 2
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus above 1 exits with a message before any device work."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
