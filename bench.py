@@ -1,10 +1,18 @@
 """Benchmark of the headline workload: ground states (energy + configuration)
-of 64 seeded 16x16 open square-lattice Ising spin glasses with Gaussian
-couplings J ~ N(0, 1) and fields h ~ N(0, 0.1^2), float32, in one batch.
+of 64 seeded 16x16 open square-lattice Ising spin glasses with couplings
+J = +-1 (int32) and h = 0, in one batch (the workload the solves/s metric
+names). The same shape with Gaussian couplings and fields is timed as a
+second figure.
 
-One step = the whole hot path on one batch: the max-plus sweep (all passes),
-the final reduction and the argmax-routing backward that returns sigma and
-dE/dJ, dE/dh. Inputs are resident in HBM before timing starts.
+One step = the whole hot path on one batch: the input check, the max-plus
+sweep (all passes, the final maximum fused into the last one) and the
+argmax-routing backward that returns sigma and dE/dJ. Inputs are resident in
+HBM before timing starts.
+
+Work is counted as max-plus ops = 2 x contraction terms + elementwise ops
+(a gate is a contraction with K = 2: two terms per output entry; diagonal and
+field absorbs, cuts and the final maximum are one op per entry), from the
+plan's own counts at the live width of every step.
 
 Prints one JSON line (metric, value = solves/s, roofline of the dominant
 kernel, CPU-oracle baseline). Only one GPU is used; --gpus above 1 exits.
@@ -21,30 +29,74 @@ sys.path.insert(0, ROOT)
 
 METRIC = "max-plus Gop/s & % VALU peak; ground-state solves/s (energy+config), 16x16 ±J"
 VALU_PEAK_OPS = 256 * 64 * 2.4e9 * 2      # max-plus ops/s: one term (add + max) per lane per cycle
-# HBM bytes per k_pass launch of the headline workload (one of the two
-# concurrent half-batch launches of a pass), by tile size, from rocprofv3
-# counter passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain
-# 256 MiB device copy reads for the same counters);
-# profiles/k_pass_square16x16_gauss_b64.txt. Emptied whenever the pass
-# kernel changes, until the counters are taken again.
-K_PASS_TRAFFIC_BYTES = {11: 16.53e6, 12: 16.47e6, 13: 16.39e6, 14: 16.34e6}
+# HBM bytes per launch of the pass kernel, by workload and tile size, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs scaled by a plain device copy
+# (the summary and its commands are in this file).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_traffic.json")
 
 
-def cpu_baseline(insts, seconds=15.0):
-    """The oracle as it stands, on a bounded sample of the same workload."""
+def pass_traffic(workload, tile_bits, parts):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        return t[workload][f"tile{tile_bits}_parts{parts}"]["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def _oracle_solve(args):
+    """One instance by the oracle (its process runs single-threaded numpy)."""
     from oracle import spinglass as O
+    n, edges, J, h = args
+    O.eliminate(n, edges, J, h, order=list(range(n)))
+    return 1
+
+
+def cpu_baseline(insts, seconds=10.0, workers=16):
+    """The oracle as it stands, on bounded samples of the same workload: one
+    thread, then `workers` processes (the machine's CPU share) over the batch."""
+    import multiprocessing as mp
     n = insts[0].n
+    work = [(n, x.edges, x.J, x.h) for x in insts]
     t0 = time.perf_counter()
     done = 0
-    for x in insts:
-        O.eliminate(n, x.edges, x.J, x.h, order=list(range(n)))
+    while time.perf_counter() - t0 < seconds:
+        _oracle_solve(work[done % len(work)])
         done += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of the 64 instances, numpy max-sum elimination (raster order) "
-                      f"with traceback, single thread, {dt:.1f} s"}
+    t1 = time.perf_counter() - t0
+    single = done / t1
+    workers = max(1, min(workers, os.cpu_count() or 1))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_solve, work[:workers])        # start-up outside the timing
+        t0 = time.perf_counter()
+        rounds = 0
+        while True:
+            pool.map(_oracle_solve, work)
+            rounds += 1
+            if time.perf_counter() - t0 > seconds / 2:
+                break
+        t2 = time.perf_counter() - t0
+    model, ncpu = host_cpu()
+    return {"value": rounds * len(work) / t2, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": f"{rounds} x the {len(work)} instances over {workers} processes in {t2:.1f} s; "
+                      f"single thread: {done} instances in {t1:.1f} s",
+            "single_thread": {"value": single, "unit": "solves/s", "cores": 1},
+            "host": {"cpu_model": model, "nproc": ncpu},
+            "method": "numpy max-sum bucket elimination (raster order) with traceback, int64 / float64"}
 
 
 def bench_tgemm(args):
@@ -210,8 +262,8 @@ def main():
                     help="instead: time the dense tropical product at M = N = K = S")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead: run a plain device copy of MIB MiB (scale for HBM byte counters)")
-    ap.add_argument("--workload", default="square16_gauss_b64",
-                    choices=["square16_gauss_b64", "chimera8x8_pm1", "square32_pm1_count", "reg3_uneven_b16"],
+    ap.add_argument("--workload", default="square16_pm1_b64",
+                    choices=["square16_pm1_b64", "chimera8x8_pm1", "square32_pm1_count", "reg3_uneven_b16"],
                     help="the headline workload (default) or one of the other measured cases")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -234,19 +286,74 @@ def main():
     from paper_2008_06888_amd import binding as B
     from paper_2008_06888_amd import instances as I
 
-    insts = I.config_instances(1)
-    L, batch = 16, len(insts)
+    L, batch = 16, 64
     n = L * L
-    plan = B.Plan(n, insts[0].edges, order=list(range(n)), has_field=True)
-    info = plan.info()
     dev = torch.device("cuda:0")
-    J = torch.tensor(np.stack([x.J for x in insts]), device=dev)
-    h = torch.tensor(np.stack([x.h for x in insts]), device=dev)
+    pm1 = I.config_instances(0, batch=batch, L=L)          # J = +-1 int32, h = 0
+    J = torch.tensor(np.stack([x.J for x in pm1]), device=dev)
+    line = run_lattice(args, B, pm1[0].edges, n, J, None, "square16x16_pm1_b64")
+    out = {
+        "metric": METRIC,
+        "value": line["solves_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": line["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "square16x16_pm1_b64", "L": L, "batch": batch, "couplings": "+-1 int32 (exact "
+                   "integers in the float32 state)", "fields": "none (h = 0)", "outputs": "E*, sigma, dE/dJ",
+                   "parallelism": "single GPU"},
+        "maxplus_gops": line["maxplus_gops"],
+        "valu_frac": line["valu_frac"],
+        "roofline": line["roofline"],
+        "roofline_one_part": line["roofline_one_part"],
+        "kernel_ms_per_step": line["kernel_ms_per_step"],
+        "plan": line["plan"],
+    }
+    if args.headline_only:
+        print(json.dumps(out))
+        return
+    # second figure: the same shape with Gaussian couplings and fields (float32)
+    gauss = I.config_instances(1)
+    Jg = torch.tensor(np.stack([x.J for x in gauss]), device=dev)
+    hg = torch.tensor(np.stack([x.h for x in gauss]), device=dev)
+    gl = run_lattice(args, B, gauss[0].edges, n, Jg, hg, "square16x16_gauss_h_b64")
+    out["gauss_h_b64"] = {k: gl[k] for k in ("solves_s", "ms_per_step", "maxplus_gops", "valu_frac", "roofline",
+                                             "kernel_ms_per_step", "plan")}
+    out["gauss_h_b64"]["outputs"] = "E*, sigma, dE/dJ, dE/dh"
+    # the plain path: the same 64 +-J instances, one eager call each
+    plan1 = B.Plan(n, pm1[0].edges, order=list(range(n)), tile_bits=line["plan"]["tile_bits"])
+    rows = [J[b:b + 1].contiguous() for b in range(batch)]
+    extra_steps = max(1, min(args.steps, 10))
 
-    # tile size chosen by the autotuner on this batch (outside the timed region)
+    def one_by_one():
+        for jb in rows:
+            B.backward(plan1, jb)
+    B.graphs_enable(False)
+    one_by_one()
+    t_single = _timed(one_by_one, extra_steps)
+    B.graphs_enable(True)
+    out["context"] = {"one_instance_per_call_solves_s": batch / t_single}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(pm1)
+    print(json.dumps(out))
+
+
+def run_lattice(args, B, edges, n, J, h, workload):
+    """Times tt_backward (E*, sigma and the gradients) on one batch: the autotuned
+    plan, `steps` timed calls, then the same calls with per-launch kernel timing,
+    and once more with the batch in one part (no concurrent halves)."""
+    import torch
+    batch = J.shape[0]
+    has_h = h is not None
+    plan = B.Plan(n, edges, order=list(range(n)), has_field=has_h)
     tile_bits, _ = B.autotune(plan, J, h, config=True)
     info = plan.info()
-    # warm-up: the second call is captured as a HIP graph, later calls replay it
     for _ in range(max(args.warmup, 2)):
         B.backward(plan, J, h)
     torch.cuda.synchronize()
@@ -254,80 +361,53 @@ def main():
     for _ in range(args.steps):
         B.backward(plan, J, h)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # kernel durations: the same steps again with every launch bracketed by HIP
-    # events on its stream (timed calls run eagerly: same kernels and grids)
-    B.prof_reset()
-    B.prof_enable(True)
-    for _ in range(args.steps):
-        B.backward(plan, J, h)
-    torch.cuda.synchronize()
-    B.prof_enable(False)
-    ms_pass, n_pass = B.prof_read("sweep_pass")
-    ms_bwd, n_bwd = B.prof_read("sweep_backward")
-    ms_red, n_red = B.prof_read("final_reduce")
+    dt = time.perf_counter() - t0
 
-    dt = t1 - t0
-    ms_per_step = dt * 1e3 / args.steps
-    solves = batch * args.steps / dt
-    # algorithmic max-plus work of one step (forward sweep + final reduction)
-    ops_step = 2.0 * info["terms"] * batch
-    ops_pass = 2.0 * (info["terms"] - info["reduce_terms"]) * batch * args.steps
-    achieved = ops_pass / (ms_pass * 1e-3) if ms_pass > 0 else 0.0
-    out = {
-        "metric": METRIC,
-        "value": solves,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "square16x16_gauss_h_b64", "L": L, "batch": batch, "couplings": "N(0,1) fp32",
-                   "fields": "N(0,0.1^2) fp32", "outputs": "E*, sigma, dE/dJ, dE/dh", "parallelism": "single GPU"},
+    def kernel_times(p, steps):
+        B.prof_reset()
+        B.prof_enable(True)
+        for _ in range(steps):
+            B.backward(p, J, h)
+        torch.cuda.synchronize()
+        B.prof_enable(False)
+        return {k: B.prof_read(k) for k in ("sweep_pass", "sweep_backward", "final_reduce", "check_inputs")}
+
+    kt = kernel_times(plan, args.steps)
+    one = B.Plan(n, edges, order=list(range(n)), has_field=has_h, tile_bits=tile_bits, parts=1)
+    B.backward(one, J, h)
+    kt1 = kernel_times(one, args.steps)
+    ops_inst = 2.0 * info["terms"] + info["elementwise"]     # the final maximum runs inside the last pass
+    ops_step = ops_inst * batch
+    large = (batch << info["width"]) >= (1 << 20)
+    parts = 2 if (large and batch >= 2) else 1
+
+    def roof(k, nparts):
+        ms, launches = k["sweep_pass"]
+        per_launch = ops_step * args.steps / max(launches, 1)
+        avg_ms = ms / max(launches, 1)
+        ach = per_launch / (avg_ms * 1e-3) if ms > 0 else 0.0
+        return {"kernel": "k_pass", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "TFLOP/s", "frac": ach / VALU_PEAK_OPS,
+                "traffic": pass_traffic(workload, tile_bits, nparts),
+                "avg_launch_ms": avg_ms, "launches": launches, "ops_per_launch": per_launch,
+                "concurrent_parts": nparts}
+
+    r = roof(kt, parts)
+    if parts > 1:
+        r["note"] = ("each launch is half a pass and runs beside the other half's launch; the whole-step "
+                     "rate is valu_frac, the unsplit per-launch rate roofline_one_part")
+    return {
+        "solves_s": batch * args.steps / dt,
+        "ms_per_step": dt * 1e3 / args.steps,
         "maxplus_gops": ops_step * args.steps / dt / 1e9,
         "valu_frac": ops_step * args.steps / dt / VALU_PEAK_OPS,
-        "roofline": {"kernel": "k_pass", "bound": "alu", "achieved": achieved / 1e12,
-                     "peak": VALU_PEAK_OPS / 1e12, "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": K_PASS_TRAFFIC_BYTES.get(tile_bits),
-                     "avg_launch_ms": ms_pass / max(n_pass, 1), "launches": n_pass,
-                     # the batch runs in parts on concurrent streams: each launch does its part's
-                     # work, so the whole-step rate (valu_frac) exceeds the per-launch one
-                     "concurrent_parts": round(n_pass / max(args.steps, 1) / max(info["n_passes"], 1))},
-        "kernel_ms_per_step": {"sweep_pass": ms_pass / args.steps, "sweep_backward": ms_bwd / args.steps,
-                               "final_reduce": ms_red / args.steps},
-        "plan": {"width": info["width"], "passes": info["n_passes"], "terms_per_instance": info["terms"],
-                 "tile_bits": tile_bits},
+        "roofline": r,
+        "roofline_one_part": roof(kt1, 1),
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+        "plan": {"width": info["width"], "passes": info["n_passes"], "tile_bits": tile_bits,
+                 "terms_per_instance": info["terms"], "elementwise_per_instance": info["elementwise"],
+                 "maxplus_ops_per_instance": ops_inst},
     }
-    if args.headline_only:
-        print(json.dumps(out))
-        return
-    # context, outside the timed region: the same shape with J = +-1 (the metric's
-    # name), and the batch solved as 64 one-instance calls
-    extra_steps = max(1, min(args.steps, 10))
-    pm1 = I.config_instances(0, batch=batch, L=L)
-    Jp = torch.tensor(np.stack([x.J for x in pm1]), device=dev)
-    pplan = B.Plan(n, pm1[0].edges, order=list(range(n)))
-    B.backward(pplan, Jp)
-    B.backward(pplan, Jp)
-    t_pm1 = _timed(lambda: B.backward(pplan, Jp), extra_steps)
-    rows = [(J[b:b + 1].contiguous(), h[b:b + 1].contiguous()) for b in range(batch)]
-
-    def one_by_one():
-        for jb, hb in rows:
-            B.backward(plan, jb, hb)
-    B.graphs_enable(False)   # the plain path: eager launches, one instance per call
-    one_by_one()
-    t_single = _timed(one_by_one, extra_steps)
-    B.graphs_enable(True)
-    out["context"] = {"pm1_int32_h0_solves_s": batch / t_pm1, "one_instance_per_call_solves_s": batch / t_single}
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(insts)
-    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -24,9 +24,19 @@
  *     shared by concurrent calls on different streams only if each call uses
  *     its own plan; device workspace is cached inside the plan.
  *   - Compute calls enqueue on `stream` (a hipStream_t, NULL = default
- *     stream) and return once enqueued; outputs are valid after the stream
- *     synchronises. tt_count additionally synchronises `stream` (its CRT
- *     guard reads residues on the host).
+ *     stream); outputs are valid after the stream synchronises.
+ *     tt_contract, tt_backward and tt_contract_uneven first check their
+ *     inputs on the device (every coupling and field finite; with int32
+ *     couplings sum|J| + sum|h| < 2^24 per instance, the range in which the
+ *     float32 state is exact): the check is the first launch of the call, and
+ *     the call returns after enqueueing all its launches and waiting for the
+ *     check's result, i.e. once the work queued on `stream` before the call
+ *     has finished. An input error is returned as TT_E_INVAL (not finite) or
+ *     TT_E_RANGE; the outputs are then unspecified. tt_count synchronises
+ *     `stream` (it checks the range and recombines the counts on the host).
+ *   - An explicit budget (tt_plan_opts.max_bytes) is checked on the host
+ *     before any device work: a call whose state would exceed it returns
+ *     TT_E_TOOBIG without touching the device.
  */
 #ifndef TT_H
 #define TT_H
@@ -44,7 +54,7 @@ typedef enum tt_status {
   TT_E_DTYPE = -2,          /* dtype not supported by this call */
   TT_E_RANGE = -3,          /* exact-integer range of the value type exceeded */
   TT_E_TOOBIG = -4,         /* planned device memory exceeds the budget */
-  TT_E_COUNT_OVERFLOW = -5, /* reserved: strict-mode count overflow */
+  TT_E_COUNT_OVERFLOW = -5, /* tt_count in strict mode: g may exceed the moduli */
   TT_E_DEVICE = -6,         /* a HIP runtime call failed (message has the code) */
   TT_E_NOMEM = -7           /* host allocation failed */
 } tt_status;
@@ -72,6 +82,9 @@ typedef struct tt_plan_opts {
   int32_t chimera_rows;     /* CHIMERA: unit-cell rows  */
   int32_t chimera_cols;     /* CHIMERA: unit-cell columns */
   int64_t max_bytes;        /* device memory budget of one call [7/8 of free] */
+  int32_t parts;            /* concurrent parts (streams) a large same-graph batch
+                               runs in: 1 or 2 [2] */
+  int32_t pad;
 } tt_plan_opts;
 
 typedef struct tt_plan_stats {
@@ -81,8 +94,12 @@ typedef struct tt_plan_stats {
   int32_t n_ops;            /* absorb/relabel/eliminate operations */
   int32_t n_passes;         /* energy-path passes (kernel launches per batch) */
   int32_t n_count_passes;   /* count-path passes */
-  double terms;             /* max-plus terms per instance (one add + one max) */
-  double reduce_terms;      /* of which the final reduction (max over the last state) */
+  /* algorithmic work per instance, at the live width of every step:
+   * max-plus ops = 2 * terms + elementwise */
+  double terms;             /* contraction terms (one add + one max): K per output entry */
+  double elementwise;       /* elementwise ops: diagonal / field absorbs (one add per
+                               entry), cuts and the final maximum (one max per entry) */
+  double reduce_ops;        /* of which the final maximum over the last state */
   double entry_updates;     /* state entries read+written per instance (energy path) */
 } tt_plan_stats;
 
@@ -129,12 +146,21 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
                 const void* h, double* energy, int8_t* sigma, float* dJ,
                 float* dh, void* stream);
 
-/* Ground-state energy and degeneracy g (Eq. 4) for integer couplings.
- * J: device int32 [batch][n_edges]; h: device int32 [batch][n_spins] or NULL.
- * energy: host int64 [batch]; residues: host uint64 [batch][3], g mod the
- * three moduli of tt_count_moduli. g counts sigma and -sigma separately. */
+/* Ground-state energy and degeneracy g (Eq. 4: tuples (x, n), n an ordinary
+ * count) for integer couplings. J: device int32 [batch][n_edges]; h: device
+ * int32 [batch][n_spins] or NULL. energy: host int64 [batch]; residues: host
+ * uint64 [batch][3], g mod the three primes of tt_count_moduli (their
+ * product M ~ 2^183). g counts sigma and -sigma separately.
+ * Exactness: g <= 2^n_spins, so for n_spins <= 182 the CRT value of the
+ * residues is g. For larger graphs the kernels carry g mod 2^64 as well and
+ * the CRT value is accepted when it agrees with it modulo 2^64 (g >= M with
+ * agreement needs floor(g / M) to be a multiple of 2^64).
+ * exact_flag: host uint8 [batch], 1 = the residues give g exactly, 0 = g may
+ * reach M (then only g mod M is known); NULL selects strict mode, in which
+ * any inexact instance makes the call return TT_E_COUNT_OVERFLOW.
+ * TT_E_RANGE when sum|J| + sum|h| >= 2^24 for an instance. */
 int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h,
-             int64_t* energy, uint64_t* residues, void* stream);
+             int64_t* energy, uint64_t* residues, uint8_t* exact_flag, void* stream);
 /* The three prime moduli (2^61-1, 2^61-31, 2^61-45). */
 int tt_count_moduli(uint64_t moduli_out[3]);
 /* Exact g from its residues by the Chinese remainder theorem, as a decimal

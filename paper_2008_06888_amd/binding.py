@@ -43,13 +43,15 @@ class PlanOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("order", C.POINTER(C.c_int32)), ("seed", C.c_uint64),
                 ("trials", C.c_int32), ("has_field", C.c_int32), ("tile_bits", C.c_int32),
                 ("count_tile_bits", C.c_int32), ("chimera_rows", C.c_int32),
-                ("chimera_cols", C.c_int32), ("max_bytes", C.c_int64)]
+                ("chimera_cols", C.c_int32), ("max_bytes", C.c_int64), ("parts", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class PlanStats(C.Structure):
     _fields_ = [("n_spins", C.c_int32), ("n_edges", C.c_int64), ("width", C.c_int32),
                 ("n_ops", C.c_int32), ("n_passes", C.c_int32), ("n_count_passes", C.c_int32),
-                ("terms", C.c_double), ("reduce_terms", C.c_double), ("entry_updates", C.c_double)]
+                ("terms", C.c_double), ("elementwise", C.c_double), ("reduce_ops", C.c_double),
+                ("entry_updates", C.c_double)]
 
 
 _vp = C.c_void_p
@@ -63,7 +65,7 @@ _lib.tt_plan_destroy.argtypes = [_vp]
 _lib.tt_plan_destroy.restype = None
 _lib.tt_contract.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
 _lib.tt_backward.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
-_lib.tt_count.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]
+_lib.tt_count.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_count_moduli.argtypes = [_vp]
 _lib.tt_count_to_decimal.argtypes = [_vp, C.c_char_p, C.c_size_t]
 _lib.tt_contract_uneven.argtypes = [C.c_int32, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -96,7 +98,8 @@ class Plan:
 
     def __init__(self, n: int, edges, *, order: Optional[Sequence[int]] = None, kind: Optional[int] = None,
                  has_field: bool = False, seed: int = 0, trials: int = 32, tile_bits: int = 0,
-                 count_tile_bits: int = 0, chimera: Optional[tuple] = None, max_bytes: int = 0):
+                 count_tile_bits: int = 0, chimera: Optional[tuple] = None, max_bytes: int = 0,
+                 parts: int = 0):
         self.n = int(n)
         self.edges = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
         self.m = int(self.edges.shape[0])
@@ -110,7 +113,7 @@ class Plan:
             self._order_buf = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
             o.order = self._order_buf.ctypes.data_as(C.POINTER(C.c_int32))
         o.seed, o.trials, o.has_field = seed, trials, int(has_field)
-        o.tile_bits, o.count_tile_bits, o.max_bytes = tile_bits, count_tile_bits, max_bytes
+        o.tile_bits, o.count_tile_bits, o.max_bytes, o.parts = tile_bits, count_tile_bits, max_bytes, parts
         if chimera:
             o.chimera_rows, o.chimera_cols = chimera
         h = _vp()
@@ -240,8 +243,7 @@ def backward(plan: Plan, J, h=None, want_grad: bool = True):
     return energy, sigma, dJ, dh
 
 
-def count(plan: Plan, J, h=None):
-    """(E* int64 numpy [batch], residues uint64 numpy [batch, 3], g as Python ints)."""
+def _count(plan: Plan, J, h, flags: bool):
     torch = _torch()
     _check_inputs(plan, J, h)
     if J.dtype != torch.int32:
@@ -249,8 +251,23 @@ def count(plan: Plan, J, h=None):
     B = J.shape[0]
     energy = np.zeros(B, np.int64)
     res = np.zeros((B, 3), np.uint64)
-    _check(_lib.tt_count(plan.handle, B, _ptr(J), _ptr(h), energy.ctypes.data, res.ctypes.data, _stream()))
-    return energy, res, [residues_to_int(r) for r in res]
+    exact = np.zeros(B, np.uint8)
+    _check(_lib.tt_count(plan.handle, B, _ptr(J), _ptr(h), energy.ctypes.data, res.ctypes.data,
+                         exact.ctypes.data if flags else None, _stream()))
+    return energy, res, [residues_to_int(r) for r in res], exact.astype(bool)
+
+
+def count(plan: Plan, J, h=None):
+    """(E* int64 numpy [batch], residues uint64 numpy [batch, 3], g as Python ints).
+
+    Strict: raises TTError (TT_E_COUNT_OVERFLOW) when a count may exceed the
+    product of the moduli instead of returning it modulo that product."""
+    return _count(plan, J, h, False)[:3]
+
+
+def count_with_flags(plan: Plan, J, h=None):
+    """(E*, residues, g mod M as Python ints, exact bool numpy [batch]): g is exact where the flag is set."""
+    return _count(plan, J, h, True)
 
 
 def contract_uneven(plans: Sequence[Plan], J_list, want_sigma: bool = True):

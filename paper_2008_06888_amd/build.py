@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtt.so")
-SOURCES = ["planner.cpp", "encode.cpp", "capi.cpp", "sweep_kernels.hip", "count_kernels.hip", "tgemm_kernels.hip", "chimera_kernels.hip"]
+SOURCES = ["planner.cpp", "encode.cpp", "capi.cpp", "sweep_kernels.hip", "count_kernels.hip", "tgemm_kernels.hip",
+           "chimera_kernels.hip", "check_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -22,22 +23,28 @@ FLAGS = [
 ]
 
 
+def _compile(src: str, objdir: str, verbose: bool) -> str:
+    obj = os.path.join(objdir, src + ".o")
+    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".hip"):
+        cmd[1:1] = ["-x", "hip"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    errs = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{errs}")
+    if verbose and errs.strip():
+        print(errs, file=sys.stderr)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
+    """Compiles every source (concurrently, one hipcc process each) and links libtt.so."""
+    from concurrent.futures import ThreadPoolExecutor
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src + ".o")
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".hip"):
-            cmd[1:1] = ["-x", "hip"]
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        errs = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
-        if res.returncode != 0:
-            raise RuntimeError(f"hipcc failed on {src}:\n{errs}")
-        if verbose and errs.strip():
-            print(errs, file=sys.stderr)
-        objs.append(obj)
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda src: _compile(src, objdir, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)

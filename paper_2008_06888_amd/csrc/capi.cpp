@@ -356,6 +356,47 @@ int64_t budget_bytes(const Plan& p) {
   return (int64_t)(fr / 8 * 7);
 }
 
+// Device state a call needs (bytes), from the plan alone.
+//   energy path, ping-pong: two buffers of batch x 2^width floats;
+//   backward (keep_all): every pass input at its own width, and the final state;
+//   chimera: two working states, plus the state after every row but the last
+//   with the backward.
+int64_t state_bytes(const Plan& p, int64_t batch, bool backward) {
+  const int64_t f = (int64_t)sizeof(float);
+  if (p.is_chimera) {
+    const int64_t per = (batch * f << p.width) + 255 & ~int64_t(255);
+    return (2 + (backward ? p.chim.rows - 1 : 0)) * per;
+  }
+  if (!backward) return 2 * batch * f << p.width;
+  int64_t need = 0;
+  const size_t np = p.passes.size();
+  for (size_t q = 0; q <= np; ++q) {
+    const int w = q < np ? p.passes[q].in_w : (np ? p.passes[np - 1].out_w : 0);
+    need += batch * f << w;
+    need = (need + 255) & ~int64_t(255);
+  }
+  return need;
+}
+
+// Count path: x plane and residue planes, one buffer when every pass runs in
+// place, else two.
+int64_t count_state_bytes(const Plan& p, int64_t batch, int nres) {
+  bool all_in_place = true;
+  for (const Pass& q : p.count_passes)
+    all_in_place = all_in_place && (q.init || (q.in_w == q.w_max && q.out_w == q.w_max));
+  const int64_t per = (batch << p.width) * (int64_t)(sizeof(float) + nres * sizeof(uint64_t));
+  return (all_in_place ? 1 : 2) * per;
+}
+
+// An explicit budget (opts.max_bytes) is checked on the host before any
+// device work; the default budget (free device memory) when buffers grow.
+int early_budget(const Plan& p, int64_t need) {
+  if (p.max_bytes > 0 && need > p.max_bytes)
+    return fail(TT_E_TOOBIG, "plan needs %lld bytes of device state (budget %lld)", (long long)need,
+                (long long)p.max_bytes);
+  return 0;
+}
+
 // Passes of the energy and counting sweeps at the plan's tile sizes.
 void partition_plan(Plan& p) {
   if (p.is_chimera) {
@@ -461,6 +502,161 @@ int stage_release(int slot, hipStream_t s) {
   return 0;
 }
 
+// ----------------------------------------------------------------------------
+// input check of a call: k_check_inputs runs first on the caller's stream and
+// its per-instance status comes back to pinned host memory by an async copy;
+// the call enqueues all its launches and only then waits for that copy, so
+// the host still runs ahead of the device by one call while every call
+// returns its own input errors.
+// ----------------------------------------------------------------------------
+struct CheckSlot {
+  uint32_t* dev = nullptr;
+  uint32_t* host = nullptr;
+  size_t cap = 0;   // instances
+  hipEvent_t ev = nullptr;
+  bool busy = false;
+};
+struct CheckRing {
+  std::vector<std::unique_ptr<CheckSlot>> slots;
+};
+std::mutex g_check_mu;
+std::map<int, CheckRing> g_checks;
+
+// A pending check: its slot (null when nothing was enqueued) and the
+// instances it covers.
+struct PendingCheck {
+  CheckSlot* slot = nullptr;
+  int64_t n = 0;
+};
+
+// The exact range of integer couplings in the float32 state.
+constexpr int64_t I32_EXACT = int64_t(1) << 24;
+
+int check_enqueue(const std::vector<CheckItem>& items, hipStream_t s, PendingCheck* pc) {
+  int64_t n = 0;
+  for (const CheckItem& c : items) n += c.batch;
+  if (n == 0) return 0;
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  CheckSlot* slot = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_check_mu);
+    CheckRing& ring = g_checks[device];
+    for (auto& c : ring.slots)
+      if (!c->busy) {
+        slot = c.get();
+        break;
+      }
+    if (!slot) {
+      ring.slots.emplace_back(new CheckSlot());
+      slot = ring.slots.back().get();
+    }
+    slot->busy = true;
+  }
+  // the slot is ours: its previous copy was waited for by its previous owner
+  if ((size_t)n > slot->cap) {
+    if (slot->host) (void)hipHostFree(slot->host);
+    if (slot->dev) (void)hipFree(slot->dev);
+    slot->host = nullptr;
+    slot->dev = nullptr;
+    slot->cap = 0;
+    const size_t c = std::max<size_t>((size_t)n, 1024);
+    hipError_t e = hipHostMalloc((void**)&slot->host, c * sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&slot->dev, c * sizeof(uint32_t));
+    if (e == hipSuccess && !slot->ev) e = hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      slot->busy = false;
+      return fail(TT_E_DEVICE, "input-check buffers: %s", hipGetErrorString(e));
+    }
+    slot->cap = c;
+  }
+  pc->slot = slot;
+  pc->n = n;
+  // launches of at most CHECK_ITEMS items, each with its own status range
+  int64_t base = 0;
+  for (size_t k0 = 0; k0 < items.size(); k0 += CHECK_ITEMS) {
+    CheckArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int64_t cnt = 0;
+    for (size_t k = k0; k < items.size() && k < k0 + CHECK_ITEMS; ++k) {
+      a.it[a.n] = items[k];
+      a.it[a.n].first = cnt;
+      cnt += items[k].batch;
+      ++a.n;
+    }
+    ProfScope ps(s, "check_inputs");
+    HIP_TRY(launch_check(a, cnt, slot->dev + base, s));
+    base += cnt;
+  }
+  HIP_TRY(hipMemcpyAsync(slot->host, slot->dev, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(slot->ev, s));
+  return 0;
+}
+
+// check_enqueue, releasing the slot again if enqueueing fails.
+int check_start(const std::vector<CheckItem>& items, hipStream_t s, PendingCheck* pc) {
+  const int r = check_enqueue(items, s, pc);
+  if (r && pc->slot) {
+    std::lock_guard<std::mutex> g(g_check_mu);
+    pc->slot->busy = false;
+    pc->slot = nullptr;
+  }
+  return r;
+}
+
+// Waits for a pending check and turns its statuses into the call's result.
+int check_finish(PendingCheck& pc, int32_t dtype) {
+  if (!pc.slot) return 0;
+  CheckSlot* slot = pc.slot;
+  pc.slot = nullptr;
+  const hipError_t e = hipEventSynchronize(slot->ev);
+  int rc = 0;
+  if (e != hipSuccess) {
+    rc = fail(TT_E_DEVICE, "input check: %s", hipGetErrorString(e));
+  } else {
+    for (int64_t i = 0; i < pc.n; ++i) {
+      const uint32_t st = slot->host[i];
+      if (st & CHK_NONFINITE) {
+        rc = fail(TT_E_INVAL, "instance %lld: a coupling or field is not finite", (long long)i);
+        break;
+      }
+      if (st & CHK_RANGE) {
+        rc = fail(TT_E_RANGE, "instance %lld: sum|J| + sum|h| reaches 2^24, beyond the exact range of %s",
+                  (long long)i, dtype == TT_I32 ? "int32 couplings in the float32 state" : "the state");
+        break;
+      }
+    }
+  }
+  std::lock_guard<std::mutex> g(g_check_mu);
+  slot->busy = false;
+  return rc;
+}
+
+// The result of a call that started a check: its own failure (rc, whose
+// message is kept) or else the check's.
+int check_end(int rc, PendingCheck& pc, int32_t dtype) {
+  if (!rc) return check_finish(pc, dtype);
+  const std::string msg = g_err;
+  (void)check_finish(pc, dtype);
+  g_err = msg;
+  return rc;
+}
+
+CheckItem check_item(const void* J, const void* h, int64_t m, int64_t n, int32_t batch, int32_t dtype) {
+  CheckItem c;
+  std::memset(&c, 0, sizeof(c));
+  c.J = m > 0 ? J : nullptr;
+  c.h = h;
+  c.m = m;
+  c.n = n;
+  c.jst = m;
+  c.hst = n;
+  c.batch = batch;
+  c.dtype = dtype == TT_F32 ? 0 : 1;
+  c.limit = I32_EXACT;
+  return c;
+}
+
 // One group = one plan over `batch` instances whose J (h, outputs) rows are
 // contiguous: the same-graph batch is one group, an uneven batch one group
 // per instance.
@@ -477,6 +673,12 @@ struct Group {
   // state buffers: bufs[q] is the input of pass q (q < np), bufs[np] the final state
   std::vector<float*> bufs;
   std::vector<int64_t> strides;   // per-instance stride of bufs[q] (entries)
+  // Offset of instance b's region in bufs[q] when the batch is cut into parts
+  // that run concurrently: b * part_st[q] entries. The ping-pong buffers hold
+  // each pass at its own width, so there a part's region must be placed by
+  // the widest pass (2^width per instance), or the regions of concurrent
+  // parts overlap across passes of different widths.
+  std::vector<int64_t> part_st;
   uint64_t* arg = nullptr;
 };
 
@@ -508,10 +710,12 @@ int prepare_group(Group& g, bool keep_all) {
   char* base = static_cast<char*>(buf.p);
   if (keep_all) {
     for (int q = 0; q <= np; ++q) g.bufs[q] = reinterpret_cast<float*>(base + off[q]);
+    g.part_st = g.strides;
   } else {
     float* pp[2] = {reinterpret_cast<float*>(base),
                     reinterpret_cast<float*>(base + need / 2)};
     for (int q = 0; q <= np; ++q) g.bufs[q] = pp[q & 1];
+    g.part_st.assign(np + 1, (int64_t)1 << p.width);
   }
   if (int r = g.dc->arg.ensure((size_t)g.batch * sizeof(uint64_t))) return r;
   g.arg = static_cast<uint64_t*>(g.dc->arg.p);
@@ -874,7 +1078,7 @@ Group sub_group(const Group& g, int b0, int nb) {
   h.sigma = g.sigma ? g.sigma + (size_t)b0 * (size_t)n : nullptr;
   h.dJ = g.dJ ? g.dJ + (size_t)b0 * (size_t)m : nullptr;
   h.dh = g.dh ? g.dh + (size_t)b0 * (size_t)n : nullptr;
-  for (size_t q = 0; q < g.bufs.size(); ++q) h.bufs[q] = g.bufs[q] + (size_t)b0 * (size_t)g.strides[q];
+  for (size_t q = 0; q < g.bufs.size(); ++q) h.bufs[q] = g.bufs[q] + (size_t)b0 * (size_t)g.part_st[q];
   h.arg = g.arg + b0;
   return h;
 }
@@ -908,7 +1112,7 @@ int run_split(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   std::lock_guard<std::mutex> lock(g_split_mu);
   AuxStreams* aux = nullptr;
   if (int r = aux_streams(&aux)) return r;
-  const int parts = std::min(SPLIT_PARTS, (int)g.batch);
+  const int parts = std::min(g.p->parts, (int)g.batch);
   std::vector<std::vector<Group>> gp(parts);
   for (int k = 0; k < parts; ++k) {
     const int b0 = (int)((int64_t)g.batch * k / parts), b1 = (int)((int64_t)g.batch * (k + 1) / parts);
@@ -943,7 +1147,7 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
   for (Group& g : groups)
     if (int r = prepare_group(g, backward)) return r;
   const bool large = large_call(groups);
-  if (large && groups[0].batch >= 2) return run_split(groups[0], dtype, backward, s);
+  if (large && groups[0].batch >= 2 && groups[0].p->parts > 1) return run_split(groups[0], dtype, backward, s);
   CallTables ct;
   DevCache* dc0 = groups[0].dc;
   const bool fuse = can_fuse_reduce(groups);
@@ -1142,6 +1346,63 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   return stage_release(slot, s);
 }
 
+// The integer 0 <= g < P0 P1 P2 with the given residues modulo the three
+// count primes (Garner's mixed-radix form g = a0 + P0 (a1 + P1 a2)), as
+// eight 32-bit limbs, little endian. Residues must be reduced.
+void crt_limbs(const uint64_t res[3], uint32_t limbs[8]) {
+  typedef unsigned __int128 u128;
+  const uint64_t P[3] = {(1ull << 61) - 1, (1ull << 61) - 31, (1ull << 61) - 45};
+  auto mulmod = [](uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); };
+  auto powmod = [&](uint64_t a, uint64_t e, uint64_t m) {
+    uint64_t r = 1 % m;
+    a %= m;
+    while (e) {
+      if (e & 1) r = mulmod(r, a, m);
+      a = mulmod(a, a, m);
+      e >>= 1;
+    }
+    return r;
+  };
+  const uint64_t a0 = res[0];
+  const uint64_t inv01 = powmod(P[0] % P[1], P[1] - 2, P[1]);
+  const uint64_t a1 = mulmod((res[1] % P[1] + P[1] - a0 % P[1]) % P[1], inv01, P[1]);
+  const uint64_t p01 = mulmod(P[0] % P[2], P[1] % P[2], P[2]);
+  const uint64_t partial = (a0 % P[2] + mulmod(a1 % P[2], P[0] % P[2], P[2])) % P[2];
+  const uint64_t inv012 = powmod(p01, P[2] - 2, P[2]);
+  const uint64_t a2 = mulmod((res[2] % P[2] + P[2] - partial) % P[2], inv012, P[2]);
+  std::vector<uint32_t> x(8, 0);
+  auto add_small = [&](uint64_t a) {
+    uint64_t carry = a;
+    for (size_t k = 0; k < x.size() && carry; ++k) {
+      const uint64_t s = (uint64_t)x[k] + (carry & 0xffffffffull);
+      x[k] = (uint32_t)s;
+      carry = (carry >> 32) + (s >> 32);
+    }
+  };
+  auto mul_small = [&](uint64_t a) {
+    std::vector<uint32_t> out(x.size(), 0);
+    const uint64_t hl[2] = {a & 0xffffffffull, a >> 32};
+    for (int part = 0; part < 2; ++part) {
+      uint64_t carry = 0;
+      for (size_t k = 0; k + part < x.size(); ++k) {
+        const uint64_t s = (uint64_t)x[k] * hl[part] + out[k + part] + carry;
+        out[k + part] = (uint32_t)s;
+        carry = s >> 32;
+      }
+    }
+    x.swap(out);
+  };
+  add_small(a2);
+  mul_small(P[1]);
+  add_small(a1);
+  mul_small(P[0]);
+  add_small(a0);
+  std::copy(x.begin(), x.end(), limbs);
+}
+
+// Spins up to which g <= 2^n stays below the product of the count primes.
+constexpr int COUNT_EXACT_SPINS = 182;
+
 }  // namespace
 
 // ============================================================================
@@ -1179,6 +1440,8 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
     if (p->tile_bits < 7 || p->tile_bits > 14) return fail(TT_E_INVAL, "tile_bits must be in [7, 14]");
     if (p->count_tile_bits < 7 || p->count_tile_bits > 12) return fail(TT_E_INVAL, "count_tile_bits must be in [7, 12]");
     p->max_bytes = o.max_bytes;
+    if (o.parts < 0 || o.parts > SPLIT_PARTS) return fail(TT_E_INVAL, "parts must be 1 or 2 (0: default)");
+    p->parts = o.parts > 0 ? o.parts : SPLIT_PARTS;
     std::string err;
     if (o.kind == TT_ORDER_GIVEN) {
       if (!o.order) return fail(TT_E_INVAL, "TT_ORDER_GIVEN needs opts.order");
@@ -1216,7 +1479,8 @@ int tt_plan_info(const tt_plan* plan, tt_plan_stats* out) {
   out->n_passes = (int32_t)p.passes.size();
   out->n_count_passes = (int32_t)p.count_passes.size();
   out->terms = p.terms;
-  out->reduce_terms = p.reduce_terms;
+  out->elementwise = p.elementwise;
+  out->reduce_ops = p.reduce_ops;
   double upd = 0;
   for (const Pass& ps : p.passes) upd += 2.0 * std::ldexp(1.0, ps.w_max);
   out->entry_updates = upd;
@@ -1293,14 +1557,19 @@ int tt_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
   try {
     if (int r = check_common(plan, batch, dtype, J, h)) return r;
     if (!energy) return fail(TT_E_INVAL, "null energy");
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    if (int r = early_budget(p, state_bytes(p, batch, false))) return r;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    PendingCheck pc;
+    if (int r = check_start({check_item(J, h, p.m, p.n, batch, dtype)}, s, &pc)) return r;
     std::vector<Group> g(1);
-    g[0].p = reinterpret_cast<Plan*>(plan);
+    g[0].p = &p;
     g[0].batch = batch;
     g[0].J = J;
     g[0].h = h;
     g[0].energy = energy;
-    if (g[0].p->is_chimera) return run_chimera(g[0], dtype, false, static_cast<hipStream_t>(stream));
-    return run_groups(g, dtype, false, static_cast<hipStream_t>(stream));
+    const int rc = p.is_chimera ? run_chimera(g[0], dtype, false, s) : run_groups(g, dtype, false, s);
+    return check_end(rc, pc, dtype);
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
   }
@@ -1314,6 +1583,10 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
     Plan& p = *reinterpret_cast<Plan*>(plan);
     if (p.n_regs != 1) return fail(TT_E_INVAL, "backward over multi-register plans is not supported");
     if (p.n > 8192) return fail(TT_E_INVAL, "too many spins for the backward walk");
+    if (int r = early_budget(p, state_bytes(p, batch, true))) return r;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    PendingCheck pc;
+    if (int r = check_start({check_item(J, h, p.m, p.n, batch, dtype)}, s, &pc)) return r;
     std::vector<Group> g(1);
     g[0].p = &p;
     g[0].batch = batch;
@@ -1323,8 +1596,8 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
     g[0].sigma = sigma;
     g[0].dJ = dJ;
     g[0].dh = dh;
-    if (p.is_chimera) return run_chimera(g[0], dtype, true, static_cast<hipStream_t>(stream));
-    return run_groups(g, dtype, true, static_cast<hipStream_t>(stream));
+    const int rc = p.is_chimera ? run_chimera(g[0], dtype, true, s) : run_groups(g, dtype, true, s);
+    return check_end(rc, pc, dtype);
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
   }
@@ -1339,12 +1612,13 @@ int tt_count_moduli(uint64_t moduli_out[3]) {
 }
 
 int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, int64_t* energy, uint64_t* residues,
-             void* stream) {
+             uint8_t* exact_flag, void* stream) {
   try {
     if (int r = check_common(plan, batch, TT_I32, J, h)) return r;
     if (!energy || !residues) return fail(TT_E_INVAL, "null output");
     Plan& p = *reinterpret_cast<Plan*>(plan);
     if (p.n_regs != 1) return fail(TT_E_INVAL, "counting over multi-register plans is not supported");
+    if (int r = early_budget(p, count_state_bytes(p, batch, p.n > COUNT_EXACT_SPINS ? 4 : 3))) return r;
     hipStream_t s = static_cast<hipStream_t>(stream);
     // exactness guard: every state value lies in [-S, S], S = sum|J| + sum|h|,
     // which float32 holds exactly below 2^24
@@ -1361,11 +1635,14 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
         if (S >= (1ll << 24)) return fail(TT_E_RANGE, "instance %d: sum|J|+sum|h| = %lld needs more than 24 bits", b, (long long)S);
       }
     }
+    // g <= 2^n < 2^182 < the product of the three primes for n <= 182: the
+    // CRT value is then exact; beyond, a fourth plane modulo 2^64 checks it
+    const int nres = p.n > COUNT_EXACT_SPINS ? 4 : 3;
     DevCache* dc = nullptr;
     if (int r = ensure_device(p, dc)) return r;
     const int64_t sst = (int64_t)1 << p.width;
     const size_t xper = (size_t)batch * sst * sizeof(float);
-    const size_t nper = (size_t)batch * sst * 3 * sizeof(uint64_t);
+    const size_t nper = (size_t)batch * sst * nres * sizeof(uint64_t);
     bool all_in_place = true;
     for (const DevPass& P : dc->cen.passes) all_in_place = all_in_place && in_place_ok(P);
     const int nb2 = all_in_place ? 1 : 2;
@@ -1404,6 +1681,7 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
         ci.init = r == 0 ? 1 : 0;
         ci.log2_blocks = lblk;
         ci.dtype = TT_I32;
+        ci.nres = nres;
         chain_items.push_back(ci);
       }
       char* host = nullptr;
@@ -1425,7 +1703,7 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
         ProfScope ps(s, "count_pass");
         const int dst = in_place_ok(P) ? cur : (cur ^ 1);
         HIP_TRY(launch_count_pass(P, static_cast<const DevOp*>(dc->d_cops.p), J, h, p.m, p.n, xb[cur], nb[cur],
-                                  xb[dst], nb[dst], sst, batch, s));
+                                  xb[dst], nb[dst], sst, batch, nres, s));
         cur = dst;
       }
       if (p.is_chimera && dc->count_chain_after[qi] >= 0)
@@ -1435,23 +1713,40 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
       if (int r = stage_release(chain_slot, s)) return r;
     const int lc = count_reduce_log2_chunks(p.final_w);
     const size_t nparts = (size_t)batch << lc;
-    const size_t bytes = nparts * sizeof(float) + nparts * 3 * sizeof(uint64_t) + (size_t)batch * 4 * sizeof(uint64_t) + 64;
+    const size_t bytes = nparts * sizeof(float) + nparts * 4 * sizeof(uint64_t) + (size_t)batch * 5 * sizeof(uint64_t) + 64;
     if (int r = dc->cpart.ensure(bytes)) return r;
     char* c = static_cast<char*>(dc->cpart.p);
     uint64_t* pn = reinterpret_cast<uint64_t*>(c);
-    uint64_t* res = pn + nparts * 3;
-    int64_t* en = reinterpret_cast<int64_t*>(res + (size_t)batch * 3);
+    uint64_t* res = pn + nparts * 4;
+    int64_t* en = reinterpret_cast<int64_t*>(res + (size_t)batch * 4);
     float* pv = reinterpret_cast<float*>(en + batch);
     {
       ProfScope ps(s, "count_reduce");
       uint64_t free_mask = 0;
       for (int c = 0; c < p.final_w; ++c)
         if (p.final_slot_spin[c] < 0) free_mask |= 1ull << c;
-      HIP_TRY(launch_count_reduce(xb[cur], nb[cur], sst, p.final_w, free_mask, batch, pv, pn, en, res, s));
+      HIP_TRY(launch_count_reduce(xb[cur], nb[cur], sst, p.final_w, free_mask, batch, nres, pv, pn, en, res, s));
     }
+    std::vector<uint64_t> r4((size_t)batch * 4);
     HIP_TRY(hipMemcpyAsync(energy, en, (size_t)batch * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(residues, res, (size_t)batch * 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(r4.data(), res, r4.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    int inexact = -1;
+    for (int b = 0; b < batch; ++b) {
+      for (int r = 0; r < 3; ++r) residues[(size_t)b * 3 + r] = r4[(size_t)b * 4 + r];
+      bool exact = true;
+      if (nres == 4) {
+        uint32_t limbs[8];
+        crt_limbs(&r4[(size_t)b * 4], limbs);
+        const uint64_t low = ((uint64_t)limbs[1] << 32) | limbs[0];   // CRT value modulo 2^64
+        exact = low == r4[(size_t)b * 4 + 3];
+      }
+      if (exact_flag) exact_flag[b] = exact ? 1 : 0;
+      if (!exact && inexact < 0) inexact = b;
+    }
+    if (!exact_flag && inexact >= 0)
+      return fail(TT_E_COUNT_OVERFLOW, "instance %d: the degeneracy reaches the product of the moduli (~2^183)",
+                  inexact);
     return TT_OK;
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
@@ -1460,60 +1755,13 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
 
 int tt_count_to_decimal(const uint64_t residues[3], char* buf, size_t len) {
   if (!residues || !buf || len == 0) return fail(TT_E_INVAL, "null argument");
-  typedef unsigned __int128 u128;
   uint64_t P[3];
   tt_count_moduli(P);
   for (int r = 0; r < 3; ++r)
     if (residues[r] >= P[r]) return fail(TT_E_INVAL, "residue %d out of range", r);
-  auto mulmod = [](uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); };
-  auto powmod = [&](uint64_t a, uint64_t e, uint64_t m) {
-    uint64_t r = 1 % m;
-    a %= m;
-    while (e) {
-      if (e & 1) r = mulmod(r, a, m);
-      a = mulmod(a, a, m);
-      e >>= 1;
-    }
-    return r;
-  };
-  // Garner: g = a0 + a1 P0 + a2 P0 P1 with 0 <= a_r < P_r
-  const uint64_t a0 = residues[0];
-  const uint64_t inv01 = powmod(P[0] % P[1], P[1] - 2, P[1]);
-  const uint64_t a1 = mulmod((residues[1] + P[1] - a0 % P[1]) % P[1], inv01, P[1]);
-  const uint64_t p01 = mulmod(P[0] % P[2], P[1] % P[2], P[2]);
-  const uint64_t partial = (a0 % P[2] + mulmod(a1 % P[2], P[0] % P[2], P[2])) % P[2];
-  const uint64_t inv012 = powmod(p01, P[2] - 2, P[2]);
-  const uint64_t a2 = mulmod((residues[2] + P[2] - partial) % P[2], inv012, P[2]);
-  // big integer in 32-bit limbs, little endian
-  std::vector<uint32_t> x(8, 0);
-  auto add_small = [&](std::vector<uint32_t>& v, uint64_t a) {
-    uint64_t carry = a;
-    for (size_t k = 0; k < v.size() && carry; ++k) {
-      const uint64_t s = (uint64_t)v[k] + (carry & 0xffffffffull);
-      v[k] = (uint32_t)s;
-      carry = (carry >> 32) + (s >> 32);
-    }
-  };
-  auto mul_small = [&](std::vector<uint32_t>& v, uint64_t a) {
-    // v *= a with a < 2^64 in two 32-bit halves
-    std::vector<uint32_t> out(v.size(), 0);
-    const uint64_t h[2] = {a & 0xffffffffull, a >> 32};
-    for (int part = 0; part < 2; ++part) {
-      uint64_t carry = 0;
-      for (size_t k = 0; k + part < v.size(); ++k) {
-        const uint64_t s = (uint64_t)v[k] * h[part] + out[k + part] + carry;
-        out[k + part] = (uint32_t)s;
-        carry = s >> 32;
-      }
-    }
-    v.swap(out);
-  };
-  // g = a0 + P0 (a1 + P1 a2)
-  add_small(x, a2);
-  mul_small(x, P[1]);
-  add_small(x, a1);
-  mul_small(x, P[0]);
-  add_small(x, a0);
+  uint32_t limbs[8];
+  crt_limbs(residues, limbs);
+  std::vector<uint32_t> x(limbs, limbs + 8);
   std::string digits;
   bool zero = false;
   while (!zero) {
@@ -1541,6 +1789,7 @@ int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype, con
     if (dtype != TT_F32 && dtype != TT_I32) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
     const size_t esz = dtype == TT_F32 ? sizeof(float) : sizeof(int32_t);
     std::vector<Group> groups(n_inst);
+    std::vector<CheckItem> checks;
     for (int i = 0; i < n_inst; ++i) {
       if (!plans[i]) return fail(TT_E_INVAL, "null plan %d", i);
       Plan& p = *reinterpret_cast<Plan*>(plans[i]);
@@ -1549,17 +1798,25 @@ int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype, con
       if (p.is_chimera) return fail(TT_E_INVAL, "chimera plans are solved with tt_contract / tt_backward");
       for (int k = 0; k < i; ++k)
         if (plans[k] == plans[i]) return fail(TT_E_INVAL, "each instance needs its own plan object");
+      if (j_off[i] < 0) return fail(TT_E_INVAL, "negative j_off[%d]", i);
+      if (sigma && s_off[i] < 0) return fail(TT_E_INVAL, "negative s_off[%d]", i);
+      if (int r = early_budget(p, state_bytes(p, 1, sigma != nullptr))) return r;
       Group& g = groups[i];
       g.p = &p;
       g.batch = 1;
       g.J = static_cast<const char*>(J) + (size_t)j_off[i] * esz;
+      checks.push_back(check_item(g.J, nullptr, p.m, p.n, 1, dtype));
       g.energy = energy + i;
       if (sigma) {
         g.sigma = sigma + s_off[i];
         g.dJ = dJ ? dJ + j_off[i] : nullptr;
       }
     }
-    return run_groups(groups, dtype, sigma != nullptr, static_cast<hipStream_t>(stream));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    PendingCheck pc;
+    if (int r = check_start(checks, s, &pc)) return r;
+    const int rc = run_groups(groups, dtype, sigma != nullptr, s);
+    return check_end(rc, pc, dtype);
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
   }
@@ -1599,7 +1856,24 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
     char* const ob = static_cast<char*>(out.p);
     std::vector<int64_t> en(nb);
     std::vector<uint64_t> res(nb * 3);
-    const bool graphs = g_graphs_on;
+    std::vector<uint8_t> flags(nb);
+    const int keep = count ? p.count_tile_bits : p.tile_bits;
+    int best_t = keep;
+    // Every exit path (a failed HIP call included) restores graph capture and
+    // leaves the plan partitioned at the kept tile size: the caller's size
+    // until a candidate has been timed, then the fastest one.
+    struct Restore {
+      Plan& p;
+      bool count, graphs;
+      const int& t;
+      ~Restore() {
+        g_graphs_on = graphs;
+        (count ? p.count_tile_bits : p.tile_bits) = t;
+        delete static_cast<DevCache*>(p.dev);
+        p.dev = nullptr;
+        partition_plan(p);
+      }
+    } restore{p, count, g_graphs_on, best_t};
     g_graphs_on = false;   // timing of eager launches; no capture of discarded plans
     // one call, left running on the stream (energy / backward modes)
     auto run_call = [&]() -> int {
@@ -1611,14 +1885,14 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
     };
     auto run_once = [&]() -> int {
       if (count) return tt_count(plan, batch, static_cast<const int32_t*>(J), static_cast<const int32_t*>(h),
-                                 en.data(), res.data(), stream);
+                                 en.data(), res.data(), flags.data(), stream);
       if (int r = run_call()) return r;
       HIP_TRY(hipStreamSynchronize(s));
       return 0;
     };
     // a large same-graph batch runs in parts on concurrent streams (see
     // run_split), so summed kernel times would count overlapping work twice
-    const bool split = !count && !p.is_chimera && batch >= 2 && large_batch(p, batch);
+    const bool split = !count && !p.is_chimera && batch >= 2 && p.parts > 1 && large_batch(p, batch);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (split) {
       HIP_TRY(hipEventCreate(&ev0));
@@ -1631,8 +1905,6 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
         if (b) (void)hipEventDestroy(b);
       }
     } ev_free{ev0, ev1};
-    const int keep = count ? p.count_tile_bits : p.tile_bits;
-    int best_t = keep;
     double best = 1e300;
     int rc = 0;
     for (int t = lo; t <= top && rc == 0; ++t) {
@@ -1684,12 +1956,10 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
         best_t = t;
       }
     }
-    g_graphs_on = graphs;
-    (count ? p.count_tile_bits : p.tile_bits) = best_t;
-    delete static_cast<DevCache*>(p.dev);
-    p.dev = nullptr;
-    partition_plan(p);
-    if (rc) return rc;
+    if (rc) {
+      best_t = keep;   // a failed trial: the caller's tile size stays
+      return rc;
+    }
     if (chosen_bits) *chosen_bits = best_t;
     if (best_ms) *best_ms = best;
     return TT_OK;

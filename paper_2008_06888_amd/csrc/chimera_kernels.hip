@@ -198,7 +198,8 @@ __global__ __launch_bounds__(CH_T) void k_chain(const ChainItem* __restrict__ it
   const uint32_t E = 1u << lb;
   const int64_t off = inst * I.sst + (int64_t)(blk << 16);
   const gptr<float> x = as_global(I.x) + off;
-  const gptr<uint64_t> nres = COUNT ? as_global(I.n) + inst * 3 * I.sst + (int64_t)(blk << 16) : nullptr;
+  const int np = I.nres;   // residue planes: three primes, and modulo 2^64 when there are four
+  const gptr<uint64_t> nres = COUNT ? as_global(I.n) + inst * np * I.sst + (int64_t)(blk << 16) : nullptr;
   const bool init = I.init != 0;
   const int64_t sst = I.sst;
   auto update = [&](uint32_t e, float g, uint64_t gc) {
@@ -208,6 +209,10 @@ __global__ __launch_bounds__(CH_T) void k_chain(const ChainItem* __restrict__ it
       for (int r = 0; r < 3; ++r) {
         const gptr<uint64_t> pr = nres + (int64_t)r * sst + e;
         __builtin_nontemporal_store(init ? gc : mulmod_small(*pr, gc, r), pr);
+      }
+      if (np > 3) {
+        const gptr<uint64_t> pr = nres + 3 * sst + e;
+        __builtin_nontemporal_store(init ? gc : *pr * gc, pr);   // wraps modulo 2^64
       }
     }
   };

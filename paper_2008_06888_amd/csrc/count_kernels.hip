@@ -4,8 +4,11 @@
 // (count 1) keeps n; the tropical sum keeps the n of the larger x and adds
 // the n's when the x's are equal. n is carried as three residues modulo the
 // primes p_r = 2^61 - 1, 2^61 - 31, 2^61 - 45 (exact recombination by CRT on
-// the host). x is an exact integer held in float32 (|x| < 2^24 is checked by
-// the caller), so every equality test of Eq. (4) is exact.
+// the host), and, for graphs of more than 182 spins (where g may reach the
+// product of the primes), a fourth residue modulo 2^64 (plain wrap-around
+// arithmetic) that the host compares with the CRT value. x is an exact
+// integer held in float32 (|x| < 2^24 is checked by the caller), so every
+// equality test of Eq. (4) is exact.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -17,13 +20,14 @@ namespace tt {
 
 constexpr int CNT = 256;        // reductions
 constexpr int CNT_PASS = 1024;  // count passes: 16 waves hide the LDS latency of the per-op sweeps
-constexpr int NRES = 3;
+constexpr int NRES = 4;   // residue planes at most (the fourth: modulo 2^64)
 
-__device__ __constant__ uint64_t c_mod[NRES] = {(1ull << 61) - 1, (1ull << 61) - 31, (1ull << 61) - 45};
+// modulus 0 stands for 2^64
+__device__ __constant__ uint64_t c_mod[NRES] = {(1ull << 61) - 1, (1ull << 61) - 31, (1ull << 61) - 45, 0};
 
 __device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t p) {
-  const uint64_t s = a + b;   // a, b < p < 2^61: no overflow
-  return s >= p ? s - p : s;
+  const uint64_t s = a + b;   // a, b < p < 2^61: no overflow; p = 0: modulo 2^64
+  return (p != 0 && s >= p) ? s - p : s;
 }
 
 __device__ __forceinline__ int cbit(uint8_t enc, uint32_t i, uint64_t base) {
@@ -48,11 +52,12 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
                                                     const int32_t* __restrict__ J, const int32_t* __restrict__ h,
                                                     int64_t jst, int64_t hst, const float* __restrict__ xin,
                                                     const uint64_t* __restrict__ nin, float* __restrict__ xout,
-                                                    uint64_t* __restrict__ nout, int64_t sst, int log2_tiles) {
+                                                    uint64_t* __restrict__ nout, int64_t sst, int log2_tiles,
+                                                    int nres) {
   extern __shared__ uint64_t csm[];
   const uint32_t size = 1u << P.t;
-  uint64_t* tn = csm;                                        // [NRES][size]
-  float* tx = reinterpret_cast<float*>(csm + NRES * size);   // [size]
+  uint64_t* tn = csm;                                        // [nres][size]
+  float* tx = reinterpret_cast<float*>(csm + nres * size);   // [size]
   __shared__ uint64_t dep_lo[256], dep_hi[256];
   const int64_t inst = (int64_t)blockIdx.x >> log2_tiles;
   const uint64_t tile_id = (uint64_t)blockIdx.x & ((1ull << log2_tiles) - 1ull);
@@ -62,15 +67,15 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
   __syncthreads();
   const uint64_t in_mask = (1ull << P.in_w) - 1ull;
   const float* xs = xin + inst * sst;
-  const uint64_t* ns = nin + inst * sst * NRES;
+  const uint64_t* ns = nin + inst * sst * nres;
   for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) {
     const uint64_t idx = (base | dep_lo[i & 255u] | dep_hi[i >> 8]) & in_mask;
     if (P.init) {
       tx[i] = 0.f;
-      for (int r = 0; r < NRES; ++r) tn[r * size + i] = 1ull;
+      for (int r = 0; r < nres; ++r) tn[r * size + i] = 1ull;
     } else {
       tx[i] = xs[idx];
-      for (int r = 0; r < NRES; ++r) tn[r * size + i] = ns[r * sst + idx];
+      for (int r = 0; r < nres; ++r) tn[r * size + i] = ns[r * sst + idx];
     }
   }
   __syncthreads();
@@ -90,7 +95,7 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
         const float c00 = a0 + Jv, c10 = a1 - Jv, c01 = a0 - Jv, c11 = a1 + Jv;
         tx[i0] = fmaxf(c00, c10);
         tx[i1] = fmaxf(c01, c11);
-        for (int r = 0; r < NRES; ++r) {
+        for (int r = 0; r < nres; ++r) {
           const uint64_t n0 = tn[r * size + i0], n1 = tn[r * size + i1];
           const uint64_t both = addmod(n0, n1, c_mod[r]);
           tn[r * size + i0] = c00 > c10 ? n0 : (c10 > c00 ? n1 : both);
@@ -110,13 +115,13 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
     }
   }
   float* xd = xout + inst * sst;
-  uint64_t* nd = nout + inst * sst * NRES;
+  uint64_t* nd = nout + inst * sst * nres;
   for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) {
     const uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
     if ((idx >> P.out_w) != 0) continue;
     // non-temporal: the next pass reads the state from memory
     __builtin_nontemporal_store(tx[i], &xd[idx]);
-    for (int r = 0; r < NRES; ++r) __builtin_nontemporal_store(tn[r * size + i], &nd[r * sst + idx]);
+    for (int r = 0; r < nres; ++r) __builtin_nontemporal_store(tn[r * size + i], &nd[r * sst + idx]);
   }
 }
 
@@ -147,16 +152,20 @@ __device__ uint64_t cblock_summod(uint64_t v, uint64_t p) {
 // (their two halves are equal), so only entries with those bits zero count.
 __global__ __launch_bounds__(CNT) void k_count_reduce1(const float* __restrict__ x, const uint64_t* __restrict__ nr,
                                                        int64_t sst, int w, int log2_chunks, uint64_t free_mask,
-                                                       float* __restrict__ pv, uint64_t* __restrict__ pn) {
+                                                       int nres, float* __restrict__ pv, uint64_t* __restrict__ pn) {
   const int64_t inst = (int64_t)blockIdx.x >> log2_chunks;
   const uint64_t chunk = (uint64_t)blockIdx.x & ((1ull << log2_chunks) - 1ull);
   const uint64_t len = 1ull << (w - log2_chunks);
   const float* xs = x + inst * sst;
-  const uint64_t* ns = nr + inst * sst * NRES;
+  const uint64_t* ns = nr + inst * sst * nres;
   float mx = -INFINITY;
   for (uint64_t k = threadIdx.x; k < len; k += CNT) mx = fmaxf(mx, xs[chunk * len + k]);
   mx = cblock_max(mx);
   for (int r = 0; r < NRES; ++r) {
+    if (r >= nres) {
+      if (threadIdx.x == 0) pn[blockIdx.x * NRES + r] = 0;
+      continue;
+    }
     uint64_t acc = 0;
     for (uint64_t k = threadIdx.x; k < len; k += CNT) {
       const uint64_t idx = chunk * len + k;
@@ -168,6 +177,7 @@ __global__ __launch_bounds__(CNT) void k_count_reduce1(const float* __restrict__
   if (threadIdx.x == 0) pv[blockIdx.x] = mx;
 }
 
+// partials and residues: NRES words per chunk / instance (unused planes 0)
 __global__ __launch_bounds__(CNT) void k_count_reduce2(const float* __restrict__ pv, const uint64_t* __restrict__ pn,
                                                        int log2_chunks, int64_t* __restrict__ energy,
                                                        uint64_t* __restrict__ residues) {
@@ -195,8 +205,9 @@ int count_reduce_log2_chunks(int w) {
 
 hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h, int64_t jst,
                              int64_t hst, const float* xin, const uint64_t* nin, float* xout, uint64_t* nout,
-                             int64_t sst, int batch, hipStream_t stream) {
-  const size_t lds = ((size_t)1 << P.t) * (sizeof(float) + NRES * sizeof(uint64_t));
+                             int64_t sst, int batch, int nres, hipStream_t stream) {
+  if (nres < 3 || nres > NRES) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)1 << P.t) * (sizeof(float) + nres * sizeof(uint64_t));
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_count_pass),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -205,15 +216,17 @@ hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* 
   const uint64_t grid = (uint64_t)batch << P.n_free;
   if (grid >= (1ull << 31)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_count_pass, dim3((uint32_t)grid), dim3(CNT_PASS), lds, stream, P, ops, J, h, jst, hst, xin, nin,
-                     xout, nout, sst, P.n_free);
+                     xout, nout, sst, P.n_free, nres);
   return hipGetLastError();
 }
 
-hipError_t launch_count_reduce(const float* x, const uint64_t* nres, int64_t sst, int w, uint64_t free_mask, int batch,
-                               float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues, hipStream_t stream) {
+hipError_t launch_count_reduce(const float* x, const uint64_t* nplanes, int64_t sst, int w, uint64_t free_mask,
+                               int batch, int nres, float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues,
+                               hipStream_t stream) {
+  if (nres < 3 || nres > NRES) return hipErrorInvalidValue;
   const int lc = count_reduce_log2_chunks(w);
-  hipLaunchKernelGGL(k_count_reduce1, dim3((uint32_t)((uint64_t)batch << lc)), dim3(CNT), 0, stream, x, nres, sst, w,
-                     lc, free_mask, pv, pn);
+  hipLaunchKernelGGL(k_count_reduce1, dim3((uint32_t)((uint64_t)batch << lc)), dim3(CNT), 0, stream, x, nplanes, sst,
+                     w, lc, free_mask, nres, pv, pn);
   hipLaunchKernelGGL(k_count_reduce2, dim3((uint32_t)batch), dim3(CNT), 0, stream, pv, pn, lc, energy, residues);
   return hipGetLastError();
 }

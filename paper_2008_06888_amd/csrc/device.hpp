@@ -173,6 +173,7 @@ struct ChainItem {
   uint64_t* n;           // residue planes (counting), else NULL
   int64_t sst;           // entries per instance (2^w)
   int32_t w, cols, batch, init, log2_blocks, dtype;
+  int32_t nres, pad;     // counting: residue planes (3, or 4 with the modulo-2^64 guard)
 };
 
 // Chimera backward finish: spins of every row from the selected addresses,
@@ -189,6 +190,25 @@ struct ChimFinishItem {
   float* dh;
   int32_t n, n_rows, cols, batch, dtype, pad;
 };
+
+// Input check of a call (k_check_inputs): one item per group of instances
+// that share row strides; instance b of the item gets status[first + b].
+struct CheckItem {
+  const void* J;         // first instance's couplings
+  const void* h;         // first instance's fields, or NULL
+  int64_t m, n;          // couplings / fields per instance
+  int64_t jst, hst;      // row strides between instances (elements)
+  int64_t first;         // status index of the item's first instance
+  int64_t limit;         // integer inputs: sum |J| + sum |h| must stay below this
+  int32_t batch, dtype;  // dtype 0 = float32, else int32
+};
+constexpr int CHECK_ITEMS = 32;   // items per launch (passed by value)
+struct CheckArgs {
+  CheckItem it[CHECK_ITEMS];
+  int32_t n, pad;
+};
+constexpr uint32_t CHK_NONFINITE = 1u;   // a coupling or field is inf or NaN
+constexpr uint32_t CHK_RANGE = 2u;       // sum |J| + sum |h| >= limit
 
 // Backward walk of one instance.
 struct BwdItem {

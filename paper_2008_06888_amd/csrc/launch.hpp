@@ -25,12 +25,17 @@ hipError_t launch_tgemm(int batch, int64_t M, int64_t N, int64_t K, const float*
 hipError_t launch_chain(const ChainItem* item, int64_t n_blocks, int dtype, bool count, hipStream_t stream);
 hipError_t launch_chim_finish(const ChimFinishItem* item, int batch, int dtype, hipStream_t stream);
 
-// counting path: state entries (x, n mod p_r), r = 0, 1, 2
+// counting path: state entries (x, n mod p_r), r < nres (r = 3: modulo 2^64);
+// residues come out as 4 words per instance (unused planes 0)
 hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h,
                              int64_t jst, int64_t hst, const float* xin, const uint64_t* nin, float* xout,
-                             uint64_t* nout, int64_t sst, int batch, hipStream_t stream);
+                             uint64_t* nout, int64_t sst, int batch, int nres, hipStream_t stream);
 int count_reduce_log2_chunks(int w);
-hipError_t launch_count_reduce(const float* x, const uint64_t* nres, int64_t sst, int w, uint64_t free_mask, int batch,
-                               float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues, hipStream_t stream);
+hipError_t launch_count_reduce(const float* x, const uint64_t* nplanes, int64_t sst, int w, uint64_t free_mask,
+                               int batch, int nres, float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues,
+                               hipStream_t stream);
+
+// input check: status[i] for the n_inst instances of the items (CHK_* flags)
+hipError_t launch_check(const CheckArgs& a, int64_t n_inst, uint32_t* status, hipStream_t stream);
 
 }  // namespace tt

@@ -120,9 +120,11 @@ struct Plan {
   int32_t max_dec = 16;
   std::vector<Pass> passes;          // energy / backward path
   std::vector<Pass> count_passes;    // count path
-  double terms = 0;                  // algorithmic max-plus terms per instance
-  double reduce_terms = 0;           // of which the final reduction
+  double terms = 0;                  // contraction terms per instance (one add + one max)
+  double elementwise = 0;            // elementwise ops per instance (absorbs, cuts, final maximum)
+  double reduce_ops = 0;             // of which the final maximum
   int64_t max_bytes = 0;
+  int32_t parts = 2;                 // concurrent parts of a large same-graph batch (1 or 2)
   std::vector<int32_t> breaks;       // op indices where a pass must begin
   bool is_chimera = false;
   ChimeraInfo chim;

@@ -187,20 +187,26 @@ std::string build_sweep_ops(Plan& p) {
   p.final_w = p.ops.empty() ? 0 : p.ops.back().w_after;
   p.final_slot_spin.assign(p.final_w, -1);
   for (int s = 0; s < p.final_w && s < (int)slot_spin.size(); ++s) p.final_slot_spin[s] = slot_spin[s];
-  // algorithmic work: a GATE or CUT makes 2 terms per state entry, a DIAG or
-  // FIELD one term (an elementwise tropical product)
-  double terms = 0;
+  // algorithmic work, at the live (not the physical) width: a GATE is a
+  // contraction with K = 2, i.e. two terms (add + max) per output entry; a
+  // DIAG or FIELD is an elementwise tropical product (one add per entry), a
+  // CUT an elementwise maximum of the two halves (one max per output entry),
+  // and the final maximum one max per entry of the last state
+  double terms = 0, elem = 0;
   int live_now = 0;
   for (auto& op : p.ops) {
     if (op.kind == OP_INTRO) live_now += 1;
     const double sz = std::ldexp(1.0, live_now);
-    if (op.kind == OP_GATE || op.kind == OP_CUT) terms += 2 * sz;
-    if (op.kind == OP_DIAG || op.kind == OP_FIELD) terms += sz;
-    if (op.kind == OP_CUT) live_now -= 1;
+    if (op.kind == OP_GATE) terms += 2 * sz;
+    if (op.kind == OP_DIAG || op.kind == OP_FIELD) elem += sz;
+    if (op.kind == OP_CUT) {
+      elem += sz / 2;
+      live_now -= 1;
+    }
   }
-  p.reduce_terms = std::ldexp(1.0, live_now);   // final reduction
-  terms += p.reduce_terms;
+  p.reduce_ops = std::ldexp(1.0, live_now);   // final reduction
   p.terms = terms;
+  p.elementwise = elem + p.reduce_ops;
   return "";
 }
 
@@ -473,12 +479,13 @@ std::string build_chimera_ops(Plan& p, int rows, int cols) {
   p.final_slot_spin.assign(w, -1);
   for (int c = 0; c < cols; ++c)
     for (int k = 0; k < 4; ++k) p.final_slot_spin[4 * c + k] = id(rows - 1, c, k);
-  // algorithmic terms: two per relabelled entry, sixteen per entry for the
-  // chain of every row (one 16-way maximum per entry), one per entry for the
-  // final maximum
+  // algorithmic work: two terms per entry for every vertical relabel (K = 2),
+  // sixteen per entry for the chain of every row (a 16-way maximum over the
+  // split chain), and the final maximum (one max per entry, elementwise)
   const double W = std::ldexp(1.0, w);
-  p.reduce_terms = W;
-  p.terms = (double)(rows - 1) * 4 * cols * 2.0 * W + (double)rows * 16.0 * W + W;
+  p.reduce_ops = W;
+  p.terms = (double)(rows - 1) * 4 * cols * 2.0 * W + (double)rows * 16.0 * W;
+  p.elementwise = W;
   return "";
 }
 

@@ -1,5 +1,6 @@
 """CPU tests of the C-ABI library: it loads, exports every declared symbol,
 and its host-side planner and CRT helper behave (no GPU needed)."""
+import ctypes as C
 import os
 import re
 
@@ -80,3 +81,59 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+# ----------------------------------------------------------------------------
+# failure injection on the host: errors returned before any device work
+# ----------------------------------------------------------------------------
+FAKE = C.c_void_p(0x1000)   # never dereferenced: the calls fail before touching the device
+
+
+def _lib_call_contract(plan, batch, dtype, J=FAKE, h=None, energy=FAKE):
+    return B.lib().tt_contract(plan.handle, batch, dtype, J, h, energy, None)
+
+
+def test_dtype_rejected():
+    p = B.Plan(16, I.square_lattice(4), order=list(range(16)))
+    assert _lib_call_contract(p, 1, 5) == B.TT_E_DTYPE
+    assert B.lib().tt_backward(p.handle, 1, 9, FAKE, None, FAKE, FAKE, None, None, None) == B.TT_E_DTYPE
+    assert B.lib().tt_contract_uneven(1, (C.c_void_p * 1)(p.handle), 3, FAKE,
+                                      np.zeros(1, np.int64).ctypes.data, FAKE, None, None, None, None) == B.TT_E_DTYPE
+
+
+def test_invalid_arguments_rejected():
+    p = B.Plan(16, I.square_lattice(4), order=list(range(16)))
+    assert _lib_call_contract(p, 0, B.TT_F32) == B.TT_E_INVAL          # empty batch
+    assert _lib_call_contract(p, 1, B.TT_F32, energy=None) == B.TT_E_INVAL
+    assert _lib_call_contract(p, 1, B.TT_F32, J=None) == B.TT_E_INVAL
+    assert _lib_call_contract(p, 1, B.TT_F32, h=FAKE) == B.TT_E_INVAL   # the plan has no fields
+    pf = B.Plan(16, I.square_lattice(4), order=list(range(16)), has_field=True)
+    assert _lib_call_contract(pf, 1, B.TT_F32) == B.TT_E_INVAL          # fields missing
+    assert B.lib().tt_backward(p.handle, 1, B.TT_F32, FAKE, None, FAKE, None, None, None, None) == B.TT_E_INVAL
+    assert B.lib().tt_count(p.handle, 1, FAKE, None, None, FAKE, None, None) == B.TT_E_INVAL
+    assert B.lib().tt_count(None, 1, FAKE, None, FAKE, FAKE, None, None) == B.TT_E_INVAL
+
+
+@pytest.mark.parametrize("call", ["contract", "backward", "count", "uneven"])
+def test_budget_checked_before_device_work(call):
+    """An explicit max_bytes below the planned state: TT_E_TOOBIG with no device touched."""
+    e = I.square_lattice(8)
+    p = B.Plan(64, e, order=list(range(64)), max_bytes=1024)
+    lib = B.lib()
+    if call == "contract":
+        rc = lib.tt_contract(p.handle, 4, B.TT_F32, FAKE, None, FAKE, None)
+    elif call == "backward":
+        rc = lib.tt_backward(p.handle, 4, B.TT_F32, FAKE, None, FAKE, FAKE, None, None, None)
+    elif call == "count":
+        rc = lib.tt_count(p.handle, 4, FAKE, None, FAKE, FAKE, None, None)
+    else:
+        rc = lib.tt_contract_uneven(1, (C.c_void_p * 1)(p.handle), B.TT_F32, FAKE,
+                                    np.zeros(1, np.int64).ctypes.data, FAKE, None, None, None, None)
+    assert rc == B.TT_E_TOOBIG
+    assert b"budget" in lib.tt_last_error()
+
+
+def test_crt_of_reduced_residues_only():
+    P = B.moduli()
+    with pytest.raises(B.TTError):
+        B.residues_to_int([P[0], 0, 0])
