@@ -254,6 +254,33 @@ def config_instances(config_id: int, batch: Optional[int] = None, L: Optional[in
     return out
 
 
+def potts_lattice(L: int, batch: int = 1, Lc: Optional[int] = None, coupling: str = "pm1",
+                  seed: int = 5) -> List[Instance]:
+    """3-state Potts glasses on an open L x Lc square lattice (Appendix C): J = +-1
+    (int32) or J ~ N(0, 1) (float32) per edge, instance b drawn from
+    ``default_rng([seed, L, b])``. ``h`` is None (the Potts Hamiltonian has no field)."""
+    Lc = L if Lc is None else Lc
+    e = square_lattice(L, Lc)
+    return [make(e, L * Lc, np.random.default_rng([seed, L, b]), coupling, name=f"potts{L}x{Lc}_{coupling}_{b}")
+            for b in range(batch)]
+
+
+def cubic_lattice(L: int) -> np.ndarray:
+    """Open L x L x L simple cubic lattice; spin (x, y, z) = (z L + y) L + x."""
+    edges = []
+    for z in range(L):
+        for y in range(L):
+            for x in range(L):
+                i = (z * L + y) * L + x
+                if x + 1 < L:
+                    edges.append((i, i + 1))
+                if y + 1 < L:
+                    edges.append((i, i + L))
+                if z + 1 < L:
+                    edges.append((i, i + L * L))
+    return _canon(edges) if edges else np.zeros((0, 2), np.int32)
+
+
 def planted(edges: np.ndarray, n: int, rng: np.random.Generator, coupling: str = "pm1"):
     """Mattis (planted) instance J_ij = tau_i tau_j |J0_ij|, h = 0.
 
