@@ -138,6 +138,23 @@ int tt_plan_ops(const tt_plan* plan, int32_t* out, int64_t cap, int32_t* final_s
 int tt_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
                 const void* h, double* energy, void* stream);
 
+/* Allocation-free tt_contract, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, checks and results as tt_contract, but
+ * every buffer the call needs besides the caller's inputs and outputs lives in
+ * a fixed workspace of TT_NOALLOC_MAX_BYTES per GPU, part of the library's
+ * device image and held until the process ends. The call makes no device
+ * allocation or free (nor does any routine it calls); it launches eagerly on
+ * `stream` (no graph replay, no concurrent parts) and returns after `stream`
+ * has synchronised. Every call on one GPU uses that GPU's one workspace:
+ * calls that overlap in time on the same GPU (other threads, other streams)
+ * race and must be serialised by the caller. A batch whose state, tables and
+ * partials do not fit (about batch x 2^width x 8 bytes plus a few KB) returns
+ * TT_E_TOOBIG before any device work; chimera plans return TT_E_INVAL. */
+#define TT_NOALLOC_MAX_BYTES (64u << 20)
+int tt_contract_noalloc(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
+                        const void* h, double* energy, void* stream);
+
 /* Energy plus one ground state (Sec. IV): sigma device int8 [batch][n_spins]
  * in {+1,-1}; dJ device float [batch][n_edges] = -s_i s_j and dh device
  * float [batch][n_spins] = -s_i (either may be NULL). Ties resolve to the

@@ -30,13 +30,14 @@ TT_OK = 0
 TT_E_INVAL, TT_E_DTYPE, TT_E_RANGE, TT_E_TOOBIG = -1, -2, -3, -4
 TT_E_COUNT_OVERFLOW, TT_E_DEVICE, TT_E_NOMEM = -5, -6, -7
 TT_F32, TT_I32 = 0, 1
+NOALLOC_MAX_BYTES = 64 << 20      # workspace of tt_contract_noalloc per GPU (TT_NOALLOC_MAX_BYTES)
 ORDER_GREEDY, ORDER_GIVEN, ORDER_CHIMERA = 0, 1, 2
 
 #: every symbol the header declares (checked by the CPU tests)
 EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy", "tt_contract",
            "tt_backward", "tt_count", "tt_count_moduli", "tt_count_to_decimal", "tt_contract_uneven",
            "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops",
-           "tt_plan_program", "tt_graphs_enable", "tt_tgemm", "tt_plan_autotune")
+           "tt_plan_program", "tt_graphs_enable", "tt_tgemm", "tt_plan_autotune", "tt_contract_noalloc")
 
 
 class PlanOpts(C.Structure):
@@ -64,6 +65,7 @@ _lib.tt_plan_program.restype = C.c_int64
 _lib.tt_plan_destroy.argtypes = [_vp]
 _lib.tt_plan_destroy.restype = None
 _lib.tt_contract.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
+_lib.tt_contract_noalloc.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
 _lib.tt_backward.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_count.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_count_moduli.argtypes = [_vp]
@@ -82,6 +84,11 @@ class TTError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"tt error {code}: {msg}")
         self.code = code
+
+
+def last_error() -> str:
+    """Message of the last failed call on this thread."""
+    return _lib.tt_last_error().decode()
 
 
 def _check(code: int):
@@ -226,6 +233,21 @@ def contract(plan: Plan, J, h=None):
     energy = torch.empty(B, dtype=torch.float64, device=J.device)
     _check(_lib.tt_contract(plan.handle, B, _dtype_code(J), _ptr(J), _ptr(h), _ptr(energy), _stream()))
     return energy
+
+
+def contract_noalloc(plan: Plan, J, h=None, out=None):
+    """E* through the allocation-free entry point (its workspace is the
+    library's fixed per-GPU array); ``out`` (device float64 [batch]) may be
+    given so that the call allocates nothing at all. Returns after the stream
+    has synchronised."""
+    torch = _torch()
+    _check_inputs(plan, J, h)
+    B = J.shape[0]
+    energy = out if out is not None else torch.empty(B, dtype=torch.float64, device=J.device)
+    if energy.dtype != torch.float64 or not energy.is_cuda or energy.numel() < B or not energy.is_contiguous():
+        raise ValueError("out must be a contiguous device float64 tensor of at least batch entries")
+    _check(_lib.tt_contract_noalloc(plan.handle, B, _dtype_code(J), _ptr(J), _ptr(h), _ptr(energy), _stream()))
+    return energy[:B]
 
 
 def backward(plan: Plan, J, h=None, want_grad: bool = True):

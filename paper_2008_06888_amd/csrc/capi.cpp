@@ -397,8 +397,27 @@ int early_budget(const Plan& p, int64_t need) {
   return 0;
 }
 
+// The host encoding of the plan's energy passes (kept with the plan until its
+// passes change).
+void drop_host_prog(Plan& p) {
+  delete static_cast<EnergyProgram*>(p.host_prog);
+  p.host_prog = nullptr;
+}
+
+int host_program(Plan& p, const EnergyProgram** out) {
+  if (!p.host_prog) {
+    std::unique_ptr<EnergyProgram> ep(new EnergyProgram());
+    const std::string err = encode_energy(p, p.passes, *ep);
+    if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
+    p.host_prog = ep.release();
+  }
+  *out = static_cast<const EnergyProgram*>(p.host_prog);
+  return 0;
+}
+
 // Passes of the energy and counting sweeps at the plan's tile sizes.
 void partition_plan(Plan& p) {
+  drop_host_prog(p);
   if (p.is_chimera) {
     // two cells (eight relabels) per pass: every pass boundary then keeps
     // six shared resident slots and the row boundaries the identity order
@@ -532,6 +551,27 @@ struct PendingCheck {
 // The exact range of integer couplings in the float32 state.
 constexpr int64_t I32_EXACT = int64_t(1) << 24;
 
+// Launches of at most CHECK_ITEMS items, each with its own status range:
+// status[i] (device) for the i-th instance of the items.
+int check_launches(const std::vector<CheckItem>& items, uint32_t* status, hipStream_t s) {
+  int64_t base = 0;
+  for (size_t k0 = 0; k0 < items.size(); k0 += CHECK_ITEMS) {
+    CheckArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int64_t cnt = 0;
+    for (size_t k = k0; k < items.size() && k < k0 + CHECK_ITEMS; ++k) {
+      a.it[a.n] = items[k];
+      a.it[a.n].first = cnt;
+      cnt += items[k].batch;
+      ++a.n;
+    }
+    ProfScope ps(s, "check_inputs");
+    HIP_TRY(launch_check(a, cnt, status + base, s));
+    base += cnt;
+  }
+  return 0;
+}
+
 int check_enqueue(const std::vector<CheckItem>& items, hipStream_t s, PendingCheck* pc) {
   int64_t n = 0;
   for (const CheckItem& c : items) n += c.batch;
@@ -572,22 +612,7 @@ int check_enqueue(const std::vector<CheckItem>& items, hipStream_t s, PendingChe
   }
   pc->slot = slot;
   pc->n = n;
-  // launches of at most CHECK_ITEMS items, each with its own status range
-  int64_t base = 0;
-  for (size_t k0 = 0; k0 < items.size(); k0 += CHECK_ITEMS) {
-    CheckArgs a;
-    std::memset(&a, 0, sizeof(a));
-    int64_t cnt = 0;
-    for (size_t k = k0; k < items.size() && k < k0 + CHECK_ITEMS; ++k) {
-      a.it[a.n] = items[k];
-      a.it[a.n].first = cnt;
-      cnt += items[k].batch;
-      ++a.n;
-    }
-    ProfScope ps(s, "check_inputs");
-    HIP_TRY(launch_check(a, cnt, slot->dev + base, s));
-    base += cnt;
-  }
+  if (int r = check_launches(items, slot->dev, s)) return r;
   HIP_TRY(hipMemcpyAsync(slot->host, slot->dev, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(slot->ev, s));
   return 0;
@@ -604,29 +629,25 @@ int check_start(const std::vector<CheckItem>& items, hipStream_t s, PendingCheck
   return r;
 }
 
+// The call's result from the per-instance statuses of its input check.
+int check_statuses(const uint32_t* st, int64_t n, int32_t dtype) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (st[i] & CHK_NONFINITE) return fail(TT_E_INVAL, "instance %lld: a coupling or field is not finite", (long long)i);
+    if (st[i] & CHK_RANGE)
+      return fail(TT_E_RANGE, "instance %lld: sum|J| + sum|h| reaches 2^24, beyond the exact range of %s",
+                  (long long)i, dtype == TT_I32 ? "int32 couplings in the float32 state" : "the state");
+  }
+  return 0;
+}
+
 // Waits for a pending check and turns its statuses into the call's result.
 int check_finish(PendingCheck& pc, int32_t dtype) {
   if (!pc.slot) return 0;
   CheckSlot* slot = pc.slot;
   pc.slot = nullptr;
   const hipError_t e = hipEventSynchronize(slot->ev);
-  int rc = 0;
-  if (e != hipSuccess) {
-    rc = fail(TT_E_DEVICE, "input check: %s", hipGetErrorString(e));
-  } else {
-    for (int64_t i = 0; i < pc.n; ++i) {
-      const uint32_t st = slot->host[i];
-      if (st & CHK_NONFINITE) {
-        rc = fail(TT_E_INVAL, "instance %lld: a coupling or field is not finite", (long long)i);
-        break;
-      }
-      if (st & CHK_RANGE) {
-        rc = fail(TT_E_RANGE, "instance %lld: sum|J| + sum|h| reaches 2^24, beyond the exact range of %s",
-                  (long long)i, dtype == TT_I32 ? "int32 couplings in the float32 state" : "the state");
-        break;
-      }
-    }
-  }
+  const int rc = e != hipSuccess ? fail(TT_E_DEVICE, "input check: %s", hipGetErrorString(e))
+                                 : check_statuses(slot->host, pc.n, dtype);
   std::lock_guard<std::mutex> g(g_check_mu);
   slot->busy = false;
   return rc;
@@ -663,6 +684,12 @@ CheckItem check_item(const void* J, const void* h, int64_t m, int64_t n, int32_t
 struct Group {
   Plan* p = nullptr;
   DevCache* dc = nullptr;
+  // the energy program: host encoding and the device copies of its passes,
+  // stages and fused ops (the plan's device cache, or a caller-free scratch)
+  const EnergyProgram* ep = nullptr;
+  const DevPass2* d_passes = nullptr;
+  const DevStage* d_stages = nullptr;
+  const FOp* d_fops = nullptr;
   int32_t batch = 1;
   const void* J = nullptr;
   const void* h = nullptr;
@@ -682,8 +709,17 @@ struct Group {
   uint64_t* arg = nullptr;
 };
 
+// Points the group at the program in its plan's device cache.
+void bind_program(Group& g) {
+  g.ep = &g.dc->ep;
+  g.d_passes = static_cast<const DevPass2*>(g.dc->d_passes.p);
+  g.d_stages = static_cast<const DevStage*>(g.dc->d_stages.p);
+  g.d_fops = static_cast<const FOp*>(g.dc->d_fops.p);
+}
+
 int prepare_group(Group& g, bool keep_all) {
   if (int r = ensure_device(*g.p, g.dc)) return r;
+  bind_program(g);
   const EnergyProgram& ep = g.dc->ep;
   const int np = (int)ep.passes.size();
   if (np == 0) return fail(TT_E_INVAL, "empty plan");
@@ -744,7 +780,7 @@ struct CallTables {
 // Partials of the final maximum per instance: with the reduction fused into
 // the last pass, one per tile of that pass, else one per fixed-size chunk.
 int red_log2_parts(const Group& g, bool fused) {
-  return fused ? g.dc->ep.passes.back().n_free : reduce_log2_chunks(g.p->final_w);
+  return fused ? g.ep->passes.back().n_free : reduce_log2_chunks(g.p->final_w);
 }
 
 // The final maximum can be taken inside the last pass when every group has
@@ -752,7 +788,7 @@ int red_log2_parts(const Group& g, bool fused) {
 // instance (the partials stay small and one workgroup per instance ranks them).
 bool can_fuse_reduce(const std::vector<Group>& groups) {
   for (const Group& g : groups)
-    if (g.dc->ep.passes.empty() || g.p->is_chimera || g.dc->ep.passes.back().n_free > 12) return false;
+    if (g.ep->passes.empty() || g.p->is_chimera || g.ep->passes.back().n_free > 12) return false;
   return true;
 }
 
@@ -767,7 +803,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
                   float* pv, uint64_t* pi) {
   ct.fused = fuse;
   int max_np = 0;
-  for (Group& g : groups) max_np = std::max(max_np, (int)g.dc->ep.passes.size());
+  for (Group& g : groups) max_np = std::max(max_np, (int)g.ep->passes.size());
   // partial of each group's first instance
   std::vector<int64_t> part_base;
   {
@@ -795,14 +831,14 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
     // its largest tile needs, so tiles of different sizes go separately
     std::vector<std::pair<int, Group*>> order;
     for (Group& g : groups)
-      if (q < (int)g.dc->ep.passes.size()) order.push_back({g.dc->ep.passes[q].t, &g});
+      if (q < (int)g.ep->passes.size()) order.push_back({g.ep->passes[q].t, &g});
     std::stable_sort(order.begin(), order.end(),
                      [](const std::pair<int, Group*>& a, const std::pair<int, Group*>& b) { return a.first < b.first; });
     int cur_t = -1;
     for (auto& og : order) {
       Group& g = *og.second;
       const size_t gi = (size_t)(og.second - groups.data());
-      const EnergyProgram& ep = g.dc->ep;
+      const EnergyProgram& ep = *g.ep;
       const DevPass2& P = ep.passes[q];
       if (P.t != cur_t) {
         flush();
@@ -812,9 +848,9 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
       lds = std::max(lds, pass_lds_bytes(P.t));
       PassItem it;
       std::memset(&it, 0, sizeof(it));
-      it.P = static_cast<const DevPass2*>(g.dc->d_passes.p) + q;
-      it.stages = static_cast<const DevStage*>(g.dc->d_stages.p);
-      it.fops = static_cast<const FOp*>(g.dc->d_fops.p);
+      it.P = g.d_passes + q;
+      it.stages = g.d_stages;
+      it.fops = g.d_fops;
       it.J = g.J;
       it.h = g.h;
       it.jst = g.p->m;
@@ -842,7 +878,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
   for (Group& g : groups) {
     const int fw = g.p->final_w;
     const int lc = red_log2_parts(g, fuse);
-    const int np = (int)g.dc->ep.passes.size();
+    const int np = (int)g.ep->passes.size();
     for (int b = 0; b < g.batch; ++b) {
       RedItem r;
       std::memset(&r, 0, sizeof(r));
@@ -1194,6 +1230,7 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
 int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   Plan& p = *g.p;
   if (int r = ensure_device(p, g.dc)) return r;
+  bind_program(g);
   DevCache* dc = g.dc;
   const ChimeraInfo& ch = p.chim;
   const int np = (int)dc->ep.passes.size();
@@ -1400,6 +1437,8 @@ void crt_limbs(const uint64_t res[3], uint32_t limbs[8]) {
   std::copy(x.begin(), x.end(), limbs);
 }
 
+static_assert(NOALLOC_SCRATCH_BYTES == (size_t)TT_NOALLOC_MAX_BYTES, "workspace size differs from the header's");
+
 // Spins up to which g <= 2^n stays below the product of the count primes.
 constexpr int COUNT_EXACT_SPINS = 182;
 
@@ -1438,7 +1477,8 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
     p->tile_bits = o.tile_bits > 0 ? o.tile_bits : 14;
     p->count_tile_bits = o.count_tile_bits > 0 ? o.count_tile_bits : 12;
     if (p->tile_bits < 7 || p->tile_bits > 14) return fail(TT_E_INVAL, "tile_bits must be in [7, 14]");
-    if (p->count_tile_bits < 7 || p->count_tile_bits > 12) return fail(TT_E_INVAL, "count_tile_bits must be in [7, 12]");
+    if (p->count_tile_bits < 7 || p->count_tile_bits > 12)
+      return fail(TT_E_INVAL, "count_tile_bits must be in [7, 12]");
     p->max_bytes = o.max_bytes;
     if (o.parts < 0 || o.parts > SPLIT_PARTS) return fail(TT_E_INVAL, "parts must be 1 or 2 (0: default)");
     p->parts = o.parts > 0 ? o.parts : SPLIT_PARTS;
@@ -1549,6 +1589,7 @@ void tt_plan_destroy(tt_plan* plan) {
   if (!plan) return;
   Plan* p = reinterpret_cast<Plan*>(plan);
   delete static_cast<DevCache*>(p->dev);
+  drop_host_prog(*p);
   delete p;
 }
 
@@ -1570,6 +1611,102 @@ int tt_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
     g[0].energy = energy;
     const int rc = p.is_chimera ? run_chimera(g[0], dtype, false, s) : run_groups(g, dtype, false, s);
     return check_end(rc, pc, dtype);
+  } catch (...) {
+    return fail(TT_E_INVAL, "unexpected failure");
+  }
+}
+
+// Allocation-free variant of tt_contract: the input statuses, the plan's
+// passes / stages / fused ops, the launch tables, both ping-pong states, the
+// partials of the final maximum and the argmax words all live in the device's
+// fixed workspace (regions 256-byte aligned, in that order: statuses, states,
+// argmax words, partials, then the uploaded image of program and tables).
+// Every region is fully written before it is read within the call (the first
+// pass starts from the zero state without reading, every partial is written
+// by the last pass), so nothing has to be cleared between calls. One eager
+// launch sequence on the caller's stream (no graph, no concurrent parts).
+int tt_contract_noalloc(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, double* energy,
+                        void* stream) {
+  try {
+    if (int r = check_common(plan, batch, dtype, J, h)) return r;
+    if (!energy) return fail(TT_E_INVAL, "null energy");
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    if (p.is_chimera || p.n_regs != 1)
+      return fail(TT_E_INVAL, "chimera plans are not supported by the allocation-free call");
+    if (int r = early_budget(p, state_bytes(p, batch, false))) return r;
+    const EnergyProgram* ep = nullptr;
+    if (int r = host_program(p, &ep)) return r;
+    const int np = (int)ep->passes.size();
+    if (np == 0) return fail(TT_E_INVAL, "empty plan");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<Group> gs(1);
+    Group& g = gs[0];
+    g.p = &p;
+    g.batch = batch;
+    g.J = J;
+    g.h = h;
+    g.energy = energy;
+    g.ep = ep;
+    const bool fuse = can_fuse_reduce(gs);
+    const int64_t nparts = red_parts_needed(gs, fuse);
+    // layout of the workspace (sizes checked before any device work)
+    const size_t cap = NOALLOC_SCRATCH_BYTES;
+    if (p.width > 26 || ((size_t)batch << p.width) > cap / sizeof(float))
+      return fail(TT_E_TOOBIG, "a state of %d x 2^%d entries exceeds the %zu-byte workspace of the allocation-free call",
+                  batch, p.width, cap);
+    const size_t half = ((size_t)batch << p.width) * sizeof(float);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off = (off + bytes + 255) & ~size_t(255);
+      return o;
+    };
+    const size_t o_status = take((size_t)batch * sizeof(uint32_t));
+    const size_t o_state = take(2 * half);
+    const size_t o_arg = take((size_t)batch * sizeof(uint64_t));
+    const size_t o_pv = take((size_t)nparts * sizeof(float));
+    const size_t o_pi = take((size_t)nparts * sizeof(uint64_t));
+    const size_t o_img = off;
+    if (o_img > cap)
+      return fail(TT_E_TOOBIG, "batch %d at width %d needs %zu bytes, beyond the %zu-byte workspace of the "
+                  "allocation-free call", batch, p.width, o_img, cap);
+    void* base = nullptr;
+    HIP_TRY(noalloc_scratch(&base));
+    char* d = static_cast<char*>(base);
+    uint32_t* status = reinterpret_cast<uint32_t*>(d + o_status);
+    float* pp[2] = {reinterpret_cast<float*>(d + o_state), reinterpret_cast<float*>(d + o_state + half)};
+    g.bufs.assign(np + 1, nullptr);
+    g.strides.assign(np + 1, 0);
+    for (int q = 0; q <= np; ++q) {
+      g.bufs[q] = pp[q & 1];
+      g.strides[q] = (int64_t)1 << (q < np ? ep->passes[q].in_w : ep->passes[np - 1].out_w);
+    }
+    g.part_st.assign(np + 1, (int64_t)1 << p.width);
+    g.arg = reinterpret_cast<uint64_t*>(d + o_arg);
+    float* pv = reinterpret_cast<float*>(d + o_pv);
+    uint64_t* pi = reinterpret_cast<uint64_t*>(d + o_pi);
+    // image = the program's passes, stages and fused ops, then the launch tables
+    CallTables ct;
+    const size_t i_passes = ct.blob.add(ep->passes.data(), ep->passes.size());
+    const size_t i_stages = ct.blob.add(ep->stages.data(), ep->stages.size());
+    const size_t i_fops = ct.blob.add(ep->fops.data(), ep->fops.size());
+    g.d_passes = reinterpret_cast<const DevPass2*>(d + o_img + i_passes);
+    g.d_stages = reinterpret_cast<const DevStage*>(d + o_img + i_stages);
+    g.d_fops = reinterpret_cast<const FOp*>(d + o_img + i_fops);
+    build_tables(gs, dtype, false, ct, fuse, pv, pi);
+    const size_t img = ct.blob.bytes.size();
+    if (o_img + img > cap)
+      return fail(TT_E_TOOBIG, "batch %d at width %d needs %zu bytes, beyond the %zu-byte workspace of the "
+                  "allocation-free call", batch, p.width, o_img + img, cap);
+    HIP_TRY(hipMemcpyAsync(d + o_img, ct.blob.bytes.data(), img, hipMemcpyHostToDevice, s));
+    if (int r = check_launches({check_item(J, h, p.m, p.n, batch, dtype)}, status, s)) return r;
+    if (int r = enqueue_launches(ct, d + o_img, pv, pi, dtype, s)) return r;
+    std::vector<uint32_t> st((size_t)batch);
+    HIP_TRY(hipMemcpyAsync(st.data(), status, (size_t)batch * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));   // the image and the statuses are host buffers of this call
+    return check_statuses(st.data(), batch, dtype);
+  } catch (const std::bad_alloc&) {
+    return fail(TT_E_NOMEM, "out of host memory");
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
   }
@@ -1602,6 +1739,7 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
     return fail(TT_E_INVAL, "unexpected failure");
   }
 }
+
 
 int tt_count_moduli(uint64_t moduli_out[3]) {
   if (!moduli_out) return fail(TT_E_INVAL, "null argument");

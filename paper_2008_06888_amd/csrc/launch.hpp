@@ -35,6 +35,11 @@ hipError_t launch_count_reduce(const float* x, const uint64_t* nplanes, int64_t 
                                int batch, int nres, float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues,
                                hipStream_t stream);
 
+// workspace of the allocation-free contraction: its size, and the current
+// device's address of it
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+hipError_t noalloc_scratch(void** ptr);
+
 // input check: status[i] for the n_inst instances of the items (CHK_* flags)
 hipError_t launch_check(const CheckArgs& a, int64_t n_inst, uint32_t* status, hipStream_t stream);
 

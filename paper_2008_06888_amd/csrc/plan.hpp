@@ -129,6 +129,7 @@ struct Plan {
   bool is_chimera = false;
   ChimeraInfo chim;
   void* dev = nullptr;               // device-side cache (owned, see capi)
+  void* host_prog = nullptr;         // host encoding of the energy passes (owned, see capi)
   uint64_t serial = 0;               // unique over the process lifetime (never reused)
 };
 
