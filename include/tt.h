@@ -84,7 +84,9 @@ typedef struct tt_plan_opts {
   int64_t max_bytes;        /* device memory budget of one call [7/8 of free] */
   int32_t parts;            /* concurrent parts (streams) a large same-graph batch
                                runs in: 1 or 2 [2] */
-  int32_t pad;
+  int32_t q;                /* labels per spin: 2 = Ising spins, 3 = 3-state Potts
+                               glass (App. C; GREEDY or GIVEN order, no fields,
+                               tt_potts_* calls only) [2] */
 } tt_plan_opts;
 
 typedef struct tt_plan_stats {
@@ -117,7 +119,8 @@ void tt_plan_destroy(tt_plan* plan);
 /* The encoded energy program the kernels execute, for host-side checks:
  * which = 0 pass descriptors, 1 stages, 2 fused ops, 3 backward candidates,
  * 4 backward terms, 5 final bit layout, 6 per pass the chimera row whose
- * chain step follows it (int32, -1 = none). Copies at most cap bytes into out
+ * chain step follows it (int32, -1 = none); for 3-state plans (opts.q = 3)
+ * 7 energy passes, 8 counting passes, 9 the final-reduction descriptor. Copies at most cap bytes into out
  * (may be NULL) and returns the total size in bytes (or a negative
  * tt_status). The record layouts are those of the library's device.hpp. */
 int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t cap);
@@ -178,6 +181,30 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
  * TT_E_RANGE when sum|J| + sum|h| >= 2^24 for an instance. */
 int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h,
              int64_t* energy, uint64_t* residues, uint8_t* exact_flag, void* stream);
+/* 3-state Potts glasses (App. C): H(s) = sum_{(i,j)} J_ij M[s_i][s_j] with
+ * labels s in {0, 1, 2} (the paper's 1, 2, 3) and M = 1 on the diagonal,
+ * -1/2 off it. The plan comes from tt_plan_create with opts.q = 3 (GREEDY or
+ * GIVEN order, no fields); its state has 3^width entries per instance
+ * (width <= 20). The contraction runs over doubled energies 2H, exact for
+ * integer couplings while 2 sum|J| < 2^24 (else TT_E_RANGE).
+ *
+ * tt_potts_contract: ground-state energy H* (a multiple of 1/2 for integer
+ * couplings) of `batch` (<= 65535) instances sharing the plan's graph.
+ * J: device [batch][n_edges] float32 or int32 (dtype); energy: device double
+ * [batch]. Inputs are checked on the device like tt_contract's (TT_E_INVAL
+ * for a non-finite coupling, TT_E_RANGE). */
+int tt_potts_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
+                      double* energy, void* stream);
+/* tt_potts_count: ground-state energy and degeneracy g (Eq. 4 tuples) for
+ * int32 couplings. energy2: host int64 [batch] = 2H*; residues: host uint64
+ * [batch][3], g modulo the primes of tt_count_moduli; g counts labelings, so
+ * it is a multiple of 3 (label permutations). g <= 3^n_spins: exact for
+ * n_spins <= 115; beyond, a plane modulo 2^64 checks the CRT value as in
+ * tt_count (exact_flag: host uint8 [batch], 1 = exact; NULL = strict mode,
+ * TT_E_COUNT_OVERFLOW). Synchronises `stream`. */
+int tt_potts_count(tt_plan* plan, int32_t batch, const int32_t* J, int64_t* energy2,
+                   uint64_t* residues, uint8_t* exact_flag, void* stream);
+
 /* The three prime moduli (2^61-1, 2^61-31, 2^61-45). */
 int tt_count_moduli(uint64_t moduli_out[3]);
 /* Exact g from its residues by the Chinese remainder theorem, as a decimal

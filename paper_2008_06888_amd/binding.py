@@ -37,7 +37,8 @@ ORDER_GREEDY, ORDER_GIVEN, ORDER_CHIMERA = 0, 1, 2
 EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy", "tt_contract",
            "tt_backward", "tt_count", "tt_count_moduli", "tt_count_to_decimal", "tt_contract_uneven",
            "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops",
-           "tt_plan_program", "tt_graphs_enable", "tt_tgemm", "tt_plan_autotune", "tt_contract_noalloc")
+           "tt_plan_program", "tt_graphs_enable", "tt_tgemm", "tt_plan_autotune", "tt_contract_noalloc",
+           "tt_potts_contract", "tt_potts_count")
 
 
 class PlanOpts(C.Structure):
@@ -45,7 +46,7 @@ class PlanOpts(C.Structure):
                 ("trials", C.c_int32), ("has_field", C.c_int32), ("tile_bits", C.c_int32),
                 ("count_tile_bits", C.c_int32), ("chimera_rows", C.c_int32),
                 ("chimera_cols", C.c_int32), ("max_bytes", C.c_int64), ("parts", C.c_int32),
-                ("pad", C.c_int32)]
+                ("q", C.c_int32)]
 
 
 class PlanStats(C.Structure):
@@ -68,6 +69,8 @@ _lib.tt_contract.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
 _lib.tt_contract_noalloc.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
 _lib.tt_backward.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_count.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tt_potts_contract.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp]
+_lib.tt_potts_count.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_count_moduli.argtypes = [_vp]
 _lib.tt_count_to_decimal.argtypes = [_vp, C.c_char_p, C.c_size_t]
 _lib.tt_contract_uneven.argtypes = [C.c_int32, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -106,7 +109,7 @@ class Plan:
     def __init__(self, n: int, edges, *, order: Optional[Sequence[int]] = None, kind: Optional[int] = None,
                  has_field: bool = False, seed: int = 0, trials: int = 32, tile_bits: int = 0,
                  count_tile_bits: int = 0, chimera: Optional[tuple] = None, max_bytes: int = 0,
-                 parts: int = 0):
+                 parts: int = 0, q: int = 2):
         self.n = int(n)
         self.edges = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
         self.m = int(self.edges.shape[0])
@@ -123,6 +126,8 @@ class Plan:
         o.tile_bits, o.count_tile_bits, o.max_bytes, o.parts = tile_bits, count_tile_bits, max_bytes, parts
         if chimera:
             o.chimera_rows, o.chimera_cols = chimera
+        o.q = q
+        self.q = q
         h = _vp()
         _check(_lib.tt_plan_create(self.n, self.m, self.edges.ctypes.data, C.byref(o), C.byref(h)))
         self._h = h
@@ -248,6 +253,39 @@ def contract_noalloc(plan: Plan, J, h=None, out=None):
         raise ValueError("out must be a contiguous device float64 tensor of at least batch entries")
     _check(_lib.tt_contract_noalloc(plan.handle, B, _dtype_code(J), _ptr(J), _ptr(h), _ptr(energy), _stream()))
     return energy[:B]
+
+
+def _check_potts(plan: Plan, J):
+    if plan.q != 3:
+        raise ValueError("plan was not built for 3-state labels (q=3)")
+    if not J.is_cuda or not J.is_contiguous() or J.dim() != 2 or J.shape[1] != plan.m:
+        raise ValueError(f"J must be a contiguous device tensor [batch, {plan.m}]")
+
+
+def potts_contract(plan: Plan, J):
+    """Ground-state energy H* of 3-state Potts glasses (device float64 [batch])."""
+    torch = _torch()
+    _check_potts(plan, J)
+    B = J.shape[0]
+    energy = torch.empty(B, dtype=torch.float64, device=J.device)
+    _check(_lib.tt_potts_contract(plan.handle, B, _dtype_code(J), _ptr(J), _ptr(energy), _stream()))
+    return energy
+
+
+def potts_count(plan: Plan, J, flags: bool = False):
+    """(2H* int64 [batch], residues [batch, 3], g as Python ints[, exact flags]) for int32 couplings."""
+    torch = _torch()
+    _check_potts(plan, J)
+    if J.dtype != torch.int32:
+        raise TypeError("counting needs int32 couplings")
+    B = J.shape[0]
+    energy2 = np.zeros(B, np.int64)
+    res = np.zeros((B, 3), np.uint64)
+    exact = np.zeros(B, np.uint8)
+    _check(_lib.tt_potts_count(plan.handle, B, _ptr(J), energy2.ctypes.data, res.ctypes.data,
+                               exact.ctypes.data if flags else None, _stream()))
+    g = [residues_to_int(r) for r in res]
+    return (energy2, res, g, exact.astype(bool)) if flags else (energy2, res, g)
 
 
 def backward(plan: Plan, J, h=None, want_grad: bool = True):

@@ -21,6 +21,7 @@
 #include "encode.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
+#include "potts.hpp"
 
 using namespace tt;
 
@@ -217,6 +218,64 @@ struct DevCache {
   DevBuf cx, cn, cpart;
 };
 
+// 3-state plans: host programs (energy tiles of four digits, counting tiles
+// of three) and their device copies, state and partial buffers.
+struct PottsCache {
+  int device = -1;
+  PottsProgram e, c;
+  DevBuf d_e, d_c, d_red, state, cstate, part;
+};
+
+int potts_ensure(Plan& p, PottsCache*& pc, bool need_device) {
+  pc = static_cast<PottsCache*>(p.potts);
+  if (!pc) {
+    std::unique_ptr<PottsCache> n(new PottsCache());
+    std::string err = encode_potts(p, p.tile_bits, n->e);
+    if (err.empty()) err = encode_potts(p, p.count_tile_bits, n->c);
+    if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
+    pc = n.release();
+    p.potts = pc;
+  }
+  if (!need_device) return 0;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (pc->device == dev) return 0;
+  // (re)upload on this device; buffers of another device are released
+  pc->state.~DevBuf();
+  new (&pc->state) DevBuf();
+  pc->cstate.~DevBuf();
+  new (&pc->cstate) DevBuf();
+  pc->part.~DevBuf();
+  new (&pc->part) DevBuf();
+  for (DevBuf* b : {&pc->d_e, &pc->d_c, &pc->d_red}) {
+    b->~DevBuf();
+    new (b) DevBuf();
+  }
+  auto up = [&](DevBuf& b, const void* src, size_t bytes) -> int {
+    if (int r = b.ensure(bytes)) return r;
+    HIP_TRY(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+    return 0;
+  };
+  if (int r = up(pc->d_e, pc->e.passes.data(), pc->e.passes.size() * sizeof(PottsPass))) return r;
+  if (int r = up(pc->d_c, pc->c.passes.data(), pc->c.passes.size() * sizeof(PottsPass))) return r;
+  if (int r = up(pc->d_red, &pc->e.red, sizeof(PottsReduce))) return r;
+  pc->device = dev;
+  return 0;
+}
+
+int potts_common(tt_plan* plan, int32_t batch, int32_t dtype, const void* J) {
+  if (!plan) return fail(TT_E_INVAL, "null plan");
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  if (p.q != 3) return fail(TT_E_INVAL, "plan is not for 3-state labels (create it with opts.q = 3)");
+  if (batch < 1 || batch > 65535) return fail(TT_E_INVAL, "batch must be in [1, 65535]");
+  if (dtype != TT_F32 && dtype != TT_I32) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
+  if (p.m > 0 && !J) return fail(TT_E_INVAL, "null J");
+  return 0;
+}
+
+// Largest |2H| the float32 state holds exactly: 2 sum |J| < 2^24.
+constexpr int64_t POTTS_EXACT = int64_t(1) << 23;
+
 int encode(const Plan& p, const std::vector<Pass>& passes, Encoded& en) {
   en.passes.clear();
   en.ops.clear();
@@ -290,6 +349,7 @@ int upload(DevBuf& b, const std::vector<T>& v) {
 }
 
 int ensure_device(Plan& p, DevCache*& dc) {
+  if (p.q != 2) return fail(TT_E_INVAL, "plan is for 3-state labels: use the tt_potts_* calls");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   dc = static_cast<DevCache*>(p.dev);
@@ -435,6 +495,7 @@ void partition_plan(Plan& p) {
 int check_common(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h) {
   if (!plan) return fail(TT_E_INVAL, "null plan");
   const Plan& p = *reinterpret_cast<Plan*>(plan);
+  if (p.q != 2) return fail(TT_E_INVAL, "plan is for 3-state labels: use the tt_potts_* calls");
   if (batch < 1) return fail(TT_E_INVAL, "batch must be >= 1");
   if (dtype != TT_F32 && dtype != TT_I32) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
   if (p.m > 0 && !J) return fail(TT_E_INVAL, "null J");
@@ -1474,14 +1535,27 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
     p->m = n_edges;
     p->edges.assign(edges, edges + 2 * n_edges);
     p->has_field = o.has_field != 0;
-    p->tile_bits = o.tile_bits > 0 ? o.tile_bits : 14;
-    p->count_tile_bits = o.count_tile_bits > 0 ? o.count_tile_bits : 12;
-    if (p->tile_bits < 7 || p->tile_bits > 14) return fail(TT_E_INVAL, "tile_bits must be in [7, 14]");
-    if (p->count_tile_bits < 7 || p->count_tile_bits > 12)
-      return fail(TT_E_INVAL, "count_tile_bits must be in [7, 12]");
+    if (o.q == 3) {   // tile sizes in base-3 digits
+      p->tile_bits = o.tile_bits > 0 ? o.tile_bits : POTTS_MAX_T;
+      p->count_tile_bits = o.count_tile_bits > 0 ? o.count_tile_bits : POTTS_COUNT_T;
+      if (p->tile_bits < 2 || p->tile_bits > POTTS_MAX_T)
+        return fail(TT_E_INVAL, "tile_bits (digits) must be in [2, %d]", POTTS_MAX_T);
+      if (p->count_tile_bits < 2 || p->count_tile_bits > POTTS_COUNT_T)
+        return fail(TT_E_INVAL, "count_tile_bits (digits) must be in [2, %d]", POTTS_COUNT_T);
+    } else {
+      p->tile_bits = o.tile_bits > 0 ? o.tile_bits : 14;
+      p->count_tile_bits = o.count_tile_bits > 0 ? o.count_tile_bits : 12;
+      if (p->tile_bits < 7 || p->tile_bits > 14) return fail(TT_E_INVAL, "tile_bits must be in [7, 14]");
+      if (p->count_tile_bits < 7 || p->count_tile_bits > 12)
+        return fail(TT_E_INVAL, "count_tile_bits must be in [7, 12]");
+    }
     p->max_bytes = o.max_bytes;
     if (o.parts < 0 || o.parts > SPLIT_PARTS) return fail(TT_E_INVAL, "parts must be 1 or 2 (0: default)");
     p->parts = o.parts > 0 ? o.parts : SPLIT_PARTS;
+    if (o.q != 0 && o.q != 2 && o.q != 3) return fail(TT_E_INVAL, "q must be 2 or 3 (0: 2)");
+    p->q = o.q == 3 ? 3 : 2;
+    if (p->q == 3 && (o.kind == TT_ORDER_CHIMERA || p->has_field))
+      return fail(TT_E_INVAL, "3-state plans take a GREEDY or GIVEN order and no fields");
     std::string err;
     if (o.kind == TT_ORDER_GIVEN) {
       if (!o.order) return fail(TT_E_INVAL, "TT_ORDER_GIVEN needs opts.order");
@@ -1496,6 +1570,14 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
       return fail(TT_E_INVAL, "unknown order kind %d", o.kind);
     }
     if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
+    if (p->q == 3) {
+      if (p->width > POTTS_MAX_W)
+        return fail(TT_E_TOOBIG, "plan needs 3^%d entries per instance (at most 3^%d)", p->width, POTTS_MAX_W);
+      PottsCache* pc = nullptr;
+      if (int r = potts_ensure(*p, pc, false)) return r;
+      *out = reinterpret_cast<tt_plan*>(p.release());
+      return TT_OK;
+    }
     if (p->width > 40) return fail(TT_E_TOOBIG, "plan width %d exceeds 40 bits", p->width);
     p->max_dec = 16;
     partition_plan(*p);
@@ -1516,6 +1598,16 @@ int tt_plan_info(const tt_plan* plan, tt_plan_stats* out) {
   out->n_edges = p.m;
   out->width = p.width;
   out->n_ops = (int32_t)p.ops.size();
+  if (p.q == 3) {
+    const PottsCache* pc = static_cast<const PottsCache*>(p.potts);
+    out->n_passes = (int32_t)pc->e.passes.size();
+    out->n_count_passes = (int32_t)pc->c.passes.size();
+    out->terms = pc->e.terms;
+    out->elementwise = pc->e.elementwise;
+    out->reduce_ops = std::pow(3.0, pc->e.red.n_live);
+    out->entry_updates = 2.0 * std::pow(3.0, p.width) * (double)pc->e.passes.size();
+    return TT_OK;
+  }
   out->n_passes = (int32_t)p.passes.size();
   out->n_count_passes = (int32_t)p.count_passes.size();
   out->terms = p.terms;
@@ -1558,6 +1650,20 @@ int tt_plan_ops(const tt_plan* plan, int32_t* out, int64_t cap, int32_t* final_s
 int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t cap) {
   if (!plan) return fail(TT_E_INVAL, "null plan");
   const Plan& p = *reinterpret_cast<const Plan*>(plan);
+  if (p.q == 3) {
+    const PottsCache* pc = static_cast<const PottsCache*>(p.potts);
+    const void* src = nullptr;
+    int64_t bytes = 0;
+    switch (which) {
+      case 7: src = pc->e.passes.data(); bytes = (int64_t)(pc->e.passes.size() * sizeof(PottsPass)); break;
+      case 8: src = pc->c.passes.data(); bytes = (int64_t)(pc->c.passes.size() * sizeof(PottsPass)); break;
+      case 9: src = &pc->e.red; bytes = (int64_t)sizeof(PottsReduce); break;
+      default: return fail(TT_E_INVAL, "program part %d does not exist for 3-state plans (7, 8, 9)", which);
+    }
+    if (out && bytes) std::memcpy(out, src, (size_t)std::min(bytes, cap));
+    return bytes;
+  }
+  if (which >= 7) return fail(TT_E_INVAL, "program parts 7-9 exist for 3-state plans only");
   EnergyProgram ep;
   const std::string err = encode_energy(p, p.passes, ep);
   if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
@@ -1590,6 +1696,7 @@ void tt_plan_destroy(tt_plan* plan) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   delete static_cast<DevCache*>(p->dev);
   drop_host_prog(*p);
+  delete static_cast<PottsCache*>(p->potts);
   delete p;
 }
 
@@ -1740,6 +1847,135 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
   }
 }
 
+int tt_potts_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, double* energy, void* stream) {
+  try {
+    if (int r = potts_common(plan, batch, dtype, J)) return r;
+    if (!energy) return fail(TT_E_INVAL, "null energy");
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    PottsCache* pc = nullptr;
+    if (int r = potts_ensure(p, pc, true)) return r;
+    const int64_t sst = (int64_t)std::llround(std::pow(3.0, p.width));
+    const int64_t need = (int64_t)batch * sst * (int64_t)sizeof(float);
+    if (int r = early_budget(p, need)) return r;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    PendingCheck chk;
+    CheckItem ci = check_item(J, nullptr, p.m, p.n, batch, dtype);
+    ci.limit = POTTS_EXACT;
+    if (int r = check_start({ci}, s, &chk)) return r;
+    int rc = 0;
+    do {
+      if (need > (int64_t)pc->state.cap && need > budget_bytes(p) + (int64_t)pc->state.cap) {
+        rc = fail(TT_E_TOOBIG, "plan needs %lld bytes of device state (budget %lld)", (long long)need,
+                  (long long)budget_bytes(p));
+        break;
+      }
+      if ((rc = pc->state.ensure((size_t)need))) break;
+      const int64_t combos = pc->e.red.combos;
+      const int64_t chunks = (combos + potts_reduce_chunk(combos) - 1) / potts_reduce_chunk(combos);
+      if ((rc = pc->part.ensure((size_t)(batch * chunks) * (sizeof(float) + 4 * sizeof(uint64_t))))) break;
+      float* x = static_cast<float*>(pc->state.p);
+      uint64_t* pn = static_cast<uint64_t*>(pc->part.p);
+      float* pv = reinterpret_cast<float*>(pn + (size_t)batch * chunks * 4);
+      const PottsPass* dp = static_cast<const PottsPass*>(pc->d_e.p);
+      for (size_t q = 0; q < pc->e.passes.size() && !rc; ++q) {
+        ProfScope ps(s, "potts_pass");
+        const hipError_t e = launch_potts_pass(dp + q, pc->e.passes[q].t, pc->e.passes[q].threads, J, p.m, dtype, x,
+                                               nullptr, 0, sst, batch, s);
+        if (e != hipSuccess) rc = fail(TT_E_DEVICE, "potts pass launch: %s", hipGetErrorString(e));
+      }
+      if (rc) break;
+      ProfScope ps(s, "potts_reduce");
+      const hipError_t e = launch_potts_reduce(static_cast<const PottsReduce*>(pc->d_red.p), combos, x, nullptr, 0, sst,
+                                               batch, pv, pn, energy, nullptr, nullptr, s);
+      if (e != hipSuccess) rc = fail(TT_E_DEVICE, "potts reduction launch: %s", hipGetErrorString(e));
+    } while (false);
+    return check_end(rc, chk, dtype);
+  } catch (const std::bad_alloc&) {
+    return fail(TT_E_NOMEM, "out of host memory");
+  } catch (...) {
+    return fail(TT_E_INVAL, "unexpected failure");
+  }
+}
+
+int tt_potts_count(tt_plan* plan, int32_t batch, const int32_t* J, int64_t* energy2, uint64_t* residues,
+                   uint8_t* exact_flag, void* stream) {
+  try {
+    if (int r = potts_common(plan, batch, TT_I32, J)) return r;
+    if (!energy2 || !residues) return fail(TT_E_INVAL, "null output");
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    PottsCache* pc = nullptr;
+    if (int r = potts_ensure(p, pc, true)) return r;
+    // g <= 3^n < 2^183 for n <= 115: the three primes give g exactly;
+    // beyond, a fourth plane modulo 2^64 checks the CRT value
+    const int nres = p.n > 115 ? 4 : 3;
+    const int64_t sst = (int64_t)std::llround(std::pow(3.0, p.width));
+    const size_t xb = ((size_t)batch * sst * sizeof(float) + 255) & ~size_t(255);   // x plane, then nres planes
+    const int64_t need = (int64_t)(xb + (size_t)batch * sst * nres * sizeof(uint64_t));
+    if (int r = early_budget(p, need)) return r;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+      std::vector<int32_t> hj((size_t)batch * p.m);
+      if (p.m) HIP_TRY(hipMemcpyAsync(hj.data(), J, hj.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (int b = 0; b < batch; ++b) {
+        int64_t S = 0;
+        for (int64_t e = 0; e < p.m; ++e) S += std::llabs((long long)hj[(size_t)b * p.m + e]);
+        if (S >= POTTS_EXACT)
+          return fail(TT_E_RANGE, "instance %d: 2 sum|J| = %lld needs more than 24 bits", b, (long long)(2 * S));
+      }
+    }
+    if (need > (int64_t)pc->cstate.cap && need > budget_bytes(p) + (int64_t)pc->cstate.cap)
+      return fail(TT_E_TOOBIG, "count path needs %lld bytes of device state (budget %lld)", (long long)need,
+                  (long long)budget_bytes(p));
+    if (int r = pc->cstate.ensure((size_t)need)) return r;
+    const int64_t combos = pc->c.red.combos;
+    const int64_t chunks = (combos + potts_reduce_chunk(combos) - 1) / potts_reduce_chunk(combos);
+    const size_t pbytes = (size_t)(batch * chunks) * (sizeof(float) + 4 * sizeof(uint64_t)) +
+                          (size_t)batch * 5 * sizeof(uint64_t);
+    if (int r = pc->part.ensure(pbytes)) return r;
+    float* x = static_cast<float*>(pc->cstate.p);
+    uint64_t* n = reinterpret_cast<uint64_t*>(static_cast<char*>(pc->cstate.p) + xb);
+    uint64_t* pn = static_cast<uint64_t*>(pc->part.p);
+    uint64_t* res = pn + (size_t)batch * chunks * 4;
+    int64_t* en = reinterpret_cast<int64_t*>(res + (size_t)batch * 4);
+    float* pv = reinterpret_cast<float*>(en + batch);
+    const PottsPass* dp = static_cast<const PottsPass*>(pc->d_c.p);
+    for (size_t q = 0; q < pc->c.passes.size(); ++q) {
+      ProfScope ps(s, "potts_count_pass");
+      HIP_TRY(launch_potts_pass(dp + q, pc->c.passes[q].t, pc->c.passes[q].threads, J, p.m, TT_I32, x, n, nres, sst,
+                                batch, s));
+    }
+    {
+      ProfScope ps(s, "potts_count_reduce");
+      HIP_TRY(launch_potts_reduce(static_cast<const PottsReduce*>(pc->d_red.p), combos, x, n, nres, sst, batch, pv,
+                                  pn, nullptr, en, res, s));
+    }
+    std::vector<uint64_t> r4((size_t)batch * 4);
+    HIP_TRY(hipMemcpyAsync(energy2, en, (size_t)batch * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(r4.data(), res, r4.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int inexact = -1;
+    for (int b = 0; b < batch; ++b) {
+      for (int r = 0; r < 3; ++r) residues[(size_t)b * 3 + r] = r4[(size_t)b * 4 + r];
+      bool exact = true;
+      if (nres == 4) {
+        uint32_t limbs[8];
+        crt_limbs(&r4[(size_t)b * 4], limbs);
+        exact = (((uint64_t)limbs[1] << 32) | limbs[0]) == r4[(size_t)b * 4 + 3];
+      }
+      if (exact_flag) exact_flag[b] = exact ? 1 : 0;
+      if (!exact && inexact < 0) inexact = b;
+    }
+    if (!exact_flag && inexact >= 0)
+      return fail(TT_E_COUNT_OVERFLOW, "instance %d: the degeneracy reaches the product of the moduli (~2^183)",
+                  inexact);
+    return TT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(TT_E_NOMEM, "out of host memory");
+  } catch (...) {
+    return fail(TT_E_INVAL, "unexpected failure");
+  }
+}
 
 int tt_count_moduli(uint64_t moduli_out[3]) {
   if (!moduli_out) return fail(TT_E_INVAL, "null argument");

@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "device.hpp"
+#include "potts.hpp"
 
 namespace tt {
 
@@ -34,6 +35,19 @@ int count_reduce_log2_chunks(int w);
 hipError_t launch_count_reduce(const float* x, const uint64_t* nplanes, int64_t sst, int w, uint64_t free_mask,
                                int batch, int nres, float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues,
                                hipStream_t stream);
+
+// 3-state Potts sweep: one pass over `batch` instances of 3^W entries (sst)
+// in place; n == nullptr: energy only, else nres residue planes of
+// batch * sst entries each
+hipError_t launch_potts_pass(const PottsPass* pass, int t, int64_t threads, const void* J, int64_t jst, int dtype,
+                             float* x, uint64_t* n, int nres, int64_t sst, int batch, hipStream_t s);
+int64_t potts_reduce_chunk(int64_t combos);
+// final maximum (and count): energy H* (double), energy2 2H* (int64), res
+// [batch][4] residues; each output may be null; pv / pn hold batch * chunks
+// partials (chunks from potts_reduce_chunk)
+hipError_t launch_potts_reduce(const PottsReduce* red, int64_t combos, const float* x, const uint64_t* n, int nres,
+                               int64_t sst, int batch, float* pv, uint64_t* pn, double* energy, int64_t* energy2,
+                               uint64_t* res, hipStream_t s);
 
 // workspace of the allocation-free contraction: its size, and the current
 // device's address of it

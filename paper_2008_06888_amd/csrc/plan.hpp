@@ -130,6 +130,8 @@ struct Plan {
   ChimeraInfo chim;
   void* dev = nullptr;               // device-side cache (owned, see capi)
   void* host_prog = nullptr;         // host encoding of the energy passes (owned, see capi)
+  int32_t q = 2;                     // labels per spin: 2 (Ising) or 3 (Potts glass, App. C)
+  void* potts = nullptr;             // 3-label programs and device cache (owned, see capi)
   uint64_t serial = 0;               // unique over the process lifetime (never reused)
 };
 
