@@ -265,20 +265,35 @@ def potts_lattice(L: int, batch: int = 1, Lc: Optional[int] = None, coupling: st
             for b in range(batch)]
 
 
-def cubic_lattice(L: int) -> np.ndarray:
-    """Open L x L x L simple cubic lattice; spin (x, y, z) = (z L + y) L + x."""
+def cubic_lattice(Lx: int, Ly: Optional[int] = None, Lz: Optional[int] = None) -> np.ndarray:
+    """Open Lx x Ly x Lz simple cubic lattice (the paper's 3D lattices; Ly, Lz
+    default to Lx); spin (x, y, z) = (z Ly + y) Lx + x."""
+    Ly = Lx if Ly is None else Ly
+    Lz = Lx if Lz is None else Lz
     edges = []
-    for z in range(L):
-        for y in range(L):
-            for x in range(L):
-                i = (z * L + y) * L + x
-                if x + 1 < L:
+    for z in range(Lz):
+        for y in range(Ly):
+            for x in range(Lx):
+                i = (z * Ly + y) * Lx + x
+                if x + 1 < Lx:
                     edges.append((i, i + 1))
-                if y + 1 < L:
-                    edges.append((i, i + L))
-                if z + 1 < L:
-                    edges.append((i, i + L * L))
+                if y + 1 < Ly:
+                    edges.append((i, i + Lx))
+                if z + 1 < Lz:
+                    edges.append((i, i + Lx * Ly))
     return _canon(edges) if edges else np.zeros((0, 2), np.int32)
+
+
+def cubic_instances(Lx: int, Ly: Optional[int] = None, Lz: Optional[int] = None, batch: int = 1,
+                    coupling: str = "pm1", field_std: Optional[float] = None, seed: int = 6) -> List[Instance]:
+    """Ising instances on an open cubic lattice; instance b drawn from
+    ``default_rng([seed, Lx, Ly, Lz, b])``."""
+    Ly = Lx if Ly is None else Ly
+    Lz = Lx if Lz is None else Lz
+    e = cubic_lattice(Lx, Ly, Lz)
+    n = Lx * Ly * Lz
+    return [make(e, n, np.random.default_rng([seed, Lx, Ly, Lz, b]), coupling, field_std=field_std,
+                 name=f"cubic{Lx}x{Ly}x{Lz}_{coupling}_{b}") for b in range(batch)]
 
 
 def planted(edges: np.ndarray, n: int, rng: np.random.Generator, coupling: str = "pm1"):
