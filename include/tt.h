@@ -166,6 +166,47 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
                 const void* h, double* energy, int8_t* sigma, float* dJ,
                 float* dh, void* stream);
 
+/* tt_backward with a choice of tie rule (Sec. IV: max returns its first
+ * argument when two are equal; other rules reach other degenerate ground
+ * states): tie = 0 is tt_backward (the first maximiser at every choice), 1
+ * the last, any other value a pseudo-random order per pass seeded by it. The
+ * rule applies to every spin the walk chooses; spins still held by the final
+ * state keep the lowest address of the final maximum. Every rule returns a
+ * ground state. Sweep plans only (chimera plans: TT_E_INVAL for tie != 0). */
+int tt_backward_tie(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
+                    const void* h, double* energy, int8_t* sigma, float* dJ,
+                    float* dh, uint64_t tie, void* stream);
+
+/* One ground state by finite differences of E* with respect to the fields
+ * (Sec. IV, the first way it names: E* is piecewise linear in h, and
+ * E*(h + delta e_i) = E* - delta sigma_i while the ground state does not
+ * change): the n + 1 copies of the instance (unperturbed, and h_i raised by
+ * delta for each spin i) are contracted as one batch. float32 couplings and
+ * fields, one instance; the plan must carry fields (h may be NULL for zero
+ * fields). J: device float [n_edges]; h: device float [n_spins] or NULL;
+ * energy: device double [1] = E*; sigma: device int8 [n_spins].
+ * consistent (host, may be NULL; then the call does not wait): 1 when
+ * Eq. (1) of sigma equals E* within 1e-5 n_spins, i.e. the ground state is
+ * unique at the resolution of delta (delta must stay below half the gap to
+ * the first excited state and well above the float32 rounding of E*). */
+int tt_config_fd(tt_plan* plan, const float* J, const float* h, double delta,
+                 double* energy, int8_t* sigma, uint8_t* consistent, void* stream);
+
+/* A ground state drawn uniformly at random from all of them (Sec. IV, the
+ * second way it names: conditional probabilities along an order of the
+ * spins): for spin k = 0, 1, ... the degeneracies of the ground states with
+ * the spins before it fixed as already drawn and sigma_k = +1 or -1 come from
+ * the counting contraction (spins fixed by fields H > sum|J| + sum|h|), and
+ * sigma_k = +1 is taken when u[k] (c+ + c-) < c+ (exact integer arithmetic
+ * on the counts). int32 couplings; one instance; the plan must carry fields.
+ * J: device int32 [n_edges]; h: device int32 [n_spins] or NULL; u: host
+ * double [n_spins] in [0, 1) (the caller's random numbers); sigma: host int8
+ * [n_spins]; energy: host int64 E*. Runs n_spins + 1 counting contractions
+ * and synchronises `stream`. TT_E_RANGE when sum|J| + sum|h| + n H >= 2^24. */
+int tt_sample_ground_state(tt_plan* plan, const int32_t* J, const int32_t* h,
+                           const double* u, int8_t* sigma, int64_t* energy,
+                           void* stream);
+
 /* Ground-state energy and degeneracy g (Eq. 4: tuples (x, n), n an ordinary
  * count) for integer couplings. J: device int32 [batch][n_edges]; h: device
  * int32 [batch][n_spins] or NULL. energy: host int64 [batch]; residues: host
@@ -210,6 +251,11 @@ int tt_count_moduli(uint64_t moduli_out[3]);
 /* Exact g from its residues by the Chinese remainder theorem, as a decimal
  * string (host). Exact whenever g < the product of the moduli (~2^183). */
 int tt_count_to_decimal(const uint64_t residues[3], char* buf, size_t len);
+
+/* Natural logarithm of g from its residues (for the residual entropy
+ * s = ln g / n_spins of Sec. V), from the exact CRT value; relative error
+ * below 1e-15. TT_E_INVAL for g = 0 or unreduced residues. */
+int tt_count_log(const uint64_t residues[3], double* log_g);
 
 /* Uneven batch: n_inst instances, each with its own plan, contracted forward
  * and backward together (one launch per pass index across instances).
@@ -271,7 +317,8 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
  * capture or replay); tt_prof_read returns the summed milliseconds and
  * launch count of the named kernel family ("sweep_pass", "sweep_backward",
  * "final_reduce", "count_pass", "count_reduce", "count_chain", "chain",
- * "row_argmax", "chimera_finish", "tgemm") since the last reset. Timing adds
+ * "row_argmax", "chimera_finish", "tgemm", "check_inputs", "potts_pass",
+ * "potts_reduce", "potts_count_pass", "potts_count_reduce") since the last reset. Timing adds
  * no work to the launches themselves. */
 int tt_prof_enable(int32_t on);
 int tt_prof_reset(void);

@@ -38,7 +38,8 @@ EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy",
            "tt_backward", "tt_count", "tt_count_moduli", "tt_count_to_decimal", "tt_contract_uneven",
            "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops",
            "tt_plan_program", "tt_graphs_enable", "tt_tgemm", "tt_plan_autotune", "tt_contract_noalloc",
-           "tt_potts_contract", "tt_potts_count")
+           "tt_potts_contract", "tt_potts_count", "tt_backward_tie", "tt_config_fd",
+           "tt_sample_ground_state", "tt_count_log")
 
 
 class PlanOpts(C.Structure):
@@ -69,6 +70,10 @@ _lib.tt_contract.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
 _lib.tt_contract_noalloc.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
 _lib.tt_backward.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_count.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tt_backward_tie.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, C.c_uint64, _vp]
+_lib.tt_config_fd.argtypes = [_vp, _vp, _vp, C.c_double, _vp, _vp, _vp, _vp]
+_lib.tt_sample_ground_state.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tt_count_log.argtypes = [_vp, _vp]
 _lib.tt_potts_contract.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp]
 _lib.tt_potts_count.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_count_moduli.argtypes = [_vp]
@@ -196,6 +201,14 @@ def residues_to_int(res) -> int:
 # compute calls (torch tensors on the current HIP device)
 # ---------------------------------------------------------------------------
 
+def count_log(res) -> float:
+    """ln g from the three residues of a count (the residual entropy is ln g / n)."""
+    r = np.ascontiguousarray(np.asarray(res, dtype=np.uint64).reshape(3))
+    out = C.c_double()
+    _check(_lib.tt_count_log(r.ctypes.data, C.byref(out)))
+    return out.value
+
+
 def _torch():
     import torch
     return torch
@@ -253,6 +266,51 @@ def contract_noalloc(plan: Plan, J, h=None, out=None):
         raise ValueError("out must be a contiguous device float64 tensor of at least batch entries")
     _check(_lib.tt_contract_noalloc(plan.handle, B, _dtype_code(J), _ptr(J), _ptr(h), _ptr(energy), _stream()))
     return energy[:B]
+
+
+def backward_tie(plan: Plan, J, h=None, tie: int = 1, want_grad: bool = True):
+    """tt_backward with another tie rule (1: the last maximiser, other: pseudo-random per pass)."""
+    torch = _torch()
+    _check_inputs(plan, J, h)
+    B = J.shape[0]
+    dev = J.device
+    energy = torch.empty(B, dtype=torch.float64, device=dev)
+    sigma = torch.empty(B, plan.n, dtype=torch.int8, device=dev)
+    dJ = torch.empty(B, plan.m, dtype=torch.float32, device=dev) if want_grad else None
+    dh = torch.empty(B, plan.n, dtype=torch.float32, device=dev) if (want_grad and plan.has_field) else None
+    _check(_lib.tt_backward_tie(plan.handle, B, _dtype_code(J), _ptr(J), _ptr(h), _ptr(energy), _ptr(sigma),
+                                _ptr(dJ), _ptr(dh), int(tie), _stream()))
+    return energy, sigma, dJ, dh
+
+
+def config_fd(plan: Plan, J, h=None, delta: float = 2.0 ** -5):
+    """(E*, sigma, consistent) of one float32 instance by finite differences of the fields."""
+    torch = _torch()
+    if J.dim() != 1 or J.dtype != torch.float32 or not J.is_cuda or J.shape[0] != plan.m:
+        raise ValueError(f"J must be a device float32 tensor [{plan.m}]")
+    if h is not None and (h.dim() != 1 or h.dtype != torch.float32 or h.shape[0] != plan.n):
+        raise ValueError(f"h must be a device float32 tensor [{plan.n}]")
+    energy = torch.empty(1, dtype=torch.float64, device=J.device)
+    sigma = torch.empty(plan.n, dtype=torch.int8, device=J.device)
+    ok = C.c_uint8(0)
+    _check(_lib.tt_config_fd(plan.handle, _ptr(J), _ptr(h), float(delta), _ptr(energy), _ptr(sigma),
+                             C.byref(ok), _stream()))
+    return energy, sigma, bool(ok.value)
+
+
+def sample_ground_state(plan: Plan, J, h=None, u=None):
+    """(E*, sigma int8 numpy [n]) drawn uniformly from the ground states; u: n numbers in [0, 1)."""
+    torch = _torch()
+    if J.dim() != 1 or J.dtype != torch.int32 or not J.is_cuda or J.shape[0] != plan.m:
+        raise ValueError(f"J must be a device int32 tensor [{plan.m}]")
+    u = np.ascontiguousarray(np.asarray(u, dtype=np.float64))
+    if u.shape != (plan.n,):
+        raise ValueError(f"u must hold {plan.n} numbers")
+    sigma = np.zeros(plan.n, np.int8)
+    energy = C.c_int64(0)
+    _check(_lib.tt_sample_ground_state(plan.handle, _ptr(J), _ptr(h), u.ctypes.data, sigma.ctypes.data,
+                                       C.byref(energy), _stream()))
+    return energy.value, sigma
 
 
 def _check_potts(plan: Plan, J):

@@ -216,6 +216,7 @@ struct DevCache {
   std::vector<int> chain_after, count_chain_after;   // pass -> chimera row whose chain follows, -1
   DevBuf state, ckpt, arg, part_v, part_i;
   DevBuf cx, cn, cpart;
+  DevBuf fd, samp;   // perturbed batches of the re-running configuration paths
 };
 
 // 3-state plans: host programs (energy tiles of four digits, counting tiles
@@ -768,6 +769,7 @@ struct Group {
   // parts overlap across passes of different widths.
   std::vector<int64_t> part_st;
   uint64_t* arg = nullptr;
+  uint64_t tie = 0;   // tie rule of the backward walk (see BwdItem)
 };
 
 // Points the group at the program in its plan's device cache.
@@ -860,8 +862,11 @@ int64_t red_parts_needed(const std::vector<Group>& groups, bool fused) {
 }
 
 // pv / pi: the partial buffers, needed when `fuse` (the last passes write them).
+// Launch tables of a call: forward passes q_begin .. q_end - 1 (one launch per
+// pass index across groups and tile size), the final reduction (with_red),
+// and with `backward` the argmax walk of every instance over the whole plan.
 void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, CallTables& ct, bool fuse,
-                  float* pv, uint64_t* pi) {
+                  float* pv, uint64_t* pi, int q_begin = 0, int q_end = INT32_MAX, bool with_red = true) {
   ct.fused = fuse;
   int max_np = 0;
   for (Group& g : groups) max_np = std::max(max_np, (int)g.ep->passes.size());
@@ -875,7 +880,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
     }
   }
   const size_t MAXI = 32;   // items per launch
-  for (int q = 0; q < max_np; ++q) {
+  for (int q = q_begin; q < std::min(max_np, q_end); ++q) {
     std::vector<PassItem> items;
     int64_t wg = 0;
     int threads = 64;
@@ -937,6 +942,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
   }
   std::vector<RedItem> red;
   for (Group& g : groups) {
+    if (!with_red) break;
     const int fw = g.p->final_w;
     const int lc = red_log2_parts(g, fuse);
     const int np = (int)g.ep->passes.size();
@@ -961,7 +967,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
     const int np = (int)g.dc->ep.passes.size();
     for (int b = 0; b < g.batch; ++b) {
       ct.ckpt_first.push_back(ptrs.size());
-      for (int q = 0; q < np; ++q) ptrs.push_back(g.bufs[q] + (int64_t)b * g.strides[q]);
+      for (int q = 0; q < np; ++q) ptrs.push_back(g.bufs[q] ? g.bufs[q] + (int64_t)b * g.strides[q] : nullptr);
     }
   }
   ct.ckpt_off = ct.blob.add(ptrs.data(), ptrs.size());
@@ -991,6 +997,9 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
       it.n_passes = np;
       it.final_w = g.p->final_w;
       it.n = g.p->n;
+      it.seg_lo = 0;
+      it.seg_hi = np - 1;
+      it.tie = g.tie;
       if (fuse) {
         const RedItem& r = red[bwd.size()];
         it.red_v = pv + r.chunk_begin;
@@ -1021,7 +1030,7 @@ int enqueue_launches(const CallTables& ct, const char* dev, float* pv, uint64_t*
                         ps.start(), ps.stop()));
     ps.launched();
   }
-  if (!ct.bwd_ranks) {
+  if (!ct.bwd_ranks && ct.n_red > 0) {
     ProfScope ps(s, "final_reduce");
     HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks, pv, pi, s,
                           ct.fused));
@@ -1085,6 +1094,7 @@ std::vector<uint64_t> call_key(const std::vector<Group>& groups, int32_t dtype, 
   for (const Group& g : groups) {
     k.push_back(plan_serial(g.p));
     k.push_back((uint64_t)g.batch);
+    k.push_back(g.tie);
     P(g.dc);
     P(g.J);
     P(g.h);
@@ -1238,9 +1248,196 @@ int run_split(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   return 0;
 }
 
+// ----------------------------------------------------------------------------
+// Backward with recomputation (Sec. IV: trading time for memory by
+// checkpointing). When the input of every pass does not fit the budget, the
+// call keeps K snapshots of pass inputs plus two working states (all of the
+// widest pass's size): the forward sweep stores the inputs of K evenly spaced
+// passes; the walk then goes down segment by segment (last first), each
+// segment recomputing what it needs from its snapshot: all its pass inputs
+// when the free snapshots hold them (one walk launch over the segment), else
+// the same split recursively with the snapshots left, and with none left one
+// pass at a time, each recomputed from the segment's start. The walk carries
+// its state between segment launches (selected entry, spins chosen so far)
+// and is the same computation as the single walk, so sigma is identical.
+// ----------------------------------------------------------------------------
+struct Recompute {
+  Group g;                     // prepared: program bound, outputs, arg / carry words
+  int np = 0;
+  int32_t dtype = 0;
+  hipStream_t s = nullptr;
+  std::vector<float*> spare;   // free snapshot buffers
+  float* work[2] = {nullptr, nullptr};
+  uint64_t* carry = nullptr;
+  float* pv = nullptr;
+  uint64_t* pi = nullptr;
+
+  Group with_bufs(const std::vector<float*>& bufs) const {
+    Group h = g;
+    h.bufs = bufs;
+    return h;
+  }
+
+  // Passes a .. c-1 (input of pass a in `in_a`; pass 0 starts from zero):
+  // the input of every pass q in (a, c] goes to store[q] when given, else to a
+  // working state; *out receives the buffer holding the input of pass c.
+  int fwd(int a, int c, const std::map<int, float*>& store, float* in_a, float** out, bool reduce) {
+    std::vector<float*> bufs(np + 1, nullptr);
+    float* src = in_a ? in_a : work[1];
+    bufs[a] = src;
+    for (int q = a + 1; q <= c; ++q) {
+      auto it = store.find(q);
+      float* dst = it != store.end() ? it->second : (src == work[0] ? work[1] : work[0]);
+      bufs[q] = dst;
+      src = dst;
+    }
+    if (out) *out = src;
+    std::vector<Group> gs(1, with_bufs(bufs));
+    CallTables ct;
+    build_tables(gs, dtype, false, ct, false, pv, pi, a, c, reduce);
+    return stage_and_enqueue(ct, pv, pi, dtype, s);
+  }
+
+  // The walk over passes lo .. hi (inputs in `in`, indexed by pass).
+  int walk(int lo, int hi, const std::vector<float*>& in) {
+    std::vector<Group> gs(1, with_bufs(in));
+    CallTables ct;
+    build_tables(gs, dtype, true, ct, false, pv, pi, 0, 0, false);
+    BwdItem* bi = reinterpret_cast<BwdItem*>(ct.blob.bytes.data() + ct.bwd_off);
+    for (int k = 0; k < ct.n_bwd; ++k) {
+      bi[k].seg_lo = lo;
+      bi[k].seg_hi = hi;
+      bi[k].carry = carry + k;
+    }
+    return stage_and_enqueue(ct, pv, pi, dtype, s);
+  }
+
+  // Walks passes a .. b-1 given the input of pass a in `in_a` (none for pass 0).
+  int reverse(int a, int b, float* in_a) {
+    const int L = b - a;
+    std::vector<float*> in(np + 1, nullptr);
+    in[a] = in_a;
+    if (L - 1 <= (int)spare.size()) {   // every input of the segment fits
+      std::map<int, float*> store;
+      std::vector<float*> taken;
+      for (int q = a + 1; q < b; ++q) {
+        taken.push_back(spare.back());
+        spare.pop_back();
+        store[q] = in[q] = taken.back();
+      }
+      if (L > 1)
+        if (int r = fwd(a, b - 1, store, in_a, nullptr, false)) return r;
+      if (int r = walk(a, b - 1, in)) return r;
+      spare.insert(spare.end(), taken.begin(), taken.end());
+      return 0;
+    }
+    if (spare.empty()) {   // one pass at a time, each recomputed from pass a
+      for (int p = b - 1; p >= a; --p) {
+        float* buf = in_a;
+        if (p > a)
+          if (int r = fwd(a, p, {}, in_a, &buf, false)) return r;
+        std::vector<float*> one(np + 1, nullptr);
+        one[p] = buf;
+        if (int r = walk(p, p, one)) return r;
+      }
+      return 0;
+    }
+    // split into k + 1 segments at k snapshots, walk them last first
+    const int k = std::min((int)spare.size(), L - 1);
+    std::vector<int> cut(k + 2);
+    cut[0] = a;
+    cut[k + 1] = b;
+    for (int j = 1; j <= k; ++j) cut[j] = a + (int)((int64_t)j * L / (k + 1));
+    std::vector<float*> snap(k + 1, nullptr);
+    snap[0] = in_a;
+    std::map<int, float*> store;
+    for (int j = 1; j <= k; ++j) {
+      snap[j] = spare.back();
+      spare.pop_back();
+      store[cut[j]] = snap[j];
+    }
+    if (int r = fwd(a, cut[k], store, in_a, nullptr, false)) return r;
+    for (int j = k; j >= 0; --j) {
+      if (int r = reverse(cut[j], cut[j + 1], snap[j])) return r;
+      if (j > 0) spare.push_back(snap[j]);
+    }
+    return 0;
+  }
+};
+
+// Bytes of one state of the widest pass for the batch (256-byte aligned).
+size_t widest_state(const Plan& p, int64_t batch) {
+  return (((size_t)batch << p.width) * sizeof(float) + 255) & ~size_t(255);
+}
+
+int run_backward_recompute(Group& g0, int32_t dtype, hipStream_t s) {
+  Plan& p = *g0.p;
+  if (int r = ensure_device(p, g0.dc)) return r;
+  bind_program(g0);
+  DevCache* dc = g0.dc;
+  const int np = (int)g0.ep->passes.size();
+  const size_t per = widest_state(p, g0.batch);
+  const int64_t budget = budget_bytes(p) + (int64_t)dc->ckpt.cap;
+  const int64_t nbuf = std::min<int64_t>(budget / (int64_t)per, np + 1);
+  if (nbuf < 2)
+    return fail(TT_E_TOOBIG, "the backward needs at least two states of %zu bytes (budget %lld)", per,
+                (long long)budget);
+  if (int r = dc->ckpt.ensure((size_t)nbuf * per)) return r;
+  char* base = static_cast<char*>(dc->ckpt.p);
+  Recompute R;
+  R.np = np;
+  R.dtype = dtype;
+  R.s = s;
+  R.work[0] = reinterpret_cast<float*>(base);
+  R.work[1] = reinterpret_cast<float*>(base + per);
+  for (int64_t k = 2; k < nbuf; ++k) R.spare.push_back(reinterpret_cast<float*>(base + (size_t)k * per));
+  if (int r = dc->arg.ensure((size_t)g0.batch * 2 * sizeof(uint64_t))) return r;
+  g0.arg = static_cast<uint64_t*>(dc->arg.p);
+  R.carry = g0.arg + g0.batch;
+  g0.strides.assign(np + 1, 0);
+  for (int q = 0; q <= np; ++q)
+    g0.strides[q] = (int64_t)1 << (q < np ? g0.ep->passes[q].in_w : g0.ep->passes[np - 1].out_w);
+  g0.part_st = g0.strides;
+  std::vector<Group> gs(1, g0);
+  const int64_t nparts = red_parts_needed(gs, false);
+  if (int r = dc->part_v.ensure((size_t)nparts * sizeof(float))) return r;
+  if (int r = dc->part_i.ensure((size_t)nparts * sizeof(uint64_t))) return r;
+  R.pv = static_cast<float*>(dc->part_v.p);
+  R.pi = static_cast<uint64_t*>(dc->part_i.p);
+  R.g = g0;
+  // the whole forward sweep with snapshots of K evenly spaced pass inputs and
+  // the final maximum (energy, selected final address)
+  const int k = std::min((int)R.spare.size(), np - 1);
+  std::vector<int> cut(k + 2);
+  cut[0] = 0;
+  cut[k + 1] = np;
+  for (int j = 1; j <= k; ++j) cut[j] = (int)((int64_t)j * np / (k + 1));
+  std::vector<float*> snap(k + 1, nullptr);
+  std::map<int, float*> store;
+  for (int j = 1; j <= k; ++j) {
+    snap[j] = R.spare.back();
+    R.spare.pop_back();
+    store[cut[j]] = snap[j];
+  }
+  if (int r = R.fwd(0, np, store, nullptr, nullptr, true)) return r;
+  for (int j = k; j >= 0; --j) {
+    if (int r = R.reverse(cut[j], cut[j + 1], snap[j])) return r;
+    if (j > 0) R.spare.push_back(snap[j]);
+  }
+  return 0;
+}
+
 // Forward passes (one launch per pass index across groups), the final
 // reduction and, with `backward`, the argmax-routing walk.
 int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStream_t s) {
+  // a same-graph backward whose pass inputs do not all fit recomputes them
+  if (backward && groups.size() == 1 && !groups[0].p->is_chimera) {
+    const Plan& p = *groups[0].p;
+    const int64_t need = state_bytes(p, groups[0].batch, true);
+    const DevCache* dc = static_cast<const DevCache*>(p.dev);
+    const int64_t have = dc ? (int64_t)dc->ckpt.cap : 0;
+    if (need > have && need > budget_bytes(p) + have) return run_backward_recompute(groups[0], dtype, s);
+  }
   for (Group& g : groups)
     if (int r = prepare_group(g, backward)) return r;
   const bool large = large_call(groups);
@@ -1499,6 +1696,45 @@ void crt_limbs(const uint64_t res[3], uint32_t limbs[8]) {
 }
 
 static_assert(NOALLOC_SCRATCH_BYTES == (size_t)TT_NOALLOC_MAX_BYTES, "workspace size differs from the header's");
+
+// Little-endian 32-bit limbs: a * k (k < 2^53) and a + b, a < b.
+std::vector<uint32_t> big_mul(const std::vector<uint32_t>& a, uint64_t k) {
+  std::vector<uint32_t> out(a.size() + 3, 0);
+  const uint64_t kl[2] = {k & 0xffffffffull, k >> 32};
+  for (int part = 0; part < 2; ++part) {
+    uint64_t carry = 0;
+    for (size_t i = 0; i < a.size() || carry; ++i) {
+      const uint64_t cur = (i < a.size() ? (uint64_t)a[i] * kl[part] : 0) + out[i + part] + carry;
+      out[i + part] = (uint32_t)cur;
+      carry = cur >> 32;
+    }
+  }
+  return out;
+}
+std::vector<uint32_t> big_add(std::vector<uint32_t> a, const std::vector<uint32_t>& b) {
+  if (a.size() < b.size()) a.resize(b.size(), 0);
+  a.push_back(0);
+  uint64_t carry = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const uint64_t cur = (uint64_t)a[i] + (i < b.size() ? b[i] : 0) + carry;
+    a[i] = (uint32_t)cur;
+    carry = cur >> 32;
+  }
+  return a;
+}
+bool big_less(std::vector<uint32_t> a, std::vector<uint32_t> b) {
+  const size_t n = std::max(a.size(), b.size());
+  a.resize(n, 0);
+  b.resize(n, 0);
+  for (size_t i = n; i-- > 0;)
+    if (a[i] != b[i]) return a[i] < b[i];
+  return false;
+}
+bool big_zero(const std::vector<uint32_t>& a) {
+  for (uint32_t x : a)
+    if (x) return false;
+  return true;
+}
 
 // Spins up to which g <= 2^n stays below the product of the count primes.
 constexpr int COUNT_EXACT_SPINS = 182;
@@ -1821,13 +2057,19 @@ int tt_contract_noalloc(tt_plan* plan, int32_t batch, int32_t dtype, const void*
 
 int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, double* energy,
                 int8_t* sigma, float* dJ, float* dh, void* stream) {
+  return tt_backward_tie(plan, batch, dtype, J, h, energy, sigma, dJ, dh, 0, stream);
+}
+
+int tt_backward_tie(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, double* energy,
+                    int8_t* sigma, float* dJ, float* dh, uint64_t tie, void* stream) {
   try {
     if (int r = check_common(plan, batch, dtype, J, h)) return r;
     if (!sigma) return fail(TT_E_INVAL, "null sigma");
     Plan& p = *reinterpret_cast<Plan*>(plan);
     if (p.n_regs != 1) return fail(TT_E_INVAL, "backward over multi-register plans is not supported");
     if (p.n > 8192) return fail(TT_E_INVAL, "too many spins for the backward walk");
-    if (int r = early_budget(p, state_bytes(p, batch, true))) return r;
+    if (int r = early_budget(p, p.is_chimera ? state_bytes(p, batch, true) : 2 * (int64_t)widest_state(p, batch)))
+      return r;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     PendingCheck pc;
     if (int r = check_start({check_item(J, h, p.m, p.n, batch, dtype)}, s, &pc)) return r;
@@ -1840,6 +2082,8 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
     g[0].sigma = sigma;
     g[0].dJ = dJ;
     g[0].dh = dh;
+    g[0].tie = tie;
+    if (tie != 0 && p.is_chimera) return check_end(fail(TT_E_INVAL, "chimera plans walk with the first maximiser only"), pc, dtype);
     const int rc = p.is_chimera ? run_chimera(g[0], dtype, true, s) : run_groups(g, dtype, true, s);
     return check_end(rc, pc, dtype);
   } catch (...) {
@@ -1879,8 +2123,9 @@ int tt_potts_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J
       const PottsPass* dp = static_cast<const PottsPass*>(pc->d_e.p);
       for (size_t q = 0; q < pc->e.passes.size() && !rc; ++q) {
         ProfScope ps(s, "potts_pass");
-        const hipError_t e = launch_potts_pass(dp + q, pc->e.passes[q].t, pc->e.passes[q].threads, J, p.m, dtype, x,
-                                               nullptr, 0, sst, batch, s);
+        const PottsPass& H = pc->e.passes[q];
+        const hipError_t e = launch_potts_pass(dp + q, H.t, H.low != 0, H.threads, J, p.m, dtype, x, nullptr, 0, sst,
+                                               batch, s);
         if (e != hipSuccess) rc = fail(TT_E_DEVICE, "potts pass launch: %s", hipGetErrorString(e));
       }
       if (rc) break;
@@ -1942,8 +2187,8 @@ int tt_potts_count(tt_plan* plan, int32_t batch, const int32_t* J, int64_t* ener
     const PottsPass* dp = static_cast<const PottsPass*>(pc->d_c.p);
     for (size_t q = 0; q < pc->c.passes.size(); ++q) {
       ProfScope ps(s, "potts_count_pass");
-      HIP_TRY(launch_potts_pass(dp + q, pc->c.passes[q].t, pc->c.passes[q].threads, J, p.m, TT_I32, x, n, nres, sst,
-                                batch, s));
+      const PottsPass& H = pc->c.passes[q];
+      HIP_TRY(launch_potts_pass(dp + q, H.t, H.low != 0, H.threads, J, p.m, TT_I32, x, n, nres, sst, batch, s));
     }
     {
       ProfScope ps(s, "potts_count_reduce");
@@ -1969,6 +2214,126 @@ int tt_potts_count(tt_plan* plan, int32_t batch, const int32_t* J, int64_t* ener
     if (!exact_flag && inexact >= 0)
       return fail(TT_E_COUNT_OVERFLOW, "instance %d: the degeneracy reaches the product of the moduli (~2^183)",
                   inexact);
+    return TT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(TT_E_NOMEM, "out of host memory");
+  } catch (...) {
+    return fail(TT_E_INVAL, "unexpected failure");
+  }
+}
+
+// ---- configurations by re-running the forward contraction (Sec. IV) ------
+
+int tt_config_fd(tt_plan* plan, const float* J, const float* h, double delta, double* energy, int8_t* sigma,
+                 uint8_t* consistent, void* stream) {
+  try {
+    if (!plan) return fail(TT_E_INVAL, "null plan");
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    if (p.q != 2 || p.is_chimera) return fail(TT_E_INVAL, "finite differences need an Ising sweep plan");
+    if (!p.has_field) return fail(TT_E_INVAL, "the plan must carry fields (opts.has_field = 1)");
+    if ((p.m > 0 && !J) || !energy || !sigma) return fail(TT_E_INVAL, "null argument");
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(TT_E_INVAL, "delta must be positive and finite");
+    if (p.n + 1 > 65535) return fail(TT_E_INVAL, "too many spins for one perturbed batch");
+    DevCache* dc = nullptr;
+    if (int r = ensure_device(p, dc)) return r;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nb = p.n + 1;
+    const size_t jb = ((size_t)nb * p.m * sizeof(float) + 255) & ~size_t(255);
+    const size_t hb = ((size_t)nb * p.n * sizeof(float) + 255) & ~size_t(255);
+    if (int r = dc->fd.ensure(jb + hb + (size_t)nb * sizeof(double) + 64)) return r;
+    char* base = static_cast<char*>(dc->fd.p);
+    float* Jb = reinterpret_cast<float*>(base);
+    float* Hb = reinterpret_cast<float*>(base + jb);
+    double* E = reinterpret_cast<double*>(base + jb + hb);
+    double* e_sigma = E + nb;
+    HIP_TRY(launch_fd_build(J, h, p.m, p.n, (float)delta, Jb, Hb, s));
+    if (int r = tt_contract(plan, (int32_t)nb, TT_F32, Jb, Hb, E, stream)) return r;
+    HIP_TRY(launch_fd_sigma(E, J, h, static_cast<const int32_t*>(dc->d_edges.p), p.m, p.n, sigma, energy, e_sigma, s));
+    if (consistent) {
+      double hv[2];
+      HIP_TRY(hipMemcpyAsync(&hv[0], energy, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(&hv[1], e_sigma, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      *consistent = std::fabs(hv[0] - hv[1]) <= 1e-5 * p.n ? 1 : 0;
+    }
+    return TT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(TT_E_NOMEM, "out of host memory");
+  } catch (...) {
+    return fail(TT_E_INVAL, "unexpected failure");
+  }
+}
+
+
+int tt_sample_ground_state(tt_plan* plan, const int32_t* J, const int32_t* h, const double* u, int8_t* sigma,
+                           int64_t* energy, void* stream) {
+  try {
+    if (!plan) return fail(TT_E_INVAL, "null plan");
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    if (p.q != 2 || p.is_chimera) return fail(TT_E_INVAL, "sampling needs an Ising sweep plan");
+    if (!p.has_field) return fail(TT_E_INVAL, "the plan must carry fields (opts.has_field = 1) to clamp spins");
+    if ((p.m > 0 && !J) || !u || !sigma || !energy) return fail(TT_E_INVAL, "null argument");
+    for (int k = 0; k < p.n; ++k)
+      if (!(u[k] >= 0.0 && u[k] < 1.0)) return fail(TT_E_INVAL, "u[%d] is not in [0, 1)", k);
+    DevCache* dc = nullptr;
+    if (int r = ensure_device(p, dc)) return r;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int32_t> hj((size_t)p.m), hh((size_t)p.n, 0);
+    if (p.m) HIP_TRY(hipMemcpyAsync(hj.data(), J, hj.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (h) HIP_TRY(hipMemcpyAsync(hh.data(), h, hh.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t S = 0;
+    for (int32_t v : hj) S += std::llabs((long long)v);
+    for (int32_t v : hh) S += std::llabs((long long)v);
+    // a clamping field H > S makes every configuration that breaks a clamp
+    // costlier than any that keeps them, so the clamped instance's ground
+    // states are the ground states with the clamped spins fixed
+    const int64_t H = S + 1;
+    if (S + (int64_t)p.n * H >= (int64_t(1) << 24))
+      return fail(TT_E_RANGE, "sum|J| + sum|h| + n H = %lld needs more than 24 bits", (long long)(S + p.n * H));
+    const size_t jb = ((size_t)2 * p.m * sizeof(int32_t) + 255) & ~size_t(255);
+    if (int r = dc->samp.ensure(jb + (size_t)2 * p.n * sizeof(int32_t) + 64)) return r;
+    int32_t* Jb = static_cast<int32_t*>(dc->samp.p);
+    int32_t* Hb = reinterpret_cast<int32_t*>(static_cast<char*>(dc->samp.p) + jb);
+    if (p.m) {
+      HIP_TRY(hipMemcpyAsync(Jb, J, (size_t)p.m * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(Jb + p.m, J, (size_t)p.m * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    // E* of the instance itself
+    std::vector<int32_t> hrows((size_t)2 * p.n);
+    std::copy(hh.begin(), hh.end(), hrows.begin());
+    HIP_TRY(hipMemcpyAsync(Hb, hrows.data(), (size_t)p.n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    int64_t e2[2];
+    uint64_t res[6];
+    uint8_t ex[2];
+    if (int r = tt_count(plan, 1, Jb, Hb, e2, res, ex, stream)) return r;
+    if (!ex[0]) return fail(TT_E_COUNT_OVERFLOW, "the degeneracy reaches the product of the moduli");
+    const int64_t Estar = e2[0];
+    std::vector<int64_t> clamp((size_t)p.n, 0);   // H s_j of the spins fixed so far
+    for (int k = 0; k < p.n; ++k) {
+      for (int b = 0; b < 2; ++b)
+        for (int i = 0; i < p.n; ++i)
+          hrows[(size_t)b * p.n + i] = (int32_t)(hh[i] + clamp[i] + (i == k ? (b == 0 ? H : -H) : 0));
+      HIP_TRY(hipMemcpyAsync(Hb, hrows.data(), hrows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      if (int r = tt_count(plan, 2, Jb, Hb, e2, res, ex, stream)) return r;
+      std::vector<uint32_t> c[2];
+      for (int b = 0; b < 2; ++b) {
+        if (!ex[b]) return fail(TT_E_COUNT_OVERFLOW, "the degeneracy reaches the product of the moduli");
+        uint32_t limbs[8];
+        crt_limbs(res + 3 * b, limbs);
+        // the clamped spins contribute -H each to the clamped instance's energy
+        const bool ground = e2[b] + H * (int64_t)(k + 1) == Estar;
+        c[b] = ground ? std::vector<uint32_t>(limbs, limbs + 8) : std::vector<uint32_t>(8, 0);
+      }
+      const std::vector<uint32_t> tot = big_add(c[0], c[1]);
+      if (big_zero(tot)) return fail(TT_E_INVAL, "internal: no ground state below the clamped prefix");
+      // sigma_k = +1 with probability c+ / (c+ + c-): floor(u 2^53) (c+ + c-) < c+ 2^53
+      const uint64_t U = (uint64_t)std::ldexp(u[k], 53);
+      const bool plus = big_less(big_mul(tot, U), big_mul(c[0], 1ull << 53));
+      sigma[k] = plus ? 1 : -1;
+      clamp[k] = plus ? H : -H;
+    }
+    *energy = Estar;
     return TT_OK;
   } catch (const std::bad_alloc&) {
     return fail(TT_E_NOMEM, "out of host memory");
@@ -2125,6 +2490,24 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
   } catch (...) {
     return fail(TT_E_INVAL, "unexpected failure");
   }
+}
+
+int tt_count_log(const uint64_t residues[3], double* log_g) {
+  if (!residues || !log_g) return fail(TT_E_INVAL, "null argument");
+  uint64_t P[3];
+  tt_count_moduli(P);
+  for (int r = 0; r < 3; ++r)
+    if (residues[r] >= P[r]) return fail(TT_E_INVAL, "residue %d out of range", r);
+  uint32_t limbs[8];
+  crt_limbs(residues, limbs);
+  int top = 7;
+  while (top >= 0 && limbs[top] == 0) --top;
+  if (top < 0) return fail(TT_E_INVAL, "the count is zero");
+  // the two leading limbs carry 33+ significant bits: ln g = ln(lead) + 32 k ln 2
+  const int k = top >= 1 ? top - 1 : 0;
+  const double lead = top >= 1 ? (double)limbs[top] * 4294967296.0 + (double)limbs[top - 1] : (double)limbs[top];
+  *log_g = std::log(lead) + 32.0 * k * std::log(2.0);
+  return TT_OK;
 }
 
 int tt_count_to_decimal(const uint64_t residues[3], char* buf, size_t len) {

@@ -236,6 +236,18 @@ struct BwdItem {
   const uint64_t* red_i;
   int64_t red_n;
   double* energy;
+  // Segment of the walk (checkpoint recomputation): passes seg_lo..seg_hi.
+  // A segment that does not end the walk (seg_hi below the last pass) starts
+  // from the selected entry in *carry and the spins already chosen, read back
+  // from sigma; one that does not reach pass 0 writes its chosen spins to
+  // sigma and the next selected entry to *carry instead of the gradients.
+  // The whole walk is the single segment 0..n_passes-1.
+  int32_t seg_lo, seg_hi;
+  uint64_t* carry;
+  // Tie rule of every choice of the walk: 0 the first maximiser, 1 the last,
+  // other values a pseudo-random order per pass (the final state's own
+  // maximum keeps the lowest address).
+  uint64_t tie;
 };
 
 }  // namespace tt

@@ -37,9 +37,10 @@ hipError_t launch_count_reduce(const float* x, const uint64_t* nplanes, int64_t 
                                hipStream_t stream);
 
 // 3-state Potts sweep: one pass over `batch` instances of 3^W entries (sst)
-// in place; n == nullptr: energy only, else nres residue planes of
+// in place (low: the pass's tile digits are slots 0 .. t-1); n == nullptr: energy only, else nres residue planes of
 // batch * sst entries each
-hipError_t launch_potts_pass(const PottsPass* pass, int t, int64_t threads, const void* J, int64_t jst, int dtype,
+hipError_t launch_potts_pass(const PottsPass* pass, int t, bool low, int64_t threads, const void* J, int64_t jst,
+                             int dtype,
                              float* x, uint64_t* n, int nres, int64_t sst, int batch, hipStream_t s);
 int64_t potts_reduce_chunk(int64_t combos);
 // final maximum (and count): energy H* (double), energy2 2H* (int64), res
@@ -48,6 +49,13 @@ int64_t potts_reduce_chunk(int64_t combos);
 hipError_t launch_potts_reduce(const PottsReduce* red, int64_t combos, const float* x, const uint64_t* n, int nres,
                                int64_t sst, int batch, float* pv, uint64_t* pn, double* energy, int64_t* energy2,
                                uint64_t* res, hipStream_t s);
+
+// configurations by finite differences of the fields: the n + 1 perturbed
+// copies of one instance, then sigma, E* and Eq. (1) of sigma from their energies
+hipError_t launch_fd_build(const float* J, const float* h, int64_t m, int n, float delta, float* Jb, float* hb,
+                           hipStream_t s);
+hipError_t launch_fd_sigma(const double* E, const float* J, const float* h, const int32_t* edges, int64_t m, int n,
+                           int8_t* sigma, double* energy, double* e_sigma, hipStream_t s);
 
 // workspace of the allocation-free contraction: its size, and the current
 // device's address of it

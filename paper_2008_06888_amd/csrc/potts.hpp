@@ -38,6 +38,7 @@ struct PottsOp {
 // registers, and writes them back in place.
 struct PottsPass {
   int32_t t, n_nt, n_ops, init;     // init: the state starts at zero (no read)
+  int32_t low, pad;                 // low: the tile digits are slots 0 .. t-1 (see the kernels)
   int64_t threads;                  // 3^(W - t) threads per instance
   int64_t tile_st[POTTS_MAX_T];     // entry stride (3^slot) of tile digit r
   int64_t nt_st[POTTS_MAX_W];       // entry strides of the non-tile digits, lowest slot first
@@ -47,7 +48,7 @@ struct PottsPass {
 // Final maximum (and count) over the entries whose free slots hold label 0:
 // the combinations of the live digits.
 struct PottsReduce {
-  int32_t n_live, pad;
+  int32_t n_live, contig;           // contig: the live digits are slots 0 .. n_live-1
   int64_t combos;                   // 3^n_live
   int64_t st[POTTS_MAX_W];          // entry strides of the live digits, lowest slot first
 };

@@ -194,85 +194,151 @@ __device__ __forceinline__ float coupling(const void* J, int64_t jst, int inst, 
   return (float)as_const(static_cast<const int32_t*>(J))[(int64_t)inst * jst + e];
 }
 
-template <int T, int NR, bool COUNT>
+// LOW passes (tile = slots 0 .. T-1): thread t of a workgroup owns the run
+// [base + t 3^T, base + (t + 1) 3^T) and the workgroup one contiguous block;
+// direct loads would send each lane of a wave to its own cache line, so the
+// block goes through LDS: coalesced loads into LDS, then each thread takes its
+// run (stride 3^T words across lanes: odd, so the lanes of a wave hit
+// distinct banks), and the reverse for the stores. One plane at a time.
+template <int T, int NR, bool COUNT, bool LOW>
 __global__ __launch_bounds__(PT) void k_potts_pass(const PottsPass* __restrict__ pass, const void* __restrict__ J,
                                                    int64_t jst, int dtype, float* __restrict__ x,
                                                    uint64_t* __restrict__ nst, int64_t sst, int64_t plane) {
   constexpr int E = ipow3(T);
   const cptr<PottsPass> P = as_const(pass);
-  const int64_t gid = (int64_t)blockIdx.x * PT + threadIdx.x;
-  if (gid >= P->threads) return;
+  const int64_t threads = P->threads;
+  const int64_t gid0 = (int64_t)blockIdx.x * PT;
+  const int64_t gid = gid0 + threadIdx.x;
+  if (!LOW && gid >= threads) return;   // (LOW workgroups stay whole for their barriers)
   const int inst = (int)blockIdx.y;
-  // this thread's non-tile digits -> base entry
-  int64_t off = (int64_t)inst * sst;
-  {
-    uint64_t g = (uint64_t)gid;
-    const int nnt = P->n_nt;
-    for (int r = 0; r < nnt; ++r) {
-      const uint64_t q = g / 3u;
-      off += (int64_t)(g - 3u * q) * P->nt_st[r];
-      g = q;
-    }
-  }
-  // tile entry i sits at off + lo[i % 3^TL] + hi[i / 3^TL]: the offsets of the
-  // low and high tile digits (32 bits: an instance has at most 3^20 entries)
-  constexpr int TL = T / 2, TH = T - TL;
-  uint32_t lo[ipow3(TL)], hi[ipow3(TH)];
-  {
-    uint32_t st[T];
-#pragma unroll
-    for (int r = 0; r < T; ++r) st[r] = (uint32_t)P->tile_st[r];
-#pragma unroll
-    for (int i = 0; i < ipow3(TL); ++i) {
-      lo[i] = 0;
-#pragma unroll
-      for (int r = 0; r < TL; ++r) lo[i] += (uint32_t)digit(i, r) * st[r];
-    }
-#pragma unroll
-    for (int i = 0; i < ipow3(TH); ++i) {
-      hi[i] = 0;
-#pragma unroll
-      for (int r = 0; r < TH; ++r) hi[i] += (uint32_t)digit(i, r) * st[TL + r];
-    }
-  }
-  auto addr = [&](int i) { return off + (int64_t)(lo[i % ipow3(TL)] + hi[i / ipow3(TL)]); };
-  float v[E];
-  Cnt<NR> n[E];
   const gptr<float> X = as_global(x);
   const gptr<uint64_t> N = as_global(nst);
-  if (P->init) {
+  float v[E];
+  Cnt<NR> n[E];
+  const bool init = P->init != 0;
+  if constexpr (LOW) {
+    extern __shared__ float lds_f[];
+    uint64_t* lds_u = reinterpret_cast<uint64_t*>(lds_f);
+    const int64_t base = (int64_t)inst * sst + gid0 * E;
+    const int64_t left = threads - gid0;
+    const int nvalid = (int)((left < PT ? left : PT) * E);
+    const int mine = (int)threadIdx.x * E;
+    if (init) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      v[i] = 0.f;
+      for (int i = 0; i < E; ++i) {
+        v[i] = 0.f;
+        if constexpr (COUNT) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) n[i].r[r] = 1;
+        }
+      }
+    } else {
+      for (int e = threadIdx.x; e < nvalid; e += PT) lds_f[e] = __builtin_nontemporal_load(&X[base + e]);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = lds_f[mine + i];
       if constexpr (COUNT) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) n[i].r[r] = 1;
+        for (int r = 0; r < NR; ++r) {
+          __syncthreads();
+          for (int e = threadIdx.x; e < nvalid; e += PT)
+            lds_u[e] = __builtin_nontemporal_load(&N[base + e + r * plane]);
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < E; ++i) n[i].r[r] = lds_u[mine + i];
+        }
       }
     }
+    const int nops = P->n_ops;
+    for (int o = 0; o < nops; ++o) {
+      const int kind = P->ops[o].kind, a = P->ops[o].a, b = P->ops[o].b, e = P->ops[o].edge;
+      const float Jv = kind == OP_CUT ? 0.f : coupling(J, jst, inst, e, dtype);
+      apply_op<T, NR, COUNT>(kind, a, b, -2.f * Jv, Jv, v, n);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds_f[mine + i] = v[i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nvalid; e += PT) __builtin_nontemporal_store(lds_f[e], &X[base + e]);
+    if constexpr (COUNT) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < E; ++i) lds_u[mine + i] = n[i].r[r];
+        __syncthreads();
+        for (int e = threadIdx.x; e < nvalid; e += PT) __builtin_nontemporal_store(lds_u[e], &N[base + e + r * plane]);
+      }
+    }
+    return;
   } else {
+    // this thread's non-tile digits -> base entry
+    int64_t off = (int64_t)inst * sst;
+    {
+      uint64_t g = (uint64_t)gid;
+      const int nnt = P->n_nt;
+      for (int r = 0; r < nnt; ++r) {
+        const uint64_t q = g / 3u;
+        off += (int64_t)(g - 3u * q) * P->nt_st[r];
+        g = q;
+      }
+    }
+    // tile entry i sits at off + lo[i % 3^TL] + hi[i / 3^TL]: the offsets of the
+    // low and high tile digits (32 bits: an instance has at most 3^20 entries)
+    constexpr int TL = T / 2, TH = T - TL;
+    uint32_t lo[ipow3(TL)], hi[ipow3(TH)];
+    {
+      uint32_t st[T];
+#pragma unroll
+      for (int r = 0; r < T; ++r) st[r] = (uint32_t)P->tile_st[r];
+#pragma unroll
+      for (int i = 0; i < ipow3(TL); ++i) {
+        lo[i] = 0;
+#pragma unroll
+        for (int r = 0; r < TL; ++r) lo[i] += (uint32_t)digit(i, r) * st[r];
+      }
+#pragma unroll
+      for (int i = 0; i < ipow3(TH); ++i) {
+        hi[i] = 0;
+#pragma unroll
+        for (int r = 0; r < TH; ++r) hi[i] += (uint32_t)digit(i, r) * st[TL + r];
+      }
+    }
+    auto addr = [&](int i) { return off + (int64_t)(lo[i % ipow3(TL)] + hi[i / ipow3(TL)]); };
+    if (init) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        v[i] = 0.f;
+        if constexpr (COUNT) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) n[i].r[r] = 1;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int64_t a = addr(i);
+        v[i] = __builtin_nontemporal_load(&X[a]);
+        if constexpr (COUNT) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) n[i].r[r] = __builtin_nontemporal_load(&N[a + r * plane]);
+        }
+      }
+    }
+    const int nops = P->n_ops;
+    for (int o = 0; o < nops; ++o) {
+      const int kind = P->ops[o].kind, a = P->ops[o].a, b = P->ops[o].b, e = P->ops[o].edge;
+      const float Jv = kind == OP_CUT ? 0.f : coupling(J, jst, inst, e, dtype);
+      apply_op<T, NR, COUNT>(kind, a, b, -2.f * Jv, Jv, v, n);
+    }
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int64_t a = addr(i);
-      v[i] = __builtin_nontemporal_load(&X[a]);
+      __builtin_nontemporal_store(v[i], &X[a]);
       if constexpr (COUNT) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) n[i].r[r] = __builtin_nontemporal_load(&N[a + r * plane]);
+        for (int r = 0; r < NR; ++r) __builtin_nontemporal_store(n[i].r[r], &N[a + r * plane]);
       }
-    }
-  }
-  const int nops = P->n_ops;
-  for (int o = 0; o < nops; ++o) {
-    const int kind = P->ops[o].kind, a = P->ops[o].a, b = P->ops[o].b, e = P->ops[o].edge;
-    const float Jv = kind == OP_CUT ? 0.f : coupling(J, jst, inst, e, dtype);
-    apply_op<T, NR, COUNT>(kind, a, b, -2.f * Jv, Jv, v, n);
-  }
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int64_t a = addr(i);
-    __builtin_nontemporal_store(v[i], &X[a]);
-    if constexpr (COUNT) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) __builtin_nontemporal_store(n[i].r[r], &N[a + r * plane]);
     }
   }
 }
@@ -297,13 +363,18 @@ __global__ __launch_bounds__(PT) void k_potts_reduce1(const PottsReduce* __restr
   const cptr<uint64_t> Nn = as_const(nst);
   float best = -INFINITY;
   uint64_t c[4] = {0, 0, 0, 0};
+  const bool contig = R->contig != 0;
   for (int64_t k = lo + threadIdx.x; k < hi; k += PT) {
     int64_t a = (int64_t)inst * sst;
-    uint64_t g = (uint64_t)k;
-    for (int r = 0; r < nl; ++r) {
-      const uint64_t q = g / 3u;
-      a += (int64_t)(g - 3u * q) * R->st[r];
-      g = q;
+    if (contig) {
+      a += k;
+    } else {
+      uint64_t g = (uint64_t)k;
+      for (int r = 0; r < nl; ++r) {
+        const uint64_t q = g / 3u;
+        a += (int64_t)(g - 3u * q) * R->st[r];
+        g = q;
+      }
     }
     const float val = X[a];
     if (COUNT) {
@@ -368,42 +439,55 @@ __global__ void k_potts_reduce2(const float* __restrict__ pv, const uint64_t* __
 }
 
 template <int T, int NR, bool COUNT>
-hipError_t launch_t(const PottsPass* pass, int64_t threads, const void* J, int64_t jst, int dtype, float* x,
+hipError_t launch_t(const PottsPass* pass, bool low, int64_t threads, const void* J, int64_t jst, int dtype, float* x,
                     uint64_t* n, int64_t sst, int64_t plane, int batch, hipStream_t s) {
   const dim3 grid((uint32_t)((threads + PT - 1) / PT), (uint32_t)batch);
-  hipLaunchKernelGGL((k_potts_pass<T, NR, COUNT>), grid, dim3(PT), 0, s, pass, J, jst, dtype, x, n, sst, plane);
+  if (!low) {
+    hipLaunchKernelGGL((k_potts_pass<T, NR, COUNT, false>), grid, dim3(PT), 0, s, pass, J, jst, dtype, x, n, sst,
+                       plane);
+    return hipGetLastError();
+  }
+  constexpr size_t lds = (size_t)PT * ipow3(T) * (COUNT ? sizeof(uint64_t) : sizeof(float));
+  static bool raised = false;   // one flag per instantiation
+  if (!raised) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_potts_pass<T, NR, COUNT, true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    raised = true;
+  }
+  hipLaunchKernelGGL((k_potts_pass<T, NR, COUNT, true>), grid, dim3(PT), lds, s, pass, J, jst, dtype, x, n, sst, plane);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_potts_pass(const PottsPass* pass, int t, int64_t threads, const void* J, int64_t jst, int dtype,
+hipError_t launch_potts_pass(const PottsPass* pass, int t, bool low, int64_t threads, const void* J, int64_t jst, int dtype,
                              float* x, uint64_t* n, int nres, int64_t sst, int batch, hipStream_t s) {
   if (batch < 1 || batch > 65535 || threads < 1 || (threads + PT - 1) / PT >= (1ll << 31))
     return hipErrorInvalidConfiguration;
   const int64_t plane = (int64_t)batch * sst;
   if (!n) {
     switch (t) {
-      case 1: return launch_t<1, 1, false>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
-      case 2: return launch_t<2, 1, false>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
-      case 3: return launch_t<3, 1, false>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
-      case 4: return launch_t<4, 1, false>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 1: return launch_t<1, 1, false>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 2: return launch_t<2, 1, false>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 3: return launch_t<3, 1, false>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 4: return launch_t<4, 1, false>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
       default: return hipErrorInvalidConfiguration;
     }
   }
   if (nres == 3) {
     switch (t) {
-      case 1: return launch_t<1, 3, true>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
-      case 2: return launch_t<2, 3, true>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
-      case 3: return launch_t<3, 3, true>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 1: return launch_t<1, 3, true>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 2: return launch_t<2, 3, true>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 3: return launch_t<3, 3, true>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
       default: return hipErrorInvalidConfiguration;
     }
   }
   if (nres == 4) {
     switch (t) {
-      case 1: return launch_t<1, 4, true>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
-      case 2: return launch_t<2, 4, true>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
-      case 3: return launch_t<3, 4, true>(pass, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 1: return launch_t<1, 4, true>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 2: return launch_t<2, 4, true>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
+      case 3: return launch_t<3, 4, true>(pass, low, threads, J, jst, dtype, x, n, sst, plane, batch, s);
       default: return hipErrorInvalidConfiguration;
     }
   }

@@ -21,11 +21,20 @@ int64_t pow3(int k) {
 // Tile digits: the touched slots, padded (when fewer than t) with the highest
 // untouched slots, so that the lowest slots stay non-tile digits, which vary
 // fastest across threads (consecutive threads read consecutive entries).
+// When every touched slot is below t the tile is slots 0 .. t-1 instead: a
+// thread's entries are then one run and a workgroup's one contiguous block,
+// which the kernel stages through LDS ("low" passes).
 void finish_pass(const std::set<int>& touched, int W, int t, PottsPass& P) {
   std::vector<int> tile(touched.begin(), touched.end());
+  const bool low = !touched.empty() && *touched.rbegin() < t;
+  if (low) {
+    tile.clear();
+    for (int s = 0; s < t; ++s) tile.push_back(s);
+  }
   for (int s = W - 1; s >= 0 && (int)tile.size() < t; --s)
     if (!touched.count(s)) tile.push_back(s);
   std::sort(tile.begin(), tile.end());
+  P.low = low ? 1 : 0;
   P.t = t;
   for (int r = 0; r < t; ++r) P.tile_st[r] = pow3(tile[r]);
   P.n_nt = 0;
@@ -89,6 +98,9 @@ std::string encode_potts(const Plan& p, int t, PottsProgram& out) {
     if (live) out.red.st[out.red.n_live++] = pow3(s);
   }
   out.red.combos = pow3(out.red.n_live);
+  out.red.contig = 1;
+  for (int r = 0; r < out.red.n_live; ++r)
+    if (out.red.st[r] != pow3(r)) out.red.contig = 0;
   // algorithmic work at the live width (base 3): a GATE is a contraction with
   // K = 3 (three terms per output entry), a DIAG one add per entry, a CUT two
   // maxima per output entry, the final maximum one per entry

@@ -1046,10 +1046,24 @@ struct BwdTerms {
   int cross_b, nterm;
   uint64_t t;
   uint32_t na;
+  uint32_t m;   // tie key of candidate a: a ^ m (m = 0: the first maximiser)
 };
 
+// Tie mask of pass p for the walk's tie rule (< na): 0 keeps the first
+// maximiser of every choice (the paper's default max), 1 the last, any other
+// value a pseudo-random rule per pass (a 32-bit mix of the value and p).
+__device__ __forceinline__ uint32_t tie_mask(uint64_t tie, int p, uint32_t na) {
+  if (tie == 0) return 0u;
+  if (tie == 1) return na - 1u;
+  uint64_t z = tie + 0x9E3779B97F4A7C15ull * (uint64_t)(p + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (uint32_t)z & (na - 1u);
+}
+
 // Scores candidates a0 + j NT, j < W (input entry + table terms + cross
-// terms) into the thread's best (value, lowest index).
+// terms) into the thread's best (value, lowest tie key a ^ m).
 template <int W>
 __device__ __forceinline__ void bwd_score(float (&val)[8], const BwdTerms& X, const float* lut_lo, const float* lut_hi,
                                           uint32_t a0, float& bv, uint32_t& bi) {
@@ -1066,9 +1080,10 @@ __device__ __forceinline__ void bwd_score(float (&val)[8], const BwdTerms& X, co
 #pragma unroll
   for (int j = 0; j < W; ++j) {
     const uint32_t a = a0 + (uint32_t)j * NT;
-    if (a < X.na && (val[j] > bv || (val[j] == bv && a < bi))) {
+    const uint32_t key = a ^ X.m;
+    if (a < X.na && (val[j] > bv || (val[j] == bv && key < bi))) {
       bv = val[j];
-      bi = a;
+      bi = key;
     }
   }
 }
@@ -1101,8 +1116,16 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   const cptr<const float*> ckpt = as_const(I.ckpt);
   const int final_w = I.final_w, n = I.n;
   const int64_t m = I.m;
-  for (int v = tid; v < n; v += NT) s_sh[v] = 0;
-  if (I.red_v) {
+  const int seg_lo = I.seg_lo, seg_hi = I.seg_hi;
+  const bool seg_top = seg_hi == I.n_passes - 1;   // the walk starts at the final state
+  const bool seg_end = seg_lo == 0;                // the walk ends here: gradients out
+  if (seg_top) {
+    for (int v = tid; v < n; v += NT) s_sh[v] = 0;
+  } else {
+    const cptr<int8_t> sg = as_const(static_cast<const int8_t*>(I.sigma));
+    for (int v = tid; v < n; v += NT) s_sh[v] = sg[v] < 0 ? 1 : 0;
+  }
+  if (seg_top && I.red_v) {
     // the final maximum over the last pass's per-tile partials: the largest
     // value, ties to the lowest address
     float bv = -INFINITY;
@@ -1134,7 +1157,9 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
     }
   }
   __syncthreads();
-  if (tid < 64) {
+  if (!seg_top) {
+    if (tid == 0) sh_t = *as_const(static_cast<const uint64_t*>(I.carry));
+  } else if (tid < 64) {
     // final state: address -> slot index; spins still in a slot take its bit
     const uint64_t addr = I.red_v ? sh_final : *as_const(I.final_addr);
     uint64_t tb = 0;
@@ -1155,6 +1180,9 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   const int lane = tid & 63;
   for (int ci = 0; ci < I.n_chunks; ++ci) {
     const BChunk CH = ldc(chunks + ci);
+    if (CH.p_lo > seg_hi || CH.p_hi < seg_lo) continue;   // outside the segment (uniform)
+    // the passes of the chunk inside the segment
+    const int top = CH.p_hi < seg_hi ? CH.p_hi : seg_hi, bot = CH.p_lo > seg_lo ? CH.p_lo : seg_lo;
     // stage the chunk: pass fields and layouts, candidates, terms (coefficients resolved)
     for (int q = tid; q <= CH.p_hi - CH.p_lo; q += NT) {
       const cptr<DevPass2> P = passes + CH.p_lo + q;
@@ -1193,17 +1221,17 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       }
     }
     __syncthreads();
-    // the chunk's last pass: its address tables, and the address of its
-    // surviving slots under the selected output entry
-    bwd_address_tables(lp[CH.p_hi - CH.p_lo], lcad, ad_lo[CH.p_hi & 1], ad_hi[CH.p_hi & 1], tid);
-    base_cur = bwd_surviving_base(lp[CH.p_hi - CH.p_lo], lpos[CH.p_hi - CH.p_lo], t_cur, lane);
+    // the chunk's last pass walked here: its address tables, and the address
+    // of its surviving slots under the selected output entry
+    bwd_address_tables(lp[top - CH.p_lo], lcad, ad_lo[top & 1], ad_hi[top & 1], tid);
+    base_cur = bwd_surviving_base(lp[top - CH.p_lo], lpos[top - CH.p_lo], t_cur, lane);
     __syncthreads();
-    for (int p = CH.p_hi; p >= CH.p_lo; --p) {
+    for (int p = top; p >= bot; --p) {
       const LPass& P = lp[p - CH.p_lo];
       const int nc = P.n_cand;
       const uint64_t surv = P.surv;
       const uint64_t t = t_cur;
-      const bool has_next = p > CH.p_lo;
+      const bool has_next = p > bot;
       if (nc == 0) {
         t_cur = t & surv;
         if (has_next) {
@@ -1264,7 +1292,8 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       const int cross_b = n_lo + n_hi;
       float bv = -INFINITY;
       uint32_t bi = ~0u;
-      const BwdTerms TT{T, cross_b, nterm, t, na};
+      const uint32_t tm = tie_mask(I.tie, p, na);
+      const BwdTerms TT{T, cross_b, nterm, t, na, tm};
       switch (wsel) {
         case 1: bwd_score<1>(val, TT, lut_lo, lut_hi, (uint32_t)tid, bv, bi); break;
         case 2: bwd_score<2>(val, TT, lut_lo, lut_hi, (uint32_t)tid, bv, bi); break;
@@ -1291,7 +1320,7 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       bv = lane < NT / 64 ? pv[lane] : -INFINITY;
       bi = lane < NT / 64 ? pi[lane] : ~0u;
       wave_best_dpp(bv, bi);
-      const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)bi, 63);
+      const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)bi, 63) ^ tm;
       uint64_t b = 0;
       if (lane < nc) {   // nc <= 16: the first row of lanes
         const uint32_t bit = (a >> lane) & 1u;
@@ -1306,6 +1335,13 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
   }
   const gptr<int8_t> sigma = as_global(I.sigma);
   const gptr<float> dh = as_global(I.dh), dJ = as_global(I.dJ);
+  if (!seg_end) {
+    // a later segment continues the walk: the spins chosen so far and the
+    // selected entry of the pass below this segment
+    for (int v = tid; v < n; v += NT) sigma[v] = (int8_t)(s_sh[v] ? -1 : 1);
+    if (tid == 0) *as_global(I.carry) = t_cur;
+    return;
+  }
   for (int v = tid; v < n; v += NT) {
     sigma[v] = (int8_t)(s_sh[v] ? -1 : 1);
     if (dh) dh[v] = s_sh[v] ? 1.f : -1.f;           // -sigma_v

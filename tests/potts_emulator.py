@@ -9,7 +9,7 @@ import struct
 import numpy as np
 
 MAX_W, MAX_T, MAX_OPS = 20, 4, 48
-PASS_FMT = "<4iq" + f"{MAX_T}q" + f"{MAX_W}q" + "".join("4Bi" for _ in range(MAX_OPS))
+PASS_FMT = "<6iq" + f"{MAX_T}q" + f"{MAX_W}q" + "".join("4Bi" for _ in range(MAX_OPS))
 PASS_SIZE = struct.calcsize(PASS_FMT)
 RED_FMT = "<2iq" + f"{MAX_W}q"
 OP_GATE, OP_CUT, OP_DIAG = 1, 2, 3
@@ -20,22 +20,27 @@ def parse_passes(raw: bytes):
     out = []
     for k in range(len(raw) // PASS_SIZE):
         f = struct.unpack_from(PASS_FMT, raw, k * PASS_SIZE)
-        t, n_nt, n_ops, init, threads = f[0:5]
-        tile_st = list(f[5:5 + MAX_T])[:t]
-        nt_st = list(f[5 + MAX_T:5 + MAX_T + MAX_W])[:n_nt]
+        t, n_nt, n_ops, init, low, _, threads = f[0:7]
+        tile_st = list(f[7:7 + MAX_T])[:t]
+        nt_st = list(f[7 + MAX_T:7 + MAX_T + MAX_W])[:n_nt]
+        if low:   # the tile is slots 0 .. t-1
+            assert tile_st == [3 ** r for r in range(t)]
         ops = []
-        base = 5 + MAX_T + MAX_W
+        base = 7 + MAX_T + MAX_W
         for o in range(n_ops):
             kind, a, b, _, edge = f[base + 5 * o:base + 5 * o + 5]
             ops.append((kind, a, b, edge))
-        out.append(dict(t=t, n_nt=n_nt, init=init, threads=threads, tile_st=tile_st, nt_st=nt_st, ops=ops))
+        out.append(dict(t=t, n_nt=n_nt, init=init, low=low, threads=threads, tile_st=tile_st, nt_st=nt_st, ops=ops))
     return out
 
 
 def parse_reduce(raw: bytes):
     f = struct.unpack_from(RED_FMT, raw, 0)
-    n_live, _, combos = f[0:3]
-    return dict(n_live=n_live, combos=combos, st=list(f[3:3 + n_live]))
+    n_live, contig, combos = f[0:3]
+    st = list(f[3:3 + n_live])
+    if contig:
+        assert st == [3 ** r for r in range(n_live)]
+    return dict(n_live=n_live, contig=contig, combos=combos, st=st)
 
 
 def _digits_offsets(strides):

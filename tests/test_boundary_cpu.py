@@ -137,3 +137,13 @@ def test_crt_of_reduced_residues_only():
     P = B.moduli()
     with pytest.raises(B.TTError):
         B.residues_to_int([P[0], 0, 0])
+
+
+def test_count_log_of_known_counts():
+    import math
+    P = B.moduli()
+    for g in (1, 2, 8, 3 ** 40, 2 ** 64, 2 ** 103 + 12345, 7 ** 60):
+        res = [g % p for p in P]
+        assert abs(B.count_log(res) - math.log(g)) <= 1e-14 * max(1.0, math.log(g)), g
+    with pytest.raises(B.TTError):
+        B.count_log([0, 0, 0])
