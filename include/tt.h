@@ -112,6 +112,34 @@ typedef struct tt_plan tt_plan;
  * no duplicates. The graph is copied. *out receives the plan. */
 int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges,
                    const tt_plan_opts* opts, tt_plan** out);
+/* Sliced plan: the sum of Eq. (1) split by the values of n_fixed spins, the
+ * index-slicing form of the contraction (the network's largest tensors lose
+ * one index per fixed spin). Each of the 2^n_fixed assignments of the fixed
+ * spins (a slice) leaves an instance of the graph without them, in which a
+ * bond J_ij to a fixed spin j is a field J_ij sigma_j on spin i and the bonds
+ * and fields among fixed spins are a constant; E* is the minimum over the
+ * slices of their energies plus constants, g the sum of the degeneracies of
+ * the slices that reach it (Eq. (4)). tt_contract, tt_backward(_tie) and
+ * tt_count accept sliced plans and run the slices as batches of the reduced
+ * graph's plan, as many at a time as the budget (opts.max_bytes, else free
+ * device memory) holds; other calls return TT_E_INVAL. tt_backward takes the
+ * first minimising slice (lowest slice index, bit j of the index = fixed spin
+ * j at -1) and walks it back. opts as tt_plan_create (GREEDY or GIVEN order
+ * over all n_spins; has_field as for the whole graph), 1 <= n_fixed <= 16,
+ * n_fixed < n_spins. fixed: host int32 [n_fixed] distinct spins, or NULL to
+ * let the planner choose them (one at a time, the spin live at the most
+ * points of the current sweep's largest width). tt_plan_info reports the
+ * reduced plan's width and passes and the work of all slices per instance;
+ * tt_plan_order the fixed spins followed by the reduced sweep's order;
+ * tt_plan_ops and tt_plan_program those of the reduced plan, in its own
+ * numbering (spins in ascending order without the fixed ones, edges in input
+ * order without those touching a fixed spin). */
+int tt_plan_create_sliced(int32_t n_spins, int64_t n_edges, const int32_t* edges,
+                          const tt_plan_opts* opts, int32_t n_fixed, const int32_t* fixed,
+                          tt_plan** out);
+/* Number of fixed spins of a plan (0 when unsliced); fixed_out (host, may be
+ * NULL) receives them, fixed index j first to last. */
+int tt_plan_slice_info(const tt_plan* plan, int32_t* fixed_out);
 int tt_plan_info(const tt_plan* plan, tt_plan_stats* out);
 /* Host copy of the spin order the plan sweeps (n_spins int32). */
 int tt_plan_order(const tt_plan* plan, int32_t* order_out);
@@ -120,7 +148,8 @@ void tt_plan_destroy(tt_plan* plan);
  * which = 0 pass descriptors, 1 stages, 2 fused ops, 3 backward candidates,
  * 4 backward terms, 5 final bit layout, 6 per pass the chimera row whose
  * chain step follows it (int32, -1 = none); for 3-state plans (opts.q = 3)
- * 7 energy passes, 8 counting passes, 9 the final-reduction descriptor. Copies at most cap bytes into out
+ * 7 energy passes, 8 counting passes, 9 the final-reduction descriptor;
+ * for Ising plans 10 the counting path's passes, 11 its ops. Copies at most cap bytes into out
  * (may be NULL) and returns the total size in bytes (or a negative
  * tt_status). The record layouts are those of the library's device.hpp. */
 int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t cap);
@@ -262,11 +291,20 @@ int tt_count_log(const uint64_t residues[3], double* log_g);
  * J: device float/int32 concatenated, instance i at j_off[i] (host int64);
  * sigma: device int8 concatenated at s_off[i] (host int64) (may be NULL);
  * dJ: device float laid out like J (may be NULL); energy: device double
- * [n_inst]. Fields are not supported here (h = 0). */
+ * [n_inst]. Every plan must be without fields (see tt_contract_uneven_fields). */
 int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype,
                        const void* J, const int64_t* j_off, double* energy,
                        int8_t* sigma, const int64_t* s_off, float* dJ,
                        void* stream);
+/* tt_contract_uneven with fields: instance i's fields (of J's dtype) at
+ * h + h_off[i] when plans[i] carries fields (h_off[i] is ignored otherwise);
+ * dh (may be NULL; needs sigma) laid out like h receives -sigma_i for the
+ * instances with fields. h may be NULL when no plan carries fields. */
+int tt_contract_uneven_fields(int32_t n_inst, tt_plan* const* plans, int32_t dtype,
+                              const void* J, const int64_t* j_off, const void* h,
+                              const int64_t* h_off, double* energy, int8_t* sigma,
+                              const int64_t* s_off, float* dJ, float* dh,
+                              void* stream);
 
 /* Dense tropical matrix product (Eq. 2 as a matrix product, the contraction
  * of two tensors over a run of shared labels):

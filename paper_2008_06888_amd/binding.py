@@ -39,7 +39,8 @@ EXPORTS = ("tt_plan_create", "tt_plan_info", "tt_plan_order", "tt_plan_destroy",
            "tt_prof_enable", "tt_prof_reset", "tt_prof_read", "tt_last_error", "tt_plan_ops",
            "tt_plan_program", "tt_graphs_enable", "tt_tgemm", "tt_plan_autotune", "tt_contract_noalloc",
            "tt_potts_contract", "tt_potts_count", "tt_backward_tie", "tt_config_fd",
-           "tt_sample_ground_state", "tt_count_log")
+           "tt_sample_ground_state", "tt_count_log", "tt_contract_uneven_fields", "tt_plan_create_sliced",
+           "tt_plan_slice_info")
 
 
 class PlanOpts(C.Structure):
@@ -59,6 +60,9 @@ class PlanStats(C.Structure):
 
 _vp = C.c_void_p
 _lib.tt_plan_create.argtypes = [C.c_int32, C.c_int64, _vp, C.POINTER(PlanOpts), C.POINTER(_vp)]
+_lib.tt_plan_create_sliced.argtypes = [C.c_int32, C.c_int64, _vp, C.POINTER(PlanOpts), C.c_int32, _vp,
+                                       C.POINTER(_vp)]
+_lib.tt_plan_slice_info.argtypes = [_vp, _vp]
 _lib.tt_plan_info.argtypes = [_vp, C.POINTER(PlanStats)]
 _lib.tt_plan_order.argtypes = [_vp, _vp]
 _lib.tt_plan_ops.argtypes = [_vp, _vp, C.c_int64, _vp, _vp]
@@ -81,6 +85,8 @@ _lib.tt_count_to_decimal.argtypes = [_vp, C.c_char_p, C.c_size_t]
 _lib.tt_contract_uneven.argtypes = [C.c_int32, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.tt_prof_enable.argtypes = [C.c_int32]
 _lib.tt_graphs_enable.argtypes = [C.c_int32]
+_lib.tt_contract_uneven_fields.argtypes = [C.c_int32, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                           _vp]
 _lib.tt_tgemm.argtypes = [C.c_int32, C.c_int64, C.c_int64, C.c_int64, _vp, C.c_int64, C.c_int64, _vp, C.c_int64,
                           C.c_int64, _vp, C.c_int64, C.c_int64, _vp]
 _lib.tt_plan_autotune.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, C.c_int32, _vp, _vp, _vp]
@@ -114,7 +120,9 @@ class Plan:
     def __init__(self, n: int, edges, *, order: Optional[Sequence[int]] = None, kind: Optional[int] = None,
                  has_field: bool = False, seed: int = 0, trials: int = 32, tile_bits: int = 0,
                  count_tile_bits: int = 0, chimera: Optional[tuple] = None, max_bytes: int = 0,
-                 parts: int = 0, q: int = 2):
+                 parts: int = 0, q: int = 2, n_fixed: int = 0, fixed: Optional[Sequence[int]] = None):
+        """n_fixed / fixed: a sliced plan (tt_plan_create_sliced) with that many
+        fixed spins, given or (fixed None) chosen by the planner."""
         self.n = int(n)
         self.edges = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
         self.m = int(self.edges.shape[0])
@@ -134,7 +142,13 @@ class Plan:
         o.q = q
         self.q = q
         h = _vp()
-        _check(_lib.tt_plan_create(self.n, self.m, self.edges.ctypes.data, C.byref(o), C.byref(h)))
+        if fixed is not None or n_fixed:
+            fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, dtype=np.int32))
+            nf = int(n_fixed) if fx is None else int(fx.size)
+            _check(_lib.tt_plan_create_sliced(self.n, self.m, self.edges.ctypes.data, C.byref(o), nf,
+                                              None if fx is None else fx.ctypes.data, C.byref(h)))
+        else:
+            _check(_lib.tt_plan_create(self.n, self.m, self.edges.ctypes.data, C.byref(o), C.byref(h)))
         self._h = h
 
     @property
@@ -150,6 +164,15 @@ class Plan:
         out = np.zeros(self.n, np.int32)
         _check(_lib.tt_plan_order(self._h, out.ctypes.data))
         return out
+
+    def fixed(self) -> np.ndarray:
+        """Fixed spins of a sliced plan (empty when unsliced)."""
+        k = _lib.tt_plan_slice_info(self._h, None)
+        if k < 0:
+            _check(k)
+        out = np.zeros(max(k, 1), np.int32)
+        _lib.tt_plan_slice_info(self._h, out.ctypes.data)
+        return out[:k]
 
     def ops(self):
         """(ops int32 [n_ops, 8], final_slot_spin int32 [final_width]); see tt_plan_ops."""
@@ -415,6 +438,47 @@ def contract_uneven(plans: Sequence[Plan], J_list, want_sigma: bool = True):
     sig = [sigma[s_off[i]:s_off[i] + plans[i].n] for i in range(n)]
     dj = [dJ[j_off[i]:j_off[i] + plans[i].m] for i in range(n)]
     return energy, sig, dj
+
+
+def contract_uneven_fields(plans: Sequence[Plan], J_list, h_list, want_sigma: bool = True):
+    """contract_uneven with fields: h_list[i] is a device tensor [n_i] for plans with fields, else None.
+    Returns (E*, sigma list, dE/dJ list, dE/dh list (None where a plan has no fields))."""
+    torch = _torch()
+    n = len(plans)
+    if n != len(J_list) or n != len(h_list) or n == 0:
+        raise ValueError("one J and one h (or None) per plan")
+    dt = J_list[0].dtype
+    Jcat = torch.cat([j.reshape(-1) for j in J_list]).contiguous()
+    hs = [h.reshape(-1) for h in h_list if h is not None]
+    hcat = torch.cat(hs).contiguous() if hs else None
+    j_off, s_off, h_off = np.zeros(n, np.int64), np.zeros(n, np.int64), np.zeros(n, np.int64)
+    hpos = 0
+    for i in range(n):
+        if i:
+            j_off[i] = j_off[i - 1] + plans[i - 1].m
+            s_off[i] = s_off[i - 1] + plans[i - 1].n
+        p, j, h = plans[i], J_list[i], h_list[i]
+        if j.numel() != p.m or j.dtype != dt or (h is not None) != p.has_field:
+            raise ValueError("J / h sizes, dtypes and fields must match the plans")
+        if h is not None:
+            if h.numel() != p.n or h.dtype != dt:
+                raise ValueError("h sizes / dtypes must match the plans")
+            h_off[i] = hpos
+            hpos += p.n
+    handles = (C.c_void_p * n)(*[p.handle for p in plans])
+    energy = torch.empty(n, dtype=torch.float64, device=Jcat.device)
+    sigma = torch.empty(int(sum(p.n for p in plans)), dtype=torch.int8, device=Jcat.device) if want_sigma else None
+    dJ = torch.empty_like(Jcat, dtype=torch.float32) if want_sigma else None
+    dh = torch.empty_like(hcat, dtype=torch.float32) if (want_sigma and hcat is not None) else None
+    _check(_lib.tt_contract_uneven_fields(n, handles, _dtype_code(Jcat), _ptr(Jcat), j_off.ctypes.data, _ptr(hcat),
+                                          h_off.ctypes.data, _ptr(energy), _ptr(sigma), s_off.ctypes.data, _ptr(dJ),
+                                          _ptr(dh), _stream()))
+    if not want_sigma:
+        return energy, None, None, None
+    sig = [sigma[s_off[i]:s_off[i] + plans[i].n] for i in range(n)]
+    dj = [dJ[j_off[i]:j_off[i] + plans[i].m] for i in range(n)]
+    dhl = [dh[h_off[i]:h_off[i] + plans[i].n] if plans[i].has_field else None for i in range(n)]
+    return energy, sig, dj, dhl
 
 
 def tgemm(A, B, out=None):

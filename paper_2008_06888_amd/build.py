@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtt.so")
 SOURCES = ["planner.cpp", "encode.cpp", "capi.cpp", "sweep_kernels.hip", "count_kernels.hip", "tgemm_kernels.hip",
            "chimera_kernels.hip", "check_kernels.hip", "noalloc.hip",
-           "potts_plan.cpp", "potts_kernels.hip", "config_kernels.hip"]
+           "potts_plan.cpp", "potts_kernels.hip", "config_kernels.hip", "slice_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

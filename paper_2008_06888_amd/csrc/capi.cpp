@@ -497,6 +497,7 @@ int check_common(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, con
   if (!plan) return fail(TT_E_INVAL, "null plan");
   const Plan& p = *reinterpret_cast<Plan*>(plan);
   if (p.q != 2) return fail(TT_E_INVAL, "plan is for 3-state labels: use the tt_potts_* calls");
+  if (p.slice) return fail(TT_E_INVAL, "sliced plans are solved with tt_contract, tt_backward(_tie) and tt_count");
   if (batch < 1) return fail(TT_E_INVAL, "batch must be >= 1");
   if (dtype != TT_F32 && dtype != TT_I32) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
   if (p.m > 0 && !J) return fail(TT_E_INVAL, "null J");
@@ -1739,6 +1740,370 @@ bool big_zero(const std::vector<uint32_t>& a) {
 // Spins up to which g <= 2^n stays below the product of the count primes.
 constexpr int COUNT_EXACT_SPINS = 182;
 
+// ----------------------------------------------------------------------------
+// sliced plans: s fixed spins, the reduced graph and its plan (see
+// slice_kernels.hip for the reduction of an instance to its slices)
+// ----------------------------------------------------------------------------
+struct SliceDev {
+  int device = -1;
+  DevBuf idx;                  // index tables of SliceArgs and the graph's edges
+  DevBuf jr, hr, c, er, kb, sr, eb, c2;
+};
+
+struct Slice {
+  int32_t s = 0;
+  std::vector<int32_t> spins, keep, emap, cross_ptr, cross_bit, cross_edge, inner_a, inner_b, inner_edge;
+  tt_plan* red = nullptr;      // plan of the reduced graph (with fields)
+  std::unique_ptr<SliceDev> d;
+  ~Slice() { tt_plan_destroy(red); }
+};
+
+// The graph without the fixed spins: keep (reduced spin -> spin), rid (spin
+// -> reduced spin or -1), the reduced edges and the edge each comes from.
+struct ReducedGraph {
+  std::vector<int32_t> keep, rid, edges, emap;
+};
+ReducedGraph reduce_graph(int32_t n, const std::vector<int32_t>& edges, const std::vector<int32_t>& fixed) {
+  ReducedGraph g;
+  std::vector<char> is_fixed(n, 0);
+  for (int32_t v : fixed) is_fixed[v] = 1;
+  g.rid.assign(n, -1);
+  for (int32_t v = 0; v < n; ++v)
+    if (!is_fixed[v]) {
+      g.rid[v] = (int32_t)g.keep.size();
+      g.keep.push_back(v);
+    }
+  const int64_t m = (int64_t)edges.size() / 2;
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t a = g.rid[edges[2 * e]], b = g.rid[edges[2 * e + 1]];
+    if (a < 0 || b < 0) continue;
+    g.edges.push_back(a);   // keep is ascending, so a < b still holds
+    g.edges.push_back(b);
+    g.emap.push_back((int32_t)e);
+  }
+  return g;
+}
+
+// Width of the sweep over the reduced graph in `order` (spins of the whole
+// graph, fixed ones skipped), or -1 when it cannot be built; `at_max`
+// receives the number of operations after which the state has that width,
+// `score` per spin the number of those after which it is live.
+int32_t reduced_width(int32_t n, const std::vector<int32_t>& edges, const std::vector<int32_t>& fixed,
+                      const std::vector<int32_t>& order, int32_t* at_max, std::vector<int32_t>* score) {
+  const ReducedGraph g = reduce_graph(n, edges, fixed);
+  if (g.keep.empty()) return -1;
+  Plan t;
+  t.n = (int32_t)g.keep.size();
+  t.m = (int64_t)g.emap.size();
+  t.edges = g.edges;
+  t.has_field = true;
+  for (int32_t v : order)
+    if (g.rid[v] >= 0) t.order.push_back(g.rid[v]);
+  if (!build_sweep_ops(t).empty()) return -1;
+  if (score) score->assign(n, 0);
+  int32_t cnt = 0;
+  std::vector<int32_t> live;
+  for (const SweepOp& o : t.ops) {
+    if (o.old_spin >= 0) {
+      auto it = std::find(live.begin(), live.end(), o.old_spin);
+      if (it != live.end()) live.erase(it);
+    }
+    if (o.new_spin >= 0 && std::find(live.begin(), live.end(), o.new_spin) == live.end()) live.push_back(o.new_spin);
+    if (o.w_after != t.width) continue;
+    ++cnt;
+    if (score)
+      for (int32_t v : live) ++(*score)[g.keep[v]];
+  }
+  if (at_max) *at_max = cnt;
+  return t.width;
+}
+
+// Fixed spins chosen one at a time: among the spins live at the most points
+// of the current sweep's largest width, the one whose removal leaves the
+// narrowest sweep (then the fewest points at that width, then the lower
+// index); after each choice a fresh greedy order of the reduced graph
+// replaces the sweep order when it is narrower.
+std::vector<int32_t> choose_fixed(int32_t n, const std::vector<int32_t>& edges, std::vector<int32_t> order,
+                                  int32_t s, uint64_t seed, int32_t trials) {
+  constexpr int CANDIDATES = 16;
+  std::vector<int32_t> fixed;
+  std::vector<int32_t> score;
+  for (int32_t j = 0; j < s; ++j) {
+    if (reduced_width(n, edges, fixed, order, nullptr, &score) < 0) break;
+    std::vector<int32_t> cand;
+    for (int32_t v = 0; v < n; ++v)
+      if (score[v] > 0 && std::find(fixed.begin(), fixed.end(), v) == fixed.end()) cand.push_back(v);
+    std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) { return score[a] > score[b]; });
+    if (cand.size() > (size_t)CANDIDATES) cand.resize(CANDIDATES);
+    int32_t best = -1, bw = 0, bc = 0;
+    for (int32_t v : cand) {
+      std::vector<int32_t> f = fixed;
+      f.push_back(v);
+      int32_t c = 0;
+      const int32_t w = reduced_width(n, edges, f, order, &c, nullptr);
+      if (w < 0) continue;
+      if (best < 0 || w < bw || (w == bw && c < bc)) {
+        best = v;
+        bw = w;
+        bc = c;
+      }
+    }
+    if (best < 0) break;
+    fixed.push_back(best);
+    const ReducedGraph g = reduce_graph(n, edges, fixed);
+    std::vector<int32_t> back;
+    for (int32_t v : greedy_order((int32_t)g.keep.size(), g.edges, seed, trials)) back.push_back(g.keep[v]);
+    int32_t cg = 0;
+    const int32_t wg = reduced_width(n, edges, fixed, back, &cg, nullptr);
+    if (wg >= 0 && (wg < bw || (wg == bw && cg < bc))) order = back;
+  }
+  return fixed;
+}
+
+int slice_device(Slice& S, const Plan& p, SliceArgs& A) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (!S.d || S.d->device != dev) {
+    S.d.reset(new (std::nothrow) SliceDev());
+    if (!S.d) return fail(TT_E_NOMEM, "out of host memory");
+    std::vector<int32_t> blob;
+    auto put = [&](const std::vector<int32_t>& v) {
+      blob.insert(blob.end(), v.begin(), v.end());
+      while (blob.size() % 64) blob.push_back(0);   // 256-byte aligned tables
+    };
+    put(S.spins);
+    put(S.keep);
+    put(S.emap);
+    put(S.cross_ptr);
+    put(S.cross_bit);
+    put(S.cross_edge);
+    put(S.inner_a);
+    put(S.inner_b);
+    put(S.inner_edge);
+    put(p.edges);
+    if (int r = upload(S.d->idx, blob)) return r;
+    S.d->device = dev;
+  }
+  const Plan& r = *reinterpret_cast<const Plan*>(S.red);
+  const int32_t* base = static_cast<const int32_t*>(S.d->idx.p);
+  size_t off = 0;
+  auto next = [&](const std::vector<int32_t>& v) {
+    const int32_t* q = base + off;
+    off += (v.size() + 63) / 64 * 64;
+    return q;
+  };
+  A.s = S.s;
+  A.n = p.n;
+  A.nr = r.n;
+  A.n_inner = (int32_t)S.inner_edge.size();
+  A.m = p.m;
+  A.mr = r.m;
+  A.spins = next(S.spins);
+  A.keep = next(S.keep);
+  A.emap = next(S.emap);
+  A.cross_ptr = next(S.cross_ptr);
+  A.cross_bit = next(S.cross_bit);
+  A.cross_edge = next(S.cross_edge);
+  A.inner_a = next(S.inner_a);
+  A.inner_b = next(S.inner_b);
+  A.inner_edge = next(S.inner_edge);
+  return 0;
+}
+const int32_t* slice_edges(const Slice& S) {
+  size_t off = 0;
+  for (const std::vector<int32_t>* v : {&S.spins, &S.keep, &S.emap, &S.cross_ptr, &S.cross_bit, &S.cross_edge,
+                                        &S.inner_a, &S.inner_b, &S.inner_edge})
+    off += (v->size() + 63) / 64 * 64;
+  return static_cast<const int32_t*>(S.d->idx.p) + off;
+}
+
+// Reduced instances per call of the reduced plan: all of them when their
+// state fits the budget, else halved until it does (at least one).
+enum SliceUse { SLICE_ENERGY, SLICE_BACKWARD, SLICE_COUNT };
+int64_t slice_chunk(const Plan& r, int64_t total, SliceUse use) {
+  const DevCache* dc = static_cast<const DevCache*>(r.dev);
+  int64_t have = 0;
+  if (dc) have = use == SLICE_COUNT ? (int64_t)(dc->cx.cap + dc->cn.cap) : (int64_t)(dc->state.cap + dc->ckpt.cap);
+  const int64_t budget = r.max_bytes > 0 ? r.max_bytes : budget_bytes(r) + have;
+  auto need = [&](int64_t c) -> int64_t {
+    if (use == SLICE_COUNT) return count_state_bytes(r, c, r.n > COUNT_EXACT_SPINS ? 4 : 3);
+    return state_bytes(r, c, false) * (use == SLICE_BACKWARD ? 2 : 1);
+  };
+  int64_t c = std::min<int64_t>(total, 65535);
+  while (c > 1 && need(c) > budget) c = (c + 1) / 2;
+  return c;
+}
+
+int check_sliced(const Plan& p, int32_t batch, int32_t dtype, const void* J, const void* h) {
+  const Slice& S = *static_cast<const Slice*>(p.slice);
+  if (batch < 1) return fail(TT_E_INVAL, "batch must be >= 1");
+  if (dtype != TT_F32 && dtype != TT_I32) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
+  if (p.m > 0 && !J) return fail(TT_E_INVAL, "null J");
+  if (p.has_field && !h) return fail(TT_E_INVAL, "plan has fields but h is NULL");
+  if (!p.has_field && h) return fail(TT_E_INVAL, "plan has no fields but h is given");
+  if (((int64_t)batch << S.s) > INT32_MAX) return fail(TT_E_INVAL, "batch x 2^%d slices exceeds 2^31", S.s);
+  return 0;
+}
+
+// Energies of all batch x 2^s slices (Er, device) and their constants (c).
+int sliced_energies(Plan& p, int32_t batch, int32_t dtype, const void* J, const void* h, SliceArgs& A,
+                    hipStream_t s) {
+  Slice& S = *static_cast<Slice*>(p.slice);
+  const Plan& r = *reinterpret_cast<const Plan*>(S.red);
+  if (int rc = slice_device(S, p, A)) return rc;
+  SliceDev& d = *S.d;
+  const int64_t total = (int64_t)batch << S.s;
+  const int64_t chunk = slice_chunk(r, total, SLICE_ENERGY);
+  if (int rc = d.jr.ensure((size_t)(chunk * std::max<int64_t>(r.m, 1) * 4))) return rc;
+  if (int rc = d.hr.ensure((size_t)(chunk * r.n * 4))) return rc;
+  if (int rc = d.c.ensure((size_t)total * sizeof(double))) return rc;
+  if (int rc = d.er.ensure((size_t)total * sizeof(double))) return rc;
+  double* c = static_cast<double*>(d.c.p);
+  double* er = static_cast<double*>(d.er.p);
+  for (int64_t r0 = 0; r0 < total; r0 += chunk) {
+    const int nr = (int)std::min<int64_t>(chunk, total - r0);
+    HIP_TRY(launch_slice_build(A, r0, nr, nullptr, dtype, J, p.has_field ? h : nullptr, d.jr.p, d.hr.p, c + r0, s));
+    if (int rc = tt_contract(S.red, nr, dtype, d.jr.p, d.hr.p, er + r0, s)) return rc;
+  }
+  return 0;
+}
+
+// The input check of the whole instances runs beside the work; its verdict
+// comes first (the reduced calls see sums of the same values).
+int sliced_checked(int rc, PendingCheck& pc, int32_t dtype) {
+  if (int r = check_finish(pc, dtype)) return r;
+  return rc;
+}
+
+int sliced_contract_run(Plan& p, int32_t batch, int32_t dtype, const void* J, const void* h, double* energy,
+                        hipStream_t s) {
+  SliceArgs A;
+  if (int rc = sliced_energies(p, batch, dtype, J, h, A, s)) return rc;
+  SliceDev& d = *static_cast<Slice*>(p.slice)->d;
+  HIP_TRY(launch_slice_min(static_cast<const double*>(d.er.p), static_cast<const double*>(d.c.p), A.s, batch, energy,
+                           nullptr, s));
+  return 0;
+}
+
+int sliced_contract(Plan& p, int32_t batch, int32_t dtype, const void* J, const void* h, double* energy,
+                    hipStream_t s) {
+  if (int rc = check_sliced(p, batch, dtype, J, h)) return rc;
+  if (!energy) return fail(TT_E_INVAL, "null energy");
+  const Plan& r = *reinterpret_cast<const Plan*>(static_cast<Slice*>(p.slice)->red);
+  if (int rc = early_budget(r, state_bytes(r, 1, false))) return rc;
+  PendingCheck pc;
+  if (int rc = check_start({check_item(J, h, p.m, p.n, batch, dtype)}, s, &pc)) return rc;
+  return sliced_checked(sliced_contract_run(p, batch, dtype, J, h, energy, s), pc, dtype);
+}
+
+// The first minimising slice of every instance, then the reduced backward on
+// those slices alone, and the configuration assembled from both.
+int sliced_backward_run(Plan& p, int32_t batch, int32_t dtype, const void* J, const void* h, double* energy,
+                        int8_t* sigma, float* dJ, float* dh, uint64_t tie, hipStream_t s) {
+  Slice& S = *static_cast<Slice*>(p.slice);
+  const Plan& r = *reinterpret_cast<const Plan*>(S.red);
+  SliceArgs A;
+  if (int rc = sliced_energies(p, batch, dtype, J, h, A, s)) return rc;
+  SliceDev& d = *S.d;
+  if (int rc = d.kb.ensure((size_t)batch * sizeof(int32_t))) return rc;
+  if (int rc = d.sr.ensure((size_t)batch * std::max<int32_t>(r.n, 1))) return rc;
+  if (int rc = d.eb.ensure((size_t)batch * sizeof(double))) return rc;
+  int32_t* kb = static_cast<int32_t*>(d.kb.p);
+  HIP_TRY(launch_slice_min(static_cast<const double*>(d.er.p), static_cast<const double*>(d.c.p), A.s, batch, energy,
+                           kb, s));
+  const int64_t chunk = std::min<int64_t>(batch, slice_chunk(r, batch, SLICE_BACKWARD));
+  if (int rc = d.jr.ensure((size_t)(chunk * std::max<int64_t>(r.m, 1) * 4))) return rc;
+  if (int rc = d.hr.ensure((size_t)(chunk * r.n * 4))) return rc;
+  if (int rc = d.c2.ensure((size_t)chunk * sizeof(double))) return rc;
+  int8_t* sr = static_cast<int8_t*>(d.sr.p);
+  for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+    const int nb = (int)std::min<int64_t>(chunk, batch - b0);
+    HIP_TRY(launch_slice_build(A, b0, nb, kb, dtype, J, p.has_field ? h : nullptr, d.jr.p, d.hr.p,
+                               static_cast<double*>(d.c2.p), s));
+    if (int rc = tt_backward_tie(S.red, nb, dtype, d.jr.p, d.hr.p, static_cast<double*>(d.eb.p) + b0,
+                                 sr + b0 * r.n, nullptr, nullptr, tie, s))
+      return rc;
+  }
+  HIP_TRY(launch_slice_pick(A, batch, sr, kb, slice_edges(S), sigma, dJ, dh, s));
+  return 0;
+}
+
+int sliced_backward(Plan& p, int32_t batch, int32_t dtype, const void* J, const void* h, double* energy,
+                    int8_t* sigma, float* dJ, float* dh, uint64_t tie, hipStream_t s) {
+  if (int rc = check_sliced(p, batch, dtype, J, h)) return rc;
+  if (!sigma) return fail(TT_E_INVAL, "null sigma");
+  if (p.n > 8192) return fail(TT_E_INVAL, "too many spins for the backward walk");
+  const Plan& r = *reinterpret_cast<const Plan*>(static_cast<Slice*>(p.slice)->red);
+  if (int rc = early_budget(r, state_bytes(r, 1, false))) return rc;
+  PendingCheck pc;
+  if (int rc = check_start({check_item(J, h, p.m, p.n, batch, dtype)}, s, &pc)) return rc;
+  return sliced_checked(sliced_backward_run(p, batch, dtype, J, h, energy, sigma, dJ, dh, tie, s), pc, dtype);
+}
+
+// Counts of every slice, combined on the host: E* = min over slices of
+// E'_k + c_k, g = the sum of g'_k over the slices that reach it (Eq. (4)).
+int sliced_count(Plan& p, int32_t batch, const int32_t* J, const int32_t* h, int64_t* energy, uint64_t* residues,
+                 uint8_t* exact_flag, hipStream_t s) {
+  if (int rc = check_sliced(p, batch, TT_I32, J, h)) return rc;
+  if (!energy || !residues) return fail(TT_E_INVAL, "null output");
+  Slice& S = *static_cast<Slice*>(p.slice);
+  const Plan& r = *reinterpret_cast<const Plan*>(S.red);
+  if (int rc = early_budget(r, count_state_bytes(r, 1, r.n > COUNT_EXACT_SPINS ? 4 : 3))) return rc;
+  SliceArgs A;
+  if (int rc = slice_device(S, p, A)) return rc;
+  SliceDev& d = *S.d;
+  const int64_t total = (int64_t)batch << S.s;
+  const int64_t chunk = slice_chunk(r, total, SLICE_COUNT);
+  if (int rc = d.jr.ensure((size_t)(chunk * std::max<int64_t>(r.m, 1) * 4))) return rc;
+  if (int rc = d.hr.ensure((size_t)(chunk * r.n * 4))) return rc;
+  if (int rc = d.c.ensure((size_t)total * sizeof(double))) return rc;
+  double* c = static_cast<double*>(d.c.p);
+  std::vector<int64_t> er((size_t)total);
+  std::vector<uint64_t> res((size_t)total * 3);
+  std::vector<uint8_t> ex((size_t)total);
+  for (int64_t r0 = 0; r0 < total; r0 += chunk) {
+    const int nr = (int)std::min<int64_t>(chunk, total - r0);
+    HIP_TRY(launch_slice_build(A, r0, nr, nullptr, TT_I32, J, p.has_field ? h : nullptr, d.jr.p, d.hr.p, c + r0, s));
+    if (int rc = tt_count(S.red, nr, static_cast<const int32_t*>(d.jr.p), static_cast<const int32_t*>(d.hr.p),
+                          er.data() + r0, res.data() + 3 * r0, ex.data() + r0, s))
+      return rc;
+  }
+  std::vector<double> ch((size_t)total);
+  HIP_TRY(hipMemcpyAsync(ch.data(), c, (size_t)total * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const uint64_t P[3] = {(1ull << 61) - 1, (1ull << 61) - 31, (1ull << 61) - 45};
+  const std::vector<uint32_t> M = big_mul(big_mul(big_mul(std::vector<uint32_t>{1u}, P[0]), P[1]), P[2]);
+  bool all_exact = true;
+  const int64_t ns = (int64_t)1 << S.s;
+  for (int64_t b = 0; b < batch; ++b) {
+    int64_t best = INT64_MAX;
+    for (int64_t k = 0; k < ns; ++k) best = std::min<int64_t>(best, er[b * ns + k] + (int64_t)std::llround(ch[b * ns + k]));
+    uint64_t acc[3] = {0, 0, 0};
+    bool exact = true;
+    std::vector<uint32_t> tot{0u};
+    for (int64_t k = 0; k < ns; ++k) {
+      const int64_t q = b * ns + k;
+      if (er[q] + (int64_t)std::llround(ch[q]) != best) continue;
+      for (int i = 0; i < 3; ++i) acc[i] = (uint64_t)(((unsigned __int128)acc[i] + res[3 * q + i]) % P[i]);
+      exact = exact && ex[q];
+      if (p.n > COUNT_EXACT_SPINS) {
+        uint32_t limbs[8];
+        crt_limbs(&res[3 * q], limbs);
+        tot = big_add(tot, std::vector<uint32_t>(limbs, limbs + 8));
+      }
+    }
+    // g <= 2^n: exact below M for n <= 182; beyond, every term must be exact
+    // and their sum below M
+    if (p.n > COUNT_EXACT_SPINS && !big_less(tot, M)) exact = false;
+    energy[b] = best;
+    for (int i = 0; i < 3; ++i) residues[3 * b + i] = acc[i];
+    if (exact_flag) exact_flag[b] = exact ? 1 : 0;
+    all_exact = all_exact && exact;
+  }
+  if (!exact_flag && !all_exact) return fail(TT_E_COUNT_OVERFLOW, "a degeneracy may exceed the count moduli");
+  return 0;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1826,6 +2191,127 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
   }
 }
 
+int tt_plan_create_sliced(int32_t n_spins, int64_t n_edges, const int32_t* edges, const tt_plan_opts* opts,
+                          int32_t n_fixed, const int32_t* fixed, tt_plan** out) {
+  try {
+    if (!out) return fail(TT_E_INVAL, "null output pointer");
+    *out = nullptr;
+    if (n_spins < 2 || n_spins > 8192) return fail(TT_E_INVAL, "n_spins must be in [2, 8192]");
+    if (n_fixed < 1 || n_fixed > 16 || n_fixed >= n_spins)
+      return fail(TT_E_INVAL, "n_fixed must be in [1, 16] and below n_spins");
+    if (n_edges < 0 || (n_edges > 0 && !edges)) return fail(TT_E_INVAL, "bad edge list");
+    tt_plan_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.q == 3 || o.kind == TT_ORDER_CHIMERA)
+      return fail(TT_E_INVAL, "sliced plans are Ising sweep plans (GREEDY or GIVEN order)");
+    if (o.kind != TT_ORDER_GREEDY && o.kind != TT_ORDER_GIVEN) return fail(TT_E_INVAL, "unknown order kind %d", o.kind);
+    // the whole graph's plan validates the graph and gives the base order
+    tt_plan* whole = nullptr;
+    tt_plan_opts wo = o;
+    wo.has_field = 1;
+    if (int r = tt_plan_create(n_spins, n_edges, edges, &wo, &whole)) {
+      if (r != TT_E_TOOBIG) return r;   // too wide to run whole is what slicing is for
+    }
+    std::vector<int32_t> base_order;
+    std::vector<int32_t> ev(edges, edges + 2 * n_edges);
+    if (whole) {
+      base_order = reinterpret_cast<Plan*>(whole)->order;
+      tt_plan_destroy(whole);
+    } else if (o.kind == TT_ORDER_GIVEN) {
+      base_order.assign(o.order, o.order + n_spins);
+    } else {
+      base_order = greedy_order(n_spins, ev, o.seed, o.trials > 0 ? o.trials : 32);
+    }
+    std::vector<int32_t> fx;
+    if (fixed) {
+      std::vector<char> seen(n_spins, 0);
+      for (int32_t j = 0; j < n_fixed; ++j) {
+        const int32_t v = fixed[j];
+        if (v < 0 || v >= n_spins || seen[v]) return fail(TT_E_INVAL, "fixed[%d] = %d is out of range or repeated", j, v);
+        seen[v] = 1;
+        fx.push_back(v);
+      }
+    } else {
+      fx = choose_fixed(n_spins, ev, base_order, n_fixed, o.seed, o.trials > 0 ? o.trials : 32);
+      if ((int32_t)fx.size() != n_fixed) return fail(TT_E_INVAL, "could not choose %d spins to fix", n_fixed);
+    }
+    const ReducedGraph g = reduce_graph(n_spins, ev, fx);
+    std::vector<int32_t> rorder;
+    for (int32_t v : base_order)
+      if (g.rid[v] >= 0) rorder.push_back(g.rid[v]);
+    if (o.kind == TT_ORDER_GREEDY) {   // a fresh search on the reduced graph, kept when narrower
+      std::vector<int32_t> gr = greedy_order((int32_t)g.keep.size(), g.edges, o.seed, o.trials > 0 ? o.trials : 32);
+      std::vector<int32_t> back;
+      for (int32_t v : gr) back.push_back(g.keep[v]);
+      const int32_t wf = reduced_width(n_spins, ev, fx, base_order, nullptr, nullptr);
+      const int32_t wg = reduced_width(n_spins, ev, fx, back, nullptr, nullptr);
+      if (wg >= 0 && (wf < 0 || wg < wf)) rorder = gr;
+    }
+    std::unique_ptr<Slice> S(new Slice());
+    S->s = n_fixed;
+    S->spins = fx;
+    S->keep = g.keep;
+    S->emap = g.emap;
+    std::vector<int32_t> bit(n_spins, -1);
+    for (int32_t j = 0; j < n_fixed; ++j) bit[fx[j]] = j;
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> cross(g.keep.size());
+    for (int64_t e = 0; e < n_edges; ++e) {
+      const int32_t a = ev[2 * e], b = ev[2 * e + 1];
+      if (bit[a] >= 0 && bit[b] >= 0) {
+        S->inner_a.push_back(bit[a]);
+        S->inner_b.push_back(bit[b]);
+        S->inner_edge.push_back((int32_t)e);
+      } else if (bit[a] >= 0) {
+        cross[g.rid[b]].push_back({bit[a], (int32_t)e});
+      } else if (bit[b] >= 0) {
+        cross[g.rid[a]].push_back({bit[b], (int32_t)e});
+      }
+    }
+    S->cross_ptr.push_back(0);
+    for (const auto& lst : cross) {
+      for (const auto& pr : lst) {
+        S->cross_bit.push_back(pr.first);
+        S->cross_edge.push_back(pr.second);
+      }
+      S->cross_ptr.push_back((int32_t)S->cross_bit.size());
+    }
+    tt_plan_opts ro = o;
+    ro.kind = TT_ORDER_GIVEN;
+    ro.order = rorder.data();
+    ro.has_field = 1;
+    if (int r = tt_plan_create((int32_t)g.keep.size(), (int64_t)g.emap.size(), g.edges.data(), &ro, &S->red)) return r;
+    static std::atomic<uint64_t> next_serial{1ull << 62};
+    std::unique_ptr<Plan> p(new Plan());
+    p->serial = next_serial.fetch_add(1);
+    p->n = n_spins;
+    p->m = n_edges;
+    p->edges = ev;
+    p->has_field = o.has_field != 0;
+    p->q = 2;
+    p->max_bytes = o.max_bytes;
+    p->order = fx;
+    for (int32_t v : reinterpret_cast<Plan*>(S->red)->order) p->order.push_back(g.keep[v]);
+    p->width = reinterpret_cast<Plan*>(S->red)->width;
+    p->slice = S.release();
+    *out = reinterpret_cast<tt_plan*>(p.release());
+    return TT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(TT_E_NOMEM, "out of host memory");
+  } catch (...) {
+    return fail(TT_E_INVAL, "planner failed");
+  }
+}
+
+int tt_plan_slice_info(const tt_plan* plan, int32_t* fixed_out) {
+  if (!plan) return fail(TT_E_INVAL, "null plan");
+  const Plan& p = *reinterpret_cast<const Plan*>(plan);
+  if (!p.slice) return 0;
+  const Slice& S = *static_cast<const Slice*>(p.slice);
+  if (fixed_out) std::copy(S.spins.begin(), S.spins.end(), fixed_out);
+  return S.s;
+}
+
 int tt_plan_info(const tt_plan* plan, tt_plan_stats* out) {
   if (!plan || !out) return fail(TT_E_INVAL, "null argument");
   const Plan& p = *reinterpret_cast<const Plan*>(plan);
@@ -1834,6 +2320,21 @@ int tt_plan_info(const tt_plan* plan, tt_plan_stats* out) {
   out->n_edges = p.m;
   out->width = p.width;
   out->n_ops = (int32_t)p.ops.size();
+  if (p.slice) {   // the reduced plan's figures, its work once per slice
+    const Slice& S = *static_cast<const Slice*>(p.slice);
+    tt_plan_stats r;
+    if (int rc = tt_plan_info(S.red, &r)) return rc;
+    const double ns = std::ldexp(1.0, S.s);
+    out->width = r.width;
+    out->n_ops = r.n_ops;
+    out->n_passes = r.n_passes;
+    out->n_count_passes = r.n_count_passes;
+    out->terms = r.terms * ns;
+    out->elementwise = r.elementwise * ns;
+    out->reduce_ops = r.reduce_ops * ns;
+    out->entry_updates = r.entry_updates * ns;
+    return TT_OK;
+  }
   if (p.q == 3) {
     const PottsCache* pc = static_cast<const PottsCache*>(p.potts);
     out->n_passes = (int32_t)pc->e.passes.size();
@@ -1865,6 +2366,7 @@ int tt_plan_order(const tt_plan* plan, int32_t* order_out) {
 int tt_plan_ops(const tt_plan* plan, int32_t* out, int64_t cap, int32_t* final_slot_spin, int32_t* final_width) {
   if (!plan) return fail(TT_E_INVAL, "null plan");
   const Plan& p = *reinterpret_cast<const Plan*>(plan);
+  if (p.slice) return tt_plan_ops(static_cast<const Slice*>(p.slice)->red, out, cap, final_slot_spin, final_width);
   const int64_t n = (int64_t)p.ops.size();
   for (int64_t k = 0; k < n && k < cap && out; ++k) {
     const SweepOp& o = p.ops[k];
@@ -1886,6 +2388,7 @@ int tt_plan_ops(const tt_plan* plan, int32_t* out, int64_t cap, int32_t* final_s
 int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t cap) {
   if (!plan) return fail(TT_E_INVAL, "null plan");
   const Plan& p = *reinterpret_cast<const Plan*>(plan);
+  if (p.slice) return tt_plan_program(static_cast<const Slice*>(p.slice)->red, which, out, cap);
   if (p.q == 3) {
     const PottsCache* pc = static_cast<const PottsCache*>(p.potts);
     const void* src = nullptr;
@@ -1896,6 +2399,15 @@ int64_t tt_plan_program(const tt_plan* plan, int32_t which, void* out, int64_t c
       case 9: src = &pc->e.red; bytes = (int64_t)sizeof(PottsReduce); break;
       default: return fail(TT_E_INVAL, "program part %d does not exist for 3-state plans (7, 8, 9)", which);
     }
+    if (out && bytes) std::memcpy(out, src, (size_t)std::min(bytes, cap));
+    return bytes;
+  }
+  if (which == 10 || which == 11) {   // the counting path's passes and ops
+    Encoded cen;
+    if (int r = encode(p, p.count_passes, cen)) return r;
+    const void* src = which == 10 ? static_cast<const void*>(cen.passes.data()) : cen.ops.data();
+    const int64_t bytes = which == 10 ? (int64_t)(cen.passes.size() * sizeof(DevPass))
+                                      : (int64_t)(cen.ops.size() * sizeof(DevOp));
     if (out && bytes) std::memcpy(out, src, (size_t)std::min(bytes, cap));
     return bytes;
   }
@@ -1933,12 +2445,16 @@ void tt_plan_destroy(tt_plan* plan) {
   delete static_cast<DevCache*>(p->dev);
   drop_host_prog(*p);
   delete static_cast<PottsCache*>(p->potts);
+  delete static_cast<Slice*>(p->slice);
   delete p;
 }
 
 int tt_contract(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, double* energy,
                 void* stream) {
   try {
+    if (plan && reinterpret_cast<Plan*>(plan)->slice)
+      return sliced_contract(*reinterpret_cast<Plan*>(plan), batch, dtype, J, h, energy,
+                             static_cast<hipStream_t>(stream));
     if (int r = check_common(plan, batch, dtype, J, h)) return r;
     if (!energy) return fail(TT_E_INVAL, "null energy");
     Plan& p = *reinterpret_cast<Plan*>(plan);
@@ -2063,6 +2579,9 @@ int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, cons
 int tt_backward_tie(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, const void* h, double* energy,
                     int8_t* sigma, float* dJ, float* dh, uint64_t tie, void* stream) {
   try {
+    if (plan && reinterpret_cast<Plan*>(plan)->slice)
+      return sliced_backward(*reinterpret_cast<Plan*>(plan), batch, dtype, J, h, energy, sigma, dJ, dh, tie,
+                             static_cast<hipStream_t>(stream));
     if (int r = check_common(plan, batch, dtype, J, h)) return r;
     if (!sigma) return fail(TT_E_INVAL, "null sigma");
     Plan& p = *reinterpret_cast<Plan*>(plan);
@@ -2229,7 +2748,7 @@ int tt_config_fd(tt_plan* plan, const float* J, const float* h, double delta, do
   try {
     if (!plan) return fail(TT_E_INVAL, "null plan");
     Plan& p = *reinterpret_cast<Plan*>(plan);
-    if (p.q != 2 || p.is_chimera) return fail(TT_E_INVAL, "finite differences need an Ising sweep plan");
+    if (p.q != 2 || p.is_chimera || p.slice) return fail(TT_E_INVAL, "finite differences need an unsliced Ising sweep plan");
     if (!p.has_field) return fail(TT_E_INVAL, "the plan must carry fields (opts.has_field = 1)");
     if ((p.m > 0 && !J) || !energy || !sigma) return fail(TT_E_INVAL, "null argument");
     if (!(delta > 0.0) || !std::isfinite(delta)) return fail(TT_E_INVAL, "delta must be positive and finite");
@@ -2270,7 +2789,7 @@ int tt_sample_ground_state(tt_plan* plan, const int32_t* J, const int32_t* h, co
   try {
     if (!plan) return fail(TT_E_INVAL, "null plan");
     Plan& p = *reinterpret_cast<Plan*>(plan);
-    if (p.q != 2 || p.is_chimera) return fail(TT_E_INVAL, "sampling needs an Ising sweep plan");
+    if (p.q != 2 || p.is_chimera || p.slice) return fail(TT_E_INVAL, "sampling needs an unsliced Ising sweep plan");
     if (!p.has_field) return fail(TT_E_INVAL, "the plan must carry fields (opts.has_field = 1) to clamp spins");
     if ((p.m > 0 && !J) || !u || !sigma || !energy) return fail(TT_E_INVAL, "null argument");
     for (int k = 0; k < p.n; ++k)
@@ -2353,6 +2872,9 @@ int tt_count_moduli(uint64_t moduli_out[3]) {
 int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, int64_t* energy, uint64_t* residues,
              uint8_t* exact_flag, void* stream) {
   try {
+    if (plan && reinterpret_cast<Plan*>(plan)->slice)
+      return sliced_count(*reinterpret_cast<Plan*>(plan), batch, J, h, energy, residues, exact_flag,
+                          static_cast<hipStream_t>(stream));
     if (int r = check_common(plan, batch, TT_I32, J, h)) return r;
     if (!energy || !residues) return fail(TT_E_INVAL, "null output");
     Plan& p = *reinterpret_cast<Plan*>(plan);
@@ -2540,9 +3062,18 @@ int tt_count_to_decimal(const uint64_t residues[3], char* buf, size_t len) {
 
 int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype, const void* J, const int64_t* j_off,
                        double* energy, int8_t* sigma, const int64_t* s_off, float* dJ, void* stream) {
+  return tt_contract_uneven_fields(n_inst, plans, dtype, J, j_off, nullptr, nullptr, energy, sigma, s_off, dJ, nullptr,
+                                   stream);
+}
+
+int tt_contract_uneven_fields(int32_t n_inst, tt_plan* const* plans, int32_t dtype, const void* J, const int64_t* j_off,
+                              const void* h, const int64_t* h_off, double* energy, int8_t* sigma, const int64_t* s_off,
+                              float* dJ, float* dh, void* stream) {
   try {
     if (n_inst < 1 || !plans || !j_off || !energy || !J) return fail(TT_E_INVAL, "bad uneven-batch arguments");
     if (sigma && !s_off) return fail(TT_E_INVAL, "sigma needs s_off");
+    if (h && !h_off) return fail(TT_E_INVAL, "h needs h_off");
+    if (dh && (!sigma || !h)) return fail(TT_E_INVAL, "dh needs sigma and h");
     if (dtype != TT_F32 && dtype != TT_I32) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
     const size_t esz = dtype == TT_F32 ? sizeof(float) : sizeof(int32_t);
     std::vector<Group> groups(n_inst);
@@ -2550,9 +3081,10 @@ int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype, con
     for (int i = 0; i < n_inst; ++i) {
       if (!plans[i]) return fail(TT_E_INVAL, "null plan %d", i);
       Plan& p = *reinterpret_cast<Plan*>(plans[i]);
-      if (p.has_field) return fail(TT_E_INVAL, "uneven batches take no fields");
+      if (p.has_field && !h) return fail(TT_E_INVAL, "plan %d has fields but h is NULL", i);
       if (p.n_regs != 1) return fail(TT_E_INVAL, "multi-register plans are not supported here");
       if (p.is_chimera) return fail(TT_E_INVAL, "chimera plans are solved with tt_contract / tt_backward");
+      if (p.slice) return fail(TT_E_INVAL, "sliced plans are solved with tt_contract / tt_backward / tt_count");
       for (int k = 0; k < i; ++k)
         if (plans[k] == plans[i]) return fail(TT_E_INVAL, "each instance needs its own plan object");
       if (j_off[i] < 0) return fail(TT_E_INVAL, "negative j_off[%d]", i);
@@ -2562,11 +3094,16 @@ int tt_contract_uneven(int32_t n_inst, tt_plan* const* plans, int32_t dtype, con
       g.p = &p;
       g.batch = 1;
       g.J = static_cast<const char*>(J) + (size_t)j_off[i] * esz;
-      checks.push_back(check_item(g.J, nullptr, p.m, p.n, 1, dtype));
+      if (p.has_field) {
+        if (h_off[i] < 0) return fail(TT_E_INVAL, "negative h_off[%d]", i);
+        g.h = static_cast<const char*>(h) + (size_t)h_off[i] * esz;
+      }
+      checks.push_back(check_item(g.J, g.h, p.m, p.n, 1, dtype));
       g.energy = energy + i;
       if (sigma) {
         g.sigma = sigma + s_off[i];
         g.dJ = dJ ? dJ + j_off[i] : nullptr;
+        g.dh = (dh && p.has_field) ? dh + h_off[i] : nullptr;
       }
     }
     const hipStream_t s = static_cast<hipStream_t>(stream);

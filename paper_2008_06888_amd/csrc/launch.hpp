@@ -57,6 +57,38 @@ hipError_t launch_fd_build(const float* J, const float* h, int64_t m, int n, flo
 hipError_t launch_fd_sigma(const double* E, const float* J, const float* h, const int32_t* edges, int64_t m, int n,
                            int8_t* sigma, double* energy, double* e_sigma, hipStream_t s);
 
+// sliced plans: index tables (device int32) that reduce an instance to its
+// 2^s slices; reduced instance r is instance r >> s with the fixed spins set
+// to the bits of r & (2^s - 1) (bit j = 1 <-> fixed spin j at sigma = -1)
+struct SliceArgs {
+  int32_t s;                  // fixed spins
+  int32_t n, nr;              // spins of the graph and of the reduced graph
+  int32_t n_inner;            // bonds between two fixed spins
+  int64_t m, mr;              // edges of the graph and of the reduced graph
+  const int32_t* spins;       // [s] spin of fixed index j
+  const int32_t* keep;        // [nr] reduced spin -> spin
+  const int32_t* emap;        // [mr] reduced edge -> edge
+  const int32_t* cross_ptr;   // [nr + 1] per reduced spin, its bonds to fixed spins:
+  const int32_t* cross_bit;   //   fixed index j of the other end
+  const int32_t* cross_edge;  //   and the edge
+  const int32_t* inner_a;     // [n_inner] fixed indices of both ends, and the edge
+  const int32_t* inner_b;
+  const int32_t* inner_edge;
+};
+// reduced couplings Jr, fields hr and constant energies c of n_red reduced
+// instances starting at r0 (kpick == nullptr), or of the slices kpick[b] of
+// instances b = r0 .. r0 + n_red - 1; h may be null (zero fields)
+hipError_t launch_slice_build(const SliceArgs& A, int64_t r0, int n_red, const int32_t* kpick, int dtype,
+                              const void* J, const void* h, void* Jr, void* hr, double* c, hipStream_t s);
+// energy[b] = min over the slices of instance b of Er + c, kbest[b] the first
+// minimising slice (either output may be null)
+hipError_t launch_slice_min(const double* Er, const double* c, int s, int batch, double* energy, int32_t* kbest,
+                            hipStream_t st);
+// sigma of each instance from the ground state sr of its chosen slice, and
+// the gradients dJ = -sigma_i sigma_j, dh = -sigma_i (either may be null)
+hipError_t launch_slice_pick(const SliceArgs& A, int batch, const int8_t* sr, const int32_t* kbest,
+                             const int32_t* edges, int8_t* sigma, float* dJ, float* dh, hipStream_t s);
+
 // workspace of the allocation-free contraction: its size, and the current
 // device's address of it
 constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;

@@ -132,6 +132,7 @@ struct Plan {
   void* host_prog = nullptr;         // host encoding of the energy passes (owned, see capi)
   int32_t q = 2;                     // labels per spin: 2 (Ising) or 3 (Potts glass, App. C)
   void* potts = nullptr;             // 3-label programs and device cache (owned, see capi)
+  void* slice = nullptr;             // sliced plan: fixed spins and the reduced plan (owned, see capi)
   uint64_t serial = 0;               // unique over the process lifetime (never reused)
 };
 
