@@ -321,6 +321,33 @@ def bench_cubic(args):
                       "entropy_per_spin": math.log(g[0]) / 216}))
 
 
+def bench_pass_profile(args):
+    """The headline batch's energy passes alone (tt_contract, one part, tile 2^bits),
+    `steps` calls: a clean per-launch shape for kernel traces and counter runs."""
+    import numpy as np
+    import torch
+
+    from paper_2008_06888_amd import binding as B
+    from paper_2008_06888_amd import instances as I
+    L, batch = 16, 64
+    pm1 = I.config_instances(0, batch=batch, L=L)
+    J = torch.tensor(np.stack([x.J for x in pm1]), device="cuda:0")
+    plan = B.Plan(L * L, pm1[0].edges, order=list(range(L * L)), tile_bits=args.pass_profile, parts=1)
+    for _ in range(max(args.warmup, 1)):
+        B.contract(plan, J)
+    torch.cuda.synchronize()
+    B.prof_reset()
+    B.prof_enable(True)
+    for _ in range(args.steps):
+        B.contract(plan, J)
+    torch.cuda.synchronize()
+    B.prof_enable(False)
+    ms, launches = B.prof_read("sweep_pass")
+    print(json.dumps({"workload": "square16x16_pm1_b64 energy passes", "tile_bits": args.pass_profile,
+                      "passes": plan.info()["n_passes"], "launches": launches,
+                      "avg_launch_ms": ms / max(launches, 1)}))
+
+
 def copy_calibration(args):
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale the counters."""
     import torch
@@ -345,6 +372,8 @@ def main():
                     help="instead: time the dense tropical product at M = N = K = S")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead: run a plain device copy of MIB MiB (scale for HBM byte counters)")
+    ap.add_argument("--pass-profile", type=int, default=0, metavar="BITS",
+                    help="instead: only the headline batch's energy passes at tile 2^BITS, one part (profiling)")
     ap.add_argument("--workload", default="square16_pm1_b64",
                     choices=["square16_pm1_b64", "chimera8x8_pm1", "square32_pm1_count", "reg3_uneven_b16",
                              "potts18_pm1", "cubic6_pm1"],
@@ -357,6 +386,8 @@ def main():
         return bench_tgemm(args)
     if args.copy_calibration:
         return copy_calibration(args)
+    if args.pass_profile:
+        return bench_pass_profile(args)
     if args.workload == "chimera8x8_pm1":
         return bench_chimera(args)
     if args.workload == "square32_pm1_count":
