@@ -195,11 +195,17 @@ def bench_square32(args):
     B.prof_enable(False)
     kern = {k: B.prof_read(k) for k in ("count_pass", "count_reduce")}
     t_e = _timed(lambda: B.contract(plan, J), max(1, min(args.steps, 5)))
+    # the same energy with int16 couplings: int16 state, packed 16-bit passes
+    J16 = J.to(torch.int16)
+    E16 = B.contract(plan, J16)
+    assert int(E16.cpu().numpy()[0]) == int(Ec[0])
+    t_e16 = _timed(lambda: B.contract(plan, J16), max(1, min(args.steps, 5)))
     print(json.dumps({"metric": "32x32 +-J ground-state energy and degeneracy wall time", "value": dt, "unit": "s",
                       "higher_is_better": False, "dtype": "f32 (integer-valued) + 3 x u64 residues",
                       "config": {"workload": "square32_pm1_count", "spins": 1024},
                       "energy": int(Ec[0]), "degeneracy": str(g[0]), "entropy_per_spin": math.log(g[0]) / 1024,
-                      "energy_only_s": t_e, "kernel_ms": {k: v[0] for k, v in kern.items()}}))
+                      "energy_only_s": t_e, "energy_only_int16_s": t_e16,
+                      "kernel_ms": {k: v[0] for k, v in kern.items()}}))
 
 
 def bench_uneven(args):
@@ -329,9 +335,11 @@ def bench_pass_profile(args):
 
     from paper_2008_06888_amd import binding as B
     from paper_2008_06888_amd import instances as I
-    L, batch = 16, 64
+    L, batch = 16, args.pass_batch
     pm1 = I.config_instances(0, batch=batch, L=L)
     J = torch.tensor(np.stack([x.J for x in pm1]), device="cuda:0")
+    if args.i16:
+        J = J.to(torch.int16)
     plan = B.Plan(L * L, pm1[0].edges, order=list(range(L * L)), tile_bits=args.pass_profile, parts=1)
     for _ in range(max(args.warmup, 1)):
         B.contract(plan, J)
@@ -343,7 +351,8 @@ def bench_pass_profile(args):
     torch.cuda.synchronize()
     B.prof_enable(False)
     ms, launches = B.prof_read("sweep_pass")
-    print(json.dumps({"workload": "square16x16_pm1_b64 energy passes", "tile_bits": args.pass_profile,
+    print(json.dumps({"workload": f"square16x16_pm1_b{batch} energy passes", "tile_bits": args.pass_profile,
+                      "couplings": str(J.dtype).replace("torch.", ""),
                       "passes": plan.info()["n_passes"], "launches": launches,
                       "avg_launch_ms": ms / max(launches, 1)}))
 
@@ -374,6 +383,8 @@ def main():
                     help="instead: run a plain device copy of MIB MiB (scale for HBM byte counters)")
     ap.add_argument("--pass-profile", type=int, default=0, metavar="BITS",
                     help="instead: only the headline batch's energy passes at tile 2^BITS, one part (profiling)")
+    ap.add_argument("--pass-batch", type=int, default=64, help="with --pass-profile: lattices per call")
+    ap.add_argument("--i16", action="store_true", help="with --pass-profile: int16 couplings (TT_I16)")
     ap.add_argument("--workload", default="square16_pm1_b64",
                     choices=["square16_pm1_b64", "chimera8x8_pm1", "square32_pm1_count", "reg3_uneven_b16",
                              "potts18_pm1", "cubic6_pm1"],
@@ -458,6 +469,9 @@ def main():
     t_single = _timed(one_by_one, extra_steps)
     B.graphs_enable(True)
     out["context"] = {"one_instance_per_call_solves_s": batch / t_single}
+    # the same batch with int16 couplings (TT_I16: int16 state, packed 16-bit passes)
+    li = run_lattice(args, B, pm1[0].edges, n, J.to(torch.int16), None, "square16x16_pm1_b64_i16")
+    out["context"]["int16_couplings"] = {k: li[k] for k in ("solves_s", "ms_per_step", "kernel_ms_per_step", "plan")}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pm1)
     print(json.dumps(out))

@@ -61,7 +61,16 @@ typedef enum tt_status {
 
 typedef enum tt_dtype {
   TT_F32 = 0,               /* J, h as float32; energies computed in float32 */
-  TT_I32 = 1                /* J, h as int32; computed exactly (|values| < 2^24) */
+  TT_I32 = 1,               /* J, h as int32; computed exactly (|values| < 2^24) */
+  TT_I16 = 2                /* J, h as int16; the state is held as int16 (half the bytes)
+                               and worked on two entries per instruction (packed 16-bit
+                               integers), exactly, for sum|J| + sum|h| < 2^13 (TT_E_RANGE
+                               otherwise; Sec. V keeps the chimera state in Int16 for the
+                               same reason). tt_contract, tt_backward(_tie) and
+                               tt_plan_autotune on sweep plans (sliced ones included);
+                               other calls and chimera plans return TT_E_DTYPE, and a
+                               backward whose pass inputs do not all fit the budget
+                               returns TT_E_TOOBIG (no recomputation at int16). */
 } tt_dtype;
 
 typedef enum tt_order_kind {

@@ -29,7 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 TT_OK = 0
 TT_E_INVAL, TT_E_DTYPE, TT_E_RANGE, TT_E_TOOBIG = -1, -2, -3, -4
 TT_E_COUNT_OVERFLOW, TT_E_DEVICE, TT_E_NOMEM = -5, -6, -7
-TT_F32, TT_I32 = 0, 1
+TT_F32, TT_I32, TT_I16 = 0, 1, 2
 NOALLOC_MAX_BYTES = 64 << 20      # workspace of tt_contract_noalloc per GPU (TT_NOALLOC_MAX_BYTES)
 ORDER_GREEDY, ORDER_GIVEN, ORDER_CHIMERA = 0, 1, 2
 
@@ -248,7 +248,9 @@ def _dtype_code(t) -> int:
         return TT_F32
     if t.dtype == torch.int32:
         return TT_I32
-    raise TypeError(f"J must be float32 or int32, got {t.dtype}")
+    if t.dtype == torch.int16:
+        return TT_I16
+    raise TypeError(f"J must be float32, int32 or int16, got {t.dtype}")
 
 
 def _ptr(t):

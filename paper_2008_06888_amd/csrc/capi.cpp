@@ -499,11 +499,22 @@ int check_common(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, con
   if (p.q != 2) return fail(TT_E_INVAL, "plan is for 3-state labels: use the tt_potts_* calls");
   if (p.slice) return fail(TT_E_INVAL, "sliced plans are solved with tt_contract, tt_backward(_tie) and tt_count");
   if (batch < 1) return fail(TT_E_INVAL, "batch must be >= 1");
-  if (dtype != TT_F32 && dtype != TT_I32) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
+  if (dtype != TT_F32 && dtype != TT_I32 && dtype != TT_I16) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
+  if (dtype == TT_I16 && (p.is_chimera || p.n_regs != 1))
+    return fail(TT_E_DTYPE, "int16 couplings run on sweep plans only (not chimera)");
   if (p.m > 0 && !J) return fail(TT_E_INVAL, "null J");
   if (p.has_field && !h) return fail(TT_E_INVAL, "plan has fields but h is NULL");
   if (!p.has_field && h) return fail(TT_E_INVAL, "plan has no fields but h is given");
   return 0;
+}
+
+// Bytes per coupling / field, and per state entry, of a dtype.
+size_t coup_esz(int32_t dtype) { return dtype == TT_I16 ? sizeof(int16_t) : sizeof(float); }
+size_t state_esz(int32_t dtype) { return dtype == TT_I16 ? sizeof(int16_t) : sizeof(float); }
+// Entry `k` of a state buffer held at the dtype's entry size (buffers are
+// typed float* on the host whatever the entry size).
+float* state_at(float* base, int64_t k, int32_t dtype) {
+  return base ? reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (size_t)k * state_esz(dtype)) : nullptr;
 }
 
 // A count pass may overwrite its input when every tile reads exactly the
@@ -613,6 +624,9 @@ struct PendingCheck {
 
 // The exact range of integer couplings in the float32 state.
 constexpr int64_t I32_EXACT = int64_t(1) << 24;
+// int16 couplings: every state value within [-S, S] and every intermediate
+// of a gate within [-3S, 3S] stays inside int16 for S below this
+constexpr int64_t I16_EXACT = int64_t(1) << 13;
 
 // Launches of at most CHECK_ITEMS items, each with its own status range:
 // status[i] (device) for the i-th instance of the items.
@@ -697,8 +711,11 @@ int check_statuses(const uint32_t* st, int64_t n, int32_t dtype) {
   for (int64_t i = 0; i < n; ++i) {
     if (st[i] & CHK_NONFINITE) return fail(TT_E_INVAL, "instance %lld: a coupling or field is not finite", (long long)i);
     if (st[i] & CHK_RANGE)
-      return fail(TT_E_RANGE, "instance %lld: sum|J| + sum|h| reaches 2^24, beyond the exact range of %s",
-                  (long long)i, dtype == TT_I32 ? "int32 couplings in the float32 state" : "the state");
+      return fail(TT_E_RANGE, "instance %lld: sum|J| + sum|h| reaches 2^%d, beyond the exact range of %s",
+                  (long long)i, dtype == TT_I16 ? 13 : 24,
+                  dtype == TT_I32   ? "int32 couplings in the float32 state"
+                  : dtype == TT_I16 ? "the int16 state"
+                                    : "the state");
   }
   return 0;
 }
@@ -736,8 +753,8 @@ CheckItem check_item(const void* J, const void* h, int64_t m, int64_t n, int32_t
   c.jst = m;
   c.hst = n;
   c.batch = batch;
-  c.dtype = dtype == TT_F32 ? 0 : 1;
-  c.limit = I32_EXACT;
+  c.dtype = dtype == TT_F32 ? 0 : dtype == TT_I16 ? 2 : 1;
+  c.limit = dtype == TT_I16 ? I16_EXACT : I32_EXACT;
   return c;
 }
 
@@ -831,6 +848,7 @@ struct CallTables {
     int64_t n_wg;
     int threads;   // the largest tile's thread count among the items
     size_t lds;    // the largest tile's bytes among the items
+    int ng;        // int16 pass: groups of 16 entries per thread (1 or 2)
   };
   std::vector<Launch> levels;
   size_t red_off = 0, bwd_off = 0, ckpt_off = 0;
@@ -886,13 +904,15 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
     int64_t wg = 0;
     int threads = 64;
     size_t lds = 0;
+    int ng = 1;
     auto flush = [&]() {
       if (items.empty()) return;
-      ct.levels.push_back({ct.blob.add(items.data(), items.size()), (int)items.size(), wg, threads, lds});
+      ct.levels.push_back({ct.blob.add(items.data(), items.size()), (int)items.size(), wg, threads, lds, ng});
       items.clear();
       wg = 0;
       threads = 64;
       lds = 0;
+      ng = 1;
     };
     // one launch per tile size: a launch's workgroups are all as large as
     // its largest tile needs, so tiles of different sizes go separately
@@ -911,8 +931,11 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
         flush();
         cur_t = P.t;
       }
-      threads = std::max(threads, 1 << P.tb);
-      lds = std::max(lds, pass_lds_bytes(P.t));
+      // int16 passes of 2^11 entries or more: two groups per thread, half the threads
+      // (a launch holds one tile size, so one tb)
+      ng = (dtype == TT_I16 && P.tb >= 7) ? 2 : 1;
+      threads = std::max(threads, 1 << (ng == 2 ? P.tb - 1 : P.tb));
+      lds = std::max(lds, dtype == TT_I16 ? (sizeof(int16_t) << P.t) : pass_lds_bytes(P.t));
       PassItem it;
       std::memset(&it, 0, sizeof(it));
       it.P = g.d_passes + q;
@@ -950,7 +973,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
     for (int b = 0; b < g.batch; ++b) {
       RedItem r;
       std::memset(&r, 0, sizeof(r));
-      r.st = fuse ? nullptr : g.bufs[np] + (int64_t)b * g.strides[np];
+      r.st = fuse ? nullptr : state_at(g.bufs[np], (int64_t)b * g.strides[np], dtype);
       r.chunk_begin = ct.chunks;
       r.energy = g.energy ? g.energy + b : nullptr;
       r.arg = g.arg + b;
@@ -968,12 +991,12 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
     const int np = (int)g.dc->ep.passes.size();
     for (int b = 0; b < g.batch; ++b) {
       ct.ckpt_first.push_back(ptrs.size());
-      for (int q = 0; q < np; ++q) ptrs.push_back(g.bufs[q] ? g.bufs[q] + (int64_t)b * g.strides[q] : nullptr);
+      for (int q = 0; q < np; ++q) ptrs.push_back(state_at(g.bufs[q], (int64_t)b * g.strides[q], dtype));
     }
   }
   ct.ckpt_off = ct.blob.add(ptrs.data(), ptrs.size());
   std::vector<BwdItem> bwd;
-  const size_t esz = dtype == TT_F32 ? sizeof(float) : sizeof(int32_t);
+  const size_t esz = coup_esz(dtype);
   for (Group& g : groups) {
     const int np = (int)g.dc->ep.passes.size();
     for (int b = 0; b < g.batch; ++b) {
@@ -1028,13 +1051,13 @@ int enqueue_launches(const CallTables& ct, const char* dev, float* pv, uint64_t*
   for (const CallTables::Launch& L : ct.levels) {
     ProfScope ps(s, "sweep_pass", true);
     HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s,
-                        ps.start(), ps.stop()));
+                        ps.start(), ps.stop(), L.ng));
     ps.launched();
   }
   if (!ct.bwd_ranks && ct.n_red > 0) {
     ProfScope ps(s, "final_reduce");
     HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks, pv, pi, s,
-                          ct.fused));
+                          ct.fused, dtype == TT_I16));
   }
   if (ct.n_bwd) {
     ProfScope ps(s, "sweep_backward");
@@ -1176,17 +1199,18 @@ int aux_streams(AuxStreams** out) {
 
 // Instances b0 .. b0 + nb - 1 of a prepared group (inputs, outputs and
 // state buffers are all instance-major).
-Group sub_group(const Group& g, int b0, int nb) {
+Group sub_group(const Group& g, int b0, int nb, int32_t dtype) {
   Group h = g;
   const int64_t n = g.p->n, m = g.p->m;
+  const size_t ce = coup_esz(dtype);
   h.batch = nb;
-  h.J = g.J ? static_cast<const char*>(g.J) + (size_t)b0 * (size_t)m * 4 : nullptr;   // fp32 or int32
-  h.h = g.h ? static_cast<const char*>(g.h) + (size_t)b0 * (size_t)n * 4 : nullptr;
+  h.J = g.J ? static_cast<const char*>(g.J) + (size_t)b0 * (size_t)m * ce : nullptr;
+  h.h = g.h ? static_cast<const char*>(g.h) + (size_t)b0 * (size_t)n * ce : nullptr;
   h.energy = g.energy ? g.energy + b0 : nullptr;
   h.sigma = g.sigma ? g.sigma + (size_t)b0 * (size_t)n : nullptr;
   h.dJ = g.dJ ? g.dJ + (size_t)b0 * (size_t)m : nullptr;
   h.dh = g.dh ? g.dh + (size_t)b0 * (size_t)n : nullptr;
-  for (size_t q = 0; q < g.bufs.size(); ++q) h.bufs[q] = g.bufs[q] + (size_t)b0 * (size_t)g.part_st[q];
+  for (size_t q = 0; q < g.bufs.size(); ++q) h.bufs[q] = state_at(g.bufs[q], (int64_t)b0 * g.part_st[q], dtype);
   h.arg = g.arg + b0;
   return h;
 }
@@ -1224,7 +1248,7 @@ int run_split(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   std::vector<std::vector<Group>> gp(parts);
   for (int k = 0; k < parts; ++k) {
     const int b0 = (int)((int64_t)g.batch * k / parts), b1 = (int)((int64_t)g.batch * (k + 1) / parts);
-    gp[k].push_back(sub_group(g, b0, b1 - b0));
+    gp[k].push_back(sub_group(g, b0, b1 - b0, dtype));
   }
   DevCache* dc = g.dc;
   const bool fuse = can_fuse_reduce(gp[0]);
@@ -1437,7 +1461,12 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
     const int64_t need = state_bytes(p, groups[0].batch, true);
     const DevCache* dc = static_cast<const DevCache*>(p.dev);
     const int64_t have = dc ? (int64_t)dc->ckpt.cap : 0;
-    if (need > have && need > budget_bytes(p) + have) return run_backward_recompute(groups[0], dtype, s);
+    if (need > have && need > budget_bytes(p) + have) {
+      if (dtype == TT_I16)
+        return fail(TT_E_TOOBIG, "the int16 backward keeps every pass input: %lld bytes (budget %lld)",
+                    (long long)need, (long long)budget_bytes(p));
+      return run_backward_recompute(groups[0], dtype, s);
+    }
   }
   for (Group& g : groups)
     if (int r = prepare_group(g, backward)) return r;
@@ -1937,7 +1966,7 @@ int64_t slice_chunk(const Plan& r, int64_t total, SliceUse use) {
 int check_sliced(const Plan& p, int32_t batch, int32_t dtype, const void* J, const void* h) {
   const Slice& S = *static_cast<const Slice*>(p.slice);
   if (batch < 1) return fail(TT_E_INVAL, "batch must be >= 1");
-  if (dtype != TT_F32 && dtype != TT_I32) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
+  if (dtype != TT_F32 && dtype != TT_I32 && dtype != TT_I16) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
   if (p.m > 0 && !J) return fail(TT_E_INVAL, "null J");
   if (p.has_field && !h) return fail(TT_E_INVAL, "plan has fields but h is NULL");
   if (!p.has_field && h) return fail(TT_E_INVAL, "plan has no fields but h is given");
@@ -2492,6 +2521,7 @@ int tt_contract_noalloc(tt_plan* plan, int32_t batch, int32_t dtype, const void*
     Plan& p = *reinterpret_cast<Plan*>(plan);
     if (p.is_chimera || p.n_regs != 1)
       return fail(TT_E_INVAL, "chimera plans are not supported by the allocation-free call");
+    if (dtype == TT_I16) return fail(TT_E_DTYPE, "the allocation-free call takes float32 or int32 couplings");
     if (int r = early_budget(p, state_bytes(p, batch, false))) return r;
     const EnergyProgram* ep = nullptr;
     if (int r = host_program(p, &ep)) return r;

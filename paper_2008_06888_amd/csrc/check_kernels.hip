@@ -38,6 +38,14 @@ __global__ __launch_bounds__(CHK_T) void k_check_inputs(CheckArgs a, uint32_t* _
     const int64_t len = part == 0 ? I.m : I.n;
     const int64_t st = part == 0 ? I.jst : I.hst;
     if (!base) continue;
+    if (I.dtype == 2) {   // int16
+      const cptr<int16_t> row = as_const(static_cast<const int16_t*>(base)) + b * st;
+      for (int64_t k = threadIdx.x; k < len; k += CHK_T) {
+        const int64_t v = row[k];
+        S += (uint64_t)(v < 0 ? -v : v);
+      }
+      continue;
+    }
     const cptr<uint32_t> row = as_const(static_cast<const uint32_t*>(base)) + b * st;
     for (int64_t k = threadIdx.x; k < len; k += CHK_T) {
       const uint32_t w = row[k];

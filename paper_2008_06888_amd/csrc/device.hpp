@@ -200,7 +200,7 @@ struct CheckItem {
   int64_t jst, hst;      // row strides between instances (elements)
   int64_t first;         // status index of the item's first instance
   int64_t limit;         // integer inputs: sum |J| + sum |h| must stay below this
-  int32_t batch, dtype;  // dtype 0 = float32, else int32
+  int32_t batch, dtype;  // dtype 0 = float32, 2 = int16, else int32
 };
 constexpr int CHECK_ITEMS = 32;   // items per launch (passed by value)
 struct CheckArgs {

@@ -42,6 +42,13 @@ __device__ __forceinline__ gptr<T> as_global(T* p) {
 using LFloat = __attribute__((address_space(3))) float;
 using LByte = __attribute__((address_space(3))) char;
 
+using LShort = __attribute__((address_space(3))) short;
+
+// The int16 at an LDS byte address (same condition as lds_at).
+__device__ __forceinline__ LShort& lds16_at(uint32_t addr) {
+  return *(LShort*)(uintptr_t)(addr);
+}
+
 // The float at an LDS byte address. Only for kernels without static LDS,
 // whose dynamic region starts at address 0 (their launchers check it).
 __device__ __forceinline__ LFloat& lds_at(uint32_t addr) {

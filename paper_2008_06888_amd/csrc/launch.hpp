@@ -9,13 +9,17 @@
 
 namespace tt {
 
-// threads: at least 2^tb of every item's pass; lds: at least 4 * 2^t bytes of every item's pass.
+// threads: at least 2^tb of every item's pass; lds: at least 4 * 2^t bytes of every item's pass
+// (2 * 2^t for dtype 2: int16 couplings and state, k_pass16).
 // t0 / t1 (optional, created events): receive the kernel's own start and end times.
+// ng (dtype 2 only): groups of 16 entries per thread, 1, or 2 with threads =
+// 2^(tb - 1) of every item's pass (tb >= 7).
 hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int threads, size_t lds, int dtype,
-                       hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                       hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, int ng = 1);
 int reduce_log2_chunks(int w);
+// state16: the items' states are int16 (int16 couplings), else float32
 hipError_t launch_reduce(const RedItem* items, int n_items, int64_t n_chunks, float* pv, uint64_t* pi,
-                         hipStream_t stream, bool partials_ready = false);
+                         hipStream_t stream, bool partials_ready = false, bool state16 = false);
 hipError_t launch_backward(const BwdItem* items, int n_items, int dtype, hipStream_t stream);
 
 hipError_t launch_tgemm(int batch, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, int64_t sA,
@@ -77,7 +81,8 @@ struct SliceArgs {
 };
 // reduced couplings Jr, fields hr and constant energies c of n_red reduced
 // instances starting at r0 (kpick == nullptr), or of the slices kpick[b] of
-// instances b = r0 .. r0 + n_red - 1; h may be null (zero fields)
+// instances b = r0 .. r0 + n_red - 1; h may be null (zero fields); dtype 0
+// float32, 1 int32, 2 int16
 hipError_t launch_slice_build(const SliceArgs& A, int64_t r0, int n_red, const int32_t* kpick, int dtype,
                               const void* J, const void* h, void* Jr, void* hr, double* c, hipStream_t s);
 // energy[b] = min over the slices of instance b of Er + c, kbest[b] the first

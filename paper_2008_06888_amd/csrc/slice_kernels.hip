@@ -126,7 +126,10 @@ hipError_t launch_slice_build(const SliceArgs& A, int64_t r0, int n_red, const i
   int64_t gx = (big + SLT - 1) / SLT;
   gx = gx < 1 ? 1 : (gx > 64 ? 64 : gx);
   const dim3 grid((uint32_t)gx, (uint32_t)n_red);
-  if (dtype == 0)
+  if (dtype == 2)
+    hipLaunchKernelGGL(k_slice_build<int16_t>, grid, dim3(SLT), 0, s, A, r0, kpick, static_cast<const int16_t*>(J),
+                       static_cast<const int16_t*>(h), static_cast<int16_t*>(Jr), static_cast<int16_t*>(hr), c);
+  else if (dtype == 0)
     hipLaunchKernelGGL(k_slice_build<float>, grid, dim3(SLT), 0, s, A, r0, kpick, static_cast<const float*>(J),
                        static_cast<const float*>(h), static_cast<float*>(Jr), static_cast<float*>(hr), c);
   else

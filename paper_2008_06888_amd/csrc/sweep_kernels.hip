@@ -759,6 +759,594 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
 }
 
 // ---------------------------------------------------------------------------
+// 16-bit pass: the program of k_pass for integer couplings given as int16,
+// with the state held as int16 in HBM and LDS (half the bytes) and each
+// group of 16 register entries packed two to a register (entry j in register
+// j & 7, half j >> 3), so every add and max of a stage handles two entries
+// per instruction (packed 16-bit integer arithmetic). With NG = 2 each thread
+// owns two groups of the tile (half the threads of k_pass), so the decoding
+// of every op (scalar work) and the set-up are shared by 32 entries. Exact:
+// with S = sum |J| + sum |h| < 2^13 every state value lies in [-S, S] and
+// every intermediate (a - 2J, a maximum before its star term) in [-3S, 3S].
+// ---------------------------------------------------------------------------
+
+typedef short s2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s2v pmax(s2v a, s2v b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ s2v pswap(s2v a) { return __builtin_shufflevector(a, a, 1, 0); }
+__device__ __forceinline__ s2v plo2(s2v a) { return __builtin_shufflevector(a, a, 0, 0); }
+__device__ __forceinline__ s2v phi2(s2v a) { return __builtin_shufflevector(a, a, 1, 1); }
+__device__ __forceinline__ s2v pcat_lo(s2v a, s2v b) { return __builtin_shufflevector(a, b, 0, 2); }
+__device__ __forceinline__ s2v pcat_hi(s2v a, s2v b) { return __builtin_shufflevector(a, b, 1, 3); }
+__device__ __forceinline__ s2v as_s2(uint32_t x) { return __builtin_bit_cast(s2v, x); }
+__device__ __forceinline__ uint32_t as_u32(s2v x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ s2v pk(int lo, int hi) { return s2v{(short)lo, (short)hi}; }
+
+// The ops of a pass resolved as 16-bit integers, one op per lane (the float
+// resolution converted exactly: every value is an integer of the state's range).
+struct OpLanes16 {
+  int32_t j2;          // 2J
+  uint32_t pm0, pm1;   // (p0, m0), (p1, m1) as int16 pairs
+  uint32_t pk;         // as OpLanes
+  int32_t x0, x1, x2;  // further partners' couplings
+  uint32_t xwl;
+};
+
+__device__ __forceinline__ OpLanes16 lanes16(const OpLanes& r) {
+  OpLanes16 o;
+  o.j2 = (int32_t)r.J2;
+  o.pm0 = as_u32(pk((int)r.p0, (int)r.m0));
+  o.pm1 = as_u32(pk((int)r.p1, (int)r.m1));
+  o.pk = r.pk;
+  o.x0 = (int32_t)r.x0;
+  o.x1 = (int32_t)r.x1;
+  o.x2 = (int32_t)r.x2;
+  o.xwl = r.xwl;
+  return o;
+}
+
+// Wave-uniform fields of op k (scalar registers).
+struct UOp16 {
+  s2v jj;        // (2J, 2J)
+  s2v pm0, pm1;  // (p0, m0), (p1, m1)
+  uint32_t kind, lidx, wf, nx, sbit, wl, sl;
+};
+
+struct XOp16 {
+  int32_t xJ[3];
+  uint32_t xwl;
+};
+
+__device__ __forceinline__ UOp16 op16_at(const OpLanes16& R, int k) {
+  UOp16 u;
+  const int j2 = __builtin_amdgcn_readlane(R.j2, k);
+  u.jj = pk(j2, j2);
+  u.pm0 = as_s2((uint32_t)__builtin_amdgcn_readlane((int)R.pm0, k));
+  u.pm1 = as_s2((uint32_t)__builtin_amdgcn_readlane((int)R.pm1, k));
+  const uint32_t pkd = (uint32_t)__builtin_amdgcn_readlane((int)R.pk, k);
+  u.kind = pkd & 15u;
+  u.lidx = (pkd >> 4) & 15u;
+  u.wf = (pkd >> 8) & 255u;
+  u.sbit = (pkd >> 16) & 255u;
+  u.wl = (pkd >> 24) & 7u;
+  u.sl = (pkd >> 27) & 7u;
+  u.nx = pkd >> 30;
+  return u;
+}
+
+__device__ __forceinline__ XOp16 xop16_at(const OpLanes16& R, int k) {
+  XOp16 x;
+  x.xJ[0] = __builtin_amdgcn_readlane(R.x0, k);
+  x.xJ[1] = __builtin_amdgcn_readlane(R.x1, k);
+  x.xJ[2] = __builtin_amdgcn_readlane(R.x2, k);
+  x.xwl = (uint32_t)__builtin_amdgcn_readlane((int)R.xwl, k);
+  return x;
+}
+
+// Gate on stage bit L < 3 (register pairs d0, d1 = d0 | 2^L, both halves at
+// once) or L == 3 (the two halves of each register), for each of the NG
+// groups. W: the first partner is stage bit W (< 4, its value per entry
+// known here) or constant over a group's entries (4: bit wf of the group
+// base, or no partner).
+template <int L, int W, int NG>
+__device__ __forceinline__ void gate16(const s2v (&a)[NG][8], s2v (&o)[NG][8], const uint32_t (&gb)[NG],
+                                       const UOp16& u) {
+  const s2v jj = u.jj;
+#pragma unroll
+  for (int gi = 0; gi < NG; ++gi) {
+    const bool bt = W == 4 && u.wf != 255 && tbit(gb[gi], u.wf);
+    if constexpr (L < 3) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int d0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+        const int d1 = d0 | (1 << L);
+        s2v c0, c1;
+        if constexpr (W < 3) {
+          const bool b = (d0 >> W) & 1;
+          c0 = b ? phi2(u.pm0) : plo2(u.pm0);
+          c1 = b ? phi2(u.pm1) : plo2(u.pm1);
+        } else if constexpr (W == 3) {
+          c0 = u.pm0;   // low half: partner +1 (p), high half: partner -1 (m)
+          c1 = u.pm1;
+        } else {
+          c0 = bt ? phi2(u.pm0) : plo2(u.pm0);
+          c1 = bt ? phi2(u.pm1) : plo2(u.pm1);
+        }
+        o[gi][d0] = pmax(a[gi][d0], a[gi][d1] - jj) + c0;
+        o[gi][d1] = pmax(a[gi][d0] - jj, a[gi][d1]) + c1;
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        s2v c;
+        if constexpr (W < 3) {
+          const bool b = (d >> W) & 1;
+          c = b ? pcat_hi(u.pm0, u.pm1) : pcat_lo(u.pm0, u.pm1);
+        } else {
+          c = bt ? pcat_hi(u.pm0, u.pm1) : pcat_lo(u.pm0, u.pm1);
+        }
+        o[gi][d] = pmax(a[gi][d], pswap(a[gi][d]) - jj) + c;
+      }
+    }
+  }
+}
+
+template <int L, int NG>
+__device__ __forceinline__ void gate16_w(const s2v (&a)[NG][8], s2v (&o)[NG][8], const uint32_t (&gb)[NG],
+                                         const UOp16& u) {
+  if constexpr (L == 3) {
+    switch (u.wl) {
+      case 0: gate16<3, 0, NG>(a, o, gb, u); break;
+      case 1: gate16<3, 1, NG>(a, o, gb, u); break;
+      case 2: gate16<3, 2, NG>(a, o, gb, u); break;
+      default: gate16<3, 4, NG>(a, o, gb, u); break;   // (a partner on the gate's own bit cannot occur)
+    }
+  } else {
+    switch (u.wl) {
+      case 0: gate16<L, 0, NG>(a, o, gb, u); break;
+      case 1: gate16<L, 1, NG>(a, o, gb, u); break;
+      case 2: gate16<L, 2, NG>(a, o, gb, u); break;
+      case 3: gate16<L, 3, NG>(a, o, gb, u); break;
+      default: gate16<L, 4, NG>(a, o, gb, u); break;
+    }
+  }
+}
+
+// Bit (0/1) of register entry j (compile-time after unrolling) for a slot
+// that is stage bit l (< 4) or non-stage tile bit w.
+__device__ __forceinline__ uint32_t rbit16(int j, uint32_t l, uint32_t w, uint32_t gb) {
+  return l < 4 ? ((uint32_t)j >> l) & 1u : tbit(gb, w);
+}
+
+// The value added to output entry j of a gate on stage bit L with further
+// resident partners (rare): as gate_x of the float pass, per entry.
+template <int L>
+__device__ __forceinline__ int gate_const16(int j, const UOp16& u, const XOp16& x, uint32_t gb) {
+  const int j0 = j & ~(1 << L);
+  const bool upper = (j >> L) & 1;
+  const bool bf = u.wf != 255 && rbit16(j0, u.wl, u.wf, gb);
+  const s2v pm = upper ? u.pm1 : u.pm0;
+  int c = bf ? pm.y : pm.x;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if ((uint32_t)k >= u.nx) break;
+    const uint32_t w = (x.xwl >> (7 * k)) & 15u, l = (x.xwl >> (7 * k + 4)) & 7u;
+    const int sk = rbit16(j0, l, w, gb) ? -x.xJ[k] : x.xJ[k];
+    c += upper ? -sk : sk;
+  }
+  return c;
+}
+
+template <int L, int NG>
+__device__ __forceinline__ void gate16_x(const s2v (&a)[NG][8], s2v (&o)[NG][8], const uint32_t (&gb)[NG],
+                                         const UOp16& u, const XOp16& x) {
+  const s2v jj = u.jj;
+#pragma unroll
+  for (int gi = 0; gi < NG; ++gi) {
+    if constexpr (L < 3) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int d0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+        const int d1 = d0 | (1 << L);
+        const s2v c0 = pk(gate_const16<L>(d0, u, x, gb[gi]), gate_const16<L>(d0 + 8, u, x, gb[gi]));
+        const s2v c1 = pk(gate_const16<L>(d1, u, x, gb[gi]), gate_const16<L>(d1 + 8, u, x, gb[gi]));
+        o[gi][d0] = pmax(a[gi][d0], a[gi][d1] - jj) + c0;
+        o[gi][d1] = pmax(a[gi][d0] - jj, a[gi][d1]) + c1;
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const s2v c = pk(gate_const16<3>(d, u, x, gb[gi]), gate_const16<3>(d + 8, u, x, gb[gi]));
+        o[gi][d] = pmax(a[gi][d], pswap(a[gi][d]) - jj) + c;
+      }
+    }
+  }
+}
+
+template <int L, int NG>
+__device__ __forceinline__ void cut16(const s2v (&a)[NG][8], s2v (&o)[NG][8]) {
+#pragma unroll
+  for (int gi = 0; gi < NG; ++gi) {
+    if constexpr (L < 3) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int d0 = ((p >> L) << (L + 1)) | (p & ((1 << L) - 1));
+        const int d1 = d0 | (1 << L);
+        const s2v m = pmax(a[gi][d0], a[gi][d1]);
+        o[gi][d0] = m;
+        o[gi][d1] = m;
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 8; ++d) o[gi][d] = pmax(a[gi][d], pswap(a[gi][d]));
+    }
+  }
+}
+
+// Star of a spin that entered without a gate: x += sigma(spin) * sw with
+// sw = p0 + sigma(first partner) m0 + further partners (per entry).
+__device__ __forceinline__ int star_val16(int j, const UOp16& u, const XOp16& x, uint32_t gb) {
+  int sw = u.pm0.x;
+  if (u.wf != 255) sw += rbit16(j, u.wl, u.wf, gb) ? -(int)u.pm0.y : (int)u.pm0.y;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if ((uint32_t)k >= u.nx) break;
+    const uint32_t w = (x.xwl >> (7 * k)) & 15u, l = (x.xwl >> (7 * k + 4)) & 7u;
+    sw += rbit16(j, l, w, gb) ? -x.xJ[k] : x.xJ[k];
+  }
+  return (u.sbit != 255 && rbit16(j, u.sl, u.sbit, gb)) ? -sw : sw;
+}
+
+template <int NG>
+__device__ __forceinline__ void star16p(const s2v (&a)[NG][8], s2v (&o)[NG][8], const uint32_t (&gb)[NG],
+                                        const UOp16& u, const XOp16& x) {
+#pragma unroll
+  for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+    for (int d = 0; d < 8; ++d) o[gi][d] = a[gi][d] + pk(star_val16(d, u, x, gb[gi]), star_val16(d + 8, u, x, gb[gi]));
+}
+
+// One op of a stage on the thread's NG groups: decoded once, applied to all.
+template <int NG>
+__device__ __forceinline__ void apply_op16(const s2v (&a)[NG][8], s2v (&o)[NG][8], const uint32_t (&gb)[NG],
+                                           const OpLanes16& R, int k) {
+  const UOp16 u = op16_at(R, k);
+  if (u.kind == FK_STAR) {
+    XOp16 x{{0, 0, 0}, 0u};
+    if (u.nx) x = xop16_at(R, k);
+    star16p<NG>(a, o, gb, u, x);
+  } else if (u.kind == FK_CUT) {
+    switch (u.lidx) {
+      case 0: cut16<0, NG>(a, o); break;
+      case 1: cut16<1, NG>(a, o); break;
+      case 2: cut16<2, NG>(a, o); break;
+      default: cut16<3, NG>(a, o); break;
+    }
+  } else if (u.nx) {
+    const XOp16 x = xop16_at(R, k);
+    switch (u.lidx) {
+      case 0: gate16_x<0, NG>(a, o, gb, u, x); break;
+      case 1: gate16_x<1, NG>(a, o, gb, u, x); break;
+      case 2: gate16_x<2, NG>(a, o, gb, u, x); break;
+      default: gate16_x<3, NG>(a, o, gb, u, x); break;
+    }
+  } else {
+    switch (u.lidx) {
+      case 0: gate16_w<0, NG>(a, o, gb, u); break;
+      case 1: gate16_w<1, NG>(a, o, gb, u); break;
+      case 2: gate16_w<2, NG>(a, o, gb, u); break;
+      default: gate16_w<3, NG>(a, o, gb, u); break;
+    }
+  }
+}
+
+// The tile index and address (low enumeration bits) of enumeration index u
+// from the pass's per-bit tables, bits q < nb.
+__device__ __forceinline__ void enum_lo(const uint32_t (&bti)[10], const uint64_t (&bad)[10], uint32_t u, int nb,
+                                        uint32_t* ti, uint64_t* ad) {
+  uint32_t t = 0;
+  uint64_t a = 0;
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    const uint32_t m = (q < nb) ? (uint32_t)0 - ((u >> q) & 1u) : 0u;
+    t |= bti[q] & m;
+    a |= bad[q] & (uint64_t)(int64_t)(int32_t)m;
+  }
+  *ti = t;
+  *ad = a;
+}
+
+// NG = 1: one group per thread, 2^tb threads (as k_pass). NG = 2: two groups
+// per thread, 2^(tb-1) threads (tb >= 7); thread i then takes enumeration
+// indices i and i + 2^(tb-1) of the loads and stores and groups i and
+// i + 2^(tb-1) of every stage.
+// (NG = 2 keeps two groups' registers: four waves per SIMD, within 128 VGPRs)
+template <int NG>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 : 6))) void k_pass16(
+    const PassItem* __restrict__ items, int n_items) {
+  // LDS holds the tile as int16 (2^t entries, dynamic, from address 0);
+  // entry i sits at byte 2 swz(i).
+  const int64_t wg = blockIdx.x;
+  int it = 0;
+  const cptr<PassItem> citems = as_const(items);
+  while (it + 1 < n_items && wg >= citems[it + 1].wg_begin) ++it;
+  const auto& I = citems[it];
+  const auto& P = *as_const(I.P);
+  const cptr<DevStage> stages = as_const(I.stages);
+  const cptr<FOp> fops = as_const(I.fops);
+  int64_t inst;
+  uint64_t tid_bits;
+  if (!wg_to_tile((uint64_t)(wg - I.wg_begin), P.n_free, I.batch, I.xcd_group, &inst, &tid_bits)) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const cptr<int16_t> Jrow = as_const(static_cast<const int16_t*>(I.J)) + inst * I.jst;
+  const cptr<int16_t> hrow = I.h ? as_const(static_cast<const int16_t*>(I.h)) + inst * I.hst : nullptr;
+  const int n_ops = P.n_ops;
+  const int li = lane < 48 ? lane : 47;
+  const uint32_t fi = P.fin[li], fo = P.fout[li], fr = P.fre[li];
+  OpIn opin;
+  opin.f = ldc(fops + P.op_begin + (lane < n_ops ? lane : 0));
+  const int t = P.t;
+  const int tb = P.tb;
+  const uint32_t size = 1u << t;
+  const uint32_t half = NG == 2 ? 1u << (tb - 1) : 0u;   // the second enumeration index / group of a thread
+  uint64_t bs = 0, in_base = 0, out_base = 0, dropped = 0;
+  {
+    if (lane < P.n_free) {
+      const uint64_t b = (tid_bits >> lane) & 1ull;
+      bs = b << fr;
+      in_base = fi != NO_POS ? b << fi : 0ull;
+      out_base = fo != NO_POS ? b << fo : 0ull;
+      dropped = fo == NO_POS ? b : 0ull;
+    }
+    bs = wave_or_dpp(bs);
+    in_base = wave_or_dpp(in_base);
+    out_base = wave_or_dpp(out_base);
+    dropped = wave_or_dpp(dropped);
+  }
+  const bool stored = dropped == 0;
+  const int16_t* in16 = reinterpret_cast<const int16_t*>(I.in) + inst * I.in_st;
+  int16_t* out16 = reinterpret_cast<int16_t*>(I.out) + inst * I.out_st;
+  const int nb_ld = t < tb ? t : tb;
+  const int nk_ld = 1 << (t - nb_ld);
+  bool loader[NG];
+  uint32_t ti_ld[NG];
+  uint64_t ad_ld[NG];
+  int16_t vals[NG][16];
+  bool fast_ld = false;
+  const int16_t* src = in16 + in_base;
+  uint64_t had_ld[16];
+  const bool init = P.init != 0;
+  {
+    uint32_t bti[10];
+    uint64_t bad[10], had[16];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      bti[q] = P.ld_bti[q];
+      bad[q] = P.ld_bad[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) had[k] = P.ld_had[k];
+    uint64_t all = 0;
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+      if (q < nb_ld) all |= bad[q];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) all |= had[k];
+#pragma unroll
+    for (int h = 0; h < NG; ++h) {
+      const uint32_t u = (uint32_t)tid + (h ? half : 0u);
+      loader[h] = u < (1u << nb_ld);
+      enum_lo(bti, bad, u, nb_ld, &ti_ld[h], &ad_ld[h]);
+    }
+    load_op_values<int16_t>(opin, Jrow, hrow);
+    __builtin_amdgcn_sched_barrier(0);
+    // the buffer covers the instance's input state from this tile's base
+    // (records in bytes): every entry the tile reads lies inside it
+    fast_ld = !init && nk_ld == 16 && all < BUF_MAX_ENTRIES;
+    const uint64_t rec = ((uint64_t)I.in_st - in_base) * 2ull;
+    const __amdgpu_buffer_rsrc_t rs =
+        raw_rsrc(src, fast_ld ? (int)(rec < 0x7fffffffull ? rec : 0x7fffffffull) : 0);
+#pragma unroll
+    for (int h = 0; h < NG; ++h) {
+      const uint32_t off = (uint32_t)ad_ld[h] << 1;
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        vals[h][k] = (int16_t)__builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, (int)(had[k] << 1), AUX_NT);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) had_ld[k] = had[k];
+  }
+  const OpLanes16 R = lanes16(resolve_lane(opin, bs));
+  if (!init && !fast_ld) {
+#pragma unroll
+    for (int h = 0; h < NG; ++h)
+      if (loader[h]) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < nk_ld) vals[h][k] = src[ad_ld[h] | had_ld[k]];
+      }
+  }
+  {
+    uint32_t hs[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) hs[k] = swz(P.ld_hti[k]) << 1;
+#pragma unroll
+    for (int h = 0; h < NG; ++h) {
+      if (!loader[h]) continue;
+      const uint32_t ls = opaque(swz(ti_ld[h]) << 1);
+      if (nk_ld == 16) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lds16_at(ls ^ hs[k]) = vals[h][k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < nk_ld) lds16_at(ls ^ hs[k]) = vals[h][k];
+      }
+    }
+  }
+  __syncthreads();
+  const int n_stages = P.n_stages;
+  const uint32_t groups = size >> 4;
+  // NG = 1 as k_pass: one group per thread (with fewer than 64 groups the
+  // first wave repeats groups); NG = 2: groups tid and tid + half, all active
+  const bool active = NG == 2 || (uint32_t)tid < (groups > 64u ? groups : 64u);
+  uint32_t g[NG];
+#pragma unroll
+  for (int h = 0; h < NG; ++h) g[h] = NG == 2 ? (uint32_t)tid + (h ? half : 0u) : ((uint32_t)tid & (groups - 1));
+  for (int s = 0; s < n_stages; ++s) {
+    if (active) {
+      const cptr<DevStage> ST = stages + P.stage_begin + s;
+      const int ob = ST->op_begin - P.op_begin, oe = ST->op_end - P.op_begin;
+      uint32_t so[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) so[j] = ST->soff[j] << 1;
+      uint32_t gb[NG], sg[NG];
+#pragma unroll
+      for (int h = 0; h < NG; ++h) {
+        gb[h] = (uint32_t)ST->g_lo[g[h] & 31u] | (uint32_t)ST->g_hi[g[h] >> 5];
+        sg[h] = opaque(((uint32_t)ST->sg_lo[g[h] & 31u] ^ (uint32_t)ST->sg_hi[g[h] >> 5]) << 1);
+      }
+      s2v va[NG][8], vb[NG][8];
+#pragma unroll
+      for (int h = 0; h < NG; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) va[h][d] = s2v{lds16_at(sg[h] ^ so[d]), lds16_at(sg[h] ^ so[d + 8])};
+      for (int o = ob; o < oe; o += 2) {
+        apply_op16<NG>(va, vb, gb, R, o);
+        if (o + 1 < oe) {
+          apply_op16<NG>(vb, va, gb, R, o + 1);
+        } else {
+#pragma unroll
+          for (int h = 0; h < NG; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) va[h][d] = vb[h][d];
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < NG; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+          lds16_at(sg[h] ^ so[d]) = va[h][d].x;
+          lds16_at(sg[h] ^ so[d + 8]) = va[h][d].y;
+        }
+    }
+    __syncthreads();
+  }
+  const int64_t red_at = I.red_base + (inst << P.n_free) + (int64_t)tid_bits;
+  if (!stored) {
+    if (I.red_v && tid == 0) {
+      as_global(I.red_v)[red_at] = -INFINITY;
+      as_global(I.red_i)[red_at] = ~0ull;
+    }
+    return;
+  }
+  {
+    const int ns = P.n_st;
+    uint32_t bti[10], hs[16];
+    uint64_t bad[10], had[16];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      bti[q] = P.st_bti[q];
+      bad[q] = P.st_bad[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      hs[k] = swz(P.st_hti[k]) << 1;
+      had[k] = P.st_had[k];
+    }
+    const int nb = ns < tb ? ns : tb;
+    const int nk = 1 << (ns - nb);
+    uint64_t all = 0;
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+      if (q < nb) all |= bad[q];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) all |= had[k];
+    bool storer[NG];
+    uint32_t ti_st[NG];
+    uint64_t ad_st[NG];
+#pragma unroll
+    for (int h = 0; h < NG; ++h) {
+      const uint32_t u = (uint32_t)tid + (h ? half : 0u);
+      storer[h] = u < (1u << nb);
+      enum_lo(bti, bad, u, nb, &ti_st[h], &ad_st[h]);
+    }
+    int16_t* dst = out16 + out_base;
+    if (I.red_v) {
+      // fused final reduction (as k_pass): the tile's maximum and its lowest
+      // output address, as a float partial
+      float bv = -INFINITY;
+      uint64_t bi = ~0ull;
+#pragma unroll
+      for (int h = 0; h < NG; ++h) {
+        if (!storer[h]) continue;
+        const uint32_t ls = opaque(swz(ti_st[h]) << 1);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          if (k < nk) {
+            const float v = (float)lds16_at(ls ^ hs[k]);
+            const uint64_t a = out_base | ad_st[h] | had[k];
+            if (v > bv || (v == bv && a < bi)) {
+              bv = v;
+              bi = a;
+            }
+          }
+        }
+      }
+      wave_best64_dpp(bv, bi);
+      __syncthreads();
+      const int wv = tid >> 6;
+      if ((tid & 63) == 63) {
+        lds_at(16 * wv) = bv;
+        lds_at(16 * wv + 4) = __uint_as_float((uint32_t)bi);
+        lds_at(16 * wv + 8) = __uint_as_float((uint32_t)(bi >> 32));
+      }
+      __syncthreads();
+      if (tid < 64) {
+        const int nw = (int)(blockDim.x >> 6);
+        bv = -INFINITY;
+        bi = ~0ull;
+        if (tid < nw) {
+          bv = lds_at(16 * tid);
+          bi = ((uint64_t)__float_as_uint(lds_at(16 * tid + 8)) << 32) | __float_as_uint(lds_at(16 * tid + 4));
+        }
+        wave_best64_dpp(bv, bi);
+        if (tid == 63) {
+          as_global(I.red_v)[red_at] = bv;
+          as_global(I.red_i)[red_at] = bi;
+        }
+      }
+      return;
+    }
+    const bool fast_st = nk == 16 && all < BUF_MAX_ENTRIES;
+    const uint64_t rec = ((uint64_t)I.out_st - out_base) * 2ull;
+    const __amdgpu_buffer_rsrc_t rs = raw_rsrc(dst, (int)(rec < 0x7fffffffull ? rec : 0x7fffffffull));
+#pragma unroll
+    for (int h = 0; h < NG; ++h) {
+      if (!storer[h]) continue;
+      const uint32_t ls = opaque(swz(ti_st[h]) << 1);
+      int16_t sv[16];
+      if (fast_st) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sv[k] = lds16_at(ls ^ hs[k]);
+        const uint32_t off = (uint32_t)ad_st[h] << 1;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          __builtin_amdgcn_raw_buffer_store_b16((uint16_t)sv[k], rs, (int)off, (int)(had[k] << 1), AUX_NT);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < nk) sv[k] = lds16_at(ls ^ hs[k]);
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < nk) __builtin_nontemporal_store(sv[k], &dst[ad_st[h] | had[k]]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // final reduction: max over the state and its lowest address (Sec. II: the
 // contraction with the product state (0, 0)^n of App. A)
 // ---------------------------------------------------------------------------
@@ -800,6 +1388,15 @@ __device__ VI block_best(VI x) {
   return r;
 }
 
+// Four consecutive state entries as floats.
+__device__ __forceinline__ float4 ld4(cptr<float> s, uint64_t i) { return ldc((cptr<float4>)(s + i)); }
+__device__ __forceinline__ float4 ld4(cptr<int16_t> s, uint64_t i) {
+  const uint2 w = ldc((cptr<uint2>)(s + i));
+  return float4{(float)(int16_t)(w.x & 0xffffu), (float)(int16_t)(w.x >> 16), (float)(int16_t)(w.y & 0xffffu),
+                (float)(int16_t)(w.y >> 16)};
+}
+
+template <typename SV>
 __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict__ items, int n_items,
                                                        float* __restrict__ pv, uint64_t* __restrict__ pi) {
   __shared__ float bt[5][256];   // bonus of each index byte (chimera row walk)
@@ -811,7 +1408,7 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict
   const uint64_t chunk = (uint64_t)(wg - I.chunk_begin);
   const uint64_t len = 1ull << (I.w - I.log2_chunks);
   const uint64_t base = chunk * len;
-  const cptr<float> s = as_const(I.st);
+  const cptr<SV> s = as_const(reinterpret_cast<const SV*>(I.st));
   const bool bonus = I.bedge != nullptr;
   if (bonus) {
     const uint64_t ref = *as_const(I.bref);
@@ -835,10 +1432,9 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict
   VI best{-INFINITY, ~0ull};
   if (len >= 4) {
     // four consecutive entries per load; ties keep the smaller address
-    const cptr<float4> s4 = (cptr<float4>)(s + base);
 #pragma unroll 4
     for (uint64_t k = threadIdx.x; k < len / 4; k += NTR) {
-      const float4 v = ldc(s4 + k);
+      const float4 v = ld4(s, base + 4 * k);
       const uint64_t i0 = base + 4 * k;
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
       if (bonus) {
@@ -862,7 +1458,7 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict
       if (bonus)
         a = bt[0][idx & 255] + bt[1][(idx >> 8) & 255] + bt[2][(idx >> 16) & 255] + bt[3][(idx >> 24) & 255] +
             bt[4][(idx >> 32) & 255];
-      best = vi_best(best, VI{s[idx] + a, idx});
+      best = vi_best(best, VI{(float)s[idx] + a, idx});
     }
   }
   best = block_best<NTR>(best);
@@ -1013,9 +1609,10 @@ __device__ __forceinline__ uint64_t opaque64(uint64_t x) {
 // Where a pass's candidates read their input entries: the checkpoint at the
 // surviving-slot address (or the zero word in the first pass, whose input is
 // all zero) and the two address tables.
+template <typename SV>
 struct BwdSrc {
   bool have;
-  cptr<float> src;
+  cptr<SV> src;   // state entries (float32, or int16 for int16 couplings)
   const uint64_t* AL;
   const uint64_t* AH;
   uint32_t na;
@@ -1029,13 +1626,13 @@ __device__ __forceinline__ bool have_src_of(const LPass& P) { return !P.init; }
 // the scoring: a candidate beyond the last reads a valid word instead
 // (offset 0; the scoring skips it), and in the first pass every candidate
 // reads the zero word.
-template <int W>
-__device__ __forceinline__ void bwd_issue(float (&val)[8], const BwdSrc& S, uint32_t a0) {
+template <int W, typename SV>
+__device__ __forceinline__ void bwd_issue(float (&val)[8], const BwdSrc<SV>& S, uint32_t a0) {
 #pragma unroll
   for (int j = 0; j < W; ++j) {
     const uint32_t a = a0 + (uint32_t)j * NT;
     const uint64_t off = S.AL[a & 255u] | S.AH[(a >> 8) & 255u];
-    val[j] = S.src[opaque64((S.have && a < S.na) ? off : 0ull)];
+    val[j] = (float)S.src[opaque64((S.have && a < S.na) ? off : 0ull)];
   }
 }
 
@@ -1088,7 +1685,7 @@ __device__ __forceinline__ void bwd_score(float (&val)[8], const BwdTerms& X, co
   }
 }
 
-template <typename IT>
+template <typename IT, typename SV = float>
 __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ items) {
   __shared__ int8_t s_sh[MAX_SPINS];
   __shared__ float lut_lo[256], lut_hi[256];
@@ -1254,8 +1851,8 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       // before, so the first batch's loads are issued here, without a
       // branch, and stay in flight while the term tables are built. Only
       // the W = 1, 2, 4 or 8 of them that cover the candidates are scored.
-      const BwdSrc S{have_src_of(P), have_src_of(P) ? as_const(ckpt[p]) + base_cur
-                                                    : as_const(reinterpret_cast<const float*>(g_zero_words)),
+      const BwdSrc<SV> S{have_src_of(P), have_src_of(P) ? as_const(reinterpret_cast<const SV*>(ckpt[p])) + base_cur
+                                                        : as_const(reinterpret_cast<const SV*>(g_zero_words)),
                      ad_lo[p & 1], ad_hi[p & 1], na};
       const int wsel = na <= (uint32_t)NT ? 1 : na <= 2u * NT ? 2 : na <= 4u * NT ? 4 : 8;
       const uint32_t nb = (na + 8u * NT - 1u) / (8u * NT);
@@ -1361,8 +1958,12 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
 // Raises the dynamic LDS limit of a kernel once (static tables come on top).
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t bytes) {
-  static int done[2] = {0, 0};
-  const int slot = (reinterpret_cast<const void*>(kernel) == reinterpret_cast<const void*>(k_pass<float>)) ? 0 : 1;
+  static int done[4] = {0, 0, 0, 0};
+  const void* kp = reinterpret_cast<const void*>(kernel);
+  const int slot = kp == reinterpret_cast<const void*>(k_pass<float>)     ? 0
+                   : kp == reinterpret_cast<const void*>(k_pass<int32_t>) ? 1
+                   : kp == reinterpret_cast<const void*>(k_pass16<1>)     ? 2
+                                                                          : 3;
   if (done[slot]) return hipSuccess;
   // the pass kernel addresses LDS from 0: it must have no static LDS
   hipFuncAttributes fa;
@@ -1376,10 +1977,20 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 }
 
 hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int threads, size_t lds, int dtype,
-                       hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
+                       hipStream_t stream, hipEvent_t t0, hipEvent_t t1, int ng) {
   if (n_wg >= (1ll << 31) || threads < 64 || threads > NT || lds > 65536) return hipErrorInvalidConfiguration;
   const dim3 grid((uint32_t)n_wg), block(threads);
-  if (dtype == 0) {
+  if (dtype == 2) {
+    // int16: two groups per thread when the host launches half the threads
+    // of a tile (ng == 2), else one
+    const auto kern = ng == 2 ? k_pass16<2> : k_pass16<1>;
+    hipError_t e = allow_lds(kern, PASS_LDS_MAX);
+    if (e != hipSuccess) return e;
+    if (t0 || t1)
+      hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)lds, stream, t0, t1, 0u, items, n_items);
+    else
+      hipLaunchKernelGGL(kern, grid, block, lds, stream, items, n_items);
+  } else if (dtype == 0) {
     hipError_t e = allow_lds(k_pass<float>, PASS_LDS_MAX);
     if (e != hipSuccess) return e;
     if (t0 || t1)
@@ -1406,15 +2017,23 @@ int reduce_log2_chunks(int w) {
 }
 
 hipError_t launch_reduce(const RedItem* items, int n_items, int64_t n_chunks, float* pv, uint64_t* pi,
-                         hipStream_t stream, bool partials_ready) {
-  if (!partials_ready)
-    hipLaunchKernelGGL(k_reduce_stage1, dim3((uint32_t)n_chunks), dim3(NTR), 0, stream, items, n_items, pv, pi);
+                         hipStream_t stream, bool partials_ready, bool state16) {
+  if (!partials_ready) {
+    if (state16)
+      hipLaunchKernelGGL(k_reduce_stage1<int16_t>, dim3((uint32_t)n_chunks), dim3(NTR), 0, stream, items, n_items,
+                         pv, pi);
+    else
+      hipLaunchKernelGGL(k_reduce_stage1<float>, dim3((uint32_t)n_chunks), dim3(NTR), 0, stream, items, n_items,
+                         pv, pi);
+  }
   hipLaunchKernelGGL(k_reduce_stage2, dim3((uint32_t)n_items), dim3(NTR), 0, stream, items, pv, pi);
   return hipGetLastError();
 }
 
 hipError_t launch_backward(const BwdItem* items, int n_items, int dtype, hipStream_t stream) {
-  if (dtype == 0)
+  if (dtype == 2)
+    hipLaunchKernelGGL((k_backward<int16_t, int16_t>), dim3(n_items), dim3(NT), 0, stream, items);
+  else if (dtype == 0)
     hipLaunchKernelGGL(k_backward<float>, dim3(n_items), dim3(NT), 0, stream, items);
   else
     hipLaunchKernelGGL(k_backward<int32_t>, dim3(n_items), dim3(NT), 0, stream, items);
