@@ -197,9 +197,62 @@ __device__ __forceinline__ float coupling(const void* J, int64_t jst, int inst, 
 // LOW passes (tile = slots 0 .. T-1): thread t of a workgroup owns the run
 // [base + t 3^T, base + (t + 1) 3^T) and the workgroup one contiguous block;
 // direct loads would send each lane of a wave to its own cache line, so the
-// block goes through LDS: coalesced loads into LDS, then each thread takes its
-// run (stride 3^T words across lanes: odd, so the lanes of a wave hit
-// distinct banks), and the reverse for the stores. One plane at a time.
+// block goes through LDS in three chunks (the entries c 3^(T-1) .. (c + 1)
+// 3^(T-1) - 1 of every run): coalesced loads of the chunk into LDS, then each
+// thread takes its part (stride 3^(T-1) words across lanes: odd, so the lanes
+// of a wave hit distinct banks), and the reverse for the stores; one plane at
+// a time. A chunk's buffer (a third of the block) leaves room for several
+// workgroups per CU.
+template <int T>
+constexpr int low_chunk() {
+  return T >= 2 ? ipow3(T - 1) : ipow3(T);
+}
+template <int T>
+constexpr int low_chunks() {
+  return ipow3(T) / low_chunk<T>();
+}
+
+// Chunk c of the block: global entry of LDS word e (thread e / EC's run).
+template <int T>
+__device__ __forceinline__ int64_t low_addr(int64_t base, int e, int c) {
+  constexpr int E = ipow3(T), EC = low_chunk<T>();
+  return base + (int64_t)(e / EC) * E + c * EC + (e % EC);
+}
+
+// Chunk c of plane `src` into LDS (words below nvalid), every load of the
+// thread issued before the first store.
+template <int T, typename V>
+__device__ __forceinline__ void low_fill(V* lds, const gptr<V> src, int64_t base, int c, int nvalid) {
+  constexpr int EC = low_chunk<T>();
+  V t[EC];
+#pragma unroll
+  for (int k = 0; k < EC; ++k) {
+    const int e = (int)threadIdx.x + k * PT;
+    t[k] = e < nvalid ? __builtin_nontemporal_load(&src[low_addr<T>(base, e, c)]) : V(0);
+  }
+#pragma unroll
+  for (int k = 0; k < EC; ++k) {
+    const int e = (int)threadIdx.x + k * PT;
+    if (e < nvalid) lds[e] = t[k];
+  }
+}
+// Chunk c from LDS to plane `dst`, every LDS read issued before the stores.
+template <int T, typename V>
+__device__ __forceinline__ void low_drain(const V* lds, gptr<V> dst, int64_t base, int c, int nvalid) {
+  constexpr int EC = low_chunk<T>();
+  V t[EC];
+#pragma unroll
+  for (int k = 0; k < EC; ++k) {
+    const int e = (int)threadIdx.x + k * PT;
+    t[k] = e < nvalid ? lds[e] : V(0);
+  }
+#pragma unroll
+  for (int k = 0; k < EC; ++k) {
+    const int e = (int)threadIdx.x + k * PT;
+    if (e < nvalid) __builtin_nontemporal_store(t[k], &dst[low_addr<T>(base, e, c)]);
+  }
+}
+
 template <int T, int NR, bool COUNT, bool LOW>
 __global__ __launch_bounds__(PT) void k_potts_pass(const PottsPass* __restrict__ pass, const void* __restrict__ J,
                                                    int64_t jst, int dtype, float* __restrict__ x,
@@ -219,10 +272,11 @@ __global__ __launch_bounds__(PT) void k_potts_pass(const PottsPass* __restrict__
   if constexpr (LOW) {
     extern __shared__ float lds_f[];
     uint64_t* lds_u = reinterpret_cast<uint64_t*>(lds_f);
+    constexpr int EC = low_chunk<T>(), NC = low_chunks<T>();
     const int64_t base = (int64_t)inst * sst + gid0 * E;
     const int64_t left = threads - gid0;
-    const int nvalid = (int)((left < PT ? left : PT) * E);
-    const int mine = (int)threadIdx.x * E;
+    const int nvalid = (int)((left < PT ? left : PT) * EC);   // words of a chunk
+    const int mine = (int)threadIdx.x * EC;
     if (init) {
 #pragma unroll
       for (int i = 0; i < E; ++i) {
@@ -233,19 +287,25 @@ __global__ __launch_bounds__(PT) void k_potts_pass(const PottsPass* __restrict__
         }
       }
     } else {
-      for (int e = threadIdx.x; e < nvalid; e += PT) lds_f[e] = __builtin_nontemporal_load(&X[base + e]);
-      __syncthreads();
 #pragma unroll
-      for (int i = 0; i < E; ++i) v[i] = lds_f[mine + i];
+      for (int c = 0; c < NC; ++c) {
+        if (c) __syncthreads();
+        low_fill<T>(lds_f, X, base, c, nvalid);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < EC; ++i) v[c * EC + i] = lds_f[mine + i];
+      }
       if constexpr (COUNT) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          __syncthreads();
-          for (int e = threadIdx.x; e < nvalid; e += PT)
-            lds_u[e] = __builtin_nontemporal_load(&N[base + e + r * plane]);
-          __syncthreads();
 #pragma unroll
-          for (int i = 0; i < E; ++i) n[i].r[r] = lds_u[mine + i];
+          for (int c = 0; c < NC; ++c) {
+            __syncthreads();
+            low_fill<T>(lds_u, N + r * plane, base, c, nvalid);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < EC; ++i) n[c * EC + i].r[r] = lds_u[mine + i];
+          }
         }
       }
     }
@@ -255,19 +315,25 @@ __global__ __launch_bounds__(PT) void k_potts_pass(const PottsPass* __restrict__
       const float Jv = kind == OP_CUT ? 0.f : coupling(J, jst, inst, e, dtype);
       apply_op<T, NR, COUNT>(kind, a, b, -2.f * Jv, Jv, v, n);
     }
-    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < E; ++i) lds_f[mine + i] = v[i];
-    __syncthreads();
-    for (int e = threadIdx.x; e < nvalid; e += PT) __builtin_nontemporal_store(lds_f[e], &X[base + e]);
+    for (int c = 0; c < NC; ++c) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < EC; ++i) lds_f[mine + i] = v[c * EC + i];
+      __syncthreads();
+      low_drain<T>(lds_f, X, base, c, nvalid);
+    }
     if constexpr (COUNT) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < E; ++i) lds_u[mine + i] = n[i].r[r];
-        __syncthreads();
-        for (int e = threadIdx.x; e < nvalid; e += PT) __builtin_nontemporal_store(lds_u[e], &N[base + e + r * plane]);
+        for (int c = 0; c < NC; ++c) {
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < EC; ++i) lds_u[mine + i] = n[c * EC + i].r[r];
+          __syncthreads();
+          low_drain<T>(lds_u, N + r * plane, base, c, nvalid);
+        }
       }
     }
     return;
@@ -447,7 +513,7 @@ hipError_t launch_t(const PottsPass* pass, bool low, int64_t threads, const void
                        plane);
     return hipGetLastError();
   }
-  constexpr size_t lds = (size_t)PT * ipow3(T) * (COUNT ? sizeof(uint64_t) : sizeof(float));
+  constexpr size_t lds = (size_t)PT * low_chunk<T>() * (COUNT ? sizeof(uint64_t) : sizeof(float));
   static bool raised = false;   // one flag per instantiation
   if (!raised) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_potts_pass<T, NR, COUNT, true>),
