@@ -67,8 +67,8 @@ typedef enum tt_dtype {
                                integers), exactly, for sum|J| + sum|h| < 2^13 (TT_E_RANGE
                                otherwise; Sec. V keeps the chimera state in Int16 for the
                                same reason). tt_contract, tt_backward(_tie) and
-                               tt_plan_autotune on sweep plans (sliced ones included);
-                               other calls and chimera plans return TT_E_DTYPE, and a
+                               tt_plan_autotune on sweep and chimera plans (sliced
+                               ones included); other calls return TT_E_DTYPE, and a
                                backward whose pass inputs do not all fit the budget
                                returns TT_E_TOOBIG (no recomputation at int16). */
 } tt_dtype;

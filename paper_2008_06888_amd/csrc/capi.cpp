@@ -500,8 +500,8 @@ int check_common(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, con
   if (p.slice) return fail(TT_E_INVAL, "sliced plans are solved with tt_contract, tt_backward(_tie) and tt_count");
   if (batch < 1) return fail(TT_E_INVAL, "batch must be >= 1");
   if (dtype != TT_F32 && dtype != TT_I32 && dtype != TT_I16) return fail(TT_E_DTYPE, "unknown dtype %d", dtype);
-  if (dtype == TT_I16 && (p.is_chimera || p.n_regs != 1))
-    return fail(TT_E_DTYPE, "int16 couplings run on sweep plans only (not chimera)");
+  if (dtype == TT_I16 && !p.is_chimera && p.n_regs != 1)
+    return fail(TT_E_DTYPE, "int16 couplings need a single-register plan");
   if (p.m > 0 && !J) return fail(TT_E_INVAL, "null J");
   if (p.has_field && !h) return fail(TT_E_INVAL, "plan has fields but h is NULL");
   if (!p.has_field && h) return fail(TT_E_INVAL, "plan has no fields but h is given");
@@ -1598,12 +1598,12 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
       for (int b = 0; b < g.batch; ++b) {
         RedItem& it = items[b];
         std::memset(&it, 0, sizeof(it));
-        it.st = row_state[r - 1] + (int64_t)b * sst;
+        it.st = state_at(row_state[r - 1], (int64_t)b * sst, dtype);
         it.chunk_begin = (int64_t)b << lc;
         it.arg = args + (size_t)(r - 1) * g.batch + b;
         it.w = w;
         it.log2_chunks = lc;
-        it.bJ = static_cast<const char*>(g.J) + (size_t)b * p.m * sizeof(float);
+        it.bJ = static_cast<const char*>(g.J) + (size_t)b * p.m * coup_esz(dtype);
         it.bedge = vert + (size_t)(r - 1) * w;
         it.bref = args + (size_t)r * g.batch + b;
         it.bdtype = dtype;
@@ -1648,7 +1648,7 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
     {
       ProfScope ps(s, "sweep_pass", true);
       HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s,
-                          ps.start(), ps.stop()));
+                          ps.start(), ps.stop(), L.ng));
       ps.launched();
     }
     if (dc->chain_after[k] >= 0)
@@ -1658,12 +1658,14 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   uint64_t* pi = static_cast<uint64_t*>(dc->part_i.p);
   {
     ProfScope ps(s, "final_reduce");
-    HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks, pv, pi, s));
+    HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + ct.red_off), ct.n_red, ct.chunks, pv, pi, s, false,
+                          dtype == TT_I16));
   }
   if (backward) {
     for (int r = rows - 1; r >= 1; --r) {
       ProfScope ps(s, "row_argmax");
-      HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + walk_off[r]), g.batch, row_chunks, pv, pi, s));
+      HIP_TRY(launch_reduce(reinterpret_cast<const RedItem*>(dev + walk_off[r]), g.batch, row_chunks, pv, pi, s,
+                            false, dtype == TT_I16));
     }
     ProfScope ps(s, "chimera_finish");
     HIP_TRY(launch_chim_finish(reinterpret_cast<const ChimFinishItem*>(dev + fin_off), g.batch, dtype, s));

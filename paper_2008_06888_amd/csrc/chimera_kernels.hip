@@ -94,7 +94,9 @@ __device__ void chain_tables(cptr<ChimeraRow> R, int cols, cptr<IT> J, cptr<IT> 
   }
 }
 
-template <typename IT, bool COUNT>
+// SV: the state's entries (float32; int16 with int16 couplings, whose chain
+// values are integers well inside int16 by the input check).
+template <typename IT, bool COUNT, typename SV = float>
 __global__ __launch_bounds__(CH_T) void k_chain(const ChainItem* __restrict__ item) {
   const auto& I = *as_const(item);
   __shared__ float K[8][256], L[8][256];
@@ -197,14 +199,14 @@ __global__ __launch_bounds__(CH_T) void k_chain(const ChainItem* __restrict__ it
   const int lb = I.w < 16 ? I.w : 16;
   const uint32_t E = 1u << lb;
   const int64_t off = inst * I.sst + (int64_t)(blk << 16);
-  const gptr<float> x = as_global(I.x) + off;
+  const gptr<SV> x = as_global(reinterpret_cast<SV*>(I.x)) + off;
   const int np = I.nres;   // residue planes: three primes, and modulo 2^64 when there are four
   const gptr<uint64_t> nres = COUNT ? as_global(I.n) + inst * np * I.sst + (int64_t)(blk << 16) : nullptr;
   const bool init = I.init != 0;
   const int64_t sst = I.sst;
   auto update = [&](uint32_t e, float g, uint64_t gc) {
     // non-temporal stores: the next launch reads the state from memory
-    __builtin_nontemporal_store(init ? g : x[e] + g, &x[e]);
+    __builtin_nontemporal_store((SV)(init ? g : (float)x[e] + g), &x[e]);
     if (COUNT) {
       for (int r = 0; r < 3; ++r) {
         const gptr<uint64_t> pr = nres + (int64_t)r * sst + e;
@@ -347,6 +349,8 @@ hipError_t launch_chain(const ChainItem* item, int64_t n_blocks, int dtype, bool
   if (n_blocks >= (1ll << 31)) return hipErrorInvalidConfiguration;
   if (count)
     hipLaunchKernelGGL((k_chain<int32_t, true>), dim3((uint32_t)n_blocks), dim3(CH_T), 0, stream, item);
+  else if (dtype == 2)
+    hipLaunchKernelGGL((k_chain<int16_t, false, int16_t>), dim3((uint32_t)n_blocks), dim3(CH_T), 0, stream, item);
   else if (dtype == 0)
     hipLaunchKernelGGL((k_chain<float, false>), dim3((uint32_t)n_blocks), dim3(CH_T), 0, stream, item);
   else
@@ -355,7 +359,9 @@ hipError_t launch_chain(const ChainItem* item, int64_t n_blocks, int dtype, bool
 }
 
 hipError_t launch_chim_finish(const ChimFinishItem* item, int batch, int dtype, hipStream_t stream) {
-  if (dtype == 0)
+  if (dtype == 2)
+    hipLaunchKernelGGL(k_chim_finish<int16_t>, dim3(batch), dim3(CH_T), 0, stream, item);
+  else if (dtype == 0)
     hipLaunchKernelGGL(k_chim_finish<float>, dim3(batch), dim3(CH_T), 0, stream, item);
   else
     hipLaunchKernelGGL(k_chim_finish<int32_t>, dim3(batch), dim3(CH_T), 0, stream, item);

@@ -158,7 +158,7 @@ struct RedItem {
   const void* bJ;        // couplings of the instance (bonus), or NULL
   const int32_t* bedge;  // [w] edge per slot, -1 = none
   const uint64_t* bref;  // selected address of the next row
-  int32_t bdtype, pad;
+  int32_t bdtype, pad;   // dtype of bJ: 0 float32, 1 int32, 2 int16
 };
 
 // Chimera row chain (see ChimeraRow): adds (init: writes) to every entry of

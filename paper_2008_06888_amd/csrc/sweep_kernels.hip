@@ -1421,8 +1421,9 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict
         if (sl >= I.w) break;
         const int e = bedge[sl];
         if (e < 0) continue;
-        const float Jv = I.bdtype == 0 ? as_const(static_cast<const float*>(I.bJ))[e]
-                                       : (float)as_const(static_cast<const int32_t*>(I.bJ))[e];
+        const float Jv = I.bdtype == 0   ? as_const(static_cast<const float*>(I.bJ))[e]
+                         : I.bdtype == 2 ? (float)as_const(static_cast<const int16_t*>(I.bJ))[e]
+                                         : (float)as_const(static_cast<const int32_t*>(I.bJ))[e];
         t += (((ref >> sl) ^ (uint64_t)(v >> q)) & 1ull) ? -Jv : Jv;
       }
       bt[b][v] = t;

@@ -176,3 +176,42 @@ def test_range_guard():
     J = torch.full((1, len(e)), 70, dtype=torch.int16, device=DEV)    # 7840 < 2^13: exact
     E = B.contract(plan, J).cpu().numpy()[0]
     assert E == -70 * len(e)
+
+
+@pytest.mark.parametrize("rows,cols,tb", [(1, 3, 0), (2, 2, 0), (3, 3, 8), (3, 4, 9), (4, 4, 0)])
+def test_chimera_int16(rows, cols, tb):
+    """Chimera plans (relabel passes, row chains, row-by-row argmax) with the
+    int16 state: bit for bit the int32 path, energies those of the oracle,
+    integer fields included."""
+    n = 8 * rows * cols
+    e = I.chimera(rows, cols)
+    rng = np.random.default_rng([18, rows, cols])
+    J = np.stack([I.pm1(len(e), rng) for _ in range(3)])
+    h = rng.integers(-1, 2, (3, n)).astype(np.int32)
+    for fields in (False, True):
+        plan = B.Plan(n, e, chimera=(rows, cols), tile_bits=tb, has_field=fields)
+        say("int16 chimera", rows, cols, "fields", fields)
+        r32, r16 = both(plan, J, h if fields else None)
+        assert_same(r32, r16)
+        for b in range(3):
+            hb = h[b] if fields else None
+            ref = O.eliminate(n, e, J[b], hb, traceback=False)
+            assert r16[0][b] == ref["energy"] and O.energy(n, e, J[b], hb, r16[1][b]) == ref["energy"], b
+
+
+def test_chimera8_int16_full_size():
+    """8 x 8 cells (2^32-entry state): the planted instance's E* = -m and
+    sigma = +-tau, and a +-J instance equal to the int32 path."""
+    e = I.chimera(8)
+    x, tau = I.planted(e, 512, np.random.default_rng(93))
+    plan = B.Plan(512, e, chimera=(8, 8))
+    say("int16 chimera 8x8 planted")
+    E, sig, _, _ = B.backward(plan, dev(x.J[None], np.int16))
+    s = sig[0].cpu().numpy()
+    assert E[0].item() == -len(e)
+    assert np.array_equal(s, tau) or np.array_equal(s, -tau)
+    y = I.make(e, 512, I.rng_for(4, 0), "pm1")
+    say("int16 chimera 8x8 pm1")
+    r32, r16 = both(plan, y.J[None])
+    assert_same(r32, r16)
+    assert O.energy(512, e, y.J, None, r16[1][0]) == r16[0][0]
