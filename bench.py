@@ -170,6 +170,7 @@ def bench_chimera(args):
     t_solve16 = _timed(lambda: B.backward(plan, J16), steps)
     plan.close()
     cplan = B.Plan(512, x.edges, chimera=(8, 8))
+    B.count(cplan, J)   # first call: device buffers (about 150 GB with four residue planes)
     t0 = time.perf_counter()
     Ec, res, g = B.count(cplan, J)
     t_count = time.perf_counter() - t0
