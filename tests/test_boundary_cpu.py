@@ -147,3 +147,15 @@ def test_count_log_of_known_counts():
         assert abs(B.count_log(res) - math.log(g)) <= 1e-14 * max(1.0, math.log(g)), g
     with pytest.raises(B.TTError):
         B.count_log([0, 0, 0])
+
+
+def test_int16_refused_where_unsupported_before_device_work():
+    """int16 couplings (TT_I16) run on sweep and chimera plans through
+    tt_contract / tt_backward; the uneven and allocation-free calls refuse
+    them before touching the device."""
+    p = B.Plan(16, I.square_lattice(4), order=list(range(16)))
+    lib = B.lib()
+    assert lib.tt_contract_noalloc(p.handle, 1, B.TT_I16, FAKE, None, FAKE, None) == B.TT_E_DTYPE
+    assert lib.tt_contract_uneven(1, (C.c_void_p * 1)(p.handle), B.TT_I16, FAKE,
+                                  np.zeros(1, np.int64).ctypes.data, FAKE, None, None, None, None) == B.TT_E_DTYPE
+    assert lib.tt_contract(p.handle, 1, 3, FAKE, None, FAKE, None) == B.TT_E_DTYPE     # no dtype 3
