@@ -96,6 +96,19 @@ typedef struct tt_plan_opts {
   int32_t q;                /* labels per spin: 2 = Ising spins, 3 = 3-state Potts
                                glass (App. C; GREEDY or GIVEN order, no fields,
                                tt_potts_* calls only) [2] */
+  int32_t z2;               /* 1: keep half of every energy-path state (plans without
+                               fields, GREEDY or GIVEN order). With h = 0 Eq. (1) is
+                               even under flipping every spin, and so is every partial
+                               contraction: entries whose top address bit is 1 are read
+                               at the complement address, and a pass runs half of its
+                               tiles, each also writing its mirror outputs. Same
+                               results (E*, a ground state, gradients) for about half
+                               the bytes and work of every pass. tt_contract,
+                               tt_backward(_tie), tt_contract_uneven(_fields) and
+                               tt_count (which counts on the full state) accept such
+                               plans; a backward that would need checkpoint
+                               recomputation returns TT_E_TOOBIG, the
+                               allocation-free call TT_E_INVAL. [0] */
 } tt_plan_opts;
 
 typedef struct tt_plan_stats {
@@ -106,7 +119,9 @@ typedef struct tt_plan_stats {
   int32_t n_passes;         /* energy-path passes (kernel launches per batch) */
   int32_t n_count_passes;   /* count-path passes */
   /* algorithmic work per instance, at the live width of every step:
-   * max-plus ops = 2 * terms + elementwise */
+   * max-plus ops = 2 * terms + elementwise; for half-state plans (z2) the
+   * entries their passes visit (half of a pass's state where the pass has a
+   * tile-id bit with an output position, and half of the final state) */
   double terms;             /* contraction terms (one add + one max): K per output entry */
   double elementwise;       /* elementwise ops: diagonal / field absorbs (one add per
                                entry), cuts and the final maximum (one max per entry) */

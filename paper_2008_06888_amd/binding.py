@@ -48,7 +48,7 @@ class PlanOpts(C.Structure):
                 ("trials", C.c_int32), ("has_field", C.c_int32), ("tile_bits", C.c_int32),
                 ("count_tile_bits", C.c_int32), ("chimera_rows", C.c_int32),
                 ("chimera_cols", C.c_int32), ("max_bytes", C.c_int64), ("parts", C.c_int32),
-                ("q", C.c_int32)]
+                ("q", C.c_int32), ("z2", C.c_int32)]
 
 
 class PlanStats(C.Structure):
@@ -120,7 +120,8 @@ class Plan:
     def __init__(self, n: int, edges, *, order: Optional[Sequence[int]] = None, kind: Optional[int] = None,
                  has_field: bool = False, seed: int = 0, trials: int = 32, tile_bits: int = 0,
                  count_tile_bits: int = 0, chimera: Optional[tuple] = None, max_bytes: int = 0,
-                 parts: int = 0, q: int = 2, n_fixed: int = 0, fixed: Optional[Sequence[int]] = None):
+                 parts: int = 0, q: int = 2, n_fixed: int = 0, fixed: Optional[Sequence[int]] = None,
+                 z2: bool = False):
         """n_fixed / fixed: a sliced plan (tt_plan_create_sliced) with that many
         fixed spins, given or (fixed None) chosen by the planner."""
         self.n = int(n)
@@ -140,6 +141,7 @@ class Plan:
         if chimera:
             o.chimera_rows, o.chimera_cols = chimera
         o.q = q
+        o.z2 = int(bool(z2))
         self.q = q
         h = _vp()
         if fixed is not None or n_fixed:

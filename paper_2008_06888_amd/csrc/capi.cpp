@@ -861,8 +861,13 @@ struct CallTables {
 
 // Partials of the final maximum per instance: with the reduction fused into
 // the last pass, one per tile of that pass, else one per fixed-size chunk.
+// Half-state plans: the tiles a pass runs (2^(n_free - 1) when it pairs them)
+// and the width of the stored half of the final state.
+int run_tile_bits(const Plan& p, const DevPass2& P) { return P.n_free - (p.z2 && P.z2_skip >= 0 ? 1 : 0); }
+int red_width(const Plan& p) { return p.final_w - (p.z2 && p.final_w > 0 ? 1 : 0); }
+
 int red_log2_parts(const Group& g, bool fused) {
-  return fused ? g.ep->passes.back().n_free : reduce_log2_chunks(g.p->final_w);
+  return fused ? run_tile_bits(*g.p, g.ep->passes.back()) : reduce_log2_chunks(red_width(*g.p));
 }
 
 // The final maximum can be taken inside the last pass when every group has
@@ -957,7 +962,8 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
         it.red_i = pi;
         it.red_base = part_base[gi];
       }
-      const int64_t n_wg = ((int64_t)g.batch << P.n_free);
+      it.z2 = g.p->z2 ? 1 : 0;
+      const int64_t n_wg = ((int64_t)g.batch << run_tile_bits(*g.p, P));
       wg += (n_wg + 7) & ~int64_t(7);
       items.push_back(it);
       if (items.size() == MAXI) flush();
@@ -967,7 +973,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
   std::vector<RedItem> red;
   for (Group& g : groups) {
     if (!with_red) break;
-    const int fw = g.p->final_w;
+    const int fw = red_width(*g.p);
     const int lc = red_log2_parts(g, fuse);
     const int np = (int)g.ep->passes.size();
     for (int b = 0; b < g.batch; ++b) {
@@ -1018,6 +1024,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
       it.dJ = g.dJ ? g.dJ + (size_t)b * g.p->m : nullptr;
       it.dh = g.dh ? g.dh + (size_t)b * g.p->n : nullptr;
       it.m = g.p->m;
+      it.z2 = g.p->z2 ? 1 : 0;
       it.n_passes = np;
       it.final_w = g.p->final_w;
       it.n = g.p->n;
@@ -1462,6 +1469,9 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
     const DevCache* dc = static_cast<const DevCache*>(p.dev);
     const int64_t have = dc ? (int64_t)dc->ckpt.cap : 0;
     if (need > have && need > budget_bytes(p) + have) {
+      if (p.z2)
+        return fail(TT_E_TOOBIG, "the half-state backward keeps every pass input: %lld bytes (budget %lld)",
+                    (long long)need, (long long)budget_bytes(p));
       if (dtype == TT_I16)
         return fail(TT_E_TOOBIG, "the int16 backward keeps every pass input: %lld bytes (budget %lld)",
                     (long long)need, (long long)budget_bytes(p));
@@ -2188,6 +2198,10 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
     p->q = o.q == 3 ? 3 : 2;
     if (p->q == 3 && (o.kind == TT_ORDER_CHIMERA || p->has_field))
       return fail(TT_E_INVAL, "3-state plans take a GREEDY or GIVEN order and no fields");
+    if (o.z2 != 0 && o.z2 != 1) return fail(TT_E_INVAL, "z2 must be 0 or 1");
+    if (o.z2 && (p->has_field || p->q != 2 || o.kind == TT_ORDER_CHIMERA))
+      return fail(TT_E_INVAL, "the half state (z2) needs an Ising sweep plan without fields");
+    p->z2 = o.z2 != 0;
     std::string err;
     if (o.kind == TT_ORDER_GIVEN) {
       if (!o.order) return fail(TT_E_INVAL, "TT_ORDER_GIVEN needs opts.order");
@@ -2236,6 +2250,7 @@ int tt_plan_create_sliced(int32_t n_spins, int64_t n_edges, const int32_t* edges
     if (opts) o = *opts;
     if (o.q == 3 || o.kind == TT_ORDER_CHIMERA)
       return fail(TT_E_INVAL, "sliced plans are Ising sweep plans (GREEDY or GIVEN order)");
+    if (o.z2) return fail(TT_E_INVAL, "sliced plans keep full states (their slices carry fields)");
     if (o.kind != TT_ORDER_GREEDY && o.kind != TT_ORDER_GIVEN) return fail(TT_E_INVAL, "unknown order kind %d", o.kind);
     // the whole graph's plan validates the graph and gives the base order
     tt_plan* whole = nullptr;
@@ -2384,6 +2399,22 @@ int tt_plan_info(const tt_plan* plan, tt_plan_stats* out) {
   double upd = 0;
   for (const Pass& ps : p.passes) upd += 2.0 * std::ldexp(1.0, ps.w_max);
   out->entry_updates = upd;
+  if (p.z2) {
+    // a half-state pass visits half of the entries (all of them when no
+    // tile-id bit has an output position), as does the final maximum
+    EnergyProgram ep;
+    const std::string err = encode_energy(p, p.passes, ep);
+    if (!err.empty()) return fail(TT_E_INVAL, "%s", err.c_str());
+    std::vector<double> scale(p.ops.size(), 1.0);
+    upd = 0;
+    for (size_t q = 0; q < p.passes.size(); ++q) {
+      const double f = ep.passes[q].z2_skip >= 0 ? 0.5 : 1.0;
+      for (int32_t k = p.passes[q].op_begin; k < p.passes[q].op_end; ++k) scale[k] = f;
+      upd += 2.0 * std::ldexp(f, p.passes[q].w_max);
+    }
+    sweep_work(p, scale.data(), p.final_w > 0 ? 0.5 : 1.0, &out->terms, &out->elementwise, &out->reduce_ops);
+    out->entry_updates = upd;
+  }
   return TT_OK;
 }
 
@@ -2524,6 +2555,7 @@ int tt_contract_noalloc(tt_plan* plan, int32_t batch, int32_t dtype, const void*
     if (p.is_chimera || p.n_regs != 1)
       return fail(TT_E_INVAL, "chimera plans are not supported by the allocation-free call");
     if (dtype == TT_I16) return fail(TT_E_DTYPE, "the allocation-free call takes float32 or int32 couplings");
+    if (p.z2) return fail(TT_E_INVAL, "the allocation-free call takes full-state plans (z2 = 0)");
     if (int r = early_budget(p, state_bytes(p, batch, false))) return r;
     const EnergyProgram* ep = nullptr;
     if (int r = host_program(p, &ep)) return r;

@@ -84,7 +84,8 @@ struct DevPass2 {
   uint32_t ld_hti[16], st_hti[16];
   uint64_t ld_had[16], st_had[16];
   int32_t tb;            // log2 of the threads a tile uses (max(6, t - 4), at most 10)
-  int32_t pad_tb;
+  int32_t z2_skip;       // half-state plans: tile-id bit k (fixed slot fre[k], one with an
+                         // output position) whose tiles at 1 are not run, -1 if none
   uint8_t fin[48];       // fre[k] -> input address bit (NO_POS if none)
   uint8_t fout[48];      // fre[k] -> output address bit (NO_POS if none)
   int32_t op_begin, n_ops;   // the pass's fused ops (all its stages)
@@ -143,6 +144,11 @@ struct PassItem {
   float* red_v;
   uint64_t* red_i;
   int64_t red_base;
+  // Half-state plan (h = 0): entries whose top address bit is 1 are read and
+  // written at the complement address; the tiles with fixed slot
+  // P.z2_skip at 1 are not run (their outputs are the complements of the
+  // others'), and red_base indexes the run tiles only.
+  int32_t z2, pad_z2;
 };
 
 // Final reduction of one instance's state (2^w entries): maximum and its
@@ -248,6 +254,9 @@ struct BwdItem {
   // other values a pseudo-random order per pass (the final state's own
   // maximum keeps the lowest address).
   uint64_t tie;
+  // Half-state plan: checkpoint entries whose top address bit is 1 are read
+  // at the complement address.
+  int32_t z2, pad_z2;
 };
 
 }  // namespace tt

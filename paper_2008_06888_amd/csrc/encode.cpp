@@ -167,6 +167,14 @@ std::string encode_energy(const Plan& p, const std::vector<Pass>& passes, Energy
     }
     // threads per tile: 16 entries each, one wave at least, 1024 at most
     d.tb = std::min(10, std::max(6, d.t - 4));
+    // half-state plans pair each tile with its complement: the lowest tile-id
+    // bit whose fixed slot has an output position separates the pairs
+    d.z2_skip = -1;
+    for (int k = 0; k < d.n_free; ++k)
+      if (d.fout[k] != NO_POS) {
+        d.z2_skip = k;
+        break;
+      }
     // enumeration orders of the load and the store
     std::vector<int> ld, st, ld_rest, st_rest;
     for (int k = 0; k < d.t; ++k) {

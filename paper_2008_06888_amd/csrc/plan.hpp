@@ -131,6 +131,7 @@ struct Plan {
   void* dev = nullptr;               // device-side cache (owned, see capi)
   void* host_prog = nullptr;         // host encoding of the energy passes (owned, see capi)
   int32_t q = 2;                     // labels per spin: 2 (Ising) or 3 (Potts glass, App. C)
+  bool z2 = false;                   // energy path keeps half of every state (h = 0 symmetry)
   void* potts = nullptr;             // 3-label programs and device cache (owned, see capi)
   void* slice = nullptr;             // sliced plan: fixed spins and the reduced plan (owned, see capi)
   uint64_t serial = 0;               // unique over the process lifetime (never reused)
@@ -138,6 +139,11 @@ struct Plan {
 
 // Builds ops from a spin order; returns "" or an error message.
 std::string build_sweep_ops(Plan& p);
+// Max-plus work per instance of the plan's ops at their live widths, each op's
+// entries scaled by op_scale[k] (null: 1) and the final maximum by
+// final_scale.
+void sweep_work(const Plan& p, const double* op_scale, double final_scale, double* terms, double* elementwise,
+                double* reduce_ops);
 // Greedy order search with restarts.
 std::vector<int32_t> greedy_order(int32_t n, const std::vector<int32_t>& edges, uint64_t seed,
                                   int trials);

@@ -187,27 +187,33 @@ std::string build_sweep_ops(Plan& p) {
   p.final_w = p.ops.empty() ? 0 : p.ops.back().w_after;
   p.final_slot_spin.assign(p.final_w, -1);
   for (int s = 0; s < p.final_w && s < (int)slot_spin.size(); ++s) p.final_slot_spin[s] = slot_spin[s];
+  sweep_work(p, nullptr, 1.0, &p.terms, &p.elementwise, &p.reduce_ops);
+  return "";
+}
+
+void sweep_work(const Plan& p, const double* op_scale, double final_scale, double* terms, double* elementwise,
+                double* reduce_ops) {
   // algorithmic work, at the live (not the physical) width: a GATE is a
   // contraction with K = 2, i.e. two terms (add + max) per output entry; a
   // DIAG or FIELD is an elementwise tropical product (one add per entry), a
   // CUT an elementwise maximum of the two halves (one max per output entry),
   // and the final maximum one max per entry of the last state
-  double terms = 0, elem = 0;
+  double t = 0, elem = 0;
   int live_now = 0;
-  for (auto& op : p.ops) {
+  for (size_t k = 0; k < p.ops.size(); ++k) {
+    const SweepOp& op = p.ops[k];
     if (op.kind == OP_INTRO) live_now += 1;
-    const double sz = std::ldexp(1.0, live_now);
-    if (op.kind == OP_GATE) terms += 2 * sz;
+    const double sz = std::ldexp(1.0, live_now) * (op_scale ? op_scale[k] : 1.0);
+    if (op.kind == OP_GATE) t += 2 * sz;
     if (op.kind == OP_DIAG || op.kind == OP_FIELD) elem += sz;
     if (op.kind == OP_CUT) {
       elem += sz / 2;
       live_now -= 1;
     }
   }
-  p.reduce_ops = std::ldexp(1.0, live_now);   // final reduction
-  p.terms = terms;
-  p.elementwise = elem + p.reduce_ops;
-  return "";
+  *reduce_ops = std::ldexp(1.0, live_now) * final_scale;   // final reduction
+  *terms = t;
+  *elementwise = elem + *reduce_ops;
 }
 
 std::vector<int32_t> greedy_order(int32_t n, const std::vector<int32_t>& edges, uint64_t seed,

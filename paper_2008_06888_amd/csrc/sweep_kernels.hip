@@ -61,6 +61,16 @@ __device__ __forceinline__ bool wg_to_tile(uint64_t b, int log2_tiles, int batch
 
 
 
+// Half-state plans (h = 0): the tile index of a run tile k (tile-id bit
+// `skip` at 0), and the stored (canonical) address of an entry: the
+// complement of every address bit when the top one is set.
+__device__ __forceinline__ uint64_t z2_tile(uint64_t k, int skip) {
+  return skip < 0 ? k : (((k >> skip) << (skip + 1)) | (k & ((1ull << skip) - 1ull)));
+}
+__device__ __forceinline__ uint64_t z2_addr(uint64_t a, int w) {
+  return (w > 0 && ((a >> (w - 1)) & 1ull)) ? a ^ ((1ull << w) - 1ull) : a;
+}
+
 // A lane value the compiler may not re-derive (keeps a pre-shifted LDS
 // address part from being folded back into a shift after the XOR).
 __device__ __forceinline__ uint32_t opaque(uint32_t x) {
@@ -486,8 +496,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
   const cptr<DevStage> stages = as_const(I.stages);
   const cptr<FOp> fops = as_const(I.fops);
   int64_t inst;
-  uint64_t tid_bits;
-  if (!wg_to_tile((uint64_t)(wg - I.wg_begin), P.n_free, I.batch, I.xcd_group, &inst, &tid_bits)) return;
+  uint64_t ktile;
+  // half-state plans run the tiles with fixed slot z2_skip at 0 only
+  const bool z2 = I.z2 != 0;
+  const int zskip = z2 ? P.z2_skip : -1;
+  const int run_bits = P.n_free - (zskip >= 0 ? 1 : 0);
+  if (!wg_to_tile((uint64_t)(wg - I.wg_begin), run_bits, I.batch, I.xcd_group, &inst, &ktile)) return;
+  const uint64_t tid_bits = z2_tile(ktile, zskip);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const cptr<IT> Jrow = as_const(static_cast<const IT*>(I.J)) + inst * I.jst;
@@ -572,7 +587,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
     // without a branch: otherwise (and in the first pass, whose state
     // starts at zero) the resource has no records and they return zeros
     // without touching memory.
-    fast_ld = !init && nk_ld == 16 && all < BUF_MAX_ENTRIES;
+    fast_ld = !init && !z2 && nk_ld == 16 && all < BUF_MAX_ENTRIES;
     const __amdgpu_buffer_rsrc_t rs = raw_rsrc(src, fast_ld ? 0x7fffffff : 0);
     const uint32_t off = (uint32_t)ad_lo << 2;
 #pragma unroll
@@ -588,12 +603,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
   // never read)
   const OpLanes R = resolve_lane(opin, bs);
   if (loader && !init && !fast_ld) {
-    // the general load (64-bit addresses or fewer than 16 entries per
-    // thread), after the resolve so that its branch does not hold back the
-    // loads above
+    // the general load (64-bit addresses, fewer than 16 entries per thread,
+    // or stored addresses of a half-state plan), after the resolve so that
+    // its branch does not hold back the loads above
+    if (z2) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-      if (k < nk_ld) vals[k] = src[ad_lo_ld | had_ld[k]];
+      for (int k = 0; k < 16; ++k)
+        if (k < nk_ld) vals[k] = in[z2_addr(in_base | ad_lo_ld | had_ld[k], P.in_w)];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk_ld) vals[k] = src[ad_lo_ld | had_ld[k]];
+    }
   }
   if (loader) {
     uint32_t hs[16];
@@ -647,7 +668,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
     }
     __syncthreads();
   }
-  const int64_t red_at = I.red_base + (inst << P.n_free) + (int64_t)tid_bits;
+  const int64_t red_at = I.red_base + (inst << run_bits) + (int64_t)ktile;
   if (!stored) {
     // a duplicate tile (a dropped slot at 1): nothing to store or rank
     if (I.red_v && tid == 0) {
@@ -697,7 +718,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
         for (int k = 0; k < 16; ++k) {
           if (k < nk) {
             const float v = lds_at(ls ^ hs[k]);
-            const uint64_t a = out_base | ad_lo | had[k];
+            const uint64_t a = z2 ? z2_addr(out_base | ad_lo | had[k], P.out_w) : (out_base | ad_lo | had[k]);
             if (v > bv || (v == bv && a < bi)) {
               bv = v;
               bi = a;
@@ -730,7 +751,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
       }
       return;
     }
-    if (tid < (1 << nb)) {
+    if (tid < (1 << nb) && z2) {
+      // half-state plan: every output at its stored address (the mirror
+      // outputs of the tile's complement included)
+      const int nk = 1 << (ns - nb);
+      const uint32_t ls = opaque(swz(ti_lo) << 2);
+      float vals[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk) vals[k] = lds_at(ls ^ hs[k]);
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < nk) __builtin_nontemporal_store(vals[k], &out[z2_addr(out_base | ad_lo | had[k], P.out_w)]);
+    } else if (tid < (1 << nb)) {
       const int nk = 1 << (ns - nb);
       const uint32_t ls = opaque(swz(ti_lo) << 2);
       float vals[16];
@@ -1075,8 +1108,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
   const cptr<DevStage> stages = as_const(I.stages);
   const cptr<FOp> fops = as_const(I.fops);
   int64_t inst;
-  uint64_t tid_bits;
-  if (!wg_to_tile((uint64_t)(wg - I.wg_begin), P.n_free, I.batch, I.xcd_group, &inst, &tid_bits)) return;
+  uint64_t ktile;
+  // half-state plans run the tiles with fixed slot z2_skip at 0 only
+  const bool z2 = I.z2 != 0;
+  const int zskip = z2 ? P.z2_skip : -1;
+  const int run_bits = P.n_free - (zskip >= 0 ? 1 : 0);
+  if (!wg_to_tile((uint64_t)(wg - I.wg_begin), run_bits, I.batch, I.xcd_group, &inst, &ktile)) return;
+  const uint64_t tid_bits = z2_tile(ktile, zskip);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const cptr<int16_t> Jrow = as_const(static_cast<const int16_t*>(I.J)) + inst * I.jst;
@@ -1143,7 +1181,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
     __builtin_amdgcn_sched_barrier(0);
     // the buffer covers the instance's input state from this tile's base
     // (records in bytes): every entry the tile reads lies inside it
-    fast_ld = !init && nk_ld == 16 && all < BUF_MAX_ENTRIES;
+    fast_ld = !init && !z2 && nk_ld == 16 && all < BUF_MAX_ENTRIES;
     const uint64_t rec = ((uint64_t)I.in_st - in_base) * 2ull;
     const __amdgpu_buffer_rsrc_t rs =
         raw_rsrc(src, fast_ld ? (int)(rec < 0x7fffffffull ? rec : 0x7fffffffull) : 0);
@@ -1162,9 +1200,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
 #pragma unroll
     for (int h = 0; h < NG; ++h)
       if (loader[h]) {
+        if (z2) {   // stored addresses of a half-state plan
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (k < nk_ld) vals[h][k] = src[ad_ld[h] | had_ld[k]];
+          for (int k = 0; k < 16; ++k)
+            if (k < nk_ld) vals[h][k] = in16[z2_addr(in_base | ad_ld[h] | had_ld[k], P.in_w)];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 16; ++k)
+            if (k < nk_ld) vals[h][k] = src[ad_ld[h] | had_ld[k]];
+        }
       }
   }
   {
@@ -1233,7 +1277,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
     }
     __syncthreads();
   }
-  const int64_t red_at = I.red_base + (inst << P.n_free) + (int64_t)tid_bits;
+  const int64_t red_at = I.red_base + (inst << run_bits) + (int64_t)ktile;
   if (!stored) {
     if (I.red_v && tid == 0) {
       as_global(I.red_v)[red_at] = -INFINITY;
@@ -1286,7 +1330,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
         for (int k = 0; k < 16; ++k) {
           if (k < nk) {
             const float v = (float)lds16_at(ls ^ hs[k]);
-            const uint64_t a = out_base | ad_st[h] | had[k];
+            const uint64_t a = z2 ? z2_addr(out_base | ad_st[h] | had[k], P.out_w) : (out_base | ad_st[h] | had[k]);
             if (v > bv || (v == bv && a < bi)) {
               bv = v;
               bi = a;
@@ -1319,7 +1363,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
       }
       return;
     }
-    const bool fast_st = nk == 16 && all < BUF_MAX_ENTRIES;
+    const bool fast_st = !z2 && nk == 16 && all < BUF_MAX_ENTRIES;
     const uint64_t rec = ((uint64_t)I.out_st - out_base) * 2ull;
     const __amdgpu_buffer_rsrc_t rs = raw_rsrc(dst, (int)(rec < 0x7fffffffull ? rec : 0x7fffffffull));
 #pragma unroll
@@ -1338,9 +1382,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
 #pragma unroll
         for (int k = 0; k < 16; ++k)
           if (k < nk) sv[k] = lds16_at(ls ^ hs[k]);
+        if (z2) {   // every output at its stored address (the mirror outputs included)
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (k < nk) __builtin_nontemporal_store(sv[k], &dst[ad_st[h] | had[k]]);
+          for (int k = 0; k < 16; ++k)
+            if (k < nk) __builtin_nontemporal_store(sv[k], &out16[z2_addr(out_base | ad_st[h] | had[k], P.out_w)]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 16; ++k)
+            if (k < nk) __builtin_nontemporal_store(sv[k], &dst[ad_st[h] | had[k]]);
+        }
       }
     }
   }
@@ -1613,10 +1663,12 @@ __device__ __forceinline__ uint64_t opaque64(uint64_t x) {
 template <typename SV>
 struct BwdSrc {
   bool have;
-  cptr<SV> src;   // state entries (float32, or int16 for int16 couplings)
+  cptr<SV> src;   // the pass's input state (float32, or int16 for int16 couplings)
   const uint64_t* AL;
   const uint64_t* AH;
   uint32_t na;
+  uint64_t base;  // input address of the surviving slots
+  int zw;         // half-state plan: the input width (stored addresses), else 0
 };
 
 __device__ __forceinline__ bool have_src_of(const LPass& P) { return !P.init; }
@@ -1633,7 +1685,8 @@ __device__ __forceinline__ void bwd_issue(float (&val)[8], const BwdSrc<SV>& S, 
   for (int j = 0; j < W; ++j) {
     const uint32_t a = a0 + (uint32_t)j * NT;
     const uint64_t off = S.AL[a & 255u] | S.AH[(a >> 8) & 255u];
-    val[j] = (float)S.src[opaque64((S.have && a < S.na) ? off : 0ull)];
+    const uint64_t ad = S.base | ((S.have && a < S.na) ? off : 0ull);
+    val[j] = (float)S.src[opaque64(S.zw ? z2_addr(ad, S.zw) : ad)];
   }
 }
 
@@ -1852,9 +1905,10 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
       // before, so the first batch's loads are issued here, without a
       // branch, and stay in flight while the term tables are built. Only
       // the W = 1, 2, 4 or 8 of them that cover the candidates are scored.
-      const BwdSrc<SV> S{have_src_of(P), have_src_of(P) ? as_const(reinterpret_cast<const SV*>(ckpt[p])) + base_cur
-                                                        : as_const(reinterpret_cast<const SV*>(g_zero_words)),
-                     ad_lo[p & 1], ad_hi[p & 1], na};
+      const bool hv = have_src_of(P);
+      const BwdSrc<SV> S{hv, hv ? as_const(reinterpret_cast<const SV*>(ckpt[p]))
+                                : as_const(reinterpret_cast<const SV*>(g_zero_words)),
+                         ad_lo[p & 1], ad_hi[p & 1], na, hv ? base_cur : 0ull, (hv && I.z2) ? P.in_w : 0};
       const int wsel = na <= (uint32_t)NT ? 1 : na <= 2u * NT ? 2 : na <= 4u * NT ? 4 : 8;
       const uint32_t nb = (na + 8u * NT - 1u) / (8u * NT);
       float val[8];

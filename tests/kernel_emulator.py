@@ -23,7 +23,7 @@ class DevPass2(C.Structure):
                 ("n_ld", C.c_int32), ("n_st", C.c_int32), ("ld_bti", C.c_uint32 * 16), ("st_bti", C.c_uint32 * 16),
                 ("ld_bad", C.c_uint64 * 16), ("st_bad", C.c_uint64 * 16), ("ld_hti", C.c_uint32 * 16),
                 ("st_hti", C.c_uint32 * 16), ("ld_had", C.c_uint64 * 16), ("st_had", C.c_uint64 * 16),
-                ("tb", C.c_int32), ("pad_tb", C.c_int32), ("fin", C.c_uint8 * 48), ("fout", C.c_uint8 * 48),
+                ("tb", C.c_int32), ("z2_skip", C.c_int32), ("fin", C.c_uint8 * 48), ("fout", C.c_uint8 * 48),
                 ("op_begin", C.c_int32), ("n_ops", C.c_int32)]
 
 
@@ -76,11 +76,19 @@ def _ebit(enc, i, bs):
     return (i >> enc) & 1 if enc < SLOT_FIXED else (bs >> (enc - SLOT_FIXED)) & 1
 
 
-def forward(prog, width, J, h, x0=None, after_pass=None):
+def z2_addr(a, w):
+    """Stored address of entry a of a half-state plan (top bit of w set: complement)."""
+    return a ^ ((1 << w) - 1) if w > 0 and (a >> (w - 1)) & 1 else a
+
+
+def forward(prog, width, J, h, x0=None, after_pass=None, z2=False):
     """Runs every pass; returns the list of pass inputs and the final state.
 
     x0: initial state (default zeros); after_pass(q, state): called on each
-    pass's output state (may modify it in place)."""
+    pass's output state (may modify it in place). z2: the half-state mode
+    (h = 0): only the tiles with tile-id bit z2_skip at 0 run, every read and
+    write goes to the stored address; every stored entry of each output must
+    be written."""
     size = 1 << width
     states = [np.zeros(size) if x0 is None else np.array(x0, dtype=np.float64)]
     for qi, P in enumerate(prog["passes"]):
@@ -92,6 +100,8 @@ def forward(prog, width, J, h, x0=None, after_pass=None):
         for k in range(P.n_free):
             assert P.fin[k] == P.in_pos[P.fre[k]] and P.fout[k] == P.out_pos[P.fre[k]]
         for tid in range(1 << P.n_free):
+            if z2 and P.z2_skip >= 0 and (tid >> P.z2_skip) & 1:
+                continue
             bs = in_base = out_base = 0
             stored = True
             for k in range(P.n_free):
@@ -114,7 +124,7 @@ def forward(prog, width, J, h, x0=None, after_pass=None):
                         a |= P.ld_bad[k]
                 ti |= P.ld_hti[hi]
                 a |= P.ld_had[hi]
-                tile[ti] = 0.0 if P.init else src[in_base | a]
+                tile[ti] = 0.0 if P.init else src[z2_addr(in_base | a, P.in_w) if z2 else in_base | a]
             assert not np.any(np.isnan(tile))
             if P.n_stages:
                 stg = prog["stages"]
@@ -178,16 +188,23 @@ def forward(prog, width, J, h, x0=None, after_pass=None):
                         a |= P.st_bad[k]
                 ti |= P.st_hti[hi]
                 a |= P.st_had[hi]
-                dst[out_base | a] = tile[ti]
+                o = z2_addr(out_base | a, P.out_w) if z2 else out_base | a
+                if z2 and not np.isnan(dst[o]):
+                    assert dst[o] == tile[ti], "two tiles wrote different values to one stored entry"
+                dst[o] = tile[ti]
+        if z2:
+            half = (1 << P.out_w) >> 1 if P.out_w > 0 else 1
+            assert not np.any(np.isnan(dst[:half])), "a stored entry of the half state was not written"
         if after_pass is not None:
             after_pass(qi, dst)
         states.append(dst)
     return states
 
 
-def backward(prog, states, final_w, final_slot_spin, n, J, h):
-    """Final argmax (lowest address) and the walk back; returns (max, sigma)."""
-    fin = states[-1][: 1 << final_w]
+def backward(prog, states, final_w, final_slot_spin, n, J, h, z2=False):
+    """Final argmax (lowest address) and the walk back; returns (max, sigma).
+    z2: half states (the final maximum over the stored half, reads at stored addresses)."""
+    fin = states[-1][: (1 << final_w) >> (1 if z2 and final_w > 0 else 0)]
     assert not np.any(np.isnan(fin)), "final state has unwritten entries"
     mx = fin.max()
     addr = int(np.argmax(fin == mx))
@@ -216,7 +233,7 @@ def backward(prog, states, final_w, final_slot_spin, n, J, h):
             for k, cd in enumerate(cands):
                 if cd.start_slot >= 0 and P.in_pos[cd.start_slot] != NO_POS and (a >> k) & 1:
                     ad |= 1 << P.in_pos[cd.start_slot]
-            val = 0.0 if P.init else states[pi][ad]
+            val = 0.0 if P.init else states[pi][z2_addr(ad, P.in_w) if z2 else ad]
             assert not np.isnan(val), "backward read an unwritten entry"
             for tm in terms:
                 c = h[tm.coef] if tm.is_field else J[tm.coef]

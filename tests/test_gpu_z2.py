@@ -1,0 +1,151 @@
+"""GPU parity of half-state plans (z2: h = 0, half of every energy-path
+state stored, reads and writes at the stored address, half the tiles of a
+pass run): energies equal to the full-state plan's and to the oracle (stored
+values for the 64 headline lattices), ground states that attain E*, exact
+gradients, over tile sizes, greedy plans, int16 couplings, the two-part
+path, graph replays, the unfused final maximum, uneven batches and the
+autotuner."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import spinglass as O
+from paper_2008_06888_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2008_06888_amd import binding as B  # noqa: E402
+
+DEV = "cuda:0"
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "parity_large.json")))
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dt=None):
+    t = torch.tensor(np.ascontiguousarray(x), device=DEV)
+    return t.to(dt) if dt is not None else t
+
+
+def check_configs(n, e, J, E, sig, dJ, tol=0.0):
+    for b in range(J.shape[0]):
+        assert abs(O.energy(n, e, J[b], None, sig[b]) - E[b]) <= tol, b
+        assert np.array_equal(dJ[b], O.ground_state_gradient(e, sig[b])[0].astype(np.float32)), b
+
+
+@pytest.mark.parametrize("tile", [7, 9, 11, 12, 14])
+@pytest.mark.parametrize("coupling", ["pm1", "gauss"])
+def test_square_lattices(tile, coupling):
+    L = 12
+    n, e = L * L, I.square_lattice(L)
+    insts = [I.make(e, n, np.random.default_rng([71, tile, b]), coupling) for b in range(3)]
+    J = np.stack([x.J for x in insts])
+    full = B.Plan(n, e, order=list(range(n)), tile_bits=tile)
+    half = B.Plan(n, e, order=list(range(n)), tile_bits=tile, z2=True)
+    say("z2 12x12", coupling, "tile", tile)
+    Ef = B.contract(full, dev(J)).cpu().numpy()
+    E = B.contract(half, dev(J)).cpu().numpy()
+    Eb, sig, dJ, _ = [x.cpu().numpy() if x is not None else None for x in B.backward(half, dev(J))]
+    assert np.array_equal(E, Ef) and np.array_equal(Eb, Ef)
+    check_configs(n, e, J, Ef, sig, dJ, tol=1e-5 * n if coupling == "gauss" else 0.0)
+    for b, x in enumerate(insts):
+        ref = O.eliminate(n, e, x.J, None, traceback=False)
+        assert abs(E[b] - ref["energy"]) <= (1e-5 * n if coupling == "gauss" else 0.0), b
+
+
+def test_headline_pm1_b64_against_stored_oracle():
+    insts = I.config_instances(0, batch=64, L=16)
+    gold = GOLD["square16_pm1_b64"]["cases"]
+    n = 256
+    J = np.stack([x.J for x in insts])
+    for tile in (12, 13):
+        plan = B.Plan(n, insts[0].edges, order=list(range(n)), tile_bits=tile, z2=True)
+        say("z2 headline b64 tile", tile)
+        E, sig, dJ, _ = [x.cpu().numpy() if x is not None else None for x in B.backward(plan, dev(J))]
+        Ec = B.contract(plan, dev(J)).cpu().numpy()
+        assert np.array_equal(E, Ec)
+        for b in range(64):
+            assert E[b] == gold[str(b)]["energy"], b
+        check_configs(n, insts[0].edges, J, E, sig, dJ)
+        E16, sig16, _, _ = B.backward(plan, dev(J, torch.int16))
+        assert np.array_equal(E16.cpu().numpy(), E)
+        assert np.array_equal(sig16.cpu().numpy(), sig)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_greedy_random_regular(seed):
+    n = 70
+    rng = np.random.default_rng([72, seed])
+    e = I.random_regular(n, 3, rng)
+    J = np.stack([I.gauss(len(e), rng) for _ in range(4)])
+    plan = B.Plan(n, e, seed=seed, z2=True)
+    full = B.Plan(n, e, seed=seed)
+    say("z2 reg3 n=70 seed", seed, "width", plan.info()["width"])
+    E, sig, dJ, _ = [x.cpu().numpy() if x is not None else None for x in B.backward(plan, dev(J))]
+    assert np.array_equal(E, B.contract(full, dev(J)).cpu().numpy())
+    check_configs(n, e, J, E, sig, dJ, tol=1e-5 * n)
+    for tie in (1, 777):
+        Et, st, _, _ = B.backward_tie(plan, dev(J), tie=tie)
+        assert np.array_equal(Et.cpu().numpy(), E)
+        for b in range(4):
+            assert abs(O.energy(n, e, J[b], None, st.cpu().numpy()[b]) - E[b]) <= 1e-5 * n
+
+
+def test_graph_replays_match_eager():
+    insts = I.config_instances(0, batch=4, L=10)
+    plan = B.Plan(100, insts[0].edges, order=list(range(100)), z2=True)
+    J = dev(np.stack([x.J for x in insts]))
+    first = [x.cpu().numpy() for x in B.backward(plan, J)[:3]]
+    for _ in range(4):
+        again = [x.cpu().numpy() for x in B.backward(plan, J)[:3]]
+        for a, b in zip(first, again):
+            assert np.array_equal(a, b)
+        torch.cuda.synchronize()
+
+
+def test_unfused_final_maximum():
+    L = 26
+    x = I.config_instances(0, batch=1, L=L)[0]
+    full = B.Plan(L * L, x.edges, order=list(range(L * L)), tile_bits=12)
+    half = B.Plan(L * L, x.edges, order=list(range(L * L)), tile_bits=12, z2=True)
+    say("z2 26x26 unfused final maximum")
+    assert np.array_equal(B.contract(half, dev(x.J[None])).cpu().numpy(),
+                          B.contract(full, dev(x.J[None])).cpu().numpy())
+
+
+def test_uneven_batch_and_count():
+    rng = np.random.default_rng(73)
+    graphs = [(n, I.random_regular(n, 3, rng)) for n in (30, 44, 58)]
+    plans = [B.Plan(n, e, seed=1, z2=True) for n, e in graphs]
+    Jints = [I.pm1(len(e), rng) for _, e in graphs]
+    Js = [dev(j.astype(np.float32)) for j in Jints]
+    res = B.contract_uneven(plans, Js)
+    Eu = res[0].cpu().numpy()
+    for i, ((n, e), p, J, Ji) in enumerate(zip(graphs, plans, Js, Jints)):
+        E1 = B.contract(p, J[None].contiguous()).cpu().numpy()[0]
+        assert Eu[i] == E1
+        assert O.energy(n, e, Ji, None, res[1][i].cpu().numpy()) == E1
+        ref = O.eliminate(n, e, Ji, None, counts="exact", traceback=False)
+        assert E1 == ref["energy"]
+        Ec, _, g = B.count(p, dev(Ji[None]))   # counting keeps the full state
+        assert Ec[0] == ref["energy"] and g[0] == ref["count"]
+
+
+def test_autotune_half_state():
+    insts = I.config_instances(0, batch=8, L=12)
+    plan = B.Plan(144, insts[0].edges, order=list(range(144)), z2=True)
+    J = dev(np.stack([x.J for x in insts]))
+    ref = B.backward(plan, J)[0].cpu().numpy()
+    bits, _ = B.autotune(plan, J, config=True)
+    say("z2 autotune", bits)
+    assert np.array_equal(B.backward(plan, J)[0].cpu().numpy(), ref)
