@@ -12,7 +12,12 @@ HBM before timing starts.
 Work is counted as max-plus ops = 2 x contraction terms + elementwise ops
 (a gate is a contraction with K = 2: two terms per output entry; diagonal and
 field absorbs, cuts and the final maximum are one op per entry), from the
-plan's own counts at the live width of every step.
+plan's own counts at the live width of every step (for a half-state plan the
+entries its passes visit).
+
+Without fields the half-state plan (z2: the energy is even under flipping all
+spins, so half of every state is stored) and the full-state plan are both
+autotuned and the faster is timed; the JSON line says which.
 
 Prints one JSON line (metric, value = solves/s, roofline of the dominant
 kernel, CPU-oracle baseline). Only one GPU is used; --gpus above 1 exits.
@@ -194,25 +199,41 @@ def bench_square32(args):
     x = I.config_instances(2)[0]
     J = torch.tensor(x.J[None], device="cuda:0")
     plan = B.Plan(1024, x.edges, order=list(range(1024)))
-    B.count(plan, J)
+    # the count on the half state (h = 0: every (x, n) state is even under
+    # flipping all spins, half of it is stored and swept) is the timed value;
+    # the full-state count is the second figure
+    hplan = B.Plan(1024, x.edges, order=list(range(1024)), z2=True)
+    B.count(hplan, J)
     B.prof_reset()
     B.prof_enable(True)
     t0 = time.perf_counter()
-    Ec, res, g = B.count(plan, J)
+    Ec, res, g = B.count(hplan, J)
     dt = time.perf_counter() - t0
     B.prof_enable(False)
     kern = {k: B.prof_read(k) for k in ("count_pass", "count_reduce")}
+    B.count(plan, J)
+    t0 = time.perf_counter()
+    Ef, _, gf = B.count(plan, J)
+    dt_full = time.perf_counter() - t0
+    assert int(Ef[0]) == int(Ec[0]) and gf[0] == g[0]
     t_e = _timed(lambda: B.contract(plan, J), max(1, min(args.steps, 5)))
     # the same energy with int16 couplings: int16 state, packed 16-bit passes
     J16 = J.to(torch.int16)
     E16 = B.contract(plan, J16)
     assert int(E16.cpu().numpy()[0]) == int(Ec[0])
     t_e16 = _timed(lambda: B.contract(plan, J16), max(1, min(args.steps, 5)))
+    # the energy on the half-state plan
+    Eh, Eh16 = B.contract(hplan, J), B.contract(hplan, J16)
+    assert float(Eh.cpu().numpy()[0]) == int(Ec[0]) and int(Eh16.cpu().numpy()[0]) == int(Ec[0])
+    t_h = _timed(lambda: B.contract(hplan, J), max(1, min(args.steps, 5)))
+    t_h16 = _timed(lambda: B.contract(hplan, J16), max(1, min(args.steps, 5)))
     print(json.dumps({"metric": "32x32 +-J ground-state energy and degeneracy wall time", "value": dt, "unit": "s",
                       "higher_is_better": False, "dtype": "f32 (integer-valued) + 3 x u64 residues",
-                      "config": {"workload": "square32_pm1_count", "spins": 1024},
+                      "config": {"workload": "square32_pm1_count", "spins": 1024, "half_state": True},
                       "energy": int(Ec[0]), "degeneracy": str(g[0]), "entropy_per_spin": math.log(g[0]) / 1024,
+                      "full_state_count_s": dt_full,
                       "energy_only_s": t_e, "energy_only_int16_s": t_e16,
+                      "energy_only_half_state_s": t_h, "energy_only_half_state_int16_s": t_h16,
                       "kernel_ms": {k: v[0] for k, v in kern.items()}}))
 
 
@@ -322,6 +343,11 @@ def bench_cubic(args):
     t_solve = _timed(lambda: B.backward(plan, J), steps)
     t_energy = _timed(lambda: B.contract(plan, J), steps)
     E, sig, _, _ = B.backward(plan, J)
+    hplan = B.Plan(216, x.edges, seed=0, z2=True)
+    Eh, sh, _, _ = B.backward(hplan, J)
+    assert float(Eh[0].item()) == float(E[0].item())
+    t_half = _timed(lambda: B.backward(hplan, J), steps)
+    hplan.close()
     B.count(plan, J)
     t0 = time.perf_counter()
     Ec, _, g, exact = B.count_with_flags(plan, J)
@@ -330,7 +356,8 @@ def bench_cubic(args):
                       "unit": "s", "higher_is_better": False, "steps": steps, "dtype": "f32 (integer-valued)",
                       "config": {"workload": "cubic6_pm1", "spins": 216, "couplers": int(len(x.edges)),
                                  "width": info["width"], "passes": info["n_passes"], "planning_s": t_plan},
-                      "energy": float(E[0].item()), "energy_only_s": t_energy, "count_s": t_count,
+                      "energy": float(E[0].item()), "energy_only_s": t_energy, "half_state_s": t_half,
+                      "count_s": t_count,
                       "count_energy": int(Ec[0]), "degeneracy": str(g[0]), "exact": bool(exact[0]),
                       "entropy_per_spin": math.log(g[0]) / 216}))
 
@@ -348,7 +375,8 @@ def bench_pass_profile(args):
     J = torch.tensor(np.stack([x.J for x in pm1]), device="cuda:0")
     if args.i16:
         J = J.to(torch.int16)
-    plan = B.Plan(L * L, pm1[0].edges, order=list(range(L * L)), tile_bits=args.pass_profile, parts=1)
+    plan = B.Plan(L * L, pm1[0].edges, order=list(range(L * L)), tile_bits=args.pass_profile, parts=1,
+                  z2=args.half)
     for _ in range(max(args.warmup, 1)):
         B.contract(plan, J)
     torch.cuda.synchronize()
@@ -360,7 +388,7 @@ def bench_pass_profile(args):
     B.prof_enable(False)
     ms, launches = B.prof_read("sweep_pass")
     print(json.dumps({"workload": f"square16x16_pm1_b{batch} energy passes", "tile_bits": args.pass_profile,
-                      "couplings": str(J.dtype).replace("torch.", ""),
+                      "couplings": str(J.dtype).replace("torch.", ""), "half_state": args.half,
                       "passes": plan.info()["n_passes"], "launches": launches,
                       "avg_launch_ms": ms / max(launches, 1)}))
 
@@ -393,6 +421,7 @@ def main():
                     help="instead: only the headline batch's energy passes at tile 2^BITS, one part (profiling)")
     ap.add_argument("--pass-batch", type=int, default=64, help="with --pass-profile: lattices per call")
     ap.add_argument("--i16", action="store_true", help="with --pass-profile: int16 couplings (TT_I16)")
+    ap.add_argument("--half", action="store_true", help="with --pass-profile: half-state plan (z2)")
     ap.add_argument("--workload", default="square16_pm1_b64",
                     choices=["square16_pm1_b64", "chimera8x8_pm1", "square32_pm1_count", "reg3_uneven_b16",
                              "potts18_pm1", "cubic6_pm1"],
@@ -445,7 +474,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "square16x16_pm1_b64", "L": L, "batch": batch, "couplings": "+-1 int32 (exact "
                    "integers in the float32 state)", "fields": "none (h = 0)", "outputs": "E*, sigma, dE/dJ",
-                   "parallelism": "single GPU"},
+                   "half_state": line["plan"]["half_state"], "parallelism": "single GPU"},
         "maxplus_gops": line["maxplus_gops"],
         "valu_frac": line["valu_frac"],
         "roofline": line["roofline"],
@@ -465,7 +494,8 @@ def main():
                                              "kernel_ms_per_step", "plan")}
     out["gauss_h_b64"]["outputs"] = "E*, sigma, dE/dJ, dE/dh"
     # the plain path: the same 64 +-J instances, one eager call each
-    plan1 = B.Plan(n, pm1[0].edges, order=list(range(n)), tile_bits=line["plan"]["tile_bits"])
+    plan1 = B.Plan(n, pm1[0].edges, order=list(range(n)), tile_bits=line["plan"]["tile_bits"],
+                   z2=line["plan"]["half_state"])
     rows = [J[b:b + 1].contiguous() for b in range(batch)]
     extra_steps = max(1, min(args.steps, 10))
 
@@ -494,6 +524,20 @@ def run_lattice(args, B, edges, n, J, h, workload):
     has_h = h is not None
     plan = B.Plan(n, edges, order=list(range(n)), has_field=has_h)
     tile_bits, _ = B.autotune(plan, J, h, config=True)
+    half = False
+    trial = {}
+    if not has_h:
+        # without fields a half-state plan (z2) is the other candidate: both
+        # autotuned, the faster over a few timed calls is the one measured
+        hplan = B.Plan(n, edges, order=list(range(n)), z2=True)
+        hbits, _ = B.autotune(hplan, J, None, config=True)
+        for _ in range(2):
+            B.backward(plan, J)
+            B.backward(hplan, J)
+        trial = {"full_state_ms": _timed(lambda: B.backward(plan, J), 20) * 1e3,
+                 "half_state_ms": _timed(lambda: B.backward(hplan, J), 20) * 1e3}
+        if trial["half_state_ms"] < trial["full_state_ms"]:
+            plan, tile_bits, half = hplan, hbits, True
     info = plan.info()
     for _ in range(max(args.warmup, 2)):
         B.backward(plan, J, h)
@@ -514,7 +558,7 @@ def run_lattice(args, B, edges, n, J, h, workload):
         return {k: B.prof_read(k) for k in ("sweep_pass", "sweep_backward", "final_reduce", "check_inputs")}
 
     kt = kernel_times(plan, args.steps)
-    one = B.Plan(n, edges, order=list(range(n)), has_field=has_h, tile_bits=tile_bits, parts=1)
+    one = B.Plan(n, edges, order=list(range(n)), has_field=has_h, tile_bits=tile_bits, parts=1, z2=half)
     B.backward(one, J, h)
     kt1 = kernel_times(one, args.steps)
     ops_inst = 2.0 * info["terms"] + info["elementwise"]     # the final maximum runs inside the last pass
@@ -529,7 +573,7 @@ def run_lattice(args, B, edges, n, J, h, workload):
         ach = per_launch / (avg_ms * 1e-3) if ms > 0 else 0.0
         return {"kernel": "k_pass", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "TFLOP/s", "frac": ach / VALU_PEAK_OPS,
-                "traffic": pass_traffic(workload, tile_bits, nparts),
+                "traffic": pass_traffic(workload + ("_half" if half else ""), tile_bits, nparts),
                 "avg_launch_ms": avg_ms, "launches": launches, "ops_per_launch": per_launch,
                 "concurrent_parts": nparts}
 
@@ -546,8 +590,9 @@ def run_lattice(args, B, edges, n, J, h, workload):
         "roofline_one_part": roof(kt1, 1),
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "plan": {"width": info["width"], "passes": info["n_passes"], "tile_bits": tile_bits,
-                 "terms_per_instance": info["terms"], "elementwise_per_instance": info["elementwise"],
-                 "maxplus_ops_per_instance": ops_inst},
+                 "half_state": half, "terms_per_instance": info["terms"],
+                 "elementwise_per_instance": info["elementwise"], "maxplus_ops_per_instance": ops_inst,
+                 **({"selection": trial} if trial else {})},
     }
 
 

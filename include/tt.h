@@ -102,10 +102,11 @@ typedef struct tt_plan_opts {
                                contraction: entries whose top address bit is 1 are read
                                at the complement address, and a pass runs half of its
                                tiles, each also writing its mirror outputs. Same
-                               results (E*, a ground state, gradients) for about half
-                               the bytes and work of every pass. tt_contract,
-                               tt_backward(_tie), tt_contract_uneven(_fields) and
-                               tt_count (which counts on the full state) accept such
+                               results (E*, a ground state, gradients, the exact
+                               degeneracy) for about half the bytes and work of
+                               every pass. tt_contract, tt_backward(_tie),
+                               tt_contract_uneven(_fields) and tt_count (whose
+                               (x, n) states are halved the same way) accept such
                                plans; a backward that would need checkpoint
                                recomputation returns TT_E_TOOBIG, the
                                allocation-free call TT_E_INVAL. [0] */

@@ -309,6 +309,14 @@ int encode(const Plan& p, const std::vector<Pass>& passes, Encoded& en) {
       d.fre[nf++] = (uint8_t)s;
     }
     d.n_free = nf;
+    // half-state plans: the tiles pair up by complementing every fixed slot of
+    // the output; the lowest such tile-id bit at 0 picks one tile of a pair
+    d.z2_skip = -1;
+    for (int k = 0; k < nf; ++k)
+      if (d.fre[k] < ps.out_w) {
+        d.z2_skip = k;
+        break;
+      }
     if (ps.w_max > 60) return fail(TT_E_TOOBIG, "state width %d exceeds the 60-bit index", ps.w_max);
     auto enc = [&](int slot) -> uint8_t {
       if (slot < 0) return 0;
@@ -439,13 +447,17 @@ int64_t state_bytes(const Plan& p, int64_t batch, bool backward) {
   return need;
 }
 
+// log2 of the entries a count-path state holds per instance and plane: a
+// half-state plan stores half of the widest state.
+int count_width(const Plan& p) { return p.width - (p.z2 && p.width > 0 ? 1 : 0); }
+
 // Count path: x plane and residue planes, one buffer when every pass runs in
 // place, else two.
 int64_t count_state_bytes(const Plan& p, int64_t batch, int nres) {
   bool all_in_place = true;
   for (const Pass& q : p.count_passes)
     all_in_place = all_in_place && (q.init || (q.in_w == q.w_max && q.out_w == q.w_max));
-  const int64_t per = (batch << p.width) * (int64_t)(sizeof(float) + nres * sizeof(uint64_t));
+  const int64_t per = (batch << count_width(p)) * (int64_t)(sizeof(float) + nres * sizeof(uint64_t));
   return (all_in_place ? 1 : 2) * per;
 }
 
@@ -2965,7 +2977,7 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
     const int nres = p.n > COUNT_EXACT_SPINS ? 4 : 3;
     DevCache* dc = nullptr;
     if (int r = ensure_device(p, dc)) return r;
-    const int64_t sst = (int64_t)1 << p.width;
+    const int64_t sst = (int64_t)1 << count_width(p);
     const size_t xper = (size_t)batch * sst * sizeof(float);
     const size_t nper = (size_t)batch * sst * nres * sizeof(uint64_t);
     bool all_in_place = true;
@@ -3028,7 +3040,7 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
         ProfScope ps(s, "count_pass");
         const int dst = in_place_ok(P) ? cur : (cur ^ 1);
         HIP_TRY(launch_count_pass(P, static_cast<const DevOp*>(dc->d_cops.p), J, h, p.m, p.n, xb[cur], nb[cur],
-                                  xb[dst], nb[dst], sst, batch, nres, s));
+                                  xb[dst], nb[dst], sst, batch, nres, p.z2, s));
         cur = dst;
       }
       if (p.is_chimera && dc->count_chain_after[qi] >= 0)
@@ -3050,7 +3062,8 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
       uint64_t free_mask = 0;
       for (int c = 0; c < p.final_w; ++c)
         if (p.final_slot_spin[c] < 0) free_mask |= 1ull << c;
-      HIP_TRY(launch_count_reduce(xb[cur], nb[cur], sst, p.final_w, free_mask, batch, nres, pv, pn, en, res, s));
+      HIP_TRY(launch_count_reduce(xb[cur], nb[cur], sst, p.final_w, free_mask, batch, nres, p.z2, pv, pn, en, res,
+                                  s));
     }
     std::vector<uint64_t> r4((size_t)batch * 4);
     HIP_TRY(hipMemcpyAsync(energy, en, (size_t)batch * sizeof(int64_t), hipMemcpyDeviceToHost, s));

@@ -14,6 +14,7 @@
 #include <cstdint>
 
 #include "device.hpp"
+#include "device_mem.hpp"
 #include "plan.hpp"
 
 namespace tt {
@@ -46,21 +47,26 @@ __device__ __forceinline__ void cbuild_deposit(const uint8_t* R, int t, uint64_t
   }
 }
 
-// State layout per instance: x plane [2^W] float, then residue planes
-// n[r][2^W] uint64 (sst = 2^W entries per plane).
+// State layout per instance: x plane [sst] float, then residue planes
+// n[r][sst] uint64 (sst = 2^W entries per plane, 2^(W-1) for half-state
+// plans). With z2 (h = 0: every state is even under flipping all of its
+// bits) only entries whose top address bit is 0 are stored, an entry with
+// the top bit set is read at the complement address, and only the tiles
+// whose tile-id bit z2_skip is 0 run: each writes its outputs at their
+// stored addresses, which cover those of the complementary tile too.
 __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp* __restrict__ ops,
                                                     const int32_t* __restrict__ J, const int32_t* __restrict__ h,
                                                     int64_t jst, int64_t hst, const float* __restrict__ xin,
                                                     const uint64_t* __restrict__ nin, float* __restrict__ xout,
                                                     uint64_t* __restrict__ nout, int64_t sst, int log2_tiles,
-                                                    int nres) {
+                                                    int nres, int z2) {
   extern __shared__ uint64_t csm[];
   const uint32_t size = 1u << P.t;
   uint64_t* tn = csm;                                        // [nres][size]
   float* tx = reinterpret_cast<float*>(csm + nres * size);   // [size]
   __shared__ uint64_t dep_lo[256], dep_hi[256];
   const int64_t inst = (int64_t)blockIdx.x >> log2_tiles;
-  const uint64_t tile_id = (uint64_t)blockIdx.x & ((1ull << log2_tiles) - 1ull);
+  const uint64_t tile_id = z2_tile((uint64_t)blockIdx.x & ((1ull << log2_tiles) - 1ull), z2 ? P.z2_skip : -1);
   uint64_t base = 0;
   for (int k = 0; k < P.n_free; ++k) base |= ((tile_id >> k) & 1ull) << P.fre[k];
   cbuild_deposit(P.R, P.t, dep_lo, dep_hi);
@@ -69,7 +75,8 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
   const float* xs = xin + inst * sst;
   const uint64_t* ns = nin + inst * sst * nres;
   for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) {
-    const uint64_t idx = (base | dep_lo[i & 255u] | dep_hi[i >> 8]) & in_mask;
+    uint64_t idx = (base | dep_lo[i & 255u] | dep_hi[i >> 8]) & in_mask;
+    if (z2) idx = z2_addr(idx, P.in_w);
     if (P.init) {
       tx[i] = 0.f;
       for (int r = 0; r < nres; ++r) tn[r * size + i] = 1ull;
@@ -117,8 +124,9 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
   float* xd = xout + inst * sst;
   uint64_t* nd = nout + inst * sst * nres;
   for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) {
-    const uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
+    uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
     if ((idx >> P.out_w) != 0) continue;
+    if (z2) idx = z2_addr(idx, P.out_w);
     // non-temporal: the next pass reads the state from memory
     __builtin_nontemporal_store(tx[i], &xd[idx]);
     for (int r = 0; r < nres; ++r) __builtin_nontemporal_store(tn[r * size + i], &nd[r * sst + idx]);
@@ -150,16 +158,19 @@ __device__ uint64_t cblock_summod(uint64_t v, uint64_t p) {
 
 // Slots that are free after the last op hold copies of every configuration
 // (their two halves are equal), so only entries with those bits zero count.
+// Half-state plans (z2) read every entry at its stored address.
 __global__ __launch_bounds__(CNT) void k_count_reduce1(const float* __restrict__ x, const uint64_t* __restrict__ nr,
                                                        int64_t sst, int w, int log2_chunks, uint64_t free_mask,
-                                                       int nres, float* __restrict__ pv, uint64_t* __restrict__ pn) {
+                                                       int nres, int z2, float* __restrict__ pv,
+                                                       uint64_t* __restrict__ pn) {
   const int64_t inst = (int64_t)blockIdx.x >> log2_chunks;
   const uint64_t chunk = (uint64_t)blockIdx.x & ((1ull << log2_chunks) - 1ull);
   const uint64_t len = 1ull << (w - log2_chunks);
   const float* xs = x + inst * sst;
   const uint64_t* ns = nr + inst * sst * nres;
   float mx = -INFINITY;
-  for (uint64_t k = threadIdx.x; k < len; k += CNT) mx = fmaxf(mx, xs[chunk * len + k]);
+  const int zw = z2 ? w : 0;
+  for (uint64_t k = threadIdx.x; k < len; k += CNT) mx = fmaxf(mx, xs[z2_addr(chunk * len + k, zw)]);
   mx = cblock_max(mx);
   for (int r = 0; r < NRES; ++r) {
     if (r >= nres) {
@@ -168,8 +179,8 @@ __global__ __launch_bounds__(CNT) void k_count_reduce1(const float* __restrict__
     }
     uint64_t acc = 0;
     for (uint64_t k = threadIdx.x; k < len; k += CNT) {
-      const uint64_t idx = chunk * len + k;
-      if ((idx & free_mask) == 0 && xs[idx] == mx) acc = addmod(acc, ns[r * sst + idx], c_mod[r]);
+      const uint64_t idx = chunk * len + k, at = z2_addr(idx, zw);
+      if ((idx & free_mask) == 0 && xs[at] == mx) acc = addmod(acc, ns[r * sst + at], c_mod[r]);
     }
     acc = cblock_summod(acc, c_mod[r]);
     if (threadIdx.x == 0) pn[blockIdx.x * NRES + r] = acc;
@@ -205,7 +216,7 @@ int count_reduce_log2_chunks(int w) {
 
 hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h, int64_t jst,
                              int64_t hst, const float* xin, const uint64_t* nin, float* xout, uint64_t* nout,
-                             int64_t sst, int batch, int nres, hipStream_t stream) {
+                             int64_t sst, int batch, int nres, bool z2, hipStream_t stream) {
   if (nres < 3 || nres > NRES) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << P.t) * (sizeof(float) + nres * sizeof(uint64_t));
   if (lds > 65536) {
@@ -213,20 +224,23 @@ hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* 
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const uint64_t grid = (uint64_t)batch << P.n_free;
+  // half-state plans run half of the tiles (all of them when no fixed slot
+  // reaches the output)
+  const int run_bits = P.n_free - ((z2 && P.z2_skip >= 0) ? 1 : 0);
+  const uint64_t grid = (uint64_t)batch << run_bits;
   if (grid >= (1ull << 31)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_count_pass, dim3((uint32_t)grid), dim3(CNT_PASS), lds, stream, P, ops, J, h, jst, hst, xin, nin,
-                     xout, nout, sst, P.n_free, nres);
+                     xout, nout, sst, run_bits, nres, z2 ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_count_reduce(const float* x, const uint64_t* nplanes, int64_t sst, int w, uint64_t free_mask,
-                               int batch, int nres, float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues,
-                               hipStream_t stream) {
+                               int batch, int nres, bool z2, float* pv, uint64_t* pn, int64_t* energy,
+                               uint64_t* residues, hipStream_t stream) {
   if (nres < 3 || nres > NRES) return hipErrorInvalidValue;
   const int lc = count_reduce_log2_chunks(w);
   hipLaunchKernelGGL(k_count_reduce1, dim3((uint32_t)((uint64_t)batch << lc)), dim3(CNT), 0, stream, x, nplanes, sst,
-                     w, lc, free_mask, nres, pv, pn);
+                     w, lc, free_mask, nres, z2 ? 1 : 0, pv, pn);
   hipLaunchKernelGGL(k_count_reduce2, dim3((uint32_t)batch), dim3(CNT), 0, stream, pv, pn, lc, energy, residues);
   return hipGetLastError();
 }

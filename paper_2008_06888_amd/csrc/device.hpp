@@ -25,7 +25,8 @@ struct DevOp {
 struct DevPass {
   int32_t in_w, out_w, w_max, t;
   int32_t op_begin, n_ops, n_dec, init;
-  int32_t n_free, reg, merge_src, pad;
+  int32_t n_free, reg, merge_src;
+  int32_t z2_skip;   // half-state plans: tile-id bit of the lowest fixed slot below out_w (-1: none)
   uint8_t R[16];     // tile bit -> slot
   uint8_t fre[48];   // slots below w_max outside the tile, ascending (tile id bits)
 };

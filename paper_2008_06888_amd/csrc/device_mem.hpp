@@ -49,6 +49,16 @@ __device__ __forceinline__ LShort& lds16_at(uint32_t addr) {
   return *(LShort*)(uintptr_t)(addr);
 }
 
+// Half-state plans (h = 0): the tile index of a run tile k (tile-id bit
+// `skip` at 0), and the stored (canonical) address of an entry: the
+// complement of every address bit when the top one is set.
+__device__ __forceinline__ uint64_t z2_tile(uint64_t k, int skip) {
+  return skip < 0 ? k : (((k >> skip) << (skip + 1)) | (k & ((1ull << skip) - 1ull)));
+}
+__device__ __forceinline__ uint64_t z2_addr(uint64_t a, int w) {
+  return (w > 0 && ((a >> (w - 1)) & 1ull)) ? a ^ ((1ull << w) - 1ull) : a;
+}
+
 // The float at an LDS byte address. Only for kernels without static LDS,
 // whose dynamic region starts at address 0 (their launchers check it).
 __device__ __forceinline__ LFloat& lds_at(uint32_t addr) {

@@ -34,11 +34,11 @@ hipError_t launch_chim_finish(const ChimFinishItem* item, int batch, int dtype, 
 // residues come out as 4 words per instance (unused planes 0)
 hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h,
                              int64_t jst, int64_t hst, const float* xin, const uint64_t* nin, float* xout,
-                             uint64_t* nout, int64_t sst, int batch, int nres, hipStream_t stream);
+                             uint64_t* nout, int64_t sst, int batch, int nres, bool z2, hipStream_t stream);
 int count_reduce_log2_chunks(int w);
 hipError_t launch_count_reduce(const float* x, const uint64_t* nplanes, int64_t sst, int w, uint64_t free_mask,
-                               int batch, int nres, float* pv, uint64_t* pn, int64_t* energy, uint64_t* residues,
-                               hipStream_t stream);
+                               int batch, int nres, bool z2, float* pv, uint64_t* pn, int64_t* energy,
+                               uint64_t* residues, hipStream_t stream);
 
 // 3-state Potts sweep: one pass over `batch` instances of 3^W entries (sst)
 // in place (low: the pass's tile digits are slots 0 .. t-1); n == nullptr: energy only, else nres residue planes of

@@ -61,16 +61,6 @@ __device__ __forceinline__ bool wg_to_tile(uint64_t b, int log2_tiles, int batch
 
 
 
-// Half-state plans (h = 0): the tile index of a run tile k (tile-id bit
-// `skip` at 0), and the stored (canonical) address of an entry: the
-// complement of every address bit when the top one is set.
-__device__ __forceinline__ uint64_t z2_tile(uint64_t k, int skip) {
-  return skip < 0 ? k : (((k >> skip) << (skip + 1)) | (k & ((1ull << skip) - 1ull)));
-}
-__device__ __forceinline__ uint64_t z2_addr(uint64_t a, int w) {
-  return (w > 0 && ((a >> (w - 1)) & 1ull)) ? a ^ ((1ull << w) - 1ull) : a;
-}
-
 // A lane value the compiler may not re-derive (keeps a pre-shifted LDS
 // address part from being folded back into a shift after the XOR).
 __device__ __forceinline__ uint32_t opaque(uint32_t x) {

@@ -38,3 +38,34 @@ def test_encoded_count_program_matches_oracle(case, ctile):
     best, g = CE.run(passes, ops, x.J, x.h, plan.info()["width"], fs)
     ref = O.eliminate(x.n, x.edges, x.J, x.h, counts="exact", traceback=False)
     assert -best == ref["energy"] and g == ref["count"]
+
+
+@pytest.mark.parametrize("L,kind", [(8, "pm1"), (9, "pm1"), (10, "pm1"), (9, "zero")])
+def test_half_state_count_program(L, kind):
+    """Half-state plans (no fields, tiles of 2^7): the same E* and degeneracy
+    from half of every state, with every stored entry of every pass written
+    (each tile writes its mirror outputs)."""
+    n, e = L * L, I.square_lattice(L)
+    J = I.pm1(len(e), np.random.default_rng([5, L])) if kind == "pm1" else np.zeros(len(e), np.int32)
+    plan = B.Plan(n, e, order=list(range(n)), count_tile_bits=7, z2=True)
+    passes, ops = CE.load(plan)
+    assert any(P.z2_skip >= 0 for P in passes)
+    _, fs = plan.ops()
+    best, g = CE.run(passes, ops, J, None, plan.info()["width"], fs, z2=True)
+    ref = O.eliminate(n, e, J, None, counts="exact", traceback=False)
+    assert -best == ref["energy"] and g == ref["count"]
+    if kind == "zero":
+        assert g == 2 ** n
+
+
+@pytest.mark.parametrize("n,seed", [(36, 0), (44, 1)])
+def test_half_state_count_random_graphs(n, seed):
+    rng = np.random.default_rng([62, seed])
+    e = I.random_regular(n, 3, rng)
+    J = I.pm1(len(e), rng)
+    plan = B.Plan(n, e, seed=seed, count_tile_bits=7, z2=True)
+    passes, ops = CE.load(plan)
+    _, fs = plan.ops()
+    best, g = CE.run(passes, ops, J, None, plan.info()["width"], fs, z2=True)
+    ref = O.eliminate(n, e, J, None, counts="exact", traceback=False)
+    assert -best == ref["energy"] and g == ref["count"]

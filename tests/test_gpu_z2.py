@@ -4,7 +4,10 @@ pass run): energies equal to the full-state plan's and to the oracle (stored
 values for the 64 headline lattices), ground states that attain E*, exact
 gradients, over tile sizes, greedy plans, int16 couplings, the two-part
 path, graph replays, the unfused final maximum, uneven batches and the
-autotuner."""
+autotuner; and the counting path on half states: E* and exact degeneracies
+equal to the oracle's, the stored values, the full-state path and closed
+forms (J = 0: g = 2^n; planted 32 x 32: g = 2), the overflow flag
+included."""
 import json
 import os
 import sys
@@ -137,7 +140,7 @@ def test_uneven_batch_and_count():
         assert O.energy(n, e, Ji, None, res[1][i].cpu().numpy()) == E1
         ref = O.eliminate(n, e, Ji, None, counts="exact", traceback=False)
         assert E1 == ref["energy"]
-        Ec, _, g = B.count(p, dev(Ji[None]))   # counting keeps the full state
+        Ec, _, g = B.count(p, dev(Ji[None]))   # half-state counting
         assert Ec[0] == ref["energy"] and g[0] == ref["count"]
 
 
@@ -149,3 +152,63 @@ def test_autotune_half_state():
     bits, _ = B.autotune(plan, J, config=True)
     say("z2 autotune", bits)
     assert np.array_equal(B.backward(plan, J)[0].cpu().numpy(), ref)
+
+
+# ----------------------------------------------------------------------------
+# counting on half states
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("ctile", [7, 9, 12])
+def test_count_square_lattices(ctile):
+    L = 12
+    n, e = L * L, I.square_lattice(L)
+    J = np.stack([I.pm1(len(e), np.random.default_rng([74, ctile, b])) for b in range(3)])
+    full = B.Plan(n, e, order=list(range(n)), count_tile_bits=ctile)
+    half = B.Plan(n, e, order=list(range(n)), count_tile_bits=ctile, z2=True)
+    say("z2 count 12x12 tile", ctile)
+    Ef, rf, gf = B.count(full, dev(J))
+    Eh, rh, gh = B.count(half, dev(J))
+    assert np.array_equal(Eh, Ef) and np.array_equal(rh, rf) and gh == gf
+    for b in range(3):
+        ref = O.eliminate(n, e, J[b], None, counts="exact", traceback=False)
+        assert Eh[b] == ref["energy"] and gh[b] == ref["count"], b
+
+
+def test_count_headline_b64_against_stored_oracle():
+    insts = I.config_instances(0, batch=64, L=16)
+    gold = GOLD["square16_pm1_b64"]["cases"]
+    plan = B.Plan(256, insts[0].edges, order=list(range(256)), z2=True)
+    say("z2 count headline b64")
+    Ec, _, g = B.count(plan, dev(np.stack([x.J for x in insts])))
+    for b in range(64):
+        assert Ec[b] == gold[str(b)]["energy"] and g[b] == int(gold[str(b)]["count"]), b
+
+
+@pytest.mark.parametrize("L", [12, 16])
+def test_count_zero_couplings(L):
+    """J = 0: E* = 0 and g = 2^n, exact for n <= 182 (12 x 12); for 16 x 16
+    (2^256, beyond the moduli) the flag is cleared and the residues equal the
+    full-state path's."""
+    n, e = L * L, I.square_lattice(L)
+    J = dev(np.zeros((1, len(e)), np.int32))
+    half = B.Plan(n, e, order=list(range(n)), z2=True)
+    say("z2 count J=0", L)
+    Eh, rh, gh, xh = B.count_with_flags(half, J)
+    assert Eh[0] == 0
+    if n <= 182:
+        assert xh[0] and gh[0] == 2 ** n
+    else:
+        Ef, rf, gf, xf = B.count_with_flags(B.Plan(n, e, order=list(range(n))), J)
+        assert not xh[0] and not xf[0] and np.array_equal(rh, rf)
+
+
+def test_count_planted_square32_full_size():
+    """32 x 32 planted instance (J_ij = tau_i tau_j): E* = -m, g = 2, on the
+    half state (2^31 stored entries of the widest state)."""
+    L = 32
+    n, e = L * L, I.square_lattice(L)
+    x, tau = I.planted(e, n, np.random.default_rng([32, 1024]))
+    plan = B.Plan(n, e, order=list(range(n)), z2=True)
+    say("z2 count 32x32 planted")
+    Ec, _, g, ex = B.count_with_flags(plan, dev(x.J[None]))
+    plan.close()
+    assert Ec[0] == -len(e) and ex[0] and g[0] == 2
