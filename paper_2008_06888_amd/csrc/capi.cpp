@@ -861,6 +861,7 @@ struct CallTables {
     int threads;   // the largest tile's thread count among the items
     size_t lds;    // the largest tile's bytes among the items
     int ng;        // int16 pass: groups of 16 entries per thread (1 or 2)
+    bool z2;       // holds items of half-state plans
   };
   std::vector<Launch> levels;
   size_t red_off = 0, bwd_off = 0, ckpt_off = 0;
@@ -922,14 +923,16 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
     int threads = 64;
     size_t lds = 0;
     int ng = 1;
+    bool z2 = false;
     auto flush = [&]() {
       if (items.empty()) return;
-      ct.levels.push_back({ct.blob.add(items.data(), items.size()), (int)items.size(), wg, threads, lds, ng});
+      ct.levels.push_back({ct.blob.add(items.data(), items.size()), (int)items.size(), wg, threads, lds, ng, z2});
       items.clear();
       wg = 0;
       threads = 64;
       lds = 0;
       ng = 1;
+      z2 = false;
     };
     // one launch per tile size: a launch's workgroups are all as large as
     // its largest tile needs, so tiles of different sizes go separately
@@ -975,6 +978,7 @@ void build_tables(std::vector<Group>& groups, int32_t dtype, bool backward, Call
         it.red_base = part_base[gi];
       }
       it.z2 = g.p->z2 ? 1 : 0;
+      z2 = z2 || g.p->z2;
       const int64_t n_wg = ((int64_t)g.batch << run_tile_bits(*g.p, P));
       wg += (n_wg + 7) & ~int64_t(7);
       items.push_back(it);
@@ -1070,7 +1074,7 @@ int enqueue_launches(const CallTables& ct, const char* dev, float* pv, uint64_t*
   for (const CallTables::Launch& L : ct.levels) {
     ProfScope ps(s, "sweep_pass", true);
     HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s,
-                        ps.start(), ps.stop(), L.ng));
+                        ps.start(), ps.stop(), L.ng, L.z2));
     ps.launched();
   }
   if (!ct.bwd_ranks && ct.n_red > 0) {
@@ -1670,7 +1674,7 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
     {
       ProfScope ps(s, "sweep_pass", true);
       HIP_TRY(launch_pass(reinterpret_cast<const PassItem*>(dev + L.off), L.n, L.n_wg, L.threads, L.lds, dtype, s,
-                          ps.start(), ps.stop(), L.ng));
+                          ps.start(), ps.stop(), L.ng, L.z2));
       ps.launched();
     }
     if (dc->chain_after[k] >= 0)

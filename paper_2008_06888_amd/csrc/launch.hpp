@@ -15,7 +15,8 @@ namespace tt {
 // ng (dtype 2 only): groups of 16 entries per thread, 1, or 2 with threads =
 // 2^(tb - 1) of every item's pass (tb >= 7).
 hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int threads, size_t lds, int dtype,
-                       hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, int ng = 1);
+                       hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, int ng = 1,
+                       bool z2 = false);
 int reduce_log2_chunks(int w);
 // state16: the items' states are int16 (int16 couplings), else float32
 hipError_t launch_reduce(const RedItem* items, int n_items, int64_t n_chunks, float* pv, uint64_t* pi,

@@ -68,6 +68,34 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
   return x;
 }
 
+// Half-state plans: entry base | lane | k of a tile (three disjoint sets of
+// address bits) is stored at itself, or, when its top address bit (w - 1)
+// is set, at its complement (base ^ fm) | (lane ^ lm) | (k ^ km), where fm
+// holds every address bit below w outside lm | km. When the top bit is a
+// lane bit the choice differs across lanes (ok = false: the per-entry path);
+// otherwise it is made per tile (the top bit in the base) or per k, both
+// wave-uniform, so the buffer accesses keep their scalar parts.
+struct Z2Fast {
+  bool ok;
+  bool tile_flip;
+  int top;
+  uint64_t fm, lm, km;
+};
+
+__device__ __forceinline__ Z2Fast z2_fast(int w, uint64_t base, uint64_t lm, uint64_t km) {
+  Z2Fast z;
+  z.top = w > 0 ? w - 1 : 0;
+  z.lm = lm;
+  z.km = km;
+  z.fm = (w > 0 ? (~0ull >> (64 - w)) : 0ull) & ~(lm | km);
+  z.ok = w > 0 && ((lm >> z.top) & 1ull) == 0;
+  // base is the same in every lane: made a scalar so the selections below are too
+  z.tile_flip = w > 0 && __builtin_amdgcn_readfirstlane((int)((base >> z.top) & 1ull)) != 0;
+  return z;
+}
+
+__device__ __forceinline__ bool z2_flip(const Z2Fast& z, uint64_t hk) { return z.tile_flip || ((hk >> z.top) & 1ull); }
+
 // Cache-policy operand of the raw buffer intrinsics: non-temporal.
 constexpr int AUX_NT = 2;
 
@@ -467,7 +495,9 @@ __device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], u
   }
 }
 
-template <typename IT>
+// Z2: the launch holds half-state items (their code is compiled out of the
+// full-state instantiation).
+template <typename IT, bool Z2>
 // Six waves per SIMD: the register budget that fits without spilling
 // vector registers, for more tile bytes in flight on the memory-bound passes
 // of large states (2^32-entry chimera passes 5% faster than at five waves).
@@ -488,7 +518,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
   int64_t inst;
   uint64_t ktile;
   // half-state plans run the tiles with fixed slot z2_skip at 0 only
-  const bool z2 = I.z2 != 0;
+  const bool z2 = Z2 && I.z2 != 0;
   const int zskip = z2 ? P.z2_skip : -1;
   const int run_bits = P.n_free - (zskip >= 0 ? 1 : 0);
   if (!wg_to_tile((uint64_t)(wg - I.wg_begin), run_bits, I.batch, I.xcd_group, &inst, &ktile)) return;
@@ -577,12 +607,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
     // without a branch: otherwise (and in the first pass, whose state
     // starts at zero) the resource has no records and they return zeros
     // without touching memory.
-    fast_ld = !init && !z2 && nk_ld == 16 && all < BUF_MAX_ENTRIES;
+    fast_ld = !init && nk_ld == 16 && all < BUF_MAX_ENTRIES;
+    Z2Fast zf{};
+    if (z2) {
+      uint64_t lm = 0, km = 0;
+#pragma unroll
+      for (int q = 0; q < 10; ++q)
+        if (q < nb_ld) lm |= bad[q];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) km |= had[k];
+      zf = z2_fast(P.in_w, in_base, lm, km);
+      fast_ld = fast_ld && zf.ok;
+    }
     const __amdgpu_buffer_rsrc_t rs = raw_rsrc(src, fast_ld ? 0x7fffffff : 0);
     const uint32_t off = (uint32_t)ad_lo << 2;
+    if (z2) {
+      // stored addresses: the complemented entries through a second buffer
+      const __amdgpu_buffer_rsrc_t rs2 = raw_rsrc(in + (in_base ^ zf.fm), fast_ld ? 0x7fffffff : 0);
+      const uint32_t off2 = (uint32_t)(ad_lo ^ zf.lm) << 2;
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-      vals[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)(had[k] << 2), AUX_NT));
+      for (int k = 0; k < 16; ++k) {
+        const bool f = z2_flip(zf, had[k]);
+        vals[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                f ? rs2 : rs, (int)(f ? off2 : off),
+                                                (int)((f ? had[k] ^ zf.km : had[k]) << 2), AUX_NT));
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        vals[k] =
+            __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, (int)(had[k] << 2), AUX_NT));
+    }
     ad_lo_ld = ad_lo;
 #pragma unroll
     for (int k = 0; k < 16; ++k) had_ld[k] = had[k];
@@ -741,23 +796,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
       }
       return;
     }
-    if (tid < (1 << nb) && z2) {
-      // half-state plan: every output at its stored address (the mirror
-      // outputs of the tile's complement included)
+    if (tid < (1 << nb)) {
       const int nk = 1 << (ns - nb);
       const uint32_t ls = opaque(swz(ti_lo) << 2);
       float vals[16];
+      bool fast = nk == 16 && all < BUF_MAX_ENTRIES;
+      Z2Fast zf{};
+      if (z2) {
+        // half-state plan: every output at its stored address (the mirror
+        // outputs of the tile's complement included)
+        uint64_t lm = 0, km = 0;
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k < nk) vals[k] = lds_at(ls ^ hs[k]);
+        for (int q = 0; q < 10; ++q)
+          if (q < nb) lm |= bad[q];
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k < nk) __builtin_nontemporal_store(vals[k], &out[z2_addr(out_base | ad_lo | had[k], P.out_w)]);
-    } else if (tid < (1 << nb)) {
-      const int nk = 1 << (ns - nb);
-      const uint32_t ls = opaque(swz(ti_lo) << 2);
-      float vals[16];
-      if (nk == 16 && all < BUF_MAX_ENTRIES) {
+        for (int k = 0; k < 16; ++k) km |= had[k];
+        zf = z2_fast(P.out_w, out_base, lm, km);
+        fast = fast && zf.ok;
+      }
+      if (fast) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) vals[k] = lds_at(ls ^ hs[k]);
         const __amdgpu_buffer_rsrc_t rs = raw_rsrc(dst);
@@ -765,10 +822,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
         // non-temporal: the next pass reads the state from memory on any XCD,
         // so it is not kept dirty in this XCD's L2 (which the end of the
         // launch would otherwise write back)
+        if (z2) {
+          const __amdgpu_buffer_rsrc_t rs2 = raw_rsrc(out + (out_base ^ zf.fm));
+          const uint32_t off2 = (uint32_t)(ad_lo ^ zf.lm) << 2;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const bool f = z2_flip(zf, had[k]);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, vals[k]), f ? rs2 : rs,
+                                                  (int)(f ? off2 : off), (int)((f ? had[k] ^ zf.km : had[k]) << 2),
+                                                  AUX_NT);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 16; ++k)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, vals[k]), rs, (int)off,
+                                                  (int)(had[k] << 2), AUX_NT);
+        }
+      } else if (z2) {
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, vals[k]), rs, (int)off,
-                                                (int)(had[k] << 2), AUX_NT);
+          if (k < nk) vals[k] = lds_at(ls ^ hs[k]);
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < nk) __builtin_nontemporal_store(vals[k], &out[z2_addr(out_base | ad_lo | had[k], P.out_w)]);
       } else {
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -1084,7 +1160,8 @@ __device__ __forceinline__ void enum_lo(const uint32_t (&bti)[10], const uint64_
 // indices i and i + 2^(tb-1) of the loads and stores and groups i and
 // i + 2^(tb-1) of every stage.
 // (NG = 2 keeps two groups' registers: four waves per SIMD, within 128 VGPRs)
-template <int NG>
+// Z2 as in k_pass.
+template <int NG, bool Z2>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 : 6))) void k_pass16(
     const PassItem* __restrict__ items, int n_items) {
   // LDS holds the tile as int16 (2^t entries, dynamic, from address 0);
@@ -1100,7 +1177,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
   int64_t inst;
   uint64_t ktile;
   // half-state plans run the tiles with fixed slot z2_skip at 0 only
-  const bool z2 = I.z2 != 0;
+  const bool z2 = Z2 && I.z2 != 0;
   const int zskip = z2 ? P.z2_skip : -1;
   const int run_bits = P.n_free - (zskip >= 0 ? 1 : 0);
   if (!wg_to_tile((uint64_t)(wg - I.wg_begin), run_bits, I.batch, I.xcd_group, &inst, &ktile)) return;
@@ -1171,16 +1248,45 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
     __builtin_amdgcn_sched_barrier(0);
     // the buffer covers the instance's input state from this tile's base
     // (records in bytes): every entry the tile reads lies inside it
-    fast_ld = !init && !z2 && nk_ld == 16 && all < BUF_MAX_ENTRIES;
+    fast_ld = !init && nk_ld == 16 && all < BUF_MAX_ENTRIES;
+    Z2Fast zf{};
+    if (z2) {
+      uint64_t lm = 0, km = 0;
+#pragma unroll
+      for (int q = 0; q < 10; ++q)
+        if (q < nb_ld) lm |= bad[q];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) km |= had[k];
+      zf = z2_fast(P.in_w, in_base, lm, km);
+      fast_ld = fast_ld && zf.ok;
+    }
     const uint64_t rec = ((uint64_t)I.in_st - in_base) * 2ull;
     const __amdgpu_buffer_rsrc_t rs =
         raw_rsrc(src, fast_ld ? (int)(rec < 0x7fffffffull ? rec : 0x7fffffffull) : 0);
+    if (z2) {
+      // stored addresses: the complemented entries through a second buffer
+      const uint64_t base2 = in_base ^ zf.fm;
+      const uint64_t rec2 = ((uint64_t)I.in_st - base2) * 2ull;
+      const __amdgpu_buffer_rsrc_t rs2 =
+          raw_rsrc(in16 + base2, fast_ld ? (int)(rec2 < 0x7fffffffull ? rec2 : 0x7fffffffull) : 0);
 #pragma unroll
-    for (int h = 0; h < NG; ++h) {
-      const uint32_t off = (uint32_t)ad_ld[h] << 1;
+      for (int h = 0; h < NG; ++h) {
+        const uint32_t off = (uint32_t)ad_ld[h] << 1, off2 = (uint32_t)(ad_ld[h] ^ zf.lm) << 1;
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        vals[h][k] = (int16_t)__builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, (int)(had[k] << 1), AUX_NT);
+        for (int k = 0; k < 16; ++k) {
+          const bool f = z2_flip(zf, had[k]);
+          vals[h][k] = (int16_t)__builtin_amdgcn_raw_buffer_load_b16(
+              f ? rs2 : rs, (int)(f ? off2 : off), (int)((f ? had[k] ^ zf.km : had[k]) << 1), AUX_NT);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < NG; ++h) {
+        const uint32_t off = (uint32_t)ad_ld[h] << 1;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          vals[h][k] = (int16_t)__builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, (int)(had[k] << 1), AUX_NT);
+      }
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) had_ld[k] = had[k];
@@ -1353,9 +1459,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
       }
       return;
     }
-    const bool fast_st = !z2 && nk == 16 && all < BUF_MAX_ENTRIES;
+    bool fast_st = nk == 16 && all < BUF_MAX_ENTRIES;
+    Z2Fast zf{};
+    if (z2) {
+      uint64_t lm = 0, km = 0;
+#pragma unroll
+      for (int q = 0; q < 10; ++q)
+        if (q < nb) lm |= bad[q];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) km |= had[k];
+      zf = z2_fast(P.out_w, out_base, lm, km);
+      fast_st = fast_st && zf.ok;
+    }
     const uint64_t rec = ((uint64_t)I.out_st - out_base) * 2ull;
     const __amdgpu_buffer_rsrc_t rs = raw_rsrc(dst, (int)(rec < 0x7fffffffull ? rec : 0x7fffffffull));
+    const uint64_t base2 = out_base ^ zf.fm;
+    const uint64_t rec2 = ((uint64_t)I.out_st - base2) * 2ull;
+    const __amdgpu_buffer_rsrc_t rs2 = raw_rsrc(out16 + base2, (int)(rec2 < 0x7fffffffull ? rec2 : 0x7fffffffull));
 #pragma unroll
     for (int h = 0; h < NG; ++h) {
       if (!storer[h]) continue;
@@ -1365,9 +1485,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 4 
 #pragma unroll
         for (int k = 0; k < 16; ++k) sv[k] = lds16_at(ls ^ hs[k]);
         const uint32_t off = (uint32_t)ad_st[h] << 1;
+        if (z2) {   // stored addresses, the complemented ones through the second buffer
+          const uint32_t off2 = (uint32_t)(ad_st[h] ^ zf.lm) << 1;
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          __builtin_amdgcn_raw_buffer_store_b16((uint16_t)sv[k], rs, (int)off, (int)(had[k] << 1), AUX_NT);
+          for (int k = 0; k < 16; ++k) {
+            const bool f = z2_flip(zf, had[k]);
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)sv[k], f ? rs2 : rs, (int)(f ? off2 : off),
+                                                  (int)((f ? had[k] ^ zf.km : had[k]) << 1), AUX_NT);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 16; ++k)
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)sv[k], rs, (int)off, (int)(had[k] << 1), AUX_NT);
+        }
       } else {
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -2000,15 +2130,11 @@ __global__ __launch_bounds__(NT) void k_backward(const BwdItem* __restrict__ ite
 // host launch wrappers (kernels are launched from this translation unit)
 // ---------------------------------------------------------------------------
 
-// Raises the dynamic LDS limit of a kernel once (static tables come on top).
+// Raises the dynamic LDS limit of a kernel once (static tables come on top);
+// slot: which of the pass kernels (0 .. 7).
 template <typename K>
-static hipError_t allow_lds(K kernel, size_t bytes) {
-  static int done[4] = {0, 0, 0, 0};
-  const void* kp = reinterpret_cast<const void*>(kernel);
-  const int slot = kp == reinterpret_cast<const void*>(k_pass<float>)     ? 0
-                   : kp == reinterpret_cast<const void*>(k_pass<int32_t>) ? 1
-                   : kp == reinterpret_cast<const void*>(k_pass16<1>)     ? 2
-                                                                          : 3;
+static hipError_t allow_lds(K kernel, int slot, size_t bytes) {
+  static int done[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (done[slot]) return hipSuccess;
   // the pass kernel addresses LDS from 0: it must have no static LDS
   hipFuncAttributes fa;
@@ -2022,34 +2148,30 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 }
 
 hipError_t launch_pass(const PassItem* items, int n_items, int64_t n_wg, int threads, size_t lds, int dtype,
-                       hipStream_t stream, hipEvent_t t0, hipEvent_t t1, int ng) {
+                       hipStream_t stream, hipEvent_t t0, hipEvent_t t1, int ng, bool z2) {
   if (n_wg >= (1ll << 31) || threads < 64 || threads > NT || lds > 65536) return hipErrorInvalidConfiguration;
   const dim3 grid((uint32_t)n_wg), block(threads);
+  // int16: two groups per thread when the host launches half the threads of
+  // a tile (ng == 2), else one; z2: the launch holds half-state items
+  using Kern = void (*)(const PassItem*, int);
+  Kern kern;
+  int slot;
   if (dtype == 2) {
-    // int16: two groups per thread when the host launches half the threads
-    // of a tile (ng == 2), else one
-    const auto kern = ng == 2 ? k_pass16<2> : k_pass16<1>;
-    hipError_t e = allow_lds(kern, PASS_LDS_MAX);
-    if (e != hipSuccess) return e;
-    if (t0 || t1)
-      hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)lds, stream, t0, t1, 0u, items, n_items);
-    else
-      hipLaunchKernelGGL(kern, grid, block, lds, stream, items, n_items);
+    kern = ng == 2 ? (z2 ? k_pass16<2, true> : k_pass16<2, false>) : (z2 ? k_pass16<1, true> : k_pass16<1, false>);
+    slot = ng == 2 ? 2 : 3;
   } else if (dtype == 0) {
-    hipError_t e = allow_lds(k_pass<float>, PASS_LDS_MAX);
-    if (e != hipSuccess) return e;
-    if (t0 || t1)
-      hipExtLaunchKernelGGL(k_pass<float>, grid, block, (uint32_t)lds, stream, t0, t1, 0u, items, n_items);
-    else
-      hipLaunchKernelGGL(k_pass<float>, grid, block, lds, stream, items, n_items);
+    kern = z2 ? k_pass<float, true> : k_pass<float, false>;
+    slot = 0;
   } else {
-    hipError_t e = allow_lds(k_pass<int32_t>, PASS_LDS_MAX);
-    if (e != hipSuccess) return e;
-    if (t0 || t1)
-      hipExtLaunchKernelGGL(k_pass<int32_t>, grid, block, (uint32_t)lds, stream, t0, t1, 0u, items, n_items);
-    else
-      hipLaunchKernelGGL(k_pass<int32_t>, grid, block, lds, stream, items, n_items);
+    kern = z2 ? k_pass<int32_t, true> : k_pass<int32_t, false>;
+    slot = 1;
   }
+  hipError_t e = allow_lds(kern, 2 * slot + (z2 ? 1 : 0), PASS_LDS_MAX);
+  if (e != hipSuccess) return e;
+  if (t0 || t1)
+    hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)lds, stream, t0, t1, 0u, items, n_items);
+  else
+    hipLaunchKernelGGL(kern, grid, block, lds, stream, items, n_items);
   return hipGetLastError();
 }
 

@@ -96,3 +96,66 @@ def test_half_state_work_counts(L, tb):
     assert full["terms"] / 2 <= half["terms"] <= full["terms"]
     if all(f == 0.5 for f in frac):
         assert half["terms"] == full["terms"] / 2 and half["elementwise"] == full["elementwise"] / 2
+
+
+def _split_addresses(w, base, lanes, ks):
+    """The buffer addressing of half-state tiles: with lm, km the lane and k
+    bit sets and fm the other address bits below w, an entry whose top bit is
+    set is read at (base ^ fm) | (lane ^ lm) | (k ^ km). Returns None where
+    the top bit is a lane bit (the kernels then address entry by entry)."""
+    lm = 0
+    for x in lanes:
+        lm |= x
+    km = 0
+    for x in ks:
+        km |= x
+    assert lm & km == 0 and base & (lm | km) == 0
+    full = (1 << w) - 1
+    fm = full & ~(lm | km)
+    top = w - 1
+    if w == 0 or (lm >> top) & 1:
+        return None
+    out = {}
+    for ln in lanes:
+        for k in ks:
+            a = base | ln | k
+            flip = (base >> top) & 1 or (k >> top) & 1
+            out[a] = ((base ^ fm) | (ln ^ lm) | (k ^ km)) if flip else a
+    return out
+
+
+@pytest.mark.parametrize("L,tb", [(12, 10), (12, 11), (14, 12), (16, 12), (16, 14)])
+def test_half_state_buffer_addressing(L, tb):
+    """Every load and store address the pass kernels form on the fast path of
+    a half-state plan equals the stored address of its entry."""
+    n = L * L
+    plan = B.Plan(n, I.square_lattice(L), order=list(range(n)), tile_bits=tb, z2=True)
+    prog = K.load_program(plan)
+    checked = 0
+    for P in prog["passes"]:
+        t, tpb = P.t, P.tb
+        fin = [P.fin[k] for k in range(P.n_free)]
+        fout = [P.fout[k] for k in range(P.n_free)]
+        run = [tid for tid in range(1 << P.n_free) if P.z2_skip < 0 or not (tid >> P.z2_skip) & 1]
+        for side in ("ld", "st"):
+            ns = t if side == "ld" else P.n_st
+            nb = min(ns, tpb)
+            nk = 1 << (ns - nb)
+            if nk != 16:
+                continue
+            bad = list(getattr(P, side + "_bad"))[:nb]
+            had = list(getattr(P, side + "_had"))[:16]
+            lanes = [sum(bad[q] for q in range(nb) if (u >> q) & 1) for u in range(1 << nb)]
+            w = P.in_w if side == "ld" else P.out_w
+            pos = fin if side == "ld" else fout
+            for tid in run[:8]:
+                if side == "st" and any(p == 255 and (tid >> k) & 1 for k, p in enumerate(pos)):
+                    continue   # a duplicate tile: nothing stored
+                base = sum(1 << p for k, p in enumerate(pos) if p != 255 and (tid >> k) & 1)
+                got = _split_addresses(w, base, lanes, had)
+                if got is None:
+                    continue
+                for a, s in got.items():
+                    assert s == K.z2_addr(a, w)
+                checked += 1
+    assert checked > 0
