@@ -479,6 +479,7 @@ def main():
         "valu_frac": line["valu_frac"],
         "roofline": line["roofline"],
         "roofline_one_part": line["roofline_one_part"],
+        **({"full_state": line["full_state"]} if "full_state" in line else {}),
         "kernel_ms_per_step": line["kernel_ms_per_step"],
         "plan": line["plan"],
     }
@@ -524,8 +525,10 @@ def run_lattice(args, B, edges, n, J, h, workload):
     has_h = h is not None
     plan = B.Plan(n, edges, order=list(range(n)), has_field=has_h)
     tile_bits, _ = B.autotune(plan, J, h, config=True)
+    fbits = tile_bits
     half = False
     trial = {}
+    full_plan = plan
     if not has_h:
         # without fields a half-state plan (z2) is the other candidate: both
         # autotuned, the faster over a few timed calls is the one measured
@@ -561,36 +564,54 @@ def run_lattice(args, B, edges, n, J, h, workload):
     one = B.Plan(n, edges, order=list(range(n)), has_field=has_h, tile_bits=tile_bits, parts=1, z2=half)
     B.backward(one, J, h)
     kt1 = kernel_times(one, args.steps)
-    ops_inst = 2.0 * info["terms"] + info["elementwise"]     # the final maximum runs inside the last pass
-    ops_step = ops_inst * batch
     large = (batch << info["width"]) >= (1 << 20)
-    parts = 2 if (large and batch >= 2) else 1
 
-    def roof(k, nparts):
+    def work(inf):
+        # max-plus ops per step (the final maximum runs inside the last pass)
+        return (2.0 * inf["terms"] + inf["elementwise"]) * batch
+
+    def roof(k, nparts, ops_step, is_half, tb):
         ms, launches = k["sweep_pass"]
         per_launch = ops_step * args.steps / max(launches, 1)
         avg_ms = ms / max(launches, 1)
         ach = per_launch / (avg_ms * 1e-3) if ms > 0 else 0.0
         return {"kernel": "k_pass", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "TFLOP/s", "frac": ach / VALU_PEAK_OPS,
-                "traffic": pass_traffic(workload + ("_half" if half else ""), tile_bits, nparts),
+                "traffic": pass_traffic(workload + ("_half" if is_half else ""), tb, nparts),
                 "avg_launch_ms": avg_ms, "launches": launches, "ops_per_launch": per_launch,
                 "concurrent_parts": nparts}
 
-    r = roof(kt, parts)
+    ops_inst = work(info) / batch
+    ops_step = work(info)
+    parts = info["parts"] if (large and batch >= 2) else 1   # the autotuner may have chosen one part
+    r = roof(kt, parts, ops_step, half, tile_bits)
     if parts > 1:
         r["note"] = ("each launch is half a pass and runs beside the other half's launch; the whole-step "
                      "rate is valu_frac, the unsplit per-launch rate roofline_one_part")
+    if half:
+        r["note_half_state"] = ("a half-state pass computes half of the entries: its ops per launch are half "
+                                "those of the full-state pass (full_state holds that plan's figures)")
+    extra = {}
+    if half:
+        # the full-state plan of the same batch, as measured in the selection
+        fi = full_plan.info()
+        fparts = fi["parts"] if (large and batch >= 2) else 1
+        extra["full_state"] = {"ms_per_step": trial["full_state_ms"],
+                               "solves_s": batch / (trial["full_state_ms"] * 1e-3),
+                               "roofline": roof(kernel_times(full_plan, args.steps), fparts, work(fi), False,
+                                                fbits),
+                               "plan": {"tile_bits": fbits, "parts": fparts, "passes": fi["n_passes"]}}
     return {
         "solves_s": batch * args.steps / dt,
         "ms_per_step": dt * 1e3 / args.steps,
         "maxplus_gops": ops_step * args.steps / dt / 1e9,
         "valu_frac": ops_step * args.steps / dt / VALU_PEAK_OPS,
         "roofline": r,
-        "roofline_one_part": roof(kt1, 1),
+        "roofline_one_part": roof(kt1, 1, ops_step, half, tile_bits),
+        **extra,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "plan": {"width": info["width"], "passes": info["n_passes"], "tile_bits": tile_bits,
-                 "half_state": half, "terms_per_instance": info["terms"],
+                 "half_state": half, "parts": parts, "terms_per_instance": info["terms"],
                  "elementwise_per_instance": info["elementwise"], "maxplus_ops_per_instance": ops_inst,
                  **({"selection": trial} if trial else {})},
     }

@@ -128,6 +128,8 @@ typedef struct tt_plan_stats {
                                entry), cuts and the final maximum (one max per entry) */
   double reduce_ops;        /* of which the final maximum over the last state */
   double entry_updates;     /* state entries read+written per instance (energy path) */
+  int32_t parts;            /* concurrent parts a large same-graph batch runs in (the
+                               autotuner may have chosen it) */
 } tt_plan_stats;
 
 typedef struct tt_plan tt_plan;
@@ -365,7 +367,9 @@ int tt_graphs_enable(int32_t on);
  * score is the summed device time of the call's kernels, the least of three
  * calls; for a same-graph batch of at least 2^20 state entries (which runs in
  * parts on concurrent streams) it is the device time from before to after the
- * call instead. Blocks until the timing is done; allocates the timed calls' outputs
+ * call instead, and when the plan left the part count to the library
+ * (tt_plan_opts.parts = 0) every tile size is also timed in one part and the
+ * faster count is kept (tt_plan_info reports it). Blocks until the timing is done; allocates the timed calls' outputs
  * (freed before it returns). chosen_bits and best_ms (milliseconds per call)
  * may be NULL. Captured graphs and device buffers of the plan are released.
  * TT_E_INVAL for an unknown mode. */

@@ -55,7 +55,7 @@ class PlanStats(C.Structure):
     _fields_ = [("n_spins", C.c_int32), ("n_edges", C.c_int64), ("width", C.c_int32),
                 ("n_ops", C.c_int32), ("n_passes", C.c_int32), ("n_count_passes", C.c_int32),
                 ("terms", C.c_double), ("elementwise", C.c_double), ("reduce_ops", C.c_double),
-                ("entry_updates", C.c_double)]
+                ("entry_updates", C.c_double), ("parts", C.c_int32)]
 
 
 _vp = C.c_void_p

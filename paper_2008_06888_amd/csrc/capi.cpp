@@ -2210,6 +2210,7 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
     p->max_bytes = o.max_bytes;
     if (o.parts < 0 || o.parts > SPLIT_PARTS) return fail(TT_E_INVAL, "parts must be 1 or 2 (0: default)");
     p->parts = o.parts > 0 ? o.parts : SPLIT_PARTS;
+    p->parts_auto = o.parts == 0;
     if (o.q != 0 && o.q != 2 && o.q != 3) return fail(TT_E_INVAL, "q must be 2 or 3 (0: 2)");
     p->q = o.q == 3 ? 3 : 2;
     if (p->q == 3 && (o.kind == TT_ORDER_CHIMERA || p->has_field))
@@ -2382,6 +2383,7 @@ int tt_plan_info(const tt_plan* plan, tt_plan_stats* out) {
   out->n_edges = p.m;
   out->width = p.width;
   out->n_ops = (int32_t)p.ops.size();
+  out->parts = p.parts;
   if (p.slice) {   // the reduced plan's figures, its work once per slice
     const Slice& S = *static_cast<const Slice*>(p.slice);
     tt_plan_stats r;
@@ -3233,22 +3235,25 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
     std::vector<uint64_t> res(nb * 3);
     std::vector<uint8_t> flags(nb);
     const int keep = count ? p.count_tile_bits : p.tile_bits;
-    int best_t = keep;
+    const int keep_parts = p.parts;
+    int best_t = keep, best_parts = keep_parts;
     // Every exit path (a failed HIP call included) restores graph capture and
-    // leaves the plan partitioned at the kept tile size: the caller's size
-    // until a candidate has been timed, then the fastest one.
+    // leaves the plan partitioned at the kept tile size and part count: the
+    // caller's until a candidate has been timed, then the fastest one.
     struct Restore {
       Plan& p;
       bool count, graphs;
       const int& t;
+      const int& parts;
       ~Restore() {
         g_graphs_on = graphs;
         (count ? p.count_tile_bits : p.tile_bits) = t;
+        p.parts = parts;
         delete static_cast<DevCache*>(p.dev);
         p.dev = nullptr;
         partition_plan(p);
       }
-    } restore{p, count, g_graphs_on, best_t};
+    } restore{p, count, g_graphs_on, best_t, best_parts};
     g_graphs_on = false;   // timing of eager launches; no capture of discarded plans
     // one call, left running on the stream (energy / backward modes)
     auto run_call = [&]() -> int {
@@ -3268,6 +3273,9 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
     // a large same-graph batch runs in parts on concurrent streams (see
     // run_split), so summed kernel times would count overlapping work twice
     const bool split = !count && !p.is_chimera && batch >= 2 && p.parts > 1 && large_batch(p, batch);
+    // with the part count left to the library, one part is a candidate too
+    // (timed the same way, from before to after the call)
+    const int n_part_opts = (split && p.parts_auto) ? 2 : 1;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (split) {
       HIP_TRY(hipEventCreate(&ev0));
@@ -3282,7 +3290,9 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
     } ev_free{ev0, ev1};
     double best = 1e300;
     int rc = 0;
-    for (int t = lo; t <= top && rc == 0; ++t) {
+    for (int cand = 0; cand < (top - lo + 1) * n_part_opts && rc == 0; ++cand) {
+      const int t = lo + cand / n_part_opts;
+      p.parts = (cand % n_part_opts) ? 1 : keep_parts;
       (count ? p.count_tile_bits : p.tile_bits) = t;
       delete static_cast<DevCache*>(p.dev);
       p.dev = nullptr;
@@ -3329,10 +3339,12 @@ int tt_plan_autotune(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
       if (rc == 0 && ms < best) {
         best = ms;
         best_t = t;
+        best_parts = p.parts;
       }
     }
     if (rc) {
-      best_t = keep;   // a failed trial: the caller's tile size stays
+      best_t = keep;   // a failed trial: the caller's tile size and part count stay
+      best_parts = keep_parts;
       return rc;
     }
     if (chosen_bits) *chosen_bits = best_t;

@@ -125,6 +125,7 @@ struct Plan {
   double reduce_ops = 0;             // of which the final maximum
   int64_t max_bytes = 0;
   int32_t parts = 2;                 // concurrent parts of a large same-graph batch (1 or 2)
+  bool parts_auto = true;            // parts left to the library (the autotuner may choose 1)
   std::vector<int32_t> breaks;       // op indices where a pass must begin
   bool is_chimera = false;
   ChimeraInfo chim;

@@ -65,6 +65,14 @@ def test_tile_bits_option_validated():
         B.Plan(16, I.square_lattice(4), order=list(range(16)), tile_bits=20)
 
 
+def test_parts_option_reported_and_validated():
+    e = I.square_lattice(4)
+    assert B.Plan(16, e, order=list(range(16))).info()["parts"] == 2
+    assert B.Plan(16, e, order=list(range(16)), parts=1).info()["parts"] == 1
+    with pytest.raises(B.TTError):
+        B.Plan(16, e, order=list(range(16)), parts=3)
+
+
 def test_autotune_mode_validated_before_any_device_work():
     p = B.Plan(16, I.square_lattice(4), order=list(range(16)))
     for mode in (-1, 3):

@@ -154,6 +154,26 @@ def test_autotune_half_state():
     assert np.array_equal(B.backward(plan, J)[0].cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("z2", [False, True])
+def test_autotune_chooses_parts_on_the_headline_batch(z2):
+    """A large batch with the part count left to the library: the autotuner
+    times one and two parts per tile and keeps the faster; results are those
+    of the stored oracle either way, and an explicit part count is kept."""
+    insts = I.config_instances(0, batch=64, L=16)
+    gold = GOLD["square16_pm1_b64"]["cases"]
+    J = dev(np.stack([x.J for x in insts]))
+    plan = B.Plan(256, insts[0].edges, order=list(range(256)), z2=z2)
+    bits, _ = B.autotune(plan, J, config=True)
+    parts = plan.info()["parts"]
+    say("autotune headline z2", z2, "tile", bits, "parts", parts)
+    assert parts in (1, 2)
+    E = B.backward(plan, J)[0].cpu().numpy()
+    assert all(E[b] == gold[str(b)]["energy"] for b in range(64))
+    fixed = B.Plan(256, insts[0].edges, order=list(range(256)), z2=z2, parts=2)
+    B.autotune(fixed, J, config=True)
+    assert fixed.info()["parts"] == 2
+
+
 # ----------------------------------------------------------------------------
 # counting on half states
 # ----------------------------------------------------------------------------
