@@ -462,14 +462,65 @@ __device__ __forceinline__ void star16(const float (&a)[16], float (&o)[16], uin
 #undef TT_STAR
 }
 
+// A star with at most one resident partner, specialised on where the
+// spin's and the partner's bits are: SL / WL a stage bit (< 4, its sign per
+// register entry known at compile time) or 4 (constant over the group: a
+// non-stage tile bit, a fixed slot or no partner; sneg / pm carry the
+// spin's sign and the signed partner term per thread). The same sums as
+// star16, one add per entry.
+template <int SL, int WL>
+__device__ __forceinline__ void star_sw(const float (&a)[16], float (&o)[16], const UOp& u, bool sneg, float pm) {
+  if constexpr (SL < 4 && WL < 4) {
+    const float v0 = u.p0 + u.m0, v1 = u.p0 - u.m0;   // partner bit 0 / 1
+#pragma unroll
+    for (int J = 0; J < 16; ++J) {
+      const float sw = ((J >> WL) & 1) ? v1 : v0;
+      o[J] = ((J >> SL) & 1) ? a[J] - sw : a[J] + sw;
+    }
+  } else if constexpr (SL < 4) {
+    const float sw = u.p0 + pm;
+#pragma unroll
+    for (int J = 0; J < 16; ++J) o[J] = ((J >> SL) & 1) ? a[J] - sw : a[J] + sw;
+  } else if constexpr (WL < 4) {
+    const float v0 = u.p0 + u.m0, v1 = u.p0 - u.m0;
+    const float c0 = sneg ? -v0 : v0, c1 = sneg ? -v1 : v1;
+#pragma unroll
+    for (int J = 0; J < 16; ++J) o[J] = a[J] + (((J >> WL) & 1) ? c1 : c0);
+  } else {
+    const float sw = u.p0 + pm;
+    const float c = sneg ? -sw : sw;
+#pragma unroll
+    for (int J = 0; J < 16; ++J) o[J] = a[J] + c;
+  }
+}
+
+__device__ __forceinline__ void star_fast(const float (&a)[16], float (&o)[16], uint32_t gb, const UOp& u) {
+  const bool sneg = u.sl == 4 && u.sbit != 255 && tbit(gb, u.sbit);
+  const float pm = (u.wl == 4 && u.wf != 255) ? (tbit(gb, u.wf) ? -u.m0 : u.m0) : 0.f;
+#define TT_SW(S, W) \
+  case S * 5 + W: star_sw<S, W>(a, o, u, sneg, pm); break;
+  switch (u.sl * 5 + u.wl) {
+    TT_SW(0, 1) TT_SW(0, 2) TT_SW(0, 3) TT_SW(0, 4)
+    TT_SW(1, 0) TT_SW(1, 2) TT_SW(1, 3) TT_SW(1, 4)
+    TT_SW(2, 0) TT_SW(2, 1) TT_SW(2, 3) TT_SW(2, 4)
+    TT_SW(3, 0) TT_SW(3, 1) TT_SW(3, 2) TT_SW(3, 4)
+    TT_SW(4, 0) TT_SW(4, 1) TT_SW(4, 2) TT_SW(4, 3)
+    default: star_sw<4, 4>(a, o, u, sneg, pm); break;
+  }
+#undef TT_SW
+}
+
 // One op of a stage: reads a, writes every entry of o.
 __device__ __forceinline__ void apply_op(const float (&a)[16], float (&o)[16], uint32_t gb, const OpLanes& R,
                                          int k) {
   const UOp u = op_at(R, k);
   if (u.kind == FK_STAR) {
-    XOp x{{0.f, 0.f, 0.f}, 0u};
-    if (u.nx) x = xop_at(R, k);
-    star16(a, o, gb, u, x);
+    if (u.nx == 0) {
+      star_fast(a, o, gb, u);
+    } else {
+      const XOp x = xop_at(R, k);
+      star16(a, o, gb, u, x);
+    }
   } else if (u.kind == FK_CUT) {
     switch (u.lidx) {
       case 0: cut_l<0>(a, o); break;
