@@ -430,18 +430,22 @@ int64_t budget_bytes(const Plan& p) {
 //   backward (keep_all): every pass input at its own width, and the final state;
 //   chimera: two working states, plus the state after every row but the last
 //   with the backward.
+// Entries of a w-bit energy state that a plan stores per instance: half of
+// them on a half-state plan (every stored address has its top bit at 0).
+int64_t stored_entries(const Plan& p, int w) { return (int64_t)1 << (w - (p.z2 && w > 0 ? 1 : 0)); }
+
 int64_t state_bytes(const Plan& p, int64_t batch, bool backward) {
   const int64_t f = (int64_t)sizeof(float);
   if (p.is_chimera) {
     const int64_t per = (batch * f << p.width) + 255 & ~int64_t(255);
     return (2 + (backward ? p.chim.rows - 1 : 0)) * per;
   }
-  if (!backward) return 2 * batch * f << p.width;
+  if (!backward) return 2 * batch * f * stored_entries(p, p.width);
   int64_t need = 0;
   const size_t np = p.passes.size();
   for (size_t q = 0; q <= np; ++q) {
     const int w = q < np ? p.passes[q].in_w : (np ? p.passes[np - 1].out_w : 0);
-    need += batch * f << w;
+    need += batch * f * stored_entries(p, w);
     need = (need + 255) & ~int64_t(255);
   }
   return need;
@@ -819,7 +823,7 @@ int prepare_group(Group& g, bool keep_all) {
   const Plan& p = *g.p;
   g.bufs.assign(np + 1, nullptr);
   g.strides.assign(np + 1, 0);
-  for (int q = 0; q <= np; ++q) g.strides[q] = (int64_t)1 << (q < np ? ep.passes[q].in_w : ep.passes[np - 1].out_w);
+  for (int q = 0; q <= np; ++q) g.strides[q] = stored_entries(p, q < np ? ep.passes[q].in_w : ep.passes[np - 1].out_w);
   size_t need = 0;
   std::vector<size_t> off(np + 1, 0);
   if (keep_all) {
@@ -829,7 +833,7 @@ int prepare_group(Group& g, bool keep_all) {
       need = (need + 255) & ~size_t(255);
     }
   } else {
-    need = 2 * (size_t)g.batch * ((size_t)1 << p.width) * sizeof(float);
+    need = 2 * (size_t)g.batch * (size_t)stored_entries(p, p.width) * sizeof(float);
   }
   DevBuf& buf = keep_all ? g.dc->ckpt : g.dc->state;
   if ((int64_t)need > (int64_t)buf.cap && (int64_t)need > budget_bytes(p) + (int64_t)buf.cap)
@@ -844,7 +848,7 @@ int prepare_group(Group& g, bool keep_all) {
     float* pp[2] = {reinterpret_cast<float*>(base),
                     reinterpret_cast<float*>(base + need / 2)};
     for (int q = 0; q <= np; ++q) g.bufs[q] = pp[q & 1];
-    g.part_st.assign(np + 1, (int64_t)1 << p.width);
+    g.part_st.assign(np + 1, stored_entries(p, p.width));
   }
   if (int r = g.dc->arg.ensure((size_t)g.batch * sizeof(uint64_t))) return r;
   g.arg = static_cast<uint64_t*>(g.dc->arg.p);
