@@ -96,8 +96,8 @@ typedef struct tt_plan_opts {
   int32_t q;                /* labels per spin: 2 = Ising spins, 3 = 3-state Potts
                                glass (App. C; GREEDY or GIVEN order, no fields,
                                tt_potts_* calls only) [2] */
-  int32_t z2;               /* 1: keep half of every energy-path state (plans without
-                               fields, GREEDY or GIVEN order). With h = 0 Eq. (1) is
+  int32_t z2;               /* 1: keep half of every energy-path state (Ising plans
+                               without fields: GREEDY, GIVEN or CHIMERA order). With h = 0 Eq. (1) is
                                even under flipping every spin, and so is every partial
                                contraction: entries whose top address bit is 1 are read
                                at the complement address, and a pass runs half of its

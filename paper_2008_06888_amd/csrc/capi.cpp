@@ -1553,7 +1553,9 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   const ChimeraInfo& ch = p.chim;
   const int np = (int)dc->ep.passes.size();
   const int w = p.width, rows = ch.rows;
-  const int64_t sst = (int64_t)1 << w;
+  // a half-state plan stores (and chains) the entries whose top bit is 0
+  const int64_t sst = stored_entries(p, w);
+  const int cw = p.z2 && w > 0 ? w - 1 : w;   // chained index bits
   const size_t per = ((size_t)g.batch * (size_t)sst * sizeof(float) + 255) & ~size_t(255);
   const int nck = backward ? rows - 1 : 0;
   const size_t need = (size_t)(2 + nck) * per;
@@ -1599,7 +1601,7 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
   if (int r = dc->part_v.ensure((size_t)std::max<int64_t>(ct.chunks, row_chunks) * sizeof(float))) return r;
   if (int r = dc->part_i.ensure((size_t)std::max<int64_t>(ct.chunks, row_chunks) * sizeof(uint64_t))) return r;
   const ChimeraRow* drows = static_cast<const ChimeraRow*>(dc->d_chim_rows.p);
-  const int lblk = w > 16 ? w - 16 : 0;
+  const int lblk = cw > 16 ? cw - 16 : 0;
   std::vector<size_t> chain_off(rows);
   for (int r = 0; r < rows; ++r) {
     ChainItem ci;
@@ -1611,7 +1613,7 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
     ci.hst = p.n;
     ci.x = row_state[r];
     ci.sst = sst;
-    ci.w = w;
+    ci.w = cw;
     ci.cols = ch.cols;
     ci.batch = g.batch;
     ci.init = r == 0 ? 1 : 0;
@@ -1637,6 +1639,7 @@ int run_chimera(Group& g, int32_t dtype, bool backward, hipStream_t s) {
         it.bedge = vert + (size_t)(r - 1) * w;
         it.bref = args + (size_t)r * g.batch + b;
         it.bdtype = dtype;
+        it.z2 = p.z2 ? 1 : 0;   // the bonus breaks the symmetry: every entry, read at its stored address
       }
       walk_off[r] = ct.blob.add(items.data(), items.size());
     }
@@ -2220,8 +2223,8 @@ int tt_plan_create(int32_t n_spins, int64_t n_edges, const int32_t* edges, const
     if (p->q == 3 && (o.kind == TT_ORDER_CHIMERA || p->has_field))
       return fail(TT_E_INVAL, "3-state plans take a GREEDY or GIVEN order and no fields");
     if (o.z2 != 0 && o.z2 != 1) return fail(TT_E_INVAL, "z2 must be 0 or 1");
-    if (o.z2 && (p->has_field || p->q != 2 || o.kind == TT_ORDER_CHIMERA))
-      return fail(TT_E_INVAL, "the half state (z2) needs an Ising sweep plan without fields");
+    if (o.z2 && (p->has_field || p->q != 2))
+      return fail(TT_E_INVAL, "the half state (z2) needs an Ising plan without fields");
     p->z2 = o.z2 != 0;
     std::string err;
     if (o.kind == TT_ORDER_GIVEN) {
@@ -2421,7 +2424,14 @@ int tt_plan_info(const tt_plan* plan, tt_plan_stats* out) {
   double upd = 0;
   for (const Pass& ps : p.passes) upd += 2.0 * std::ldexp(1.0, ps.w_max);
   out->entry_updates = upd;
-  if (p.z2) {
+  if (p.z2 && p.is_chimera) {
+    // every pass and row chain of a half-state chimera plan visits half of
+    // the entries (the row state's fixed slots always reach the output)
+    out->terms *= 0.5;
+    out->elementwise *= 0.5;
+    out->reduce_ops *= 0.5;
+    out->entry_updates *= 0.5;
+  } else if (p.z2) {
     // a half-state pass visits half of the entries (all of them when no
     // tile-id bit has an output position), as does the final maximum
     EnergyProgram ep;
@@ -3008,7 +3018,8 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
     std::vector<ChainItem> chain_items;
     char* chain_dev = nullptr;
     int chain_slot = -1;
-    const int lblk = p.width > 16 ? p.width - 16 : 0;
+    const int cw = count_width(p);   // chained index bits (half the entries on a half-state plan)
+    const int lblk = cw > 16 ? cw - 16 : 0;
     if (p.is_chimera) {
       if (!all_in_place) return fail(TT_E_INVAL, "internal: chimera count passes must run in place");
       for (int r = 0; r < p.chim.rows; ++r) {
@@ -3022,7 +3033,7 @@ int tt_count(tt_plan* plan, int32_t batch, const int32_t* J, const int32_t* h, i
         ci.x = xb[0];
         ci.n = nb[0];
         ci.sst = sst;
-        ci.w = p.width;
+        ci.w = cw;
         ci.cols = p.chim.cols;
         ci.batch = batch;
         ci.init = r == 0 ? 1 : 0;

@@ -165,7 +165,8 @@ struct RedItem {
   const void* bJ;        // couplings of the instance (bonus), or NULL
   const int32_t* bedge;  // [w] edge per slot, -1 = none
   const uint64_t* bref;  // selected address of the next row
-  int32_t bdtype, pad;   // dtype of bJ: 0 float32, 1 int32, 2 int16
+  int32_t bdtype;        // dtype of bJ: 0 float32, 1 int32, 2 int16
+  int32_t z2;            // half-state plan: entries of the w-bit state read at their stored address
 };
 
 // Chimera row chain (see ChimeraRow): adds (init: writes) to every entry of

@@ -1652,12 +1652,21 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict
     __syncthreads();
   }
   VI best{-INFINITY, ~0ull};
+  // half-state plan: four consecutive entries of the upper half (top bit set;
+  // with w >= 3 they share it) are stored reversed at the complement addresses
+  const uint64_t wmask = I.w > 0 ? (~0ull >> (64 - I.w)) : 0ull;
   if (len >= 4) {
     // four consecutive entries per load; ties keep the smaller address
 #pragma unroll 4
     for (uint64_t k = threadIdx.x; k < len / 4; k += NTR) {
-      const float4 v = ld4(s, base + 4 * k);
       const uint64_t i0 = base + 4 * k;
+      float4 v;
+      if (I.z2 && ((i0 >> (I.w - 1)) & 1ull)) {
+        const float4 r = ld4(s, wmask ^ (i0 + 3));   // entries i0 + 3 .. i0, in that order
+        v = float4{r.w, r.z, r.y, r.x};
+      } else {
+        v = ld4(s, i0);
+      }
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
       if (bonus) {
         const float hi = bt[1][(i0 >> 8) & 255] + bt[2][(i0 >> 16) & 255] + bt[3][(i0 >> 24) & 255] +
@@ -1680,7 +1689,7 @@ __global__ __launch_bounds__(NTR) void k_reduce_stage1(const RedItem* __restrict
       if (bonus)
         a = bt[0][idx & 255] + bt[1][(idx >> 8) & 255] + bt[2][(idx >> 16) & 255] + bt[3][(idx >> 24) & 255] +
             bt[4][(idx >> 32) & 255];
-      best = vi_best(best, VI{(float)s[idx] + a, idx});
+      best = vi_best(best, VI{(float)s[I.z2 ? z2_addr(idx, I.w) : idx] + a, idx});
     }
   }
   best = block_best<NTR>(best);

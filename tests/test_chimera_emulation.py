@@ -100,9 +100,9 @@ class Couplers:
         return out
 
 
-def emulate(rows, cols, edges, J, h, tile_bits=0):
+def emulate(rows, cols, edges, J, h, tile_bits=0, z2=False):
     n = 8 * rows * cols
-    plan = B.Plan(n, edges, chimera=(rows, cols), has_field=h is not None, tile_bits=tile_bits)
+    plan = B.Plan(n, edges, chimera=(rows, cols), has_field=h is not None, tile_bits=tile_bits, z2=z2)
     prog = K.load_program(plan)
     cp = Couplers(rows, cols, edges, J, h)
     w = 4 * cols
@@ -116,9 +116,19 @@ def emulate(rows, cols, edges, J, h, tile_bits=0):
             state += cp.chain(after[q])
 
     x0 = cp.chain(0)
-    states = K.forward(prog, w, cp.J, cp.h, x0=x0, after_pass=hook)
+    if z2:
+        # half state: only the stored entries (top bit 0) are kept; the chain
+        # is even under flipping every spin, so adding it everywhere is the
+        # same on them
+        x0 = np.where(np.arange(1 << w) < (1 << (w - 1)), x0, np.nan)
+    states = K.forward(prog, w, cp.J, cp.h, x0=x0, after_pass=hook, z2=z2)
     # the state after each row: x0, then the output of each row's last pass
     row_state = [x0] + [states[q + 1] for q in range(len(after)) if after[q] >= 0]
+    if z2:
+        # every entry read at its stored address, as the kernels do
+        idx = np.array([K.z2_addr(i, w) for i in range(1 << w)])
+        assert not np.any(np.isnan(np.stack([r[: 1 << (w - 1)] for r in row_state])))
+        row_state = [r[idx] for r in row_state]
     final = row_state[-1]
     E = -final.max()
     Ws = [0] * rows
@@ -200,3 +210,17 @@ def test_chimera_full_size_plan_shape():
     passes = K.load_program(plan)["passes"]
     for P in passes:   # six low index bits shared by every pair of neighbouring tiles
         assert P.t == 14 and P.n_ld >= 6 and P.n_st >= 6
+
+
+@pytest.mark.parametrize("rows,cols,tb", [(2, 2, 0), (3, 2, 0), (2, 3, 0), (3, 3, 8), (2, 4, 9), (3, 4, 10)])
+def test_chimera_half_state_matches_oracle(rows, cols, tb):
+    """Half-state chimera plans: passes on the stored half (every stored entry
+    written), the row chain on stored entries, the row walk reading every
+    entry at its stored address: E* and a ground state of the oracle's."""
+    rng = np.random.default_rng([73, rows, cols])
+    e = I.chimera(rows, cols)
+    J = I.pm1(len(e), rng)
+    E, sigma, _ = emulate(rows, cols, e, J, None, tb, z2=True)
+    ref = O.eliminate(8 * rows * cols, e, J, None)
+    assert E == ref["energy"]
+    assert O.energy(8 * rows * cols, e, J, None, sigma) == E

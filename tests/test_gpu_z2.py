@@ -232,3 +232,69 @@ def test_count_planted_square32_full_size():
     Ec, _, g, ex = B.count_with_flags(plan, dev(x.J[None]))
     plan.close()
     assert Ec[0] == -len(e) and ex[0] and g[0] == 2
+
+
+# ----------------------------------------------------------------------------
+# chimera plans on half states
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("rows,cols,tb", [(2, 2, 0), (3, 3, 0), (3, 3, 8), (2, 4, 0), (3, 4, 9), (4, 4, 10)])
+def test_chimera_half_state_against_oracle(rows, cols, tb):
+    """E*, sigma (E(sigma) = E*, dE/dJ), exact g against the oracle and the
+    full-state chimera plan, float32 and int16 couplings."""
+    n = 8 * rows * cols
+    e = I.chimera(rows, cols)
+    insts = [I.make(e, n, I.rng_for(95, b), "pm1") for b in range(3 if rows * cols < 16 else 1)]
+    J = np.stack([x.J for x in insts])
+    half = B.Plan(n, e, chimera=(rows, cols), tile_bits=tb, z2=True)
+    full = B.Plan(n, e, chimera=(rows, cols), tile_bits=tb)
+    say("z2 chimera", rows, cols, "tile", tb)
+    E, sig, dJ, _ = [x.cpu().numpy() if x is not None else None for x in B.backward(half, dev(J))]
+    E16, sig16, _, _ = B.backward(half, dev(J, torch.int16))
+    Ec, res, g = B.count(half, dev(J))
+    Efull = B.contract(full, dev(J.astype(np.float32))).cpu().numpy()
+    _, resf, gf = B.count(full, dev(J))
+    assert np.array_equal(E, Efull) and np.array_equal(E16.cpu().numpy(), E)
+    assert np.array_equal(res, resf) and g == gf
+    for b, x in enumerate(insts):
+        ref = O.eliminate(n, e, x.J, None, counts="exact")
+        assert E[b] == ref["energy"] and Ec[b] == ref["energy"] and g[b] == ref["count"], b
+        assert O.energy(n, e, x.J, None, sig[b]) == ref["energy"], b
+        assert O.energy(n, e, x.J, None, sig16.cpu().numpy()[b]) == ref["energy"], b
+        assert np.array_equal(dJ[b], -(sig[b][e[:, 0]].astype(np.float32) * sig[b][e[:, 1]])), b
+
+
+def test_chimera_half_state_full_size_planted():
+    """8 x 8 cells on the half state (2^31 stored entries): the Mattis
+    instance's E* = -m, sigma = +-tau and g = 2."""
+    e = I.chimera(8)
+    x, tau = I.planted(e, 512, np.random.default_rng(96))
+    plan = B.Plan(512, e, chimera=(8, 8), z2=True)
+    say("z2 chimera 8x8 planted: backward")
+    E, sig, _, _ = B.backward(plan, dev(x.J[None]))
+    s = sig[0].cpu().numpy()
+    assert E[0].item() == -len(e)
+    assert np.array_equal(s, tau) or np.array_equal(s, -tau)
+    say("z2 chimera 8x8 planted: count")
+    Ec, _, g = B.count(plan, dev(x.J[None]))
+    plan.close()
+    assert Ec[0] == -len(e) and g[0] == 2
+
+
+def test_chimera_half_state_full_size_random():
+    """8 x 8 random +-J: the half-state plan's E*, residues and g equal the
+    full-state plan's; E(sigma) = E*."""
+    x = I.config_instances(4)[0]
+    e = x.edges
+    half = B.Plan(512, e, chimera=(8, 8), z2=True)
+    say("z2 chimera 8x8 pm1: backward and count")
+    E, sig, _, _ = B.backward(half, dev(x.J[None]))
+    E = E[0].item()
+    assert O.energy(512, e, x.J, None, sig[0].cpu().numpy()) == E
+    Ec, res, g = B.count(half, dev(x.J[None]))
+    half.close()
+    full = B.Plan(512, e, chimera=(8, 8))
+    say("z2 chimera 8x8 pm1: full-state reference")
+    Ef = B.contract(full, dev(x.J[None]).float().contiguous()).cpu().numpy()[0]
+    Ecf, resf, gf = B.count(full, dev(x.J[None]))
+    full.close()
+    assert E == Ef and Ec[0] == Ecf[0] and np.array_equal(res, resf) and g[0] == gf[0]

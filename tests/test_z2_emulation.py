@@ -72,7 +72,7 @@ def test_z2_needs_a_plan_without_fields():
     with pytest.raises(B.TTError):
         B.Plan(16, I.square_lattice(4), order=list(range(16)), has_field=True, z2=True)
     with pytest.raises(B.TTError):
-        B.Plan(32, I.chimera(2, 2), chimera=(2, 2), z2=True)
+        B.Plan(32, I.chimera(2, 2), chimera=(2, 2), has_field=True, z2=True)
     with pytest.raises(B.TTError):
         B.Plan(16, I.square_lattice(4), order=list(range(16)), z2=True, n_fixed=2)
     with pytest.raises(B.TTError):
