@@ -22,6 +22,7 @@ namespace tt {
 constexpr int CNT = 256;        // reductions
 constexpr int CNT_PASS = 1024;  // count passes: 16 waves hide the LDS latency of the per-op sweeps
 constexpr int NRES = 4;   // residue planes at most (the fourth: modulo 2^64)
+constexpr int CNT_MAX_OPS = 64;   // ops of one pass (the partitioner's bound)
 
 // modulus 0 stands for 2^64
 __device__ __constant__ uint64_t c_mod[NRES] = {(1ull << 61) - 1, (1ull << 61) - 31, (1ull << 61) - 45, 0};
@@ -65,11 +66,24 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
   uint64_t* tn = csm;                                        // [nres][size]
   float* tx = reinterpret_cast<float*>(csm + nres * size);   // [size]
   __shared__ uint64_t dep_lo[256], dep_hi[256];
+  __shared__ DevOp s_op[CNT_MAX_OPS];
+  __shared__ float s_val[CNT_MAX_OPS];
   const int64_t inst = (int64_t)blockIdx.x >> log2_tiles;
   const uint64_t tile_id = z2_tile((uint64_t)blockIdx.x & ((1ull << log2_tiles) - 1ull), z2 ? P.z2_skip : -1);
   uint64_t base = 0;
   for (int k = 0; k < P.n_free; ++k) base |= ((tile_id >> k) & 1ull) << P.fre[k];
   cbuild_deposit(P.R, P.t, dep_lo, dep_hi);
+  // the pass's ops and their couplings / fields, read once per tile and all
+  // at the same time (a dependent read per op would stall every op)
+  const int32_t* Jrow = J + inst * jst;
+  const int32_t* hrow = h ? h + inst * hst : nullptr;
+  for (int o = threadIdx.x; o < P.n_ops; o += CNT_PASS) {
+    const DevOp op = ops[P.op_begin + o];
+    s_op[o] = op;
+    s_val[o] = (op.kind == OP_GATE || op.kind == OP_DIAG) ? (float)Jrow[op.param]
+               : (op.kind == OP_FIELD && hrow)              ? (float)hrow[op.param]
+                                                            : 0.f;
+  }
   __syncthreads();
   const uint64_t in_mask = (1ull << P.in_w) - 1ull;
   const float* xs = xin + inst * sst;
@@ -86,13 +100,10 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
     }
   }
   __syncthreads();
-  const int32_t* Jrow = J + inst * jst;
-  const int32_t* hrow = h ? h + inst * hst : nullptr;
-  const DevOp* po = ops + P.op_begin;
   for (int o = 0; o < P.n_ops; ++o) {
-    const DevOp op = po[o];
+    const DevOp op = s_op[o];
     if (op.kind == OP_GATE || op.kind == OP_CUT) {
-      const float Jv = op.kind == OP_GATE ? (float)Jrow[op.param] : 0.f;
+      const float Jv = s_val[o];
       const int b = op.a;
       const uint32_t lowmask = (1u << b) - 1u;
       for (uint32_t p = threadIdx.x; p < (size >> 1); p += CNT_PASS) {
@@ -111,12 +122,12 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
       }
       __syncthreads();
     } else if (op.kind == OP_DIAG) {
-      const float Jv = (float)Jrow[op.param];
+      const float Jv = s_val[o];
       for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS)
         tx[i] += (cbit(op.a, i, base) ^ cbit(op.b, i, base)) ? -Jv : Jv;
       __syncthreads();
     } else if (op.kind == OP_FIELD) {
-      const float hv = (float)hrow[op.param];
+      const float hv = s_val[o];
       for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) tx[i] += cbit(op.a, i, base) ? -hv : hv;
       __syncthreads();
     }
@@ -217,7 +228,7 @@ int count_reduce_log2_chunks(int w) {
 hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h, int64_t jst,
                              int64_t hst, const float* xin, const uint64_t* nin, float* xout, uint64_t* nout,
                              int64_t sst, int batch, int nres, bool z2, hipStream_t stream) {
-  if (nres < 3 || nres > NRES) return hipErrorInvalidValue;
+  if (nres < 3 || nres > NRES || P.n_ops > CNT_MAX_OPS) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << P.t) * (sizeof(float) + nres * sizeof(uint64_t));
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_count_pass),
