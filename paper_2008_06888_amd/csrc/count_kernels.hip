@@ -27,6 +27,12 @@ constexpr int CNT_MAX_OPS = 64;   // ops of one pass (the partitioner's bound)
 // modulus 0 stands for 2^64
 __device__ __constant__ uint64_t c_mod[NRES] = {(1ull << 61) - 1, (1ull << 61) - 31, (1ull << 61) - 45, 0};
 
+// The modulus of residue plane r as a compile-time constant (r known at
+// compile time after unrolling): no memory read in the inner loops.
+__host__ __device__ constexpr uint64_t mod_of(int r) {
+  return r == 0 ? (1ull << 61) - 1 : r == 1 ? (1ull << 61) - 31 : r == 2 ? (1ull << 61) - 45 : 0ull;
+}
+
 __device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t p) {
   const uint64_t s = a + b;   // a, b < p < 2^61: no overflow; p = 0: modulo 2^64
   return (p != 0 && s >= p) ? s - p : s;
@@ -113,12 +119,22 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
         const float c00 = a0 + Jv, c10 = a1 - Jv, c01 = a0 - Jv, c11 = a1 + Jv;
         tx[i0] = fmaxf(c00, c10);
         tx[i1] = fmaxf(c01, c11);
-        for (int r = 0; r < nres; ++r) {
-          const uint64_t n0 = tn[r * size + i0], n1 = tn[r * size + i1];
-          const uint64_t both = addmod(n0, n1, c_mod[r]);
-          tn[r * size + i0] = c00 > c10 ? n0 : (c10 > c00 ? n1 : both);
-          tn[r * size + i1] = c01 > c11 ? n0 : (c11 > c01 ? n1 : both);
-        }
+        // every plane's reads issue together, then the updates (the planes
+        // and their moduli unrolled at compile time)
+        uint64_t n0[NRES], n1[NRES];
+#pragma unroll
+        for (int r = 0; r < NRES; ++r)
+          if (r < nres) {
+            n0[r] = tn[r * size + i0];
+            n1[r] = tn[r * size + i1];
+          }
+#pragma unroll
+        for (int r = 0; r < NRES; ++r)
+          if (r < nres) {
+            const uint64_t both = addmod(n0[r], n1[r], mod_of(r));
+            tn[r * size + i0] = c00 > c10 ? n0[r] : (c10 > c00 ? n1[r] : both);
+            tn[r * size + i1] = c01 > c11 ? n0[r] : (c11 > c01 ? n1[r] : both);
+          }
       }
       __syncthreads();
     } else if (op.kind == OP_DIAG) {
