@@ -23,6 +23,8 @@ constexpr int CNT = 256;        // reductions
 constexpr int CNT_PASS = 1024;  // count passes: 16 waves hide the LDS latency of the per-op sweeps
 constexpr int NRES = 4;   // residue planes at most (the fourth: modulo 2^64)
 constexpr int CNT_MAX_OPS = 64;   // ops of one pass (the partitioner's bound)
+constexpr int CNT_MAX_T = 12;     // tile bits at most (the count tile option's bound)
+constexpr int CNT_PER_THREAD = (1 << CNT_MAX_T) / CNT_PASS;   // tile entries per thread at most
 
 // modulus 0 stands for 2^64
 __device__ __constant__ uint64_t c_mod[NRES] = {(1ull << 61) - 1, (1ull << 61) - 31, (1ull << 61) - 45, 0};
@@ -94,15 +96,36 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
   const uint64_t in_mask = (1ull << P.in_w) - 1ull;
   const float* xs = xin + inst * sst;
   const uint64_t* ns = nin + inst * sst * nres;
-  for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) {
-    uint64_t idx = (base | dep_lo[i & 255u] | dep_hi[i >> 8]) & in_mask;
-    if (z2) idx = z2_addr(idx, P.in_w);
-    if (P.init) {
-      tx[i] = 0.f;
-      for (int r = 0; r < nres; ++r) tn[r * size + i] = 1ull;
-    } else {
-      tx[i] = xs[idx];
-      for (int r = 0; r < nres; ++r) tn[r * size + i] = ns[r * sst + idx];
+  {
+    // every load of the thread's entries (at most CNT_PER_THREAD) is issued
+    // before the first is written to LDS, so the tile arrives in one round
+    // trip instead of one per entry
+    float xv[CNT_PER_THREAD];
+    uint64_t nv[CNT_PER_THREAD][NRES];
+#pragma unroll
+    for (int k = 0; k < CNT_PER_THREAD; ++k) {
+      const uint32_t i = threadIdx.x + (uint32_t)k * CNT_PASS;
+      xv[k] = 0.f;
+#pragma unroll
+      for (int r = 0; r < NRES; ++r) nv[k][r] = 1ull;
+      if (i < size && !P.init) {
+        uint64_t idx = (base | dep_lo[i & 255u] | dep_hi[i >> 8]) & in_mask;
+        if (z2) idx = z2_addr(idx, P.in_w);
+        xv[k] = xs[idx];
+#pragma unroll
+        for (int r = 0; r < NRES; ++r)
+          if (r < nres) nv[k][r] = ns[r * sst + idx];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CNT_PER_THREAD; ++k) {
+      const uint32_t i = threadIdx.x + (uint32_t)k * CNT_PASS;
+      if (i < size) {
+        tx[i] = xv[k];
+#pragma unroll
+        for (int r = 0; r < NRES; ++r)
+          if (r < nres) tn[r * size + i] = nv[k][r];
+      }
     }
   }
   __syncthreads();
@@ -244,7 +267,7 @@ int count_reduce_log2_chunks(int w) {
 hipError_t launch_count_pass(const DevPass& P, const DevOp* ops, const int32_t* J, const int32_t* h, int64_t jst,
                              int64_t hst, const float* xin, const uint64_t* nin, float* xout, uint64_t* nout,
                              int64_t sst, int batch, int nres, bool z2, hipStream_t stream) {
-  if (nres < 3 || nres > NRES || P.n_ops > CNT_MAX_OPS) return hipErrorInvalidValue;
+  if (nres < 3 || nres > NRES || P.n_ops > CNT_MAX_OPS || P.t > CNT_MAX_T) return hipErrorInvalidValue;
   const size_t lds = ((size_t)1 << P.t) * (sizeof(float) + nres * sizeof(uint64_t));
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_count_pass),
