@@ -135,51 +135,79 @@ __global__ __launch_bounds__(CNT_PASS) void k_count_pass(DevPass P, const DevOp*
       const float Jv = s_val[o];
       const int b = op.a;
       const uint32_t lowmask = (1u << b) - 1u;
-      for (uint32_t p = threadIdx.x; p < (size >> 1); p += CNT_PASS) {
-        const uint32_t i0 = ((p & ~lowmask) << 1) | (p & lowmask);
-        const uint32_t i1 = i0 | (1u << b);
-        const float a0 = tx[i0], a1 = tx[i1];
-        const float c00 = a0 + Jv, c10 = a1 - Jv, c01 = a0 - Jv, c11 = a1 + Jv;
-        tx[i0] = fmaxf(c00, c10);
-        tx[i1] = fmaxf(c01, c11);
-        // every plane's reads issue together, then the updates (the planes
-        // and their moduli unrolled at compile time)
-        uint64_t n0[NRES], n1[NRES];
+      // the thread's pairs (at most two): every LDS read of both issued
+      // before the updates, the residue planes and their moduli unrolled at
+      // compile time
+      constexpr int PP = CNT_PER_THREAD / 2;
+      uint32_t j0[PP], j1[PP];
+      float a0[PP], a1[PP];
+      uint64_t n0[PP][NRES], n1[PP][NRES];
+#pragma unroll
+      for (int q = 0; q < PP; ++q) {
+        const uint32_t p = threadIdx.x + (uint32_t)q * CNT_PASS;
+        j0[q] = ((p & ~lowmask) << 1) | (p & lowmask);
+        j1[q] = j0[q] | (1u << b);
+        if (p < (size >> 1)) {
+          a0[q] = tx[j0[q]];
+          a1[q] = tx[j1[q]];
+#pragma unroll
+          for (int r = 0; r < NRES; ++r)
+            if (r < nres) {
+              n0[q][r] = tn[r * size + j0[q]];
+              n1[q][r] = tn[r * size + j1[q]];
+            }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PP; ++q) {
+        const uint32_t p = threadIdx.x + (uint32_t)q * CNT_PASS;
+        if (p >= (size >> 1)) continue;
+        const float c00 = a0[q] + Jv, c10 = a1[q] - Jv, c01 = a0[q] - Jv, c11 = a1[q] + Jv;
+        tx[j0[q]] = fmaxf(c00, c10);
+        tx[j1[q]] = fmaxf(c01, c11);
 #pragma unroll
         for (int r = 0; r < NRES; ++r)
           if (r < nres) {
-            n0[r] = tn[r * size + i0];
-            n1[r] = tn[r * size + i1];
-          }
-#pragma unroll
-        for (int r = 0; r < NRES; ++r)
-          if (r < nres) {
-            const uint64_t both = addmod(n0[r], n1[r], mod_of(r));
-            tn[r * size + i0] = c00 > c10 ? n0[r] : (c10 > c00 ? n1[r] : both);
-            tn[r * size + i1] = c01 > c11 ? n0[r] : (c11 > c01 ? n1[r] : both);
+            const uint64_t both = addmod(n0[q][r], n1[q][r], mod_of(r));
+            tn[r * size + j0[q]] = c00 > c10 ? n0[q][r] : (c10 > c00 ? n1[q][r] : both);
+            tn[r * size + j1[q]] = c01 > c11 ? n0[q][r] : (c11 > c01 ? n1[q][r] : both);
           }
       }
       __syncthreads();
-    } else if (op.kind == OP_DIAG) {
-      const float Jv = s_val[o];
-      for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS)
-        tx[i] += (cbit(op.a, i, base) ^ cbit(op.b, i, base)) ? -Jv : Jv;
-      __syncthreads();
-    } else if (op.kind == OP_FIELD) {
-      const float hv = s_val[o];
-      for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) tx[i] += cbit(op.a, i, base) ? -hv : hv;
+    } else if (op.kind == OP_DIAG || op.kind == OP_FIELD) {
+      const float v = s_val[o];
+      const bool diag = op.kind == OP_DIAG;
+      float xv[CNT_PER_THREAD];
+#pragma unroll
+      for (int k = 0; k < CNT_PER_THREAD; ++k) {
+        const uint32_t i = threadIdx.x + (uint32_t)k * CNT_PASS;
+        if (i < size) xv[k] = tx[i];
+      }
+#pragma unroll
+      for (int k = 0; k < CNT_PER_THREAD; ++k) {
+        const uint32_t i = threadIdx.x + (uint32_t)k * CNT_PASS;
+        if (i < size) {
+          const int s = diag ? (cbit(op.a, i, base) ^ cbit(op.b, i, base)) : cbit(op.a, i, base);
+          tx[i] = xv[k] + (s ? -v : v);
+        }
+      }
       __syncthreads();
     }
   }
   float* xd = xout + inst * sst;
   uint64_t* nd = nout + inst * sst * nres;
-  for (uint32_t i = threadIdx.x; i < size; i += CNT_PASS) {
+#pragma unroll
+  for (int k = 0; k < CNT_PER_THREAD; ++k) {
+    const uint32_t i = threadIdx.x + (uint32_t)k * CNT_PASS;
+    if (i >= size) continue;
     uint64_t idx = base | dep_lo[i & 255u] | dep_hi[i >> 8];
     if ((idx >> P.out_w) != 0) continue;
     if (z2) idx = z2_addr(idx, P.out_w);
     // non-temporal: the next pass reads the state from memory
     __builtin_nontemporal_store(tx[i], &xd[idx]);
-    for (int r = 0; r < nres; ++r) __builtin_nontemporal_store(tn[r * size + i], &nd[r * sst + idx]);
+#pragma unroll
+    for (int r = 0; r < NRES; ++r)
+      if (r < nres) __builtin_nontemporal_store(tn[r * size + i], &nd[r * sst + idx]);
   }
 }
 
