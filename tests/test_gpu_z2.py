@@ -298,3 +298,23 @@ def test_chimera_half_state_full_size_random():
     Ecf, resf, gf = B.count(full, dev(x.J[None]))
     full.close()
     assert E == Ef and Ec[0] == Ecf[0] and np.array_equal(res, resf) and g[0] == gf[0]
+
+
+@pytest.mark.parametrize("case", ["edge", "path3", "ring4", "star5", "zero_ring6"])
+def test_tiny_graphs(case):
+    """Degenerate widths (a 1- or 2-bit state, J = 0 ties): E*, a ground
+    state and g against the oracle on the half state."""
+    graphs = {"edge": (2, [(0, 1)]), "path3": (3, [(0, 1), (1, 2)]), "ring4": (4, [(0, 1), (1, 2), (2, 3), (0, 3)]),
+              "star5": (5, [(0, 1), (0, 2), (0, 3), (0, 4)]), "zero_ring6": (6, [(i, (i + 1) % 6) for i in range(6)])}
+    n, el = graphs[case]
+    e = np.array(sorted((min(a, b), max(a, b)) for a, b in el), dtype=np.int32)
+    rng = np.random.default_rng([97, n])
+    J = np.zeros((2, len(e)), np.int32) if case.startswith("zero") else np.stack([I.pm1(len(e), rng) for _ in range(2)])
+    plan = B.Plan(n, e, seed=0, z2=True)
+    say("z2 tiny", case, "width", plan.info()["width"])
+    E, sig, dJ, _ = [x.cpu().numpy() if x is not None else None for x in B.backward(plan, dev(J))]
+    Ec, _, g = B.count(plan, dev(J))
+    for b in range(2):
+        ref = O.eliminate(n, e, J[b], None, counts="exact", traceback=False)
+        assert E[b] == ref["energy"] and Ec[b] == ref["energy"] and g[b] == ref["count"], b
+        assert O.energy(n, e, J[b], None, sig[b]) == ref["energy"], b
