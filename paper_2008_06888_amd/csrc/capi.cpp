@@ -437,7 +437,7 @@ int64_t stored_entries(const Plan& p, int w) { return (int64_t)1 << (w - (p.z2 &
 int64_t state_bytes(const Plan& p, int64_t batch, bool backward) {
   const int64_t f = (int64_t)sizeof(float);
   if (p.is_chimera) {
-    const int64_t per = (batch * f << p.width) + 255 & ~int64_t(255);
+    const int64_t per = (batch * f * stored_entries(p, p.width) + 255) & ~int64_t(255);
     return (2 + (backward ? p.chim.rows - 1 : 0)) * per;
   }
   if (!backward) return 2 * batch * f * stored_entries(p, p.width);
