@@ -318,3 +318,19 @@ def test_tiny_graphs(case):
         ref = O.eliminate(n, e, J[b], None, counts="exact", traceback=False)
         assert E[b] == ref["energy"] and Ec[b] == ref["energy"] and g[b] == ref["count"], b
         assert O.energy(n, e, J[b], None, sig[b]) == ref["energy"], b
+
+
+def test_uneven_batch_mixing_half_and_full_state_plans():
+    """One uneven call over half-state and full-state plans (launches hold
+    both kinds of items): E* and sigma equal to one call per instance."""
+    rng = np.random.default_rng(98)
+    graphs = [(n, I.random_regular(n, 3, rng)) for n in (24, 36, 48, 60)]
+    plans = [B.Plan(n, e, seed=2, z2=(k % 2 == 0)) for k, (n, e) in enumerate(graphs)]
+    Js = [dev(I.gauss(len(e), rng).astype(np.float32)) for _, e in graphs]
+    say("z2 uneven mixed")
+    res = B.contract_uneven(plans, Js)
+    Eu = res[0].cpu().numpy()
+    for i, ((n, e), p, J) in enumerate(zip(graphs, plans, Js)):
+        E1, s1, _, _ = B.backward(p, J[None].contiguous())
+        assert abs(Eu[i] - E1.cpu().numpy()[0]) <= 1e-5 * n, i
+        assert abs(O.energy(n, e, J.cpu().numpy(), None, res[1][i].cpu().numpy()) - Eu[i]) <= 1e-5 * n, i
