@@ -68,9 +68,9 @@ typedef enum tt_dtype {
                                otherwise; Sec. V keeps the chimera state in Int16 for the
                                same reason). tt_contract, tt_backward(_tie) and
                                tt_plan_autotune on sweep and chimera plans (sliced
-                               ones included); other calls return TT_E_DTYPE, and a
+                               ones included); other calls return TT_E_DTYPE. A
                                backward whose pass inputs do not all fit the budget
-                               returns TT_E_TOOBIG (no recomputation at int16). */
+                               recomputes them from int16 snapshots. */
 } tt_dtype;
 
 typedef enum tt_order_kind {
@@ -107,9 +107,9 @@ typedef struct tt_plan_opts {
                                every pass. tt_contract, tt_backward(_tie),
                                tt_contract_uneven(_fields) and tt_count (whose
                                (x, n) states are halved the same way) accept such
-                               plans; a backward that would need checkpoint
-                               recomputation returns TT_E_TOOBIG, the
-                               allocation-free call TT_E_INVAL. [0] */
+                               plans (a backward whose pass inputs do not all fit
+                               recomputes them from half-size snapshots); the
+                               allocation-free call returns TT_E_INVAL. [0] */
 } tt_plan_opts;
 
 typedef struct tt_plan_stats {
@@ -217,7 +217,12 @@ int tt_contract_noalloc(tt_plan* plan, int32_t batch, int32_t dtype, const void*
 /* Energy plus one ground state (Sec. IV): sigma device int8 [batch][n_spins]
  * in {+1,-1}; dJ device float [batch][n_edges] = -s_i s_j and dh device
  * float [batch][n_spins] = -s_i (either may be NULL). Ties resolve to the
- * first argument of every max along the plan. */
+ * first argument of every max along the plan. When the input of every pass
+ * does not fit the budget, a same-graph sweep plan keeps as many snapshots of
+ * pass inputs as fit, each the size of the widest stored state, and
+ * recomputes the others segment by segment (Sec. IV: memory traded for
+ * time); the results are the same bit for bit. Fewer than two such states
+ * within the budget: TT_E_TOOBIG. */
 int tt_backward(tt_plan* plan, int32_t batch, int32_t dtype, const void* J,
                 const void* h, double* energy, int8_t* sigma, float* dJ,
                 float* dh, void* stream);

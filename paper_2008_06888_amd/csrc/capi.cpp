@@ -1420,9 +1420,11 @@ struct Recompute {
   }
 };
 
-// Bytes of one state of the widest pass for the batch (256-byte aligned).
-size_t widest_state(const Plan& p, int64_t batch) {
-  return (((size_t)batch << p.width) * sizeof(float) + 255) & ~size_t(255);
+// Bytes of one state of the widest pass for the batch (256-byte aligned):
+// its stored entries (half of them on a half-state plan) in the state's
+// element type (int16 with int16 couplings, else float).
+size_t widest_state(const Plan& p, int64_t batch, int32_t dtype = TT_F32) {
+  return ((size_t)batch * (size_t)stored_entries(p, p.width) * state_esz(dtype) + 255) & ~size_t(255);
 }
 
 int run_backward_recompute(Group& g0, int32_t dtype, hipStream_t s) {
@@ -1431,9 +1433,17 @@ int run_backward_recompute(Group& g0, int32_t dtype, hipStream_t s) {
   bind_program(g0);
   DevCache* dc = g0.dc;
   const int np = (int)g0.ep->passes.size();
-  const size_t per = widest_state(p, g0.batch);
-  const int64_t budget = budget_bytes(p) + (int64_t)dc->ckpt.cap;
-  const int64_t nbuf = std::min<int64_t>(budget / (int64_t)per, np + 1);
+  const size_t per = widest_state(p, g0.batch, dtype);
+  // states the call keeps (snapshots and two working states): an explicit
+  // budget bounds the buffer itself; the default one (a share of the free
+  // device memory) adds to what the plan holds already, which is kept as it
+  // is unless the free memory allows a quarter more states or more (growing
+  // frees and allocates the whole buffer again)
+  const int64_t held = (int64_t)(dc->ckpt.cap / per);
+  const int64_t budget = p.max_bytes > 0 ? p.max_bytes : budget_bytes(p) + (int64_t)dc->ckpt.cap;
+  int64_t nbuf = budget / (int64_t)per;
+  if (p.max_bytes <= 0 && held >= 2 && nbuf < held + held / 4 + 1) nbuf = held;
+  nbuf = std::min<int64_t>(nbuf, np + 1);
   if (nbuf < 2)
     return fail(TT_E_TOOBIG, "the backward needs at least two states of %zu bytes (budget %lld)", per,
                 (long long)budget);
@@ -1451,7 +1461,7 @@ int run_backward_recompute(Group& g0, int32_t dtype, hipStream_t s) {
   R.carry = g0.arg + g0.batch;
   g0.strides.assign(np + 1, 0);
   for (int q = 0; q <= np; ++q)
-    g0.strides[q] = (int64_t)1 << (q < np ? g0.ep->passes[q].in_w : g0.ep->passes[np - 1].out_w);
+    g0.strides[q] = stored_entries(p, q < np ? g0.ep->passes[q].in_w : g0.ep->passes[np - 1].out_w);
   g0.part_st = g0.strides;
   std::vector<Group> gs(1, g0);
   const int64_t nparts = red_parts_needed(gs, false);
@@ -1491,15 +1501,7 @@ int run_groups(std::vector<Group>& groups, int32_t dtype, bool backward, hipStre
     const int64_t need = state_bytes(p, groups[0].batch, true);
     const DevCache* dc = static_cast<const DevCache*>(p.dev);
     const int64_t have = dc ? (int64_t)dc->ckpt.cap : 0;
-    if (need > have && need > budget_bytes(p) + have) {
-      if (p.z2)
-        return fail(TT_E_TOOBIG, "the half-state backward keeps every pass input: %lld bytes (budget %lld)",
-                    (long long)need, (long long)budget_bytes(p));
-      if (dtype == TT_I16)
-        return fail(TT_E_TOOBIG, "the int16 backward keeps every pass input: %lld bytes (budget %lld)",
-                    (long long)need, (long long)budget_bytes(p));
-      return run_backward_recompute(groups[0], dtype, s);
-    }
+    if (need > have && need > budget_bytes(p) + have) return run_backward_recompute(groups[0], dtype, s);
   }
   for (Group& g : groups)
     if (int r = prepare_group(g, backward)) return r;
@@ -2686,7 +2688,7 @@ int tt_backward_tie(tt_plan* plan, int32_t batch, int32_t dtype, const void* J, 
     Plan& p = *reinterpret_cast<Plan*>(plan);
     if (p.n_regs != 1) return fail(TT_E_INVAL, "backward over multi-register plans is not supported");
     if (p.n > 8192) return fail(TT_E_INVAL, "too many spins for the backward walk");
-    if (int r = early_budget(p, p.is_chimera ? state_bytes(p, batch, true) : 2 * (int64_t)widest_state(p, batch)))
+    if (int r = early_budget(p, p.is_chimera ? state_bytes(p, batch, true) : 2 * (int64_t)widest_state(p, batch, dtype)))
       return r;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     PendingCheck pc;

@@ -33,8 +33,10 @@ def dev(x):
     return torch.tensor(np.ascontiguousarray(x), device=DEV)
 
 
-def widest(batch, width):
-    return ((batch << width) * 4 + 255) & ~255
+def widest(batch, width, esz=4):
+    """Bytes of one state of the widest pass (256-byte aligned): width is log2
+    of the entries stored per instance, esz the bytes of one entry."""
+    return ((batch << width) * esz + 255) & ~255
 
 
 def solve(L, insts, tile, max_bytes=0):
@@ -101,4 +103,52 @@ def test_square32_pm1_ground_state_by_recomputation():
     E, s = E.cpu().numpy()[0], sig.cpu().numpy()[0]
     assert E == E0
     assert O.energy(1024, x.edges, x.J, None, s) == E0 and O.energy(1024, x.edges, x.J, None, -s) == E0
+    assert np.array_equal(dJ.cpu().numpy()[0], O.ground_state_gradient(x.edges, s)[0].astype(np.float32))
+
+
+@pytest.mark.parametrize("snapshots", [0, 2, 5])
+@pytest.mark.parametrize("kind", ["half", "int16", "half_int16"])
+def test_recompute_half_state_and_int16(kind, snapshots):
+    # half-state plans (h = 0: half of every state stored) and int16 states:
+    # snapshots of the stored entries in the state's element type; the walk is
+    # that of the store-all backward of the same plan and dtype
+    L, batch = 14, 3
+    n = L * L
+    z2, i16 = kind.startswith("half"), kind.endswith("int16")
+    insts = I.config_instances(0, batch=batch, L=L)
+    J = np.stack([x.J for x in insts])
+    Jd = dev(J.astype(np.int16)) if i16 else dev(J)
+
+    def run(max_bytes):
+        plan = B.Plan(n, insts[0].edges, order=list(range(n)), tile_bits=8, parts=1, z2=z2, max_bytes=max_bytes)
+        return plan, [t.cpu().numpy() for t in B.backward(plan, Jd)[:3]]
+
+    ref_plan, ref = run(0)
+    info = ref_plan.info()
+    per = widest(batch, info["width"] - (1 if z2 else 0), 2 if i16 else 4)
+    say("recompute 14x14 pm1", kind, "passes", info["n_passes"], "snapshots", snapshots, "state bytes", per)
+    _, got = run((snapshots + 2) * per)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    full = B.Plan(n, insts[0].edges, order=list(range(n)), tile_bits=8)
+    E32 = B.contract(full, dev(J)).cpu().numpy()
+    assert np.array_equal(got[0], E32)
+    for k, x in enumerate(insts):
+        assert O.energy(n, x.edges, x.J, None, got[1][k]) == got[0][k]
+        assert np.array_equal(got[2][k], O.ground_state_gradient(x.edges, got[1][k])[0].astype(np.float32))
+
+
+def test_square32_pm1_ground_state_half_state_int16_by_recomputation():
+    # the half-state plan with int16 couplings keeps snapshots of 4 GiB (2^31
+    # stored entries of two bytes) instead of 16 GiB
+    x = I.config_instances(2)[0]
+    say("square32 pm1 energy, full state, float32 couplings")
+    E32 = B.contract(B.Plan(1024, x.edges, order=list(range(1024))), dev(x.J[None])).cpu().numpy()[0]
+    plan = B.Plan(1024, x.edges, order=list(range(1024)), z2=True)
+    J = dev(x.J[None].astype(np.int16))
+    say("square32 pm1 backward with recomputation, half state, int16")
+    E, sig, dJ, _ = B.backward(plan, J)
+    E, s = E.cpu().numpy()[0], sig.cpu().numpy()[0]
+    assert E == E32
+    assert O.energy(1024, x.edges, x.J, None, s) == E32 and O.energy(1024, x.edges, x.J, None, -s) == E32
     assert np.array_equal(dJ.cpu().numpy()[0], O.ground_state_gradient(x.edges, s)[0].astype(np.float32))
