@@ -152,3 +152,8 @@ def test_square32_pm1_ground_state_half_state_int16_by_recomputation():
     assert E == E32
     assert O.energy(1024, x.edges, x.J, None, s) == E32 and O.energy(1024, x.edges, x.J, None, -s) == E32
     assert np.array_equal(dJ.cpu().numpy()[0], O.ground_state_gradient(x.edges, s)[0].astype(np.float32))
+    # a second call keeps the snapshot buffer the first one allocated: same results
+    say("square32 pm1 backward with recomputation, second call")
+    E2, sig2, dJ2, _ = B.backward(plan, J)
+    assert E2.cpu().numpy()[0] == E and np.array_equal(sig2.cpu().numpy()[0], s)
+    assert np.array_equal(dJ2.cpu().numpy(), dJ.cpu().numpy())
