@@ -18,11 +18,10 @@ entries its passes visit).
 Without fields the half-state plan (z2: the energy is even under flipping all
 spins, so half of every state is stored) and the full-state plan are both
 autotuned and the faster is timed; the JSON line says which. The steps are
-timed one after another on one stream, and going round two or three plans
-of the chosen configuration on as many streams (two or three batches in
-flight, so that one batch's walk and passes overlap the next batches'
-passes); the fastest schedule is the measured figure and the line gives all
-three.
+timed one after another on one stream, and going round two, three or four
+plans of the chosen configuration on as many streams (batches in flight, so
+that one batch's walk and passes overlap the next batches' passes); the
+fastest schedule is the measured figure and the line gives all four.
 
 Prints one JSON line (metric, value = solves/s, roofline of the dominant
 kernel, CPU-oracle baseline). Only one GPU is used; --gpus above 1 exits.
@@ -617,14 +616,19 @@ def run_lattice(args, B, edges, n, J, h, workload):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
-    # batches in flight: further plans of the same configuration, each on a
+    # batches in flight: k plans of the chosen configuration, each on a
     # stream of its own, consecutive steps going round them, so that one
     # batch's walk (one workgroup per instance) and passes overlap the next
-    # batches' passes; every step still solves a whole batch
+    # batches' passes; every step still solves a whole batch. The streams are
+    # k consecutive ones of torch's pool, not the current stream: the pool's
+    # streams take the device's hardware queues in turn, so consecutive ones
+    # (up to the number of queues, four) run on different queues, while
+    # the current stream may share its queue with one of them
     def in_flight(k):
-        ring = [(plan, torch.cuda.current_stream())]
-        ring += [(B.Plan(n, edges, order=list(range(n)), has_field=has_h, tile_bits=tile_bits,
-                         parts=info["parts"], z2=half), torch.cuda.Stream()) for _ in range(k - 1)]
+        torch.cuda.synchronize()
+        streams = [torch.cuda.Stream() for _ in range(k)]
+        ring = [(plan if j == 0 else B.Plan(n, edges, order=list(range(n)), has_field=has_h, tile_bits=tile_bits,
+                                           parts=info["parts"], z2=half), streams[j]) for j in range(k)]
 
         def step(i):
             p, st = ring[i % k]
@@ -641,7 +645,7 @@ def run_lattice(args, B, edges, n, J, h, workload):
         for p, _ in ring[1:]:
             p.close()
         return t
-    dt_k = {1: dt, 2: in_flight(2), 3: in_flight(3)}
+    dt_k = {1: dt, 2: in_flight(2), 3: in_flight(3), 4: in_flight(4)}
 
     def kernel_times(p, steps):
         B.prof_reset()

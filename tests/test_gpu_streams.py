@@ -41,7 +41,9 @@ def test_two_streams_alternating_batches(z2):
     ref_plan = B.Plan(n, insts[0].edges, order=list(range(n)), tile_bits=12, parts=1, z2=z2)
     ref = [[t.cpu().numpy() for t in B.backward(ref_plan, J)[:3]] for J in Js]
     plans = [B.Plan(n, insts[0].edges, order=list(range(n)), tile_bits=12, parts=1, z2=z2) for _ in range(2)]
-    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    # two consecutive streams of torch's pool: they take different hardware
+    # queues, so the calls really overlap
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     torch.cuda.synchronize()
     outs = []
     for i, J in enumerate(Js):
