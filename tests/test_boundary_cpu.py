@@ -167,3 +167,22 @@ def test_int16_refused_where_unsupported_before_device_work():
     assert lib.tt_contract_uneven(1, (C.c_void_p * 1)(p.handle), B.TT_I16, FAKE,
                                   np.zeros(1, np.int64).ctypes.data, FAKE, None, None, None, None) == B.TT_E_DTYPE
     assert lib.tt_contract(p.handle, 1, 3, FAKE, None, FAKE, None) == B.TT_E_DTYPE     # no dtype 3
+
+
+@pytest.mark.parametrize("z2,dtype", [(False, "f32"), (True, "f32"), (False, "i16"), (True, "i16")])
+def test_backward_budget_counts_stored_entries_in_their_type(z2, dtype):
+    """The backward needs at least two states of the widest pass (its working
+    states when inputs are recomputed): stored entries (half of them on a
+    half-state plan) of the state's element type (two bytes with int16
+    couplings), 256-byte aligned. One byte less than that is refused before
+    any device work, and the message names the amount."""
+    e = I.square_lattice(8)
+    p = B.Plan(64, e, order=list(range(64)), z2=z2, max_bytes=1)
+    width, batch = p.info()["width"], 4
+    esz = 2 if dtype == "i16" else 4
+    need = 2 * (((batch << (width - (1 if z2 else 0))) * esz + 255) & ~255)
+    q = B.Plan(64, e, order=list(range(64)), z2=z2, max_bytes=need - 1)
+    code = B.TT_I16 if dtype == "i16" else B.TT_F32
+    rc = B.lib().tt_backward(q.handle, batch, code, FAKE, None, FAKE, FAKE, None, None, None)
+    assert rc == B.TT_E_TOOBIG
+    assert f"needs {need} bytes".encode() in B.lib().tt_last_error()
